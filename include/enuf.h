@@ -1,0 +1,129 @@
+/*
+ * enuf.h -- C ABI of the MI355X (gfx950) ENUF electrostatics library.
+ *
+ * ENUF (Ewald summation with the non-uniform FFT, Wang, Laaksonen & Lu,
+ * Sec. 3) evaluates the electrostatic energy and per-particle forces of N
+ * point or Slater-smeared charges in a periodic cubic box of edge L:
+ *
+ *   E = E_real + E_recip + E_self                                   (eq. 16)
+ *   E_real  = sum_{i<j, r<r_cut} q_i q_j [erfc(alpha r) - (1 + r/lambda) e^{-2r/lambda}] / r
+ *             (eq. 31 plus the Slater correction of eq. 27, additive reading)
+ *   E_recip = 1/(2 pi L) sum_{0<|k|<Kc} exp(-pi^2 k^2/(alpha L)^2)/k^2 |S(k)|^2   (eq. 18)
+ *   S(k)    = sum_j q_j exp(-2 pi i k . r_j / L)                    (eq. 19)
+ *   E_self  = -(alpha/sqrt(pi)) sum_j q_j^2                        (eq. 16)
+ *
+ * S(k) is approximated by the transposed NFFT (eq. 14): the charges are
+ * spread onto an M^3 mesh with a window of half-width p mesh cells, the mesh
+ * is Fourier transformed and deconvolved.  Forces are the exact gradient of
+ * that approximate energy through the window (an inverse FFT of the
+ * influence-weighted spectrum, gathered with the window gradient) plus the
+ * exact gradient of E_real.  The Coulomb prefactor 1/(4 pi eps0 epsr) is 1.
+ *
+ * Conventions shared by every entry point below:
+ *  - Pointers named pos, q, forces, energy are DEVICE pointers on the device
+ *    that was current when the plan was created.  Work is only enqueued on
+ *    the plan's stream (default: the null stream); the call returns before
+ *    it completes, and the caller keeps the buffers alive until then.
+ *  - Return values are ENUF_* status codes; a NULL plan from a *_create call
+ *    means failure.  enuf_last_error() then holds a message (per thread).
+ *  - A plan is not thread safe.  Different plans may be used concurrently.
+ */
+#ifndef ENUF_H
+#define ENUF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define ENUF_OK            0
+#define ENUF_EINVAL       -1   /* invalid argument (detected on the host, synchronously) */
+#define ENUF_ENOMEM       -2   /* device allocation failed */
+#define ENUF_EDEVICE      -3   /* a HIP runtime call failed */
+#define ENUF_ENONNEUTRAL  -4   /* |sum q| > 1e-10 sum |q| (the method assumes neutrality, Sec. 3.1) */
+#define ENUF_ENONFINITE   -5   /* a position or charge is NaN or infinite */
+#define ENUF_EBUSY        -6   /* resource limit reached (serving / batching) */
+#define ENUF_ECOINCIDENT  -7   /* two point charges (lambda = 0) at the same position */
+#define ENUF_EOVERFLOW    -8   /* a cell held more charges than its capacity, or a
+                                  fixed-point accumulator left its range */
+
+/* Precision modes. */
+#define ENUF_FP64   0   /* every stage in FP64 */
+#define ENUF_MIXED  1   /* spread, FFT and gather in FP32; influence coefficients,
+                           energy reduction and the real-space term in FP64 */
+
+/* Window functions of the NFFT. */
+#define ENUF_WINDOW_KB     0   /* Kaiser-Bessel (default) */
+#define ENUF_WINDOW_GAUSS  1   /* Gaussian, the window named in Sec. 4 */
+
+typedef struct enuf_plan enuf_plan;
+
+/*
+ * Create a plan for N particles (charged or not) in a cubic box of edge `box`.
+ *   alpha  : Ewald splitting parameter (> 0), eq. 16.
+ *   p      : window half-width in mesh cells; 2p points per axis (1 <= p <= 15, 2p <= M/2).
+ *   sigma  : oversampling factor sigma_s >= 1 (Sec. 3.3); enters the Kaiser-Bessel
+ *            shape b = pi (2 - 1/sigma) and the Gaussian width.
+ *   M      : FFT mesh points per side; even and of the form 2^a 3^b 5^c.
+ *   Kc     : reciprocal cutoff; integer wave vectors with 0 < |k| < Kc are summed
+ *            (1 <= Kc <= M/(2 sigma)).
+ *   r_cut  : real-space cutoff, 0 < r_cut <= box/2 (minimum image).
+ *   lambda : Slater decay length lambda_e of eq. 26 (>= 0); 0 means point charges.
+ * Allocates all device scratch on the current device.  Returns NULL on error.
+ */
+enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma,
+                            int M, int Kc, double r_cut, double lambda);
+
+/* Release the plan and its device memory.  Synchronises the plan's stream.  NULL is a no-op. */
+void enuf_destroy(enuf_plan *plan);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *enuf_last_error(void);
+
+/* Bind the plan to a HIP stream (a hipStream_t passed as void*; NULL = null stream). */
+int enuf_plan_set_stream(enuf_plan *plan, void *hip_stream);
+
+/* Choose the precision mode (ENUF_FP64 / ENUF_MIXED) and window (ENUF_WINDOW_*). */
+int enuf_plan_set_options(enuf_plan *plan, int precision, int window);
+
+/*
+ * Energy and forces (eq. 16, 18, 22-25, 27, 31).
+ *   pos    : N x 3 row-major FP64 positions; any real values, wrapped into [0, box)
+ *            internally and never modified.
+ *   q      : N FP64 charges; zero marks a neutral particle.
+ *   forces : N x 3 FP64, OVERWRITTEN with the force on each particle (0 for neutral ones).
+ *   energy : one FP64, overwritten with the total energy.
+ * Data-dependent failures (non-neutral charges, non-finite input, coincident point
+ * charges, cell overflow) are recorded in the plan's sticky status word; read it
+ * with enuf_plan_status.
+ */
+int enuf_compute(enuf_plan *plan, const double *pos, const double *q,
+                 double *forces, double *energy);
+
+/*
+ * As enuf_compute, with the energy split into five FP64 values:
+ *   energy5[0] = E_real   (whole short-range sum: erfc term + Slater correction)
+ *   energy5[1] = E_slater (the Slater part of E_real; diagnostic)
+ *   energy5[2] = E_recip  (k-space sum of the NFFT approximation)
+ *   energy5[3] = E_self
+ *   energy5[4] = E_recip recomputed from the gathered potential (Parseval check)
+ * and the total E = energy5[0] + energy5[2] + energy5[3].
+ */
+int enuf_compute_components(enuf_plan *plan, const double *pos, const double *q,
+                            double *forces, double *energy5);
+
+/* Synchronise the plan's stream and return the sticky status word in *status
+ * (ENUF_OK or the first data-dependent error since the last call); clears it. */
+int enuf_plan_status(enuf_plan *plan, int *status);
+
+/* Device bytes held by the plan (for admission control). 0 for NULL. */
+size_t enuf_plan_footprint_bytes(const enuf_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENUF_H */

@@ -1,0 +1,72 @@
+"""ctypes binding of libenuf.so (the C ABI declared in include/enuf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.
+There is no CPU fallback: importing this module raises if the library has not
+been built.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libenuf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1303_4523_amd/build.py` (hipcc, gfx950)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_i64, _int, _dbl, _vp, _sz = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+lib.enuf_plan_create.argtypes = [_i64, _dbl, _dbl, _int, _dbl, _int, _int, _dbl, _dbl]
+lib.enuf_plan_create.restype = _vp
+lib.enuf_destroy.argtypes = [_vp]
+lib.enuf_destroy.restype = None
+lib.enuf_last_error.argtypes = []
+lib.enuf_last_error.restype = ctypes.c_char_p
+lib.enuf_plan_set_stream.argtypes = [_vp, _vp]
+lib.enuf_plan_set_stream.restype = _int
+lib.enuf_plan_set_options.argtypes = [_vp, _int, _int]
+lib.enuf_plan_set_options.restype = _int
+lib.enuf_compute.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.enuf_compute.restype = _int
+lib.enuf_compute_components.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.enuf_compute_components.restype = _int
+lib.enuf_plan_status.argtypes = [_vp, ctypes.POINTER(_int)]
+lib.enuf_plan_status.restype = _int
+lib.enuf_plan_footprint_bytes.argtypes = [_vp]
+lib.enuf_plan_footprint_bytes.restype = _sz
+
+# Every function the header declares (checked by the CPU test suite).
+EXPORTED = [
+    "enuf_plan_create", "enuf_destroy", "enuf_last_error", "enuf_plan_set_stream",
+    "enuf_plan_set_options", "enuf_compute", "enuf_compute_components", "enuf_plan_status",
+    "enuf_plan_footprint_bytes",
+]
+
+# Status codes (include/enuf.h).
+OK, EINVAL, ENOMEM, EDEVICE, ENONNEUTRAL, ENONFINITE, EBUSY, ECOINCIDENT, EOVERFLOW = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+                ENONNEUTRAL: "ENONNEUTRAL", ENONFINITE: "ENONFINITE", EBUSY: "EBUSY",
+                ECOINCIDENT: "ECOINCIDENT", EOVERFLOW: "EOVERFLOW"}
+FP64, MIXED = 0, 1
+WINDOW_KB, WINDOW_GAUSS = 0, 1
+
+
+class EnufError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib.enuf_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)} ({msg})")
+
+
+def last_error() -> str:
+    return lib.enuf_last_error().decode(errors="replace")
+
+
+def check(code, where):
+    if code != OK:
+        raise EnufError(code, where)

@@ -1,0 +1,772 @@
+// enuf_kernels.hip -- HIP kernels (gfx950) of one ENUF energy + force evaluation.
+//
+// Pipeline of enuf_compute (all on one stream):
+//   k_prep_count    count charged particles per block; clear cell counts
+//   k_prep_compact  wrap positions, compact the charges in index order, bin
+//                   them into the real-space cell grid, reduce sum q, |q|, q^2
+//   k_real          real-space pair term (eq. 31 + Slater correction eq. 27)
+//   k_recip_fwd     per x-plane: window spread (transposed NFFT, eq. 14) into
+//                   an LDS plane, z real-to-complex FFT, y FFT, keep |k| < Kc
+//   k_recip_x       per ky row: x FFT, influence multiply and FP64 energy
+//                   (eq. 18/20), inverse x FFT
+//   k_recip_bwd     per x-plane: inverse y FFT, complex-to-real z FFT, gather
+//                   of potential and window gradient at the charges (eq. 22-25)
+//   k_combine       per particle: add the 2p plane partials and the real-space
+//                   force, scatter to the output; final energies
+// Accumulations that cross threads are either fixed-order reductions or exact
+// int64 fixed-point sums, so results are bitwise reproducible.
+#include "enuf_device.h"
+
+namespace enuf {
+
+template <typename T> struct CplxOf;
+template <> struct CplxOf<double> { using type = double2; };
+template <> struct CplxOf<float> { using type = float2; };
+
+// ---------------------------------------------------------------------------
+// Block reductions with a fixed order of additions.
+// scratch needs blockDim.x / 64 entries.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ T block_sum(T v, T *scratch) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  return s;
+}
+
+__device__ int block_sum_int(int v, int *scratch) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  int s = 0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  return s;
+}
+
+__device__ inline double wrap_coord(double x, double L) {
+  double y = x - L * floor(x / L);
+  if (!(y < L) || y < 0.0) y = 0.0;
+  return y;
+}
+
+__device__ inline void set_status(DevScalars *sc, int code) { atomicCAS(&sc->status, 0, code); }
+
+// ---------------------------------------------------------------------------
+// Preparation
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kPrepThreads)
+k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, int ncell3,
+             unsigned long long *eacc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int flag = (i < N) && (q[i] != 0.0);
+  const int c = __syncthreads_count(flag);
+  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = c;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < ncell3; k += stride) ccnt[k] = 0;
+  if (i < 2) eacc[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
+               double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
+               double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, int *cgrid,
+               unsigned *done, DevScalars *sc) {
+  __shared__ int s_int[kPrepThreads / kWave];
+  __shared__ int s_wcnt[kPrepThreads / kWave];
+  __shared__ double s_dbl[kPrepThreads / kWave];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+
+  int part = 0;
+  for (int b = tid; b < (int)blockIdx.x; b += blockDim.x) part += blk_cnt[b];
+  const int off = block_sum_int(part, s_int);
+
+  double x = 0.0, y = 0.0, z = 0.0, qi = 0.0;
+  int charged = 0, bad = 0;
+  if (i < N) {
+    qi = q[i];
+    charged = (qi != 0.0);
+    x = pos[3 * i];
+    y = pos[3 * i + 1];
+    z = pos[3 * i + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qi))) {
+      bad = 1;
+      x = y = z = 0.0;
+      qi = 0.0;
+    }
+    x = wrap_coord(x, L);
+    y = wrap_coord(y, L);
+    z = wrap_coord(z, L);
+  }
+  const unsigned long long m = __ballot(charged);
+  const int rank = __popcll(m & __lanemask_lt());
+  if (lane == 0) s_wcnt[w] = __popcll(m);
+  __syncthreads();
+  int woff = 0;
+  for (int k = 0; k < w; ++k) woff += s_wcnt[k];
+  if (i < N) {
+    if (charged) {
+      const int j = off + woff + rank;
+      xq[j] = make_double4(x, y, z, qi);
+      idx[j] = (int)i;
+      slot[i] = j;
+      int cx = (int)(x * cp.inv_cell), cy = (int)(y * cp.inv_cell), cz = (int)(z * cp.inv_cell);
+      cx = cx < cp.ncell ? cx : cp.ncell - 1;
+      cy = cy < cp.ncell ? cy : cp.ncell - 1;
+      cz = cz < cp.ncell ? cz : cp.ncell - 1;
+      const int cell = (cx * cp.ncell + cy) * cp.ncell + cz;
+      const int s = atomicAdd(&ccnt[cell], 1);
+      if (s < cp.cap)
+        cgrid[(size_t)cell * cp.cap + s] = j;
+      else
+        set_status(sc, kEOverflow);
+    } else {
+      slot[i] = -1;
+    }
+    if (bad) set_status(sc, kENonFinite);
+  }
+  const double sq = block_sum(qi, s_dbl);
+  const double sa = block_sum(fabs(qi), s_dbl);
+  const double s2 = block_sum(qi * qi, s_dbl);
+  if (tid == 0) {
+    blk_sums[3 * blockIdx.x] = sq;
+    blk_sums[3 * blockIdx.x + 1] = sa;
+    blk_sums[3 * blockIdx.x + 2] = s2;
+    __threadfence();
+    const unsigned t = atomicAdd(&done[0], 1u);
+    s_last = (t == (unsigned)nblk - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double a = 0.0, b = 0.0, c = 0.0;
+    int nq = 0;
+    for (int k = tid; k < nblk; k += blockDim.x) {
+      a += blk_sums[3 * k];
+      b += blk_sums[3 * k + 1];
+      c += blk_sums[3 * k + 2];
+      nq += blk_cnt[k];
+    }
+    a = block_sum(a, s_dbl);
+    b = block_sum(b, s_dbl);
+    c = block_sum(c, s_dbl);
+    nq = block_sum_int(nq, s_int);
+    if (tid == 0) {
+      sc->nq = nq;
+      sc->sum_q = a;
+      sc->sum_absq = b;
+      sc->sum_q2 = c;
+      // Mesh values are bounded by sum |q| (the window is <= 1): choose the
+      // largest power of two keeping sum|q| * scale below 2^61.
+      int e;
+      frexp(b + 1.0, &e);
+      sc->scale = ldexp(1.0, 61 - e);
+      sc->inv_scale = ldexp(1.0, e - 61);
+      if (fabs(a) > 1e-10 * b) set_status(sc, kENonNeutral);
+      done[0] = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Real space: eq. 31 with the additive Slater correction of eq. 27.
+// u(r) = [erfc(a r) - (1 + x) e^{-2x}]/r, x = r/lambda; force factor
+// f = -u'(r)/r so that F_i = q_i q_j f (r_i - r_j).  For x < 1/2 the
+// closed forms cancel; there u = e^{-2x} b1/lambda - (2a/sqrt(pi)) e^{-a^2r^2} g0
+// and f = e^{-2x} b2/lambda^3 - (2a^3/sqrt(pi)) e^{-a^2r^2} g1 with the
+// all-positive series b1 = 1 + sum_{n>=2} 2^n x^{n-1}/n!,
+// b2 = sum_{n>=3} 2^n x^{n-3}/n!, g0 = sum_{n>=0} 2^n z^{2n}/(2n+1)!!,
+// g1 = sum_{n>=1} 2^n z^{2n-2}/(2n+1)!! (z = a r; the erf series is
+// Abramowitz & Stegun 7.1.6).
+// ---------------------------------------------------------------------------
+__device__ inline bool real_pair(double r, double a, double lam, double *u, double *us, double *f) {
+  const double k2 = 1.1283791670955125739;  // 2/sqrt(pi)
+  if (lam > 0.0 && r < 0.5 * lam) {
+    const double x = r / lam, y = 2.0 * x, z = a * r, z2 = z * z;
+    double b2 = 4.0 / 3.0, term = 4.0 / 3.0, b1 = 1.0 + 2.0 * x + b2 * x * x;
+    for (int n = 4; n < 30; ++n) {
+      term *= y / n;
+      b2 += term;
+      b1 += term * x * x;
+    }
+    double t0 = 1.0, g0 = 1.0;
+    for (int n = 1; n < 20; ++n) {
+      t0 *= 2.0 * z2 / (2.0 * n + 1.0);
+      g0 += t0;
+    }
+    double t1 = 2.0 / 3.0, g1 = 0.0;
+    for (int n = 1; n < 20; ++n) {
+      g1 += t1;
+      t1 *= 2.0 * z2 / (2.0 * n + 3.0);
+    }
+    const double ex = exp(-y), ez = exp(-z2);
+    *u = ex * b1 / lam - k2 * a * ez * g0;
+    *us = (r > 0.0) ? -(1.0 + x) * ex / r : 0.0;
+    *f = (r > 0.0) ? (ex * b2 / (lam * lam * lam) - k2 * a * a * a * ez * g1) : 0.0;
+    return true;
+  }
+  if (r == 0.0) return false;
+  const double ar = a * r, ec = erfc(ar), r2 = r * r;
+  double uu = ec / r;
+  double ff = (ec / r + k2 * a * exp(-ar * ar)) / r2;
+  double ss = 0.0;
+  if (lam > 0.0) {
+    const double x = r / lam, ex = exp(-2.0 * x);
+    ss = -(1.0 + x) * ex / r;
+    ff -= (1.0 + 2.0 * x + 2.0 * x * x) * ex / (r2 * r);
+  }
+  *u = uu + ss;
+  *us = ss;
+  *f = ff;
+  return true;
+}
+
+__device__ inline bool cell_offset_valid(int o, int n) {
+  return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
+}
+
+// One wavefront per charge: lanes 0..53 take one of the 27 neighbour cells
+// and every other slot in it.
+__global__ void __launch_bounds__(256)
+k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *__restrict__ cgrid,
+       CellParams cp, double L, double alpha, double rc2, double lam, DevScalars *sc,
+       long long *freal, unsigned long long *eacc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wpb = blockDim.x / kWave;
+  const int nq = sc->nq;
+  const double invL = 1.0 / L;
+  for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < nq; j += gridDim.x * wpb) {
+    const double4 ci = xq[j];
+    int cx = (int)(ci.x * cp.inv_cell), cy = (int)(ci.y * cp.inv_cell), cz = (int)(ci.z * cp.inv_cell);
+    cx = cx < cp.ncell ? cx : cp.ncell - 1;
+    cy = cy < cp.ncell ? cy : cp.ncell - 1;
+    cz = cz < cp.ncell ? cz : cp.ncell - 1;
+    long long fx = 0, fy = 0, fz = 0, ee = 0, es = 0;
+    int err = 0;
+    if (lane < 54) {
+      const int o = lane % 27, par = lane / 27;
+      const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+      const int n = cp.ncell;
+      if (cell_offset_valid(ox, n) && cell_offset_valid(oy, n) && cell_offset_valid(oz, n)) {
+        const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
+        int cnt = ccnt[c];
+        cnt = cnt < cp.cap ? cnt : cp.cap;
+        for (int s = par; s < cnt; s += 2) {
+          const int k = cgrid[(size_t)c * cp.cap + s];
+          if (k == j) continue;
+          const double4 cj = xq[k];
+          double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+          dx -= L * rint(dx * invL);
+          dy -= L * rint(dy * invL);
+          dz -= L * rint(dz * invL);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (!(r2 < rc2)) continue;
+          double u, us, f;
+          if (!real_pair(sqrt(r2), alpha, lam, &u, &us, &f)) {
+            err = kECoincident;
+            continue;
+          }
+          const double qq = ci.w * cj.w;
+          const double g = qq * f;
+          if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
+          fx += to_fixed(g * dx, kRealFxScale);
+          fy += to_fixed(g * dy, kRealFxScale);
+          fz += to_fixed(g * dz, kRealFxScale);
+          ee += to_fixed(0.5 * qq * u, kRealFxScale);
+          es += to_fixed(0.5 * qq * us, kRealFxScale);
+        }
+      }
+    }
+    if (err) set_status(sc, err);
+    fx = wave_sum_ll(fx);
+    fy = wave_sum_ll(fy);
+    fz = wave_sum_ll(fz);
+    ee = wave_sum_ll(ee);
+    es = wave_sum_ll(es);
+    if (lane == 0) {
+      freal[3 * (size_t)j] = fx;
+      freal[3 * (size_t)j + 1] = fy;
+      freal[3 * (size_t)j + 2] = fz;
+      atomicAdd(&eacc[0], (unsigned long long)ee);
+      atomicAdd(&eacc[1], (unsigned long long)es);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mesh pass 1: spread + z R2C FFT + y FFT for one x-plane.
+// LDS: int64 accumulator plane [M][Mp] (aliased by the T plane after
+// conversion), spectrum lines Zre/Zim [Kc][Mz], twiddles, a charge queue.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_fwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp,
+            const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+  const int wv = tid / kWave, nw = nt / kWave;
+  const int x0 = blockIdx.x;
+
+  long long *acc = reinterpret_cast<long long *>(smem);
+  T *plane = reinterpret_cast<T *>(smem);
+  const size_t plane_bytes = (size_t)M * Mp * sizeof(long long);
+  T *Zre;
+  size_t off = plane_bytes;
+  if (sizeof(T) == 8) {
+    Zre = reinterpret_cast<T *>(smem + off);
+    off += 2 * (size_t)Kc * Mz * sizeof(T);
+  } else {
+    Zre = reinterpret_cast<T *>(smem + (size_t)M * Mp * sizeof(T));
+  }
+  T *Zim = Zre + (size_t)Kc * Mz;
+  T *twr = reinterpret_cast<T *>(smem + off);
+  T *twi = twr + M;
+  off += 2 * (size_t)M * sizeof(T);
+  int *queue = reinterpret_cast<int *>(smem + off);
+  off += (size_t)nt * sizeof(int);
+  int *qn = reinterpret_cast<int *>(smem + off);
+
+  for (int m = tid; m < M; m += nt) {
+    twr[m] = tw[m].x;
+    twi[m] = tw[m].y;
+  }
+  for (int k = tid; k < M * Mp; k += nt) acc[k] = 0;
+  const int nq = sc->nq;
+  const double scale = sc->scale, inv_scale = sc->inv_scale;
+  __syncthreads();
+
+  for (int base = 0; base < nq; base += nt) {
+    if (tid == 0) *qn = 0;
+    __syncthreads();
+    const int j = base + tid;
+    if (j < nq) {
+      double t;
+      const int cx = mesh_cell(xq[j].x, mp.m_over_l, M, &t);
+      if (mod_pos(x0 - (cx - p + 1), M) < P2) queue[atomicAdd(qn, 1)] = j;
+    }
+    __syncthreads();
+    const int cnt = *qn;
+    for (int e = wv; e < cnt; e += nw) {
+      const double4 c = xq[queue[e]];
+      double tx, ty, tz;
+      const int bx = mesh_cell(c.x, mp.m_over_l, M, &tx) - p + 1;
+      const int by = mesh_cell(c.y, mp.m_over_l, M, &ty) - p + 1;
+      const int bz = mesh_cell(c.z, mp.m_over_l, M, &tz) - p + 1;
+      const int sx = mod_pos(x0 - bx, M);
+      T wval = (T)0, wder;
+      if (lane < P2)
+        window_eval<T>(mp.win, (T)(ty - (double)(by + lane)), &wval, &wder);
+      else if (lane < 2 * P2)
+        window_eval<T>(mp.win, (T)(tz - (double)(bz + lane - P2)), &wval, &wder);
+      else if (lane == 2 * P2)
+        window_eval<T>(mp.win, (T)(tx - (double)(bx + sx)), &wval, &wder);
+      const T qwx = (T)c.w * __shfl(wval, 2 * P2, kWave);
+      for (int f0 = 0; f0 < P2 * P2; f0 += kWave) {
+        const int f = f0 + lane;
+        const bool act = f < P2 * P2;
+        const int sy = act ? f / P2 : 0, sz = act ? f % P2 : 0;
+        const T wy = __shfl(wval, sy, kWave);
+        const T wz = __shfl(wval, P2 + sz, kWave);
+        if (act) {
+          const int row = mod_pos(by + sy, M), col = mod_pos(bz + sz, M);
+          const double v = (double)(qwx * wy * wz);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&acc[row * Mp + col]),
+                    (unsigned long long)to_fixed(v, scale));
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // fixed point -> T plane (in place; FP32 rows move down in chunks)
+  if (sizeof(T) == 8) {
+    for (int k = tid; k < M * Mp; k += nt) {
+      const long long v = acc[k];
+      plane[k] = (T)((double)v * inv_scale);
+    }
+    __syncthreads();
+  } else {
+    int R = (4 * nt) / Mp;
+    R = R < 1 ? 1 : R;
+    for (int r0 = 0; r0 < M; r0 += R) {
+      const int n = ((M - r0) < R ? (M - r0) : R) * Mp;
+      long long v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = tid + u * nt;
+        if (k < n) v[u] = acc[(size_t)r0 * Mp + k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = tid + u * nt;
+        if (k < n) plane[(size_t)r0 * Mp + k] = (T)((double)v[u] * inv_scale);
+      }
+      __syncthreads();
+    }
+  }
+
+  // z: rows 2c (real part) and 2c+1 (imaginary part) form complex line c
+  lds_fft<T>(plane, plane + Mp, 2 * Mp, M / 2, mp.fft, twr, twi, false);
+  for (int id = tid; id < (M / 2) * Kc; id += nt) {
+    const int c = id / Kc, k = id % Kc, mk = (M - k) % M;
+    const T zr = plane[2 * c * Mp + k], zi = plane[(2 * c + 1) * Mp + k];
+    const T mr = plane[2 * c * Mp + mk], mi = plane[(2 * c + 1) * Mp + mk];
+    Zre[k * Mz + 2 * c] = (T)0.5 * (zr + mr);
+    Zim[k * Mz + 2 * c] = (T)0.5 * (zi - mi);
+    Zre[k * Mz + 2 * c + 1] = (T)0.5 * (zi + mi);
+    Zim[k * Mz + 2 * c + 1] = (T)0.5 * (mr - zr);
+  }
+  __syncthreads();
+  // y: one complex line per kz
+  lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, false);
+  const int nky = mp.nky;
+  for (int id = tid; id < nky * Kc; id += nt) {
+    const int kyi = id / Kc, kz = id % Kc;
+    const int m = mod_pos(kyi - (Kc - 1), M);
+    typename CplxOf<T>::type v;
+    v.x = Zre[kz * Mz + m];
+    v.y = Zim[kz * Mz + m];
+    gzy[((size_t)x0 * nky + kyi) * Kc + kz] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mesh pass 2: x FFT, influence multiply + energy, inverse x FFT for one ky.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_x(MeshParams mp, const double *__restrict__ atab,
+          const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy,
+          double *epart) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int M = mp.M, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int kyi = blockIdx.x, ky = kyi - (Kc - 1);
+  T *Xre = reinterpret_cast<T *>(smem);
+  T *Xim = Xre + (size_t)Kc * Mz;
+  T *twr = Xim + (size_t)Kc * Mz;
+  T *twi = twr + M;
+  const size_t red_off = ((2 * (size_t)Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
+  double *red = reinterpret_cast<double *>(smem + red_off);
+
+  int nkz = 0;
+  while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
+
+  for (int m = tid; m < M; m += nt) {
+    twr[m] = tw[m].x;
+    twi[m] = tw[m].y;
+  }
+  for (int id = tid; id < M * nkz; id += nt) {
+    const int x = id / nkz, kz = id % nkz;
+    const typename CplxOf<T>::type v = gzy[((size_t)x * nky + kyi) * Kc + kz];
+    Xre[kz * Mz + x] = v.x;
+    Xim[kz * Mz + x] = v.y;
+  }
+  __syncthreads();
+  lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, false);
+
+  const double ay = atab[kyi];
+  double e = 0.0;
+  for (int id = tid; id < nkz * M; id += nt) {
+    const int kz = id / M, m = id % M;
+    const int kx = m < M / 2 ? m : m - M;
+    const int k2 = kx * kx + ky * ky + kz * kz;
+    T hr = (T)0, hi = (T)0;
+    if (kx > -Kc && kx < Kc && k2 < Kc * Kc && k2 > 0) {
+      const double c = atab[kx + Kc - 1] * ay * atab[kz + Kc - 1] / (double)k2;
+      const double gr = (double)Xre[kz * Mz + m], gi = (double)Xim[kz * Mz + m];
+      e += (kz > 0 ? 2.0 : 1.0) * c * (gr * gr + gi * gi);
+      hr = (T)(c * gr);
+      hi = (T)(c * gi);
+    }
+    Xre[kz * Mz + m] = hr;
+    Xim[kz * Mz + m] = hi;
+  }
+  e = block_sum(e, red);
+  if (tid == 0) epart[kyi] = e;
+  __syncthreads();
+  lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, true);
+  for (int id = tid; id < M * Kc; id += nt) {
+    const int x = id / Kc, kz = id % Kc;
+    typename CplxOf<T>::type v;
+    v.x = kz < nkz ? Xre[kz * Mz + x] : (T)0;
+    v.y = kz < nkz ? Xim[kz * Mz + x] : (T)0;
+    gzy[((size_t)x * nky + kyi) * Kc + kz] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mesh pass 3: inverse y FFT, complex-to-real z FFT and gather for one plane.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_bwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp,
+            const typename CplxOf<T>::type *__restrict__ tw,
+            const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+  const int wv = tid / kWave, nw = nt / kWave;
+  const int x0 = blockIdx.x;
+
+  T *plane = reinterpret_cast<T *>(smem);
+  size_t off = (size_t)M * Mp * sizeof(T);
+  T *Zre = reinterpret_cast<T *>(smem + off);
+  T *Zim = Zre + (size_t)Kc * Mz;
+  off += 2 * (size_t)Kc * Mz * sizeof(T);
+  T *twr = reinterpret_cast<T *>(smem + off);
+  T *twi = twr + M;
+  off += 2 * (size_t)M * sizeof(T);
+  int *queue = reinterpret_cast<int *>(smem + off);
+  off += (size_t)nt * sizeof(int);
+  int *qn = reinterpret_cast<int *>(smem + off);
+
+  for (int m = tid; m < M; m += nt) {
+    twr[m] = tw[m].x;
+    twi[m] = tw[m].y;
+  }
+  for (int k = tid; k < 2 * Kc * Mz; k += nt) Zre[k] = (T)0;
+  __syncthreads();
+  for (int id = tid; id < nky * Kc; id += nt) {
+    const int kyi = id / Kc, kz = id % Kc;
+    const int m = mod_pos(kyi - (Kc - 1), M);
+    const typename CplxOf<T>::type v = gzy[((size_t)x0 * nky + kyi) * Kc + kz];
+    Zre[kz * Mz + m] = v.x;
+    Zim[kz * Mz + m] = v.y;
+  }
+  __syncthreads();
+  lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
+
+  // Hermitian z spectra of rows 2c and 2c+1 packed as H1 + i H2
+  for (int id = tid; id < (M / 2) * M; id += nt) {
+    const int c = id / M, k = id % M;
+    T re = (T)0, im = (T)0;
+    if (k < Kc) {
+      const T h1r = Zre[k * Mz + 2 * c], h1i = Zim[k * Mz + 2 * c];
+      const T h2r = Zre[k * Mz + 2 * c + 1], h2i = Zim[k * Mz + 2 * c + 1];
+      if (k == 0) {
+        re = h1r;
+        im = h2r;
+      } else {
+        re = h1r - h2i;
+        im = h1i + h2r;
+      }
+    } else if (k > M - Kc) {
+      const int kk = M - k;
+      const T h1r = Zre[kk * Mz + 2 * c], h1i = Zim[kk * Mz + 2 * c];
+      const T h2r = Zre[kk * Mz + 2 * c + 1], h2i = Zim[kk * Mz + 2 * c + 1];
+      re = h1r + h2i;
+      im = h2r - h1i;
+    }
+    plane[2 * c * Mp + k] = re;
+    plane[(2 * c + 1) * Mp + k] = im;
+  }
+  __syncthreads();
+  lds_fft<T>(plane, plane + Mp, 2 * Mp, M / 2, mp.fft, twr, twi, true);
+
+  const int nq = sc->nq;
+  for (int base = 0; base < nq; base += nt) {
+    if (tid == 0) *qn = 0;
+    __syncthreads();
+    const int j = base + tid;
+    if (j < nq) {
+      double t;
+      const int cx = mesh_cell(xq[j].x, mp.m_over_l, M, &t);
+      if (mod_pos(x0 - (cx - p + 1), M) < P2) queue[atomicAdd(qn, 1)] = j;
+    }
+    __syncthreads();
+    const int cnt = *qn;
+    for (int e = wv; e < cnt; e += nw) {
+      const int jj = queue[e];
+      const double4 c = xq[jj];
+      double tx, ty, tz;
+      const int bx = mesh_cell(c.x, mp.m_over_l, M, &tx) - p + 1;
+      const int by = mesh_cell(c.y, mp.m_over_l, M, &ty) - p + 1;
+      const int bz = mesh_cell(c.z, mp.m_over_l, M, &tz) - p + 1;
+      const int sx = mod_pos(x0 - bx, M);
+      T wval = (T)0, wder = (T)0;
+      if (lane < P2)
+        window_eval<T>(mp.win, (T)(ty - (double)(by + lane)), &wval, &wder);
+      else if (lane < 2 * P2)
+        window_eval<T>(mp.win, (T)(tz - (double)(bz + lane - P2)), &wval, &wder);
+      else if (lane == 2 * P2)
+        window_eval<T>(mp.win, (T)(tx - (double)(bx + sx)), &wval, &wder);
+      const T wx = __shfl(wval, 2 * P2, kWave), dwx = __shfl(wder, 2 * P2, kWave);
+      T A = (T)0, By = (T)0, Bz = (T)0;
+      for (int f0 = 0; f0 < P2 * P2; f0 += kWave) {
+        const int f = f0 + lane;
+        const bool act = f < P2 * P2;
+        const int sy = act ? f / P2 : 0, sz = act ? f % P2 : 0;
+        const T wy = __shfl(wval, sy, kWave), dwy = __shfl(wder, sy, kWave);
+        const T wz = __shfl(wval, P2 + sz, kWave), dwz = __shfl(wder, P2 + sz, kWave);
+        if (act) {
+          const T h = plane[mod_pos(by + sy, M) * Mp + mod_pos(bz + sz, M)];
+          A += h * wy * wz;
+          By += h * dwy * wz;
+          Bz += h * wy * dwz;
+        }
+      }
+      A = wave_sum(A);
+      By = wave_sum(By);
+      Bz = wave_sum(Bz);
+      if (lane == 0)
+        part[(size_t)jj * P2 + sx] = make_double4((double)(dwx * A), (double)(wx * By),
+                                                  (double)(wx * Bz), (double)(wx * A));
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Combine: forces per particle and the final energies (last block).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kPrepThreads)
+k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
+          const long long *__restrict__ freal, const double4 *__restrict__ part, int P2,
+          double fscale, double inv2piL, double alpha, int nblk, double *blk_eg, unsigned *done,
+          const double *__restrict__ epart, int nky, const unsigned long long *eacc,
+          const DevScalars *sc, double *forces, double *energy, double *energy5) {
+  __shared__ double s_dbl[kPrepThreads / kWave];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  double eg = 0.0;
+  if (i < N) {
+    const int j = slot[i];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (j >= 0) {
+      double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
+      for (int s = 0; s < P2; ++s) {
+        const double4 v = part[(size_t)j * P2 + s];
+        bx += v.x;
+        by += v.y;
+        bz += v.z;
+        a += v.w;
+      }
+      const double qj = xq[j].w;
+      fx = (double)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
+      fy = (double)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
+      fz = (double)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
+      eg = qj * a;
+    }
+    forces[3 * i] = fx;
+    forces[3 * i + 1] = fy;
+    forces[3 * i + 2] = fz;
+  }
+  eg = block_sum(eg, s_dbl);
+  if (tid == 0) {
+    blk_eg[blockIdx.x] = eg;
+    __threadfence();
+    const unsigned t = atomicAdd(&done[1], 1u);
+    s_last = (t == (unsigned)nblk - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double g = 0.0, k = 0.0;
+    for (int b = tid; b < nblk; b += blockDim.x) g += blk_eg[b];
+    for (int b = tid; b < nky; b += blockDim.x) k += epart[b];
+    g = block_sum(g, s_dbl);
+    k = block_sum(k, s_dbl);
+    if (tid == 0) {
+      const double e_real = (double)(long long)eacc[0] * kRealFxInv;
+      const double e_sl = (double)(long long)eacc[1] * kRealFxInv;
+      const double e_rec = k * inv2piL;
+      const double e_self = -alpha * 0.56418958354775628695 * sc->sum_q2;  // 1/sqrt(pi)
+      if (energy) energy[0] = e_real + e_rec + e_self;
+      if (energy5) {
+        energy5[0] = e_real;
+        energy5[1] = e_sl;
+        energy5[2] = e_rec;
+        energy5[3] = e_self;
+        energy5[4] = g * inv2piL;
+      }
+      done[1] = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd) {
+  const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
+  const size_t misc = (size_t)kPassThreads * sizeof(int) + 16;
+  const size_t acc = (size_t)m.M * m.Mp * sizeof(long long);
+  const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
+  const size_t tw = 2 * (size_t)m.M * ts;
+  *fwd = (ts == 8 ? acc + zp : acc) + tw + misc;
+  *x = ((zp + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) + 16;
+  *bwd = (size_t)m.M * m.Mp * ts + zp + tw + misc;
+}
+
+hipError_t configure_kernels(size_t max_lds) {
+  const int v = (int)max_lds;
+  hipError_t e;
+  e = hipFuncSetAttribute((const void *)k_recip_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_recip_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_recip_x<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_recip_x<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_recip_bwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_recip_bwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}
+
+template <typename T>
+static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st) {
+  using C = typename CplxOf<T>::type;
+  const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
+  C *gzy = reinterpret_cast<C *>(b.gzy);
+  const MeshParams &mp = cfg.mesh;
+  hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, b.xq, b.sc, mp, tw, gzy);
+  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy, b.epart);
+  hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, b.xq, b.sc, mp, tw,
+                     (const C *)gzy, b.part);
+}
+
+hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
+                          const double *q, double *forces, double *energy_total, double *energy5,
+                          hipStream_t st) {
+  const int nblk = cfg.nblk;
+  const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
+  hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
+                     ncell3, b.eacc);
+  hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
+                     (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
+                     b.done, b.sc);
+  int grid_real = (int)((cfg.N + 3) / 4);
+  grid_real = grid_real < 2048 ? grid_real : 2048;
+  hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(256), 0, st, (const double4 *)b.xq, (const int *)b.ccnt,
+                     (const int *)b.cgrid, cfg.cells, cfg.L, cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda,
+                     b.sc, b.freal, b.eacc);
+  if (cfg.precision == 0)
+    launch_mesh<double>(cfg, b, st);
+  else
+    launch_mesh<float>(cfg, b, st);
+  const double L = cfg.L;
+  const double fscale = (double)cfg.mesh.M / (M_PI * L * L);
+  const double inv2piL = 1.0 / (2.0 * M_PI * L);
+  hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
+                     (const double4 *)b.xq, (const long long *)b.freal, (const double4 *)b.part,
+                     2 * cfg.mesh.win.p, fscale, inv2piL, cfg.alpha, nblk, b.blk_eg, b.done,
+                     (const double *)b.epart, cfg.mesh.nky, (const unsigned long long *)b.eacc,
+                     (const DevScalars *)b.sc, forces, energy_total, energy5);
+  return hipGetLastError();
+}
+
+}  // namespace enuf

@@ -1,0 +1,333 @@
+// enuf_runtime.cpp -- host side of the ENUF C ABI: argument validation, window
+// and influence tables, FFT factorisation, device buffers and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/enuf.h"
+#include "enuf_internal.h"
+
+using namespace enuf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+#define HIP_OR_RETURN(call, code)                                             \
+  do {                                                                        \
+    hipError_t _e = (call);                                                   \
+    if (_e != hipSuccess) {                                                   \
+      set_error(std::string(#call) + ": " + hipGetErrorString(_e));           \
+      return code;                                                            \
+    }                                                                         \
+  } while (0)
+
+// Modified Bessel function I0 by its power series sum (x/2)^{2k} / (k!)^2
+// (all terms positive; long double keeps ~18 digits for the arguments used).
+long double bessel_i0(long double x) {
+  const long double h = x * x / 4.0L;
+  long double term = 1.0L, sum = 1.0L;
+  for (int k = 1; k < 500; ++k) {
+    term *= h / ((long double)k * (long double)k);
+    sum += term;
+    if (term < sum * 1e-21L) break;
+  }
+  return sum;
+}
+
+bool factor_235(int n, FftPlan *pl) {
+  pl->n = n;
+  pl->npass = 0;
+  int m = n;
+  const int order[4] = {4, 2, 3, 5};
+  for (int oi = 0; oi < 4; ++oi) {
+    const int r = order[oi];
+    while (m % r == 0) {
+      if (pl->npass >= kMaxRadixPasses) return false;
+      pl->radix[pl->npass++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+}  // namespace
+
+struct enuf_plan {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0;
+  double L = 0, alpha = 0, sigma = 0, r_cut = 0, lambda = 0;
+  int p = 0, M = 0, Kc = 0;
+  int precision = ENUF_FP64, window = ENUF_WINDOW_KB;
+  size_t max_lds = 0;
+  ComputeConfig cfg{};
+  ComputeBuffers buf{};
+  std::vector<void *> allocations;
+  size_t bytes = 0;
+
+  void *alloc(size_t n) {
+    void *ptr = nullptr;
+    if (n == 0) n = 16;
+    if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
+    allocations.push_back(ptr);
+    bytes += n;
+    return ptr;
+  }
+  ~enuf_plan() {
+    for (void *ptr : allocations) (void)hipFree(ptr);
+  }
+};
+
+namespace {
+
+WindowParams make_window(int kind, int p, double sigma) {
+  WindowParams w{};
+  w.kind = kind;
+  w.p = p;
+  w.b = M_PI * (2.0 - 1.0 / sigma);
+  w.c1 = 1.0 / (1.0 - std::exp(-2.0 * w.b * p));
+  w.inv_sinh_bp = 1.0 / std::sinh(w.b * p);
+  const double bg = 2.0 * sigma * p / ((2.0 * sigma - 1.0) * M_PI);
+  w.inv_bg = 1.0 / bg;
+  return w;
+}
+
+// Fourier transform of the normalised window at xi = k / M:
+//   Kaiser-Bessel  Phi(xi) = I0(p sqrt(b^2 - (2 pi xi)^2)) * pi p / sinh(b p)
+//   Gaussian       Phi(xi) = sqrt(pi b_G) exp(-b_G pi^2 xi^2)
+long double window_hat(const WindowParams &w, long double xi) {
+  if (w.kind == ENUF_WINDOW_GAUSS) {
+    const long double bg = 1.0L / (long double)w.inv_bg;
+    return std::sqrt((long double)M_PI * bg) * std::exp(-bg * (long double)M_PI * (long double)M_PI * xi * xi);
+  }
+  const long double b = w.b, p = w.p;
+  const long double om = 2.0L * (long double)M_PI * xi;
+  const long double arg = p * std::sqrt(b * b - om * om);
+  return bessel_i0(arg) * (long double)M_PI * p / std::sinh(b * p);
+}
+
+int upload_tables(enuf_plan *pl) {
+  const int Kc = pl->Kc, M = pl->M, nky = 2 * Kc - 1;
+  const WindowParams &w = pl->cfg.mesh.win;
+  std::vector<double> atab(nky);
+  const long double aL = (long double)pl->alpha * pl->L;
+  for (int i = 0; i < nky; ++i) {
+    const long double k = (long double)(i - (Kc - 1));
+    const long double ph = window_hat(w, k / (long double)M);
+    atab[i] = (double)(std::exp(-(long double)M_PI * (long double)M_PI * k * k / (aL * aL)) / (ph * ph));
+  }
+  std::vector<double2> tw64(M);
+  std::vector<float2> tw32(M);
+  for (int m = 0; m < M; ++m) {
+    const long double ang = -2.0L * (long double)M_PI * (long double)m / (long double)M;
+    tw64[m] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+    tw32[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  HIP_OR_RETURN(hipMemcpy(pl->buf.atab, atab.data(), nky * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipMemcpy(pl->buf.tw64, tw64.data(), M * sizeof(double2), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipMemcpy(pl->buf.tw32, tw32.data(), M * sizeof(float2), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  return ENUF_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *enuf_last_error(void) { return g_last_error.c_str(); }
+
+enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc,
+                            double r_cut, double lambda) {
+  g_last_error.clear();
+  // ---- validation (host only; no device call before it passes) ----
+  if (N < 1 || N > (int64_t)1 << 28) { set_error("N must be in [1, 2^28]"); return nullptr; }
+  if (!finite_pos(box)) { set_error("box must be finite and > 0"); return nullptr; }
+  if (!finite_pos(alpha)) { set_error("alpha must be finite and > 0"); return nullptr; }
+  if (!(std::isfinite(sigma) && sigma >= 1.0)) { set_error("sigma must be finite and >= 1"); return nullptr; }
+  if (p < 1 || p > 15) { set_error("p must be in [1, 15]"); return nullptr; }
+  if (M < 4 || M % 2 != 0 || M > 4096) { set_error("M must be even and in [4, 4096]"); return nullptr; }
+  FftPlan fp{};
+  if (!factor_235(M, &fp)) { set_error("M must be of the form 2^a 3^b 5^c"); return nullptr; }
+  if (2 * p > M / 2) { set_error("need 2p <= M/2"); return nullptr; }
+  if (Kc < 1 || (double)Kc > (double)M / (2.0 * sigma)) { set_error("need 1 <= Kc <= M/(2 sigma)"); return nullptr; }
+  if (!finite_pos(r_cut) || r_cut > 0.5 * box) { set_error("need 0 < r_cut <= box/2"); return nullptr; }
+  if (!(std::isfinite(lambda) && lambda >= 0.0)) { set_error("lambda must be finite and >= 0"); return nullptr; }
+
+  enuf_plan *pl = new enuf_plan();
+  pl->N = N; pl->L = box; pl->alpha = alpha; pl->sigma = sigma; pl->r_cut = r_cut; pl->lambda = lambda;
+  pl->p = p; pl->M = M; pl->Kc = Kc;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    set_error("hipGetDevice failed");
+    delete pl;
+    return nullptr;
+  }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) != hipSuccess) {
+    set_error("hipDeviceGetAttribute failed");
+    delete pl;
+    return nullptr;
+  }
+  pl->max_lds = (size_t)lds;
+
+  ComputeConfig &c = pl->cfg;
+  c.N = N;
+  c.nblk = (int)((N + kPrepThreads - 1) / kPrepThreads);
+  c.L = box; c.alpha = alpha; c.r_cut = r_cut; c.lambda = lambda;
+  c.precision = ENUF_FP64;
+  MeshParams &m = c.mesh;
+  m.M = M; m.Mp = M + 1; m.Mz = M + 1; m.Kc = Kc; m.nky = 2 * Kc - 1;
+  m.L = box; m.m_over_l = (double)M / box;
+  m.win = make_window(ENUF_WINDOW_KB, p, sigma);
+  m.fft = fp;
+  int ncell = (int)std::floor(box / r_cut);
+  ncell = ncell < 1 ? 1 : (ncell > 1024 ? 1024 : ncell);
+  const double mean = (double)N / ((double)ncell * ncell * ncell);
+  c.cells.ncell = ncell;
+  c.cells.cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+  c.cells.inv_cell = (double)ncell / box;
+  mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
+
+  ComputeBuffers &b = pl->buf;
+  const size_t nblk = c.nblk, n = (size_t)N, ncell3 = (size_t)ncell * ncell * ncell;
+  const size_t P2 = 2 * (size_t)p;
+  b.blk_cnt = (int *)pl->alloc(nblk * sizeof(int));
+  b.blk_sums = (double *)pl->alloc(nblk * 3 * sizeof(double));
+  b.done = (unsigned *)pl->alloc(4 * sizeof(unsigned));
+  b.sc = (DevScalars *)pl->alloc(sizeof(DevScalars));
+  b.xq = (double4 *)pl->alloc(n * sizeof(double4));
+  b.idx = (int *)pl->alloc(n * sizeof(int));
+  b.slot = (int *)pl->alloc(n * sizeof(int));
+  b.ccnt = (int *)pl->alloc(ncell3 * sizeof(int));
+  b.cgrid = (int *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(int));
+  b.freal = (long long *)pl->alloc(n * 3 * sizeof(long long));
+  b.eacc = (unsigned long long *)pl->alloc(4 * sizeof(unsigned long long));
+  b.gzy = pl->alloc((size_t)M * m.nky * Kc * sizeof(double2));
+  b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
+  b.part = (double4 *)pl->alloc(n * P2 * sizeof(double4));
+  b.blk_eg = (double *)pl->alloc(nblk * sizeof(double));
+  b.atab = (double *)pl->alloc((size_t)m.nky * sizeof(double));
+  b.tw64 = (double2 *)pl->alloc((size_t)M * sizeof(double2));
+  b.tw32 = (float2 *)pl->alloc((size_t)M * sizeof(float2));
+  if (pl->allocations.size() != 18) {  // alloc() records successful allocations only
+    set_error("device allocation failed");
+    delete pl;
+    return nullptr;
+  }
+  if (hipMemset(b.done, 0, 4 * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess) {
+    set_error("hipMemset failed");
+    delete pl;
+    return nullptr;
+  }
+  if (upload_tables(pl) != ENUF_OK) {
+    delete pl;
+    return nullptr;
+  }
+  static bool configured = false;
+  if (!configured) {
+    if (configure_kernels(pl->max_lds) != hipSuccess) {
+      set_error("hipFuncSetAttribute failed");
+      delete pl;
+      return nullptr;
+    }
+    configured = true;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    set_error("device synchronisation after plan setup failed");
+    delete pl;
+    return nullptr;
+  }
+  return pl;
+}
+
+void enuf_destroy(enuf_plan *plan) {
+  if (!plan) return;
+  (void)hipStreamSynchronize(plan->stream);
+  delete plan;
+}
+
+int enuf_plan_set_stream(enuf_plan *plan, void *hip_stream) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  plan->stream = (hipStream_t)hip_stream;
+  return ENUF_OK;
+}
+
+int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  if (precision != ENUF_FP64 && precision != ENUF_MIXED) { set_error("unknown precision"); return ENUF_EINVAL; }
+  if (window != ENUF_WINDOW_KB && window != ENUF_WINDOW_GAUSS) { set_error("unknown window"); return ENUF_EINVAL; }
+  size_t f, x, bw;
+  mesh_lds_bytes(plan->cfg.mesh, precision, &f, &x, &bw);
+  if (f > plan->max_lds || x > plan->max_lds || bw > plan->max_lds) {
+    set_error("mesh too large for one LDS plane in this precision (need " + std::to_string(f > bw ? f : bw) +
+              " bytes, have " + std::to_string(plan->max_lds) + ")");
+    return ENUF_EINVAL;
+  }
+  const bool window_changed = window != plan->window;
+  plan->precision = precision;
+  plan->window = window;
+  plan->cfg.precision = precision;
+  plan->cfg.lds_fwd = f;
+  plan->cfg.lds_x = x;
+  plan->cfg.lds_bwd = bw;
+  if (window_changed) {
+    plan->cfg.mesh.win = make_window(window, plan->p, plan->sigma);
+    // the stream may still read the old table
+    HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+    return upload_tables(plan);
+  }
+  return ENUF_OK;
+}
+
+static int compute_impl(enuf_plan *plan, const double *pos, const double *q, double *forces,
+                        double *energy, double *energy5) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  if (!pos || !q || !forces || (!energy && !energy5)) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  const ComputeConfig &c = plan->cfg;
+  if (c.lds_fwd > plan->max_lds || c.lds_bwd > plan->max_lds || c.lds_x > plan->max_lds) {
+    set_error("mesh too large for one LDS plane in this precision");
+    return ENUF_EINVAL;
+  }
+  int dev = -1;
+  HIP_OR_RETURN(hipGetDevice(&dev), ENUF_EDEVICE);
+  if (dev != plan->device) HIP_OR_RETURN(hipSetDevice(plan->device), ENUF_EDEVICE);
+  hipError_t e = launch_compute(c, plan->buf, pos, q, forces, energy, energy5, plan->stream);
+  if (dev != plan->device) (void)hipSetDevice(dev);
+  if (e != hipSuccess) {
+    set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return ENUF_EDEVICE;
+  }
+  return ENUF_OK;
+}
+
+int enuf_compute(enuf_plan *plan, const double *pos, const double *q, double *forces, double *energy) {
+  return compute_impl(plan, pos, q, forces, energy, nullptr);
+}
+
+int enuf_compute_components(enuf_plan *plan, const double *pos, const double *q, double *forces,
+                            double *energy5) {
+  return compute_impl(plan, pos, q, forces, nullptr, energy5);
+}
+
+int enuf_plan_status(enuf_plan *plan, int *status) {
+  if (!plan || !status) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  int s = 0;
+  HIP_OR_RETURN(hipMemcpy(&s, &plan->buf.sc->status, sizeof(int), hipMemcpyDeviceToHost), ENUF_EDEVICE);
+  const int zero = 0;
+  HIP_OR_RETURN(hipMemcpy(&plan->buf.sc->status, &zero, sizeof(int), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  *status = s;
+  return ENUF_OK;
+}
+
+size_t enuf_plan_footprint_bytes(const enuf_plan *plan) { return plan ? plan->bytes : 0; }
+
+}  // extern "C"

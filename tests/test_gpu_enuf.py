@@ -1,0 +1,192 @@
+"""GPU parity of enuf_compute against the FP64 CPU oracle (direct Ewald).
+
+Bars (BASELINE the benchmark spec): relative force RMS <= 1e-5 and relative energy
+<= 1e-6 for the FP64 path; <= 5e-4 and <= 1e-4 for the mixed path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4523_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": (1e-5, 1e-6), "mixed": (5e-4, 1e-4)}
+
+
+def _plan(N, e, precision="fp64", window="kb"):
+    from paper_1303_4523_amd import Plan
+    return Plan(N, e["L"], e["alpha"], e["p"], e["sigma"], e["M"], e["Kc"], e["r_cut"], e["lam"],
+                precision=precision, window=window)
+
+
+def _run(plan, pos, q, components=True):
+    dev = torch.device("cuda", 0)
+    tp = torch.tensor(pos, dtype=torch.float64, device=dev).contiguous()
+    tq = torch.tensor(q, dtype=torch.float64, device=dev).contiguous()
+    if components:
+        F, E = plan.compute_components(tp, tq)
+    else:
+        F, E = plan.compute(tp, tq)
+    torch.cuda.synchronize()
+    return F.cpu().numpy(), E.cpu().numpy(), plan.status()
+
+
+def _errors(F, E5, ref):
+    ef = np.linalg.norm(F - ref["F"]) / np.linalg.norm(ref["F"])
+    Et = E5[0] + E5[2] + E5[3]
+    ee = abs(Et - ref["E"]) / abs(ref["E"])
+    return ef, ee, Et
+
+
+def _case(sys_, precision="fp64", window="kb", **over):
+    e = dict(sys_.meta["enuf"], **over)
+    print(f"case: {sys_.meta.get('name')} precision={precision} window={window} {e}", flush=True)
+    plan = _plan(sys_.N, e, precision, window)
+    F, E5, st = _run(plan, sys_.pos, sys_.q)
+    ref = oracle.ewald(sys_.pos, sys_.q, e["L"], e["alpha"], e["Kc"], e["r_cut"], e["lam"])
+    plan.close()
+    return F, E5, st, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_eval_small_parity(precision):
+    """L = 10, N = 3000, 300 charges, M = 32, Kc = 8, p = 4 (Kaiser-Bessel)."""
+    s = wl.single_eval_small()
+    F, E5, st, ref = _case(s, precision)
+    assert st == 0
+    ef, ee, Et = _errors(F, E5, ref)
+    print(f"force rel rms {ef:.3e}  energy rel {ee:.3e}  E={Et:.10f} ref={ref['E']:.10f}")
+    tf, te = TOL[precision]
+    assert ef <= tf and ee <= te
+    # components: the real-space and self terms are exact sums
+    assert abs(E5[0] - ref["E_real"]) < 1e-9 * abs(ref["E_real"]) + 1e-9
+    assert abs(E5[1] - ref["E_slater"]) < 1e-9 * abs(ref["E_slater"]) + 1e-9
+    assert abs(E5[3] - ref["E_self"]) < 1e-12 * abs(ref["E_self"])
+    # Parseval: the gathered potential reproduces the k-space energy
+    assert abs(E5[4] - E5[2]) < (1e-9 if precision == "fp64" else 1e-4) * abs(E5[2])
+    # neutral particles get exactly zero force
+    assert np.all(F[s.q == 0.0] == 0.0)
+
+
+def test_real_space_forces_exact():
+    """The real-space forces are exact sums (fixed-point rounding 2^-36 only)."""
+    s = wl.single_eval_small()
+    e = s.meta["enuf"]
+    # a Kc = 1 plan has no wave vectors: the output is real space only
+    from paper_1303_4523_amd import Plan
+    p0 = Plan(s.N, e["L"], e["alpha"], e["p"], e["sigma"], e["M"], 1, e["r_cut"], e["lam"])
+    F, E5, st = _run(p0, s.pos, s.q)
+    p0.close()
+    Fr, Ee, Es = oracle.real_space(s.pos, s.q, e["L"], e["alpha"], e["r_cut"], e["lam"])
+    assert st == 0
+    assert E5[2] == 0.0
+    assert np.abs(F - Fr).max() < 1e-9
+    assert abs(E5[0] - Ee) < 1e-8
+
+
+@pytest.mark.parametrize("M,Kc,p,N,L", [(24, 6, 3, 257, 6.0), (30, 7, 3, 500, 7.5), (40, 10, 4, 1000, 8.0),
+                                         (48, 12, 5, 1100, 12.0)])
+def test_mixed_radix_meshes(M, Kc, p, N, L):
+    """Meshes with radix 2, 3, 4 and 5 passes, ragged particle counts."""
+    s = wl.electrolyte(L, N, N // 10, N // 10, 4242 + M)
+    e = dict(alpha=0.35, p=p, sigma=2.0, M=M, Kc=Kc, r_cut=min(3.0, L / 2), lam=0.25, L=L)
+    s.meta["enuf"] = e
+    s.meta["name"] = f"mesh M={M}"
+    F, E5, st, ref = _case(s)
+    ef, ee, _ = _errors(F, E5, ref)
+    print(f"M={M} p={p}: force {ef:.3e} energy {ee:.3e}")
+    assert st == 0
+    # p = 3 windows are less accurate; the bar scales with the NFFT error
+    tf = 1e-5 if p >= 4 else 1e-4
+    assert ef <= tf and ee <= 1e-6
+
+
+def test_gaussian_window_p6():
+    s = wl.single_eval_small()
+    F, E5, st, ref = _case(s, "fp64", "gauss", p=6)
+    ef, ee, _ = _errors(F, E5, ref)
+    print(f"gauss p=6: force {ef:.3e} energy {ee:.3e}")
+    assert st == 0 and ef <= 1e-5 and ee <= 1e-6
+
+
+def test_deterministic_bitwise():
+    s = wl.single_eval_small()
+    plan = _plan(s.N, s.meta["enuf"])
+    a = _run(plan, s.pos, s.q)
+    b = _run(plan, s.pos, s.q)
+    plan.close()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_edge_cases():
+    e = dict(L=10.0, alpha=0.3, p=4, sigma=2.0, M=32, Kc=8, r_cut=3.0, lam=0.25)
+    rs = np.random.default_rng(0)
+    # no charges at all
+    pos = rs.uniform(0, 10, (50, 3))
+    plan = _plan(50, e)
+    F, E5, st = _run(plan, pos, np.zeros(50))
+    assert st == 0 and np.all(F == 0.0) and np.all(E5 == 0.0)
+    # one neutral particle
+    plan1 = _plan(1, e)
+    F, E5, st = _run(plan1, pos[:1], np.zeros(1))
+    assert st == 0 and np.all(F == 0.0)
+    plan1.close()
+    # coincident Slater pair: E = -1/lambda, no force
+    pos2 = np.array([[3.0, 3.0, 3.0], [3.0, 3.0, 3.0]] + [[1.0, 1.0, 1.0]] * 48)
+    q2 = np.zeros(50)
+    q2[0], q2[1] = 1.0, -1.0
+    F, E5, st = _run(plan, pos2, q2)
+    ref = oracle.ewald(pos2, q2, 10.0, 0.3, 8, 3.0, 0.25)
+    assert st == 0
+    assert abs(E5[0] + E5[2] + E5[3] - ref["E"]) < 1e-6 * abs(ref["E"])
+    assert np.abs(F).max() < 1e-9
+    # non-neutral input is flagged
+    q3 = np.zeros(50)
+    q3[:3] = 1.0
+    _, _, st = _run(plan, pos, q3)
+    assert st == -4
+    # non-finite input is flagged and the call still completes
+    pos4 = pos.copy()
+    pos4[7, 1] = np.nan
+    q4 = np.zeros(50)
+    q4[7], q4[8] = 1.0, -1.0
+    _, _, st = _run(plan, pos4, q4)
+    assert st == -5
+    # positions far outside the box are wrapped
+    q5 = np.zeros(50)
+    q5[:10] = 1.0
+    q5[10:20] = -1.0
+    a = _run(plan, pos, q5)
+    b = _run(plan, pos + 10.0 * rs.integers(-5, 6, (50, 3)), q5)
+    assert np.abs(a[0] - b[0]).max() < 1e-9
+    plan.close()
+    # coincident point charges are an error
+    e0 = dict(e, lam=0.0)
+    plan0 = _plan(50, e0)
+    _, _, st = _run(plan0, pos2, q2)
+    plan0.close()
+    assert st == -7
+
+
+def test_force_is_gradient_of_gpu_energy():
+    """The window-gradient force is the exact derivative of the NFFT energy."""
+    s = wl.electrolyte(8.0, 400, 40, 40, 99)
+    e = dict(L=8.0, alpha=0.4, p=4, sigma=2.0, M=32, Kc=8, r_cut=3.0, lam=0.25)
+    plan = _plan(s.N, e)
+    F0, _, _ = _run(plan, s.pos, s.q)
+    h = 1e-4
+    qi = np.nonzero(s.q)[0]
+    for i in qi[:4]:
+        for a in range(3):
+            pp = s.pos.copy(); pp[i, a] += h
+            pm = s.pos.copy(); pm[i, a] -= h
+            _, Ep, _ = _run(plan, pp, s.q)
+            _, Em, _ = _run(plan, pm, s.q)
+            fd = -((Ep[0] + Ep[2]) - (Em[0] + Em[2])) / (2 * h)
+            assert abs(fd - F0[i, a]) < 1e-5 * (1 + abs(fd))
+    plan.close()
