@@ -122,6 +122,90 @@ int enuf_plan_status(enuf_plan *plan, int *status);
 /* Device bytes held by the plan (for admission control). 0 for NULL. */
 size_t enuf_plan_footprint_bytes(const enuf_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * DPD trajectories with ENUF electrostatics (Sec. 2 and Table 2).
+ *
+ * Reduced units R_c = m = k_B T = 1.  Pair forces act for r < 1 (eq. 2-7):
+ *   F^C = a (1 - r) rhat,  F^D = -gamma (1 - r)^2 (v_ij . rhat) rhat,
+ *   F^R = sigma (1 - r) theta_ij rhat / sqrt(dt),
+ * theta_ij uniform on [-sqrt 3, sqrt 3) from Philox4x64-10 with counter
+ * (min(i,j), max(i,j), step, 0) and key (seed, 0); harmonic bonds
+ * F = -K (r - r_eq) rhat; electrostatics kappa times the ENUF force.
+ * One step is Table 2: v0 = v + lam dt F; v += dt F/2; r += dt v (wrapped
+ * into [0, box)); F = F(r, v0); v += dt F/2.
+ * ------------------------------------------------------------------------ */
+typedef struct enuf_dpd enuf_dpd;
+
+typedef struct {
+  double a;        /* conservative amplitude a_ij (one species), eq. 3 */
+  double gamma;    /* dissipation strength, eq. 4 */
+  double sigma;    /* noise amplitude, eq. 5 (sigma^2 = 2 gamma k_B T, eq. 6) */
+  double dt;       /* time step (> 0) */
+  double lam;      /* velocity prediction parameter of the modified velocity Verlet */
+  double k_bond;   /* spring constant K^S */
+  double r0_bond;  /* bond rest length r_eq */
+  double kappa;    /* coupling that multiplies the ENUF energy and forces */
+  uint64_t seed;   /* random-force stream */
+} enuf_dpd_params;
+
+/*
+ * Create a DPD integrator for N particles in a cubic box (box >= 2).
+ *   plan   : ENUF plan for the same N and box, or NULL for no electrostatics.
+ *            Not owned; it must outlive the integrator.
+ *   q      : DEVICE pointer to N charges, copied at creation (charges are fixed).
+ *   bonds  : HOST pointer to nbonds (i, j) index pairs (int64), copied.
+ * Returns NULL on error (enuf_last_error).  Allocates device scratch.
+ */
+enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *params, enuf_plan *plan,
+                          const double *q, int64_t nbonds, const int64_t *bonds);
+
+/* Bind the integrator (and its ENUF plan) to a HIP stream; NULL = null stream. */
+int enuf_dpd_set_stream(enuf_dpd *dpd, void *hip_stream);
+
+/* Total force at pos with the velocities vel standing in for the predicted
+ * ones and the random numbers of `step` (device pointers, N x 3 FP64).
+ * force is overwritten.  pos is wrapped into the box in place. */
+int enuf_dpd_forces(enuf_dpd *dpd, double *pos, const double *vel, double *force, uint64_t step);
+
+/* Advance nsteps steps in place.  On entry force holds the force of the last
+ * step (from enuf_dpd_forces or a previous run); step s uses the random
+ * numbers of step s, s = first_step .. first_step + nsteps - 1. */
+int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_t first_step,
+                 int nsteps);
+
+/* Copy (on the stream) the ENUF energy components of the last force
+ * evaluation, unscaled by kappa, into the device array energy5 (as in
+ * enuf_compute_components).  Without a plan all five are 0. */
+int enuf_dpd_energy(enuf_dpd *dpd, double *energy5);
+
+/* Synchronise and return (and clear) the sticky status of the integrator and
+ * of its plan (ENUF_EOVERFLOW if a DPD cell overflowed). */
+int enuf_dpd_status(enuf_dpd *dpd, int *status);
+
+/* Release the integrator (not its plan).  NULL is a no-op. */
+void enuf_dpd_destroy(enuf_dpd *dpd);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support).  While enabled, an integrator records
+ * a pair of HIP events on its stream around each launch of one kernel of the
+ * step, for at most max_launches launches; enuf_dpd_kernel_time synchronises
+ * and returns the summed milliseconds and the number of timed launches.
+ * ------------------------------------------------------------------------ */
+#define ENUF_K_DPD_PRE       0
+#define ENUF_K_DPD_PAIR      1
+#define ENUF_K_PREP_COUNT    2
+#define ENUF_K_PREP_COMPACT  3
+#define ENUF_K_REAL          4
+#define ENUF_K_MESH_FWD      5   /* spread + z/y FFT per x-plane */
+#define ENUF_K_MESH_X        6   /* x FFT + influence multiply + inverse x FFT */
+#define ENUF_K_MESH_BWD      7   /* inverse y/z FFT + gather per x-plane */
+#define ENUF_K_COMBINE       8
+#define ENUF_K_DPD_POST      9
+
+/* kernel = ENUF_K_* to start timing it (resets the totals), -1 to stop. */
+int enuf_dpd_time_kernel(enuf_dpd *dpd, int kernel, int max_launches);
+int enuf_dpd_kernel_time(enuf_dpd *dpd, double *total_ms, int *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,8 @@ def _load():
     lib.oracle_real.restype = ctypes.c_int
     lib.oracle_recip.argtypes = [i64, ip, ip, d, d, ctypes.c_int, i64, ip, ip, ip]
     lib.oracle_recip.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_self.argtypes = [i64, ip, d]
     lib.oracle_self.restype = d
     lib.oracle_philox4x64_10.argtypes = [ip, ip, ip]
@@ -129,6 +131,11 @@ def recip_direct(pos, q, L, alpha, Kc, sel=None):
                           0 if s is None else len(s), _ptr(s), _ptr(F), _ptr(E))
     _check(st, "oracle_recip")
     return F, float(E[0])
+
+
+def num_threads():
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(_load().oracle_num_threads())
 
 
 def self_energy(q, alpha):

@@ -31,6 +31,7 @@
  * energies and forces by its coupling constant.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -378,6 +379,9 @@ int oracle_recip(int64_t n, const double *pos, const double *q, double L,
     free(w);
     return OR_OK;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_num_threads(void) { return omp_get_max_threads(); }
 
 /* Self term of eq. 16: -(alpha/sqrt(pi)) sum_j q_j^2. */
 double oracle_self(int64_t n, const double *q, double alpha)

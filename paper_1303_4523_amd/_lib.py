@@ -39,11 +39,45 @@ lib.enuf_plan_status.restype = _int
 lib.enuf_plan_footprint_bytes.argtypes = [_vp]
 lib.enuf_plan_footprint_bytes.restype = _sz
 
+
+
+class DpdParams(ctypes.Structure):
+    """enuf_dpd_params of include/enuf.h."""
+    _fields_ = [("a", _dbl), ("gamma", _dbl), ("sigma", _dbl), ("dt", _dbl), ("lam", _dbl),
+                ("k_bond", _dbl), ("r0_bond", _dbl), ("kappa", _dbl), ("seed", ctypes.c_uint64)]
+
+
+lib.enuf_dpd_create.argtypes = [_i64, _dbl, ctypes.POINTER(DpdParams), _vp, _vp, _i64, _vp]
+lib.enuf_dpd_create.restype = _vp
+lib.enuf_dpd_set_stream.argtypes = [_vp, _vp]
+lib.enuf_dpd_set_stream.restype = _int
+lib.enuf_dpd_forces.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
+lib.enuf_dpd_forces.restype = _int
+lib.enuf_dpd_run.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64, _int]
+lib.enuf_dpd_run.restype = _int
+lib.enuf_dpd_energy.argtypes = [_vp, _vp]
+lib.enuf_dpd_energy.restype = _int
+lib.enuf_dpd_status.argtypes = [_vp, ctypes.POINTER(_int)]
+lib.enuf_dpd_status.restype = _int
+lib.enuf_dpd_destroy.argtypes = [_vp]
+lib.enuf_dpd_destroy.restype = None
+lib.enuf_dpd_time_kernel.argtypes = [_vp, _int, _int]
+lib.enuf_dpd_time_kernel.restype = _int
+lib.enuf_dpd_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_int)]
+lib.enuf_dpd_kernel_time.restype = _int
+
+# Kernel ids of the timing hook (ENUF_K_* in include/enuf.h).
+KERNELS = {"dpd_pre": 0, "dpd_pair": 1, "prep_count": 2, "prep_compact": 3, "real": 4,
+           "mesh_fwd": 5, "mesh_x": 6, "mesh_bwd": 7, "combine": 8, "dpd_post": 9}
+
 # Every function the header declares (checked by the CPU test suite).
 EXPORTED = [
     "enuf_plan_create", "enuf_destroy", "enuf_last_error", "enuf_plan_set_stream",
     "enuf_plan_set_options", "enuf_compute", "enuf_compute_components", "enuf_plan_status",
     "enuf_plan_footprint_bytes",
+    "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_forces", "enuf_dpd_run",
+    "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
+    "enuf_dpd_time_kernel", "enuf_dpd_kernel_time",
 ]
 
 # Status codes (include/enuf.h).

@@ -115,9 +115,27 @@ struct ComputeConfig {
   size_t lds_fwd, lds_x, lds_bwd;  // dynamic LDS bytes of the three mesh passes
 };
 
+// Optional event timing of one kernel class (kernel ids as ENUF_K_* in enuf.h).
+struct KernelTimer {
+  int kernel = -1;
+  int cap = 0;
+  int count = 0;
+  hipEvent_t *ev = nullptr;  // 2 * cap events
+  void before(int k, hipStream_t s) {
+    if (k == kernel && count < cap) (void)hipEventRecord(ev[2 * count], s);
+  }
+  void after(int k, hipStream_t s) {
+    if (k == kernel && count < cap) {
+      (void)hipEventRecord(ev[2 * count + 1], s);
+      ++count;
+    }
+  }
+};
+
 hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b,
                           const double *pos, const double *q, double *forces,
-                          double *energy_total, double *energy5, hipStream_t stream);
+                          double *energy_total, double *energy5, hipStream_t stream,
+                          KernelTimer *timer = nullptr);
 
 // LDS bytes the three mesh passes need for the given geometry and precision.
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd);

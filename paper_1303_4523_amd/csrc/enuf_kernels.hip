@@ -728,44 +728,58 @@ hipError_t configure_kernels(size_t max_lds) {
 }
 
 template <typename T>
-static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st) {
+static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st, KernelTimer *tm) {
   using C = typename CplxOf<T>::type;
   const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
   C *gzy = reinterpret_cast<C *>(b.gzy);
   const MeshParams &mp = cfg.mesh;
+  if (tm) tm->before(5, st);
   hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, b.xq, b.sc, mp, tw, gzy);
+  if (tm) tm->after(5, st);
+  if (tm) tm->before(6, st);
   hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy, b.epart);
+  if (tm) tm->after(6, st);
+  if (tm) tm->before(7, st);
   hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, b.xq, b.sc, mp, tw,
                      (const C *)gzy, b.part);
+  if (tm) tm->after(7, st);
 }
 
 hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
                           const double *q, double *forces, double *energy_total, double *energy5,
-                          hipStream_t st) {
+                          hipStream_t st, KernelTimer *tm) {
   const int nblk = cfg.nblk;
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
+  if (tm) tm->before(2, st);
   hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
                      ncell3, b.eacc);
+  if (tm) tm->after(2, st);
+  if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
                      (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
                      b.done, b.sc);
+  if (tm) tm->after(3, st);
   int grid_real = (int)((cfg.N + 3) / 4);
   grid_real = grid_real < 2048 ? grid_real : 2048;
+  if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(256), 0, st, (const double4 *)b.xq, (const int *)b.ccnt,
                      (const int *)b.cgrid, cfg.cells, cfg.L, cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda,
                      b.sc, b.freal, b.eacc);
+  if (tm) tm->after(4, st);
   if (cfg.precision == 0)
-    launch_mesh<double>(cfg, b, st);
+    launch_mesh<double>(cfg, b, st, tm);
   else
-    launch_mesh<float>(cfg, b, st);
+    launch_mesh<float>(cfg, b, st, tm);
   const double L = cfg.L;
   const double fscale = (double)cfg.mesh.M / (M_PI * L * L);
   const double inv2piL = 1.0 / (2.0 * M_PI * L);
+  if (tm) tm->before(8, st);
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
                      (const double4 *)b.xq, (const long long *)b.freal, (const double4 *)b.part,
                      2 * cfg.mesh.win.p, fscale, inv2piL, cfg.alpha, nblk, b.blk_eg, b.done,
                      (const double *)b.epart, cfg.mesh.nky, (const unsigned long long *)b.eacc,
                      (const DevScalars *)b.sc, forces, energy_total, energy5);
+  if (tm) tm->after(8, st);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/enuf.h"
+#include "enuf_dpd.h"
 #include "enuf_internal.h"
 
 using namespace enuf;
@@ -329,5 +330,242 @@ int enuf_plan_status(enuf_plan *plan, int *status) {
 }
 
 size_t enuf_plan_footprint_bytes(const enuf_plan *plan) { return plan ? plan->bytes : 0; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// DPD integrator
+// ---------------------------------------------------------------------------
+struct enuf_dpd {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t N = 0;
+  DpdParams P{};
+  enuf_plan *plan = nullptr;  // not owned
+  double *q = nullptr;        // [N]
+  double *v0 = nullptr;       // [N * 3] predicted velocities
+  double *fdpd = nullptr;     // [N * 3]
+  double *felec = nullptr;    // [N * 3]
+  double *e5 = nullptr;       // [5]
+  int *dcnt = nullptr;        // [ncell^3]
+  int *dgrid = nullptr;       // [ncell^3 * cap]
+  int *bond_start = nullptr;  // [N + 1]
+  int *bond_to = nullptr;     // [2 nbonds]
+  int *status = nullptr;      // [1]
+  std::vector<void *> allocations;
+  KernelTimer timer;
+  std::vector<hipEvent_t> events;
+
+  void *alloc(size_t n) {
+    void *ptr = nullptr;
+    if (n == 0) n = 16;
+    if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
+    allocations.push_back(ptr);
+    return ptr;
+  }
+  void drop_events() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
+    timer = KernelTimer();
+  }
+  ~enuf_dpd() {
+    drop_events();
+    for (void *ptr : allocations) (void)hipFree(ptr);
+  }
+};
+
+extern "C" {
+
+enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enuf_plan *plan,
+                          const double *q, int64_t nbonds, const int64_t *bonds) {
+  g_last_error.clear();
+  if (N < 1 || N > (int64_t)1 << 28) { set_error("N must be in [1, 2^28]"); return nullptr; }
+  if (!(std::isfinite(box) && box >= 2.0)) { set_error("box must be finite and >= 2 (R_c = 1)"); return nullptr; }
+  if (!prm) { set_error("NULL params"); return nullptr; }
+  const double vals[8] = {prm->a, prm->gamma, prm->sigma, prm->dt, prm->lam, prm->k_bond, prm->r0_bond, prm->kappa};
+  for (double v : vals)
+    if (!std::isfinite(v)) { set_error("non-finite DPD parameter"); return nullptr; }
+  if (!(prm->dt > 0.0)) { set_error("dt must be > 0"); return nullptr; }
+  if (!q) { set_error("NULL charges"); return nullptr; }
+  if (nbonds < 0 || (nbonds > 0 && !bonds)) { set_error("invalid bond list"); return nullptr; }
+  if (plan && (plan->N != N || plan->L != box)) { set_error("plan N / box differ from the integrator's"); return nullptr; }
+  std::vector<int> deg(N + 1, 0);
+  for (int64_t b = 0; b < nbonds; ++b) {
+    const int64_t i = bonds[2 * b], j = bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= N || j >= N || i == j) { set_error("bond index out of range"); return nullptr; }
+    ++deg[i + 1];
+    ++deg[j + 1];
+  }
+  for (int64_t i = 0; i < N; ++i) deg[i + 1] += deg[i];
+  std::vector<int> to(2 * nbonds > 0 ? 2 * nbonds : 1), fill(deg.begin(), deg.end() - 1);
+  for (int64_t b = 0; b < nbonds; ++b) {
+    const int i = (int)bonds[2 * b], j = (int)bonds[2 * b + 1];
+    to[fill[i]++] = j;
+    to[fill[j]++] = i;
+  }
+
+  enuf_dpd *d = new enuf_dpd();
+  d->N = N;
+  d->plan = plan;
+  if (hipGetDevice(&d->device) != hipSuccess) { set_error("hipGetDevice failed"); delete d; return nullptr; }
+  if (plan) d->stream = plan->stream;
+  DpdParams &P = d->P;
+  P.L = box; P.a = prm->a; P.gamma = prm->gamma; P.sigma = prm->sigma; P.dt = prm->dt; P.lam = prm->lam;
+  P.k_bond = prm->k_bond; P.r0_bond = prm->r0_bond; P.kappa = prm->kappa; P.seed = prm->seed;
+  int nc = (int)std::floor(box);  // cell edge box / nc >= 1 = R_c
+  nc = nc < 1 ? 1 : (nc > 1024 ? 1024 : nc);
+  P.ncell = nc;
+  const double mean = (double)N / ((double)nc * nc * nc);
+  P.cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+  P.inv_cell = (double)nc / box;
+  const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
+  d->q = (double *)d->alloc(n * sizeof(double));
+  d->v0 = (double *)d->alloc(3 * n * sizeof(double));
+  d->fdpd = (double *)d->alloc(3 * n * sizeof(double));
+  d->felec = (double *)d->alloc(3 * n * sizeof(double));
+  d->e5 = (double *)d->alloc(5 * sizeof(double));
+  d->dcnt = (int *)d->alloc(nc3 * sizeof(int));
+  d->dgrid = (int *)d->alloc(nc3 * (size_t)P.cap * sizeof(int));
+  d->bond_start = (int *)d->alloc((n + 1) * sizeof(int));
+  d->bond_to = (int *)d->alloc(to.size() * sizeof(int));
+  d->status = (int *)d->alloc(sizeof(int));
+  if (d->allocations.size() != 10) { set_error("device allocation failed"); delete d; return nullptr; }
+  if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+      hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
+      hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    set_error("device setup of the DPD integrator failed");
+    delete d;
+    return nullptr;
+  }
+  return d;
+}
+
+int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  d->stream = (hipStream_t)hip_stream;
+  if (d->plan) d->plan->stream = d->stream;
+  return ENUF_OK;
+}
+
+static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step) {
+  const int64_t N = d->N;
+  KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
+  hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->dgrid, d->status, d->stream, tm);
+  if (e == hipSuccess)
+    e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->dgrid, d->bond_start, d->bond_to, d->fdpd,
+                        d->stream, tm);
+  if (e == hipSuccess && d->plan) {
+    enuf_plan *pl = d->plan;
+    pl->stream = d->stream;
+    e = launch_compute(pl->cfg, pl->buf, pos, d->q, d->felec, nullptr, d->e5, d->stream, tm);
+  }
+  if (e == hipSuccess)
+    e = launch_dpd_post(N, mode, d->P, d->fdpd, d->plan ? d->felec : nullptr, force, vel, d->dcnt, d->stream,
+                        tm);
+  if (e != hipSuccess) {
+    set_error(std::string("DPD kernel launch failed: ") + hipGetErrorString(e));
+    return ENUF_EDEVICE;
+  }
+  return ENUF_OK;
+}
+
+static int dpd_check(enuf_dpd *d, const void *a, const void *b, const void *c) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  if (!a || !b || !c) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  if (d->plan) {
+    const ComputeConfig &cf = d->plan->cfg;
+    if (cf.lds_fwd > d->plan->max_lds || cf.lds_bwd > d->plan->max_lds) {
+      set_error("mesh too large for one LDS plane in this precision");
+      return ENUF_EINVAL;
+    }
+  }
+  return ENUF_OK;
+}
+
+int enuf_dpd_forces(enuf_dpd *d, double *pos, const double *vel, double *force, uint64_t step) {
+  int rc = dpd_check(d, pos, vel, force);
+  if (rc != ENUF_OK) return rc;
+  return dpd_eval(d, 1, pos, const_cast<double *>(vel), force, step);
+}
+
+int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t first_step, int nsteps) {
+  int rc = dpd_check(d, pos, vel, force);
+  if (rc != ENUF_OK) return rc;
+  if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
+  for (int s = 0; s < nsteps; ++s) {
+    rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s);
+    if (rc != ENUF_OK) return rc;
+  }
+  return ENUF_OK;
+}
+
+int enuf_dpd_energy(enuf_dpd *d, double *energy5) {
+  if (!d || !energy5) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipMemcpyAsync(energy5, d->e5, 5 * sizeof(double), hipMemcpyDeviceToDevice, d->stream), ENUF_EDEVICE);
+  return ENUF_OK;
+}
+
+int enuf_dpd_status(enuf_dpd *d, int *status) {
+  if (!d || !status) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  int s = 0;
+  HIP_OR_RETURN(hipMemcpy(&s, d->status, sizeof(int), hipMemcpyDeviceToHost), ENUF_EDEVICE);
+  const int zero = 0;
+  HIP_OR_RETURN(hipMemcpy(d->status, &zero, sizeof(int), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  if (s == 0 && d->plan) return enuf_plan_status(d->plan, status);
+  if (d->plan) {
+    int ps = 0;
+    (void)enuf_plan_status(d->plan, &ps);
+  }
+  *status = s;
+  return ENUF_OK;
+}
+
+int enuf_dpd_time_kernel(enuf_dpd *d, int kernel, int max_launches) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  d->drop_events();
+  if (kernel < 0) return ENUF_OK;
+  if (kernel > ENUF_K_DPD_POST || max_launches < 1 || max_launches > (1 << 20)) {
+    set_error("invalid kernel id or launch count");
+    return ENUF_EINVAL;
+  }
+  d->events.resize(2 * (size_t)max_launches);
+  for (size_t k = 0; k < d->events.size(); ++k) {
+    if (hipEventCreate(&d->events[k]) != hipSuccess) {
+      d->events.resize(k);
+      d->drop_events();
+      set_error("hipEventCreate failed");
+      return ENUF_EDEVICE;
+    }
+  }
+  d->timer.kernel = kernel;
+  d->timer.cap = max_launches;
+  d->timer.count = 0;
+  d->timer.ev = d->events.data();
+  return ENUF_OK;
+}
+
+int enuf_dpd_kernel_time(enuf_dpd *d, double *total_ms, int *launches) {
+  if (!d || !total_ms || !launches) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  double t = 0.0;
+  for (int k = 0; k < d->timer.count; ++k) {
+    float ms = 0.0f;
+    HIP_OR_RETURN(hipEventElapsedTime(&ms, d->events[2 * k], d->events[2 * k + 1]), ENUF_EDEVICE);
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = d->timer.count;
+  return ENUF_OK;
+}
+
+void enuf_dpd_destroy(enuf_dpd *d) {
+  if (!d) return;
+  (void)hipStreamSynchronize(d->stream);
+  delete d;
+}
 
 }  // extern "C"

@@ -7,6 +7,15 @@ from . import _lib
 from ._lib import EnufError, check, lib
 
 
+def _device(device):
+    """torch.device for a CUDA index, a torch.device, or None (current device)."""
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    if isinstance(device, torch.device):
+        return device if device.index is not None else torch.device("cuda", torch.cuda.current_device())
+    return torch.device("cuda", int(device))
+
+
 def _dev_ptr(t, name, shape, dtype=torch.float64):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA tensor")
@@ -26,7 +35,7 @@ class Plan:
                  window="kb", device=None):
         self.N = int(N)
         self.params = dict(box=box, alpha=alpha, p=p, sigma=sigma, M=M, Kc=Kc, r_cut=r_cut, lam=lam)
-        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = _device(device)
         with torch.cuda.device(self.device):
             h = lib.enuf_plan_create(self.N, float(box), float(alpha), int(p), float(sigma), int(M),
                                      int(Kc), float(r_cut), float(lam))

@@ -1,0 +1,159 @@
+"""GPU DPD step (Table 2 with ENUF electrostatics) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4523_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV).contiguous()
+
+
+def _system(L=8.0, density=3.0, nq=120, chain=12, seed=5):
+    rs = np.random.default_rng(seed)
+    n = int(round(density * L ** 3))
+    pos = rs.uniform(0.0, L, (n, 3))
+    for i in range(1, chain):
+        pos[i] = (pos[i - 1] + 0.7 * rs.normal(size=3) / math.sqrt(3)) % L
+    vel = rs.normal(size=(n, 3))
+    vel -= vel.mean(0)
+    q = np.zeros(n)
+    q[chain:chain + nq // 2] = 1.0
+    q[chain + nq // 2:chain + nq] = -1.0
+    bonds = np.array([(i, i + 1) for i in range(chain - 1)], dtype=np.int64)
+    return pos, vel, q, bonds
+
+
+PRM = dict(a=25.0, gamma=4.5, sigma=3.0, dt=0.03, lam=0.65, k_bond=4.0, r0_bond=0.7, kappa=1.1, seed=17)
+ENUF = dict(alpha=0.3, p=4, sigma=2.0, r_cut=3.0, lam=0.25)
+
+
+def _oracle_params(L, elec=True):
+    return dict(PRM, L=L, alpha=ENUF["alpha"], r_cut=ENUF["r_cut"], lambda_e=ENUF["lam"],
+                Kc=int(0.8 * L), use_elec=int(elec))
+
+
+def _mesh(n):
+    """Smallest even 2^a 3^b 5^c >= n."""
+    m = int(math.ceil(n))
+    while True:
+        k = m
+        for r in (2, 3, 5):
+            while k % r == 0:
+                k //= r
+        if k == 1 and m % 2 == 0:
+            return m
+        m += 1
+
+
+def _gpu(L, q, bonds, elec=True, precision="fp64"):
+    from paper_1303_4523_amd.dpd import DPD
+    e = dict(ENUF, M=_mesh(3.2 * L), Kc=int(0.8 * L)) if elec else None
+    return DPD(L, q, PRM, bonds=bonds, enuf=e, precision=precision, device=0)
+
+
+@pytest.mark.parametrize("elec", [False, True])
+def test_initial_forces(elec):
+    L = 10.0
+    pos, vel, q, bonds = _system(L)
+    d = _gpu(L, q, bonds, elec)
+    tp, tv = _t(pos), _t(vel)
+    F = torch.empty_like(tp)
+    d.forces(tp, tv, F, step=0)
+    Fg = F.cpu().numpy()
+    st = d.status()
+    d.close()
+    Fo, _ = oracle.dpd_forces(pos, vel, q, bonds, _oracle_params(L, elec), seed=PRM["seed"], step=0)
+    err = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
+    print(f"elec={elec}: force rel rms {err:.3e}")
+    assert st == 0
+    assert err < (1e-6 if elec else 1e-11)
+    if not elec:
+        assert np.abs(Fg.sum(0)).max() < 1e-8   # momentum, up to fixed-point rounding
+
+
+def test_trajectory_segment_matches_oracle():
+    """Ten steps on both sides with the same random numbers."""
+    L = 8.0
+    pos, vel, q, bonds = _system(L, nq=80)
+    d = _gpu(L, q, bonds, True)
+    tp, tv = _t(pos), _t(vel)
+    F = torch.empty_like(tp)
+    d.forces(tp, tv, F, step=0)
+    d.run(tp, tv, F, 1, 10)
+    st = d.status()
+    gp, gv, gF = tp.cpu().numpy(), tv.cpu().numpy(), F.cpu().numpy()
+    e5 = d.energy().cpu().numpy()
+    d.close()
+    P = _oracle_params(L)
+    Fo, _ = oracle.dpd_forces(pos, vel, q, bonds, P, seed=PRM["seed"], step=0)
+    op, ov = pos.copy(), vel.copy()
+    for s in range(1, 11):
+        op, ov, Fo, Eo = oracle.dpd_step(op, ov, Fo, q, bonds, P, seed=PRM["seed"], step=s)
+    dp = gp - op
+    dp -= L * np.round(dp / L)
+    print(f"10 steps: max |dr| {np.abs(dp).max():.3e}  max |dv| {np.abs(gv - ov).max():.3e}")
+    assert st == 0
+    assert np.abs(dp).max() < 1e-6
+    assert np.abs(gv - ov).max() < 1e-5
+    assert np.linalg.norm(gF - Fo) / np.linalg.norm(Fo) < 1e-5
+    Eg = PRM["kappa"] * (e5[0] + e5[2] + e5[3])
+    assert abs(Eg - Eo) < 1e-5 * abs(Eo)
+
+
+def test_cell_overflow_is_reported():
+    """Far more particles in one DPD cell than its capacity: flagged, no crash."""
+    L = 6.0
+    n = 200
+    pos = np.full((n, 3), 0.5) + 1e-3 * np.arange(n)[:, None]
+    pos[:, 1] = 0.5
+    vel = np.zeros((n, 3))
+    q = np.zeros(n)
+    d = _gpu(L, q, None, False)
+    tp, tv = _t(pos), _t(vel)
+    F = torch.empty_like(tp)
+    d.forces(tp, tv, F)
+    st = d.status()
+    d.close()
+    assert st == -8
+
+
+def test_dpd_polyelectrolyte_24k_first_steps():
+    """The benchmark workload: forces at step 0 and after 3 steps."""
+    s = wl.dpd_polyelectrolyte_24k()
+    from paper_1303_4523_amd.dpd import DPD
+    e = s.meta["enuf"]
+    dp = s.meta["dpd"]
+    prm = dict(dp, seed=1)
+    d = DPD(s.L, s.q, prm, bonds=s.bonds, enuf=e, device=0)
+    tp, tv = _t(s.pos), _t(s.vel)
+    F = torch.empty_like(tp)
+    d.forces(tp, tv, F, step=0)
+    F0 = F.cpu().numpy()
+    d.run(tp, tv, F, 1, 3)
+    st = d.status()
+    gp, gF = tp.cpu().numpy(), F.cpu().numpy()
+    d.close()
+    P = dict(dp, alpha=e["alpha"], r_cut=e["r_cut"], lambda_e=e["lam"], Kc=e["Kc"], use_elec=1)
+    Fo, _ = oracle.dpd_forces(s.pos, s.vel, s.q, s.bonds, P, seed=1, step=0)
+    assert st == 0
+    assert np.linalg.norm(F0 - Fo) / np.linalg.norm(Fo) < 1e-6
+    op, ov = s.pos.copy(), s.vel.copy()
+    for k in range(1, 4):
+        op, ov, Fo, _ = oracle.dpd_step(op, ov, Fo, s.q, s.bonds, P, seed=1, step=k)
+    ddp = gp - op
+    ddp -= s.L * np.round(ddp / s.L)
+    # the random forces are identical; the positions differ only through the
+    # NFFT force error dF (<= ~1e-4 absolute) integrated over n = 3 steps:
+    # |dr| <~ n^2 dt^2 dF / 2 ~ 4e-8
+    print(f"3 steps: max |dr| {np.abs(ddp).max():.3e}")
+    assert np.abs(ddp).max() < 1e-6
+    assert np.linalg.norm(gF - Fo) / np.linalg.norm(Fo) < 1e-6
