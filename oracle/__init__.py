@@ -15,8 +15,8 @@ Contents
 * ``dpd_forces`` / ``dpd_step``: the modified velocity-Verlet DPD step of
   Table 2 with the pair forces of eq. 2-7, harmonic bonds and the
   electrostatic force above.
-* ``philox4x64_10`` / ``theta``: the counter-based generator that supplies
-  the random variable theta_ij.
+* ``philox4x32_10`` / ``theta``: the counter-based generator that supplies
+  the random variable theta_ij (``philox4x64_10`` is kept and pinned too).
 * ``nfft_mirror``: a NumPy re-statement of the NFFT reciprocal path (window
   spread, FFT, deconvolution, window-gradient gather) for checking GPU
   intermediates; it is not the parity target.
@@ -63,6 +63,8 @@ def _load():
     lib.oracle_self.restype = d
     lib.oracle_philox4x64_10.argtypes = [ip, ip, ip]
     lib.oracle_philox4x64_10.restype = None
+    lib.oracle_philox4x32_10.argtypes = [ip, ip, ip]
+    lib.oracle_philox4x32_10.restype = None
     lib.oracle_theta.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i64, i64]
     lib.oracle_theta.restype = d
     lib.oracle_dpd_forces.argtypes = [i64, ip, ip, ip, i64, ip, ctypes.POINTER(_DPDParams),
@@ -166,6 +168,15 @@ def philox4x64_10(counter, key):
     k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
     out = np.zeros(4, dtype=np.uint64)
     _load().oracle_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox4x32_10(counter, key):
+    """Philox4x32 with 10 rounds: four 32-bit counter words, two key words."""
+    c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    _load().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 

@@ -24,8 +24,8 @@
  *  * One step of the modified velocity-Verlet DPD integrator (Table 2,
  *    steps 0-6) with conservative, dissipative and random pair forces
  *    (eq. 2-7), harmonic bonds (Sec. 2) and the electrostatic force above.
- *  * Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11) for the random
- *    variable theta_ij of the random force.
+ *  * Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) for the random
+ *    variable theta_ij of the random force (Philox4x64-10 is kept as well).
  *
  * Units: the Coulomb prefactor 1/(4 pi eps0 epsr) is 1; a driver scales
  * energies and forces by its coupling constant.
@@ -420,17 +420,36 @@ void oracle_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], ui
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Philox4x32-10 (same paper): 32-bit words, multipliers 0xD2511F53 and
+ * 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85. */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
 /*
  * theta_ij for the random force: zero mean, unit variance (eq. 5 text),
- * uniform on [-sqrt(3), sqrt(3)).  Counter (min(i,j), max(i,j), step, 0),
- * key (seed, 0); the first 64-bit output word supplies 53 random bits.
+ * uniform on [-sqrt(3), sqrt(3)).  Philox4x32-10 with counter
+ * (min(i,j), max(i,j), low and high word of the step) and key (low and high
+ * word of the seed); 53 random bits from the first two output words.
  */
 double oracle_theta(uint64_t seed, uint64_t step, int64_t i, int64_t j)
 {
-    uint64_t lo = (uint64_t)(i < j ? i : j), hi = (uint64_t)(i < j ? j : i);
-    uint64_t ctr[4] = {lo, hi, step, 0}, key[2] = {seed, 0}, out[4];
-    oracle_philox4x64_10(ctr, key, out);
-    double u = (double)(out[0] >> 11) * (1.0 / 9007199254740992.0);
+    uint32_t lo = (uint32_t)(i < j ? i : j), hi = (uint32_t)(i < j ? j : i);
+    uint32_t ctr[4] = {lo, hi, (uint32_t)step, (uint32_t)(step >> 32)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    uint64_t bits = ((uint64_t)out[0] << 21) | (uint64_t)(out[1] >> 11);
+    double u = (double)bits * (1.0 / 9007199254740992.0);
     return sqrt(3.0) * (2.0 * u - 1.0);
 }
 

@@ -21,6 +21,17 @@ def test_philox_known_answers():
         assert [int(x) for x in out] == v[6:10]
 
 
+def test_philox4x32_known_answers():
+    """Philox4x32-10 (the generator of theta_ij) against the published vectors."""
+    with open(os.path.join(GOLD, "philox4x32_10_kat.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 3
+    for row in rows:
+        v = [int(x, 16) for x in row]
+        out = oracle.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
 def test_philox_matches_numpy_bit_generator():
     """numpy.random.Philox is Philox4x64-10; it increments the counter before
     each block, so counter c - 1 yields the block of counter c."""
