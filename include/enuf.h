@@ -128,8 +128,9 @@ size_t enuf_plan_footprint_bytes(const enuf_plan *plan);
  * Reduced units R_c = m = k_B T = 1.  Pair forces act for r < 1 (eq. 2-7):
  *   F^C = a (1 - r) rhat,  F^D = -gamma (1 - r)^2 (v_ij . rhat) rhat,
  *   F^R = sigma (1 - r) theta_ij rhat / sqrt(dt),
- * theta_ij uniform on [-sqrt 3, sqrt 3) from Philox4x64-10 with counter
- * (min(i,j), max(i,j), step, 0) and key (seed, 0); harmonic bonds
+ * theta_ij uniform on [-sqrt 3, sqrt 3) from Philox4x32-10 with counter
+ * (min(i,j), max(i,j), step low word, step high word) and key (seed low word,
+ * seed high word), 53 bits from the first two output words; harmonic bonds
  * F = -K (r - r_eq) rhat; electrostatics kappa times the ENUF force.
  * One step is Table 2: v0 = v + lam dt F; v += dt F/2; r += dt v (wrapped
  * into [0, box)); F = F(r, v0); v += dt F/2.

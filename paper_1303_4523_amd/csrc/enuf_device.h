@@ -108,11 +108,13 @@ __device__ inline long long to_fixed(double v, double scale) {
 // (j / Ns) Ns R + k + r Ns, which leaves the result in natural order after
 // the last pass.  Passes are done in place: each thread first loads all of
 // its butterflies into registers, the block synchronises, then stores.
-// Lines are processed in groups small enough for kMaxBfly butterflies per
+// Lines are processed in groups small enough for MaxBfly butterflies per
 // thread.  inverse: the unnormalised inverse via conj(FFT(conj(x))).
 // All threads of the block must call this function.
 // ---------------------------------------------------------------------------
-constexpr int kMaxBfly = 4;
+// Butterflies per thread per sweep: bounded so that the register arrays of a
+// radix-5 pass stay small.
+template <typename T> struct MaxBfly { static constexpr int value = 2; };
 
 template <typename T, int R>
 __device__ inline void dft_radix(T *xr, T *xi) {
@@ -165,6 +167,7 @@ __device__ void stockham_pass(T *re, T *im, int ls, int nlines, int n, int Ns, c
   const int nt = blockDim.x, tid = threadIdx.x;
   const int nb = n / R;
   const int tstep = n / (Ns * R);
+  constexpr int kMaxBfly = MaxBfly<T>::value;
   int lg = (kMaxBfly * nt) / nb;  // whole lines per sweep
   if (lg < 1) lg = 1;
   for (int l0 = 0; l0 < nlines; l0 += lg) {

@@ -3,7 +3,7 @@
 //   k_dpd_pre    (0) v0 = v + lam dt F, (1) v += dt F / 2, (2) r += dt v (wrapped);
 //                bin particles into the DPD cell grid (cell edge >= R_c = 1)
 //   k_dpd_pair   (3) conservative, dissipative and random pair forces (eq. 2-7)
-//                with theta_ij from Philox4x64-10, plus harmonic bonds
+//                with theta_ij from Philox4x32-10, plus harmonic bonds
 //   [enuf_compute (4): electrostatic forces and energy]
 //   k_dpd_post   (5) F = F_dpd + kappa F_elec, (6) v += dt F / 2; clear the grid
 #include "enuf_device.h"
@@ -11,21 +11,20 @@
 
 namespace enuf {
 
-// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of
 // (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
 // with the key bumped by the Weyl constants between rounds.
-__device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r > 0) {
-      k0 += W0;
-      k1 += W1;
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
     }
-    const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-    const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
+    const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;
     c[2] = n2;
@@ -34,11 +33,13 @@ __device__ inline void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
 }
 
 // theta_ij: uniform on [-sqrt 3, sqrt 3) (zero mean, unit variance), keyed by
-// the unordered pair, the step and the seed; 53 bits of the first word.
+// the unordered pair, the step and the seed; 53 bits of the first two words.
 __device__ inline double dpd_theta(uint64_t seed, uint64_t step, int i, int j) {
-  uint64_t c[4] = {(uint64_t)(i < j ? i : j), (uint64_t)(i < j ? j : i), step, 0ull};
-  philox4x64_10(c, seed, 0ull);
-  const double u = (double)(c[0] >> 11) * (1.0 / 9007199254740992.0);
+  uint32_t c[4] = {(uint32_t)(i < j ? i : j), (uint32_t)(i < j ? j : i), (uint32_t)step,
+                   (uint32_t)(step >> 32)};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t bits = ((uint64_t)c[0] << 21) | (uint64_t)(c[1] >> 11);
+  const double u = (double)bits * (1.0 / 9007199254740992.0);
   return 1.7320508075688772935 * (2.0 * u - 1.0);
 }
 
@@ -54,13 +55,16 @@ __device__ inline int dpd_cell_of(double x, double inv_cell, int n) {
 }
 
 // mode 0: full predictor / half kick / drift; mode 1: forces only (v0 = v).
+// Each particle is binned into a slot of its DPD cell together with its
+// position (and index) and predicted velocity, so that the pair kernel reads
+// neighbour data contiguously.
 __global__ void __launch_bounds__(256)
 k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__restrict__ vel,
-          const double *__restrict__ force, double *__restrict__ v0, int *dcnt, int *dgrid,
-          int *status) {
+          const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
+          double4 *cvel, int *status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  double r[3], v[3], f[3];
+  double r[3], v[3], f[3], w[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     r[a] = pos[3 * i + a];
@@ -70,44 +74,58 @@ k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__
   if (mode == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      v0[3 * i + a] = v[a] + P.lam * P.dt * f[a];
+      w[a] = v[a] + P.lam * P.dt * f[a];
       v[a] += 0.5 * P.dt * f[a];
       r[a] = wrap_box(r[a] + P.dt * v[a], P.L);
       vel[3 * i + a] = v[a];
-      pos[3 * i + a] = r[a];
     }
   } else {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      v0[3 * i + a] = v[a];
+      w[a] = v[a];
       r[a] = wrap_box(r[a], P.L);
-      pos[3 * i + a] = r[a];
     }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    pos[3 * i + a] = r[a];
+    v0[3 * i + a] = w[a];
   }
   const int n = P.ncell;
   const int cell = (dpd_cell_of(r[0], P.inv_cell, n) * n + dpd_cell_of(r[1], P.inv_cell, n)) * n +
                    dpd_cell_of(r[2], P.inv_cell, n);
   const int s = atomicAdd(&dcnt[cell], 1);
-  if (s < P.cap)
-    dgrid[(size_t)cell * P.cap + s] = (int)i;
-  else
+  if (s < P.cap) {
+    cpos[(size_t)cell * P.cap + s] = make_double4(r[0], r[1], r[2], (double)i);
+    cvel[(size_t)cell * P.cap + s] = make_double4(w[0], w[1], w[2], 0.0);
+  } else {
     atomicCAS(status, 0, kEOverflow);
+  }
 }
 
 __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// One thread per particle; every pair is evaluated from both sides (the
-// random number is symmetric in i, j).  Sums are exact int64 fixed point so
-// that the visiting order inside a cell does not change the result.
+__device__ inline void atomic_add_fx(unsigned long long *acc, double v) {
+  atomicAdd(acc, (unsigned long long)to_fixed(v, kRealFxScale));
+}
+
+// Four lanes per particle i split the 27 neighbour cells.  Each pair is
+// evaluated once, by the lower index (Newton's third law): the force on i is
+// summed in registers, the opposite force goes to j through an int64 atomic.
+// All sums are exact fixed point (2^-36), so the result does not depend on
+// the order in which pairs are visited.
 __global__ void __launch_bounds__(256)
 k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos,
-           const double *__restrict__ v0, const int *__restrict__ dcnt, const int *__restrict__ dgrid,
+           const double *__restrict__ v0, const int *__restrict__ dcnt,
+           const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to,
-           double *__restrict__ fdpd) {
-  const int64_t i64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i64 >= N) return;
+           unsigned long long *facc) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i64 = g >> 2;
+  const int quad = (int)(g & 3);
+  if (i64 >= N) return;  // whole quads leave together
   const int i = (int)i64;
   const double L = P.L, invL = 1.0 / L, isdt = 1.0 / sqrt(P.dt);
   const double rx = pos[3 * i], ry = pos[3 * i + 1], rz = pos[3 * i + 2];
@@ -116,55 +134,79 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
   const int cx = dpd_cell_of(rx, P.inv_cell, n), cy = dpd_cell_of(ry, P.inv_cell, n),
             cz = dpd_cell_of(rz, P.inv_cell, n);
   long long fx = 0, fy = 0, fz = 0;
-  for (int o = 0; o < 27; ++o) {
+  for (int o = quad; o < 27; o += 4) {
     const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
     if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
     const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
     int cnt = dcnt[c];
     cnt = cnt < P.cap ? cnt : P.cap;
+    const double4 *cp = cpos + (size_t)c * P.cap;
     for (int s = 0; s < cnt; ++s) {
-      const int j = dgrid[(size_t)c * P.cap + s];
-      if (j == i) continue;
-      double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
+      const double4 e = cp[s];
+      const int j = (int)e.w;
+      if (j <= i) continue;
+      double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
       dx -= L * rint(dx * invL);
       dy -= L * rint(dy * invL);
       dz -= L * rint(dz * invL);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (!(r2 < 1.0) || r2 == 0.0) continue;
+      const double4 vj = cvel[(size_t)c * P.cap + s];
       const double r = sqrt(r2), ir = 1.0 / r;
       const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
       const double wr = 1.0 - r;
-      const double vdot = (vx - v0[3 * j]) * ex + (vy - v0[3 * j + 1]) * ey + (vz - v0[3 * j + 2]) * ez;
+      const double vdot = (vx - vj.x) * ex + (vy - vj.y) * ey + (vz - vj.z) * ez;
       const double th = dpd_theta(P.seed, step, i, j);
       const double mag = P.a * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
-      fx += to_fixed(mag * ex, kRealFxScale);
-      fy += to_fixed(mag * ey, kRealFxScale);
-      fz += to_fixed(mag * ez, kRealFxScale);
+      const long long ax = to_fixed(mag * ex, kRealFxScale), ay = to_fixed(mag * ey, kRealFxScale),
+                      az = to_fixed(mag * ez, kRealFxScale);
+      fx += ax;
+      fy += ay;
+      fz += az;
+      atomicAdd(&facc[3 * (size_t)j], (unsigned long long)(-ax));
+      atomicAdd(&facc[3 * (size_t)j + 1], (unsigned long long)(-ay));
+      atomicAdd(&facc[3 * (size_t)j + 2], (unsigned long long)(-az));
     }
   }
-  double gx = (double)fx * kRealFxInv, gy = (double)fy * kRealFxInv, gz = (double)fz * kRealFxInv;
-  // harmonic bonds, F_i = -K (r - r0) rhat_ij, in the order the bonds were given
-  for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
-    const int j = bond_to[b];
-    double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
-    dx -= L * rint(dx * invL);
-    dy -= L * rint(dy * invL);
-    dz -= L * rint(dz * invL);
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r == 0.0) continue;
-    const double mag = -P.k_bond * (r - P.r0_bond) / r;
-    gx += mag * dx;
-    gy += mag * dy;
-    gz += mag * dz;
+  // harmonic bonds with j > i, F_i = -K (r - r0) rhat_ij
+  if (quad == 0) {
+    for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
+      const int j = bond_to[b];
+      if (j <= i) continue;
+      double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
+      dx -= L * rint(dx * invL);
+      dy -= L * rint(dy * invL);
+      dz -= L * rint(dz * invL);
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (r == 0.0) continue;
+      const double mag = -P.k_bond * (r - P.r0_bond) / r;
+      const long long ax = to_fixed(mag * dx, kRealFxScale), ay = to_fixed(mag * dy, kRealFxScale),
+                      az = to_fixed(mag * dz, kRealFxScale);
+      fx += ax;
+      fy += ay;
+      fz += az;
+      atomicAdd(&facc[3 * (size_t)j], (unsigned long long)(-ax));
+      atomicAdd(&facc[3 * (size_t)j + 1], (unsigned long long)(-ay));
+      atomicAdd(&facc[3 * (size_t)j + 2], (unsigned long long)(-az));
+    }
   }
-  fdpd[3 * i] = gx;
-  fdpd[3 * i + 1] = gy;
-  fdpd[3 * i + 2] = gz;
+  fx += __shfl_xor(fx, 1, kWave);
+  fy += __shfl_xor(fy, 1, kWave);
+  fz += __shfl_xor(fz, 1, kWave);
+  fx += __shfl_xor(fx, 2, kWave);
+  fy += __shfl_xor(fy, 2, kWave);
+  fz += __shfl_xor(fz, 2, kWave);
+  if (quad == 0) {
+    atomicAdd(&facc[3 * (size_t)i], (unsigned long long)fx);
+    atomicAdd(&facc[3 * (size_t)i + 1], (unsigned long long)fy);
+    atomicAdd(&facc[3 * (size_t)i + 2], (unsigned long long)fz);
+  }
 }
 
-// mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces only.
+// mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
+// only.  Clears the pair accumulator and the cell counts for the next step.
 __global__ void __launch_bounds__(256)
-k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
+k_dpd_post(int64_t N, int mode, DpdParams P, unsigned long long *facc,
            const double *__restrict__ felec, double *__restrict__ force, double *__restrict__ vel,
            int *dcnt, int ncell3) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,7 +215,8 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
   if (i >= N) return;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double f = fdpd[3 * i + a];
+    double f = (double)(long long)facc[3 * i + a] * kRealFxInv;
+    facc[3 * i + a] = 0ull;
     if (felec) f += P.kappa * felec[3 * i + a];
     force[3 * i + a] = f;
     if (mode == 0) vel[3 * i + a] += 0.5 * P.dt * f;
@@ -181,34 +224,35 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
 }
 
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
-                          const double *force, double *v0, int *dcnt, int *dgrid, int *status,
-                          hipStream_t st, KernelTimer *tm) {
+                          const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
+                          int *status, hipStream_t st, KernelTimer *tm) {
   const int nb = (int)((N + 255) / 256);
   if (tm) tm->before(0, st);
-  hipLaunchKernelGGL(k_dpd_pre, dim3(nb), dim3(256), 0, st, N, mode, P, pos, vel, force, v0, dcnt, dgrid,
-                     status);
+  hipLaunchKernelGGL(k_dpd_pre, dim3(nb), dim3(256), 0, st, N, mode, P, pos, vel, force, v0, dcnt, cpos,
+                     cvel, status);
   if (tm) tm->after(0, st);
   return hipGetLastError();
 }
 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
-                           const double *v0, const int *dcnt, const int *dgrid, const int *bond_start,
-                           const int *bond_to, double *fdpd, hipStream_t st, KernelTimer *tm) {
-  const int nb = (int)((N + 255) / 256);
+                           const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
+                           const int *bond_start, const int *bond_to, unsigned long long *facc,
+                           hipStream_t st, KernelTimer *tm) {
+  const int nb = (int)((4 * N + 255) / 256);
   if (tm) tm->before(1, st);
-  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(256), 0, st, N, P, step, pos, v0, dcnt, dgrid, bond_start,
-                     bond_to, fdpd);
+  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(256), 0, st, N, P, step, pos, v0, dcnt, cpos, cvel,
+                     bond_start, bond_to, facc);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }
 
-hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
+hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, unsigned long long *facc,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,
                            KernelTimer *tm) {
   const int nb = (int)((N + 255) / 256);
   const int ncell3 = P.ncell * P.ncell * P.ncell;
   if (tm) tm->before(9, st);
-  hipLaunchKernelGGL(k_dpd_post, dim3(nb), dim3(256), 0, st, N, mode, P, fdpd, felec, force, vel, dcnt,
+  hipLaunchKernelGGL(k_dpd_post, dim3(nb), dim3(256), 0, st, N, mode, P, facc, felec, force, vel, dcnt,
                      ncell3);
   if (tm) tm->after(9, st);
   return hipGetLastError();

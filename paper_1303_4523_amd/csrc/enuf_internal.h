@@ -9,7 +9,7 @@ namespace enuf {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kPrepThreads = 256;  // threads per block of the particle-parallel kernels
-constexpr int kPassThreads = 256;  // threads per block of the mesh-plane kernels
+constexpr int kPassThreads = 512;  // threads per block of the mesh-plane kernels
 constexpr int kMaxRadixPasses = 16;
 
 // Device-resident scalars produced by the preparation kernels of one compute.
@@ -88,13 +88,17 @@ struct ComputeBuffers {
   int *slot;             // [N] compact slot of particle i, or -1
   // real-space cell grid
   int *ccnt;             // [ncell^3]
-  int *cgrid;            // [ncell^3 * cap]
-  long long *freal;      // [N * 3] fixed-point real-space forces per slot
+  double4 *cgrid;        // [ncell^3 * cap] (x, y, z, q) per cell slot
+  int *cidx;             // [ncell^3 * cap] compact index per cell slot
+  unsigned long long *freal;  // [N * 3] fixed-point real-space forces per slot (zero between calls)
   unsigned long long *eacc;  // [2] fixed-point E_real (whole), E_slater
   // reciprocal
   void *gzy;             // [M * nky * Kc] complex (double2 or float2)
   double *epart;         // [nky] k-space energy per ky row
   double4 *part;         // [N * 2p] gather partials (dwx A, wx By, wx Bz, wx A)
+  void *winv;            // [N * 3 * 2p] window values per charge, axis, offset (double or float)
+  void *wind;            // [N * 3 * 2p] window derivatives
+  int *mbase;            // [N * 4] first stencil index per axis
   double *blk_eg;        // [nblk] per-block sums of q * A
   // tables
   double *atab;          // [nky] exp(-pi^2 k^2/(alpha L)^2) / Phi(k/M)^2

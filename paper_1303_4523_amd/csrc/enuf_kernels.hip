@@ -5,6 +5,7 @@
 //   k_prep_compact  wrap positions, compact the charges in index order, bin
 //                   them into the real-space cell grid, reduce sum q, |q|, q^2
 //   k_real          real-space pair term (eq. 31 + Slater correction eq. 27)
+//   k_window        window values and derivatives of every charge, per axis
 //   k_recip_fwd     per x-plane: window spread (transposed NFFT, eq. 14) into
 //                   an LDS plane, z real-to-complex FFT, y FFT, keep |k| < Kc
 //   k_recip_x       per ky row: x FFT, influence multiply and FP64 energy
@@ -77,8 +78,8 @@ k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, i
 __global__ void __launch_bounds__(kPrepThreads)
 k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
                double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
-               double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, int *cgrid,
-               unsigned *done, DevScalars *sc) {
+               double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
+               int *cidx, unsigned *done, DevScalars *sc) {
   __shared__ int s_int[kPrepThreads / kWave];
   __shared__ int s_wcnt[kPrepThreads / kWave];
   __shared__ double s_dbl[kPrepThreads / kWave];
@@ -125,10 +126,12 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
       cz = cz < cp.ncell ? cz : cp.ncell - 1;
       const int cell = (cx * cp.ncell + cy) * cp.ncell + cz;
       const int s = atomicAdd(&ccnt[cell], 1);
-      if (s < cp.cap)
-        cgrid[(size_t)cell * cp.cap + s] = j;
-      else
+      if (s < cp.cap) {
+        cgrid[(size_t)cell * cp.cap + s] = make_double4(x, y, z, qi);
+        cidx[(size_t)cell * cp.cap + s] = j;
+      } else {
         set_status(sc, kEOverflow);
+      }
     } else {
       slot[i] = -1;
     }
@@ -234,12 +237,15 @@ __device__ inline bool cell_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// One wavefront per charge: lanes 0..53 take one of the 27 neighbour cells
-// and every other slot in it.
+// One wavefront per charge j: lanes 0..53 take one of the 27 neighbour cells
+// and every other slot in it.  Each pair is evaluated once, by its lower
+// compact index (Newton's third law): the force on j is summed in registers,
+// the opposite force goes to k through an int64 atomic; energies count the
+// whole pair.  All sums are exact fixed point.
 __global__ void __launch_bounds__(256)
-k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *__restrict__ cgrid,
-       CellParams cp, double L, double alpha, double rc2, double lam, DevScalars *sc,
-       long long *freal, unsigned long long *eacc) {
+k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
+       const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
+       DevScalars *sc, unsigned long long *freal, unsigned long long *eacc) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wpb = blockDim.x / kWave;
   const int nq = sc->nq;
@@ -260,10 +266,12 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *
         const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
         int cnt = ccnt[c];
         cnt = cnt < cp.cap ? cnt : cp.cap;
+        const double4 *cg = cgrid + (size_t)c * cp.cap;
+        const int *ck = cidx + (size_t)c * cp.cap;
         for (int s = par; s < cnt; s += 2) {
-          const int k = cgrid[(size_t)c * cp.cap + s];
-          if (k == j) continue;
-          const double4 cj = xq[k];
+          const int k = ck[s];
+          if (k <= j) continue;
+          const double4 cj = cg[s];
           double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
           dx -= L * rint(dx * invL);
           dy -= L * rint(dy * invL);
@@ -278,11 +286,16 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *
           const double qq = ci.w * cj.w;
           const double g = qq * f;
           if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
-          fx += to_fixed(g * dx, kRealFxScale);
-          fy += to_fixed(g * dy, kRealFxScale);
-          fz += to_fixed(g * dz, kRealFxScale);
-          ee += to_fixed(0.5 * qq * u, kRealFxScale);
-          es += to_fixed(0.5 * qq * us, kRealFxScale);
+          const long long ax = to_fixed(g * dx, kRealFxScale), ay = to_fixed(g * dy, kRealFxScale),
+                          az = to_fixed(g * dz, kRealFxScale);
+          fx += ax;
+          fy += ay;
+          fz += az;
+          atomicAdd(&freal[3 * (size_t)k], (unsigned long long)(-ax));
+          atomicAdd(&freal[3 * (size_t)k + 1], (unsigned long long)(-ay));
+          atomicAdd(&freal[3 * (size_t)k + 2], (unsigned long long)(-az));
+          ee += to_fixed(qq * u, kRealFxScale);
+          es += to_fixed(qq * us, kRealFxScale);
         }
       }
     }
@@ -293,9 +306,9 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *
     ee = wave_sum_ll(ee);
     es = wave_sum_ll(es);
     if (lane == 0) {
-      freal[3 * (size_t)j] = fx;
-      freal[3 * (size_t)j + 1] = fy;
-      freal[3 * (size_t)j + 2] = fz;
+      atomicAdd(&freal[3 * (size_t)j], (unsigned long long)fx);
+      atomicAdd(&freal[3 * (size_t)j + 1], (unsigned long long)fy);
+      atomicAdd(&freal[3 * (size_t)j + 2], (unsigned long long)fz);
       atomicAdd(&eacc[0], (unsigned long long)ee);
       atomicAdd(&eacc[1], (unsigned long long)es);
     }
@@ -303,18 +316,53 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const int *
 }
 
 // ---------------------------------------------------------------------------
+// Window values phi(u) and derivatives phi'(u) of every charge, for the 2p
+// stencil offsets of each axis: winv[(j * 3 + a) * 2p + s] at
+// u = M x_a / L - (b_a + s), b_a = floor(M x_a / L) - p + 1 (stored in mbase).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_window(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp, T *winv,
+         T *wind, int *mbase) {
+  const int p = mp.win.p, P2 = 2 * p, per = 3 * P2;
+  const int64_t total = (int64_t)sc->nq * per;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(t / per), r = (int)(t % per), a = r / P2, s = r % P2;
+    const double4 c = xq[j];
+    const double x = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+    double tt;
+    const int b = mesh_cell(x, mp.m_over_l, mp.M, &tt) - p + 1;
+    T v, d;
+    window_eval<T>(mp.win, (T)(tt - (double)(b + s)), &v, &d);
+    winv[t] = v;
+    wind[t] = d;
+    if (s == 0) mbase[4 * (size_t)j + a] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Mesh pass 1: spread + z R2C FFT + y FFT for one x-plane.
 // LDS: int64 accumulator plane [M][Mp] (aliased by the T plane after
 // conversion), spectrum lines Zre/Zim [Kc][Mz], twiddles, a charge queue.
+// Work items of the spread are (queued charge, stencil row sy): each adds the
+// 2p products q wx wy[sy] wz[sz] of one mesh row.
 // ---------------------------------------------------------------------------
+__device__ inline int pow2_at_least(int v) {
+  int r = 1;
+  while (r < v) r <<= 1;
+  return r;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
-k_recip_fwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp,
+k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const T *__restrict__ winv,
+            const DevScalars *__restrict__ sc, MeshParams mp,
             const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p;
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
-  const int wv = tid / kWave, nw = nt / kWave;
+  const int P2pad = pow2_at_least(P2);
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int x0 = blockIdx.x;
 
   long long *acc = reinterpret_cast<long long *>(smem);
@@ -332,9 +380,9 @@ k_recip_fwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, M
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  int *queue = reinterpret_cast<int *>(smem + off);
-  off += (size_t)nt * sizeof(int);
-  int *qn = reinterpret_cast<int *>(smem + off);
+  int *qj = reinterpret_cast<int *>(smem + off);
+  int *qs = qj + nt;
+  int *qn = qs + nt;
 
   for (int m = tid; m < M; m += nt) {
     twr[m] = tw[m].x;
@@ -350,39 +398,29 @@ k_recip_fwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, M
     __syncthreads();
     const int j = base + tid;
     if (j < nq) {
-      double t;
-      const int cx = mesh_cell(xq[j].x, mp.m_over_l, M, &t);
-      if (mod_pos(x0 - (cx - p + 1), M) < P2) queue[atomicAdd(qn, 1)] = j;
+      const int sx = mod_pos(x0 - mbase[4 * (size_t)j], M);
+      if (sx < P2) {
+        const int e = atomicAdd(qn, 1);
+        qj[e] = j;
+        qs[e] = sx;
+      }
     }
     __syncthreads();
     const int cnt = *qn;
-    for (int e = wv; e < cnt; e += nw) {
-      const double4 c = xq[queue[e]];
-      double tx, ty, tz;
-      const int bx = mesh_cell(c.x, mp.m_over_l, M, &tx) - p + 1;
-      const int by = mesh_cell(c.y, mp.m_over_l, M, &ty) - p + 1;
-      const int bz = mesh_cell(c.z, mp.m_over_l, M, &tz) - p + 1;
-      const int sx = mod_pos(x0 - bx, M);
-      T wval = (T)0, wder;
-      if (lane < P2)
-        window_eval<T>(mp.win, (T)(ty - (double)(by + lane)), &wval, &wder);
-      else if (lane < 2 * P2)
-        window_eval<T>(mp.win, (T)(tz - (double)(bz + lane - P2)), &wval, &wder);
-      else if (lane == 2 * P2)
-        window_eval<T>(mp.win, (T)(tx - (double)(bx + sx)), &wval, &wder);
-      const T qwx = (T)c.w * __shfl(wval, 2 * P2, kWave);
-      for (int f0 = 0; f0 < P2 * P2; f0 += kWave) {
-        const int f = f0 + lane;
-        const bool act = f < P2 * P2;
-        const int sy = act ? f / P2 : 0, sz = act ? f % P2 : 0;
-        const T wy = __shfl(wval, sy, kWave);
-        const T wz = __shfl(wval, P2 + sz, kWave);
-        if (act) {
-          const int row = mod_pos(by + sy, M), col = mod_pos(bz + sz, M);
-          const double v = (double)(qwx * wy * wz);
-          atomicAdd(reinterpret_cast<unsigned long long *>(&acc[row * Mp + col]),
-                    (unsigned long long)to_fixed(v, scale));
-        }
+    for (int it = tid; it < cnt * P2pad; it += nt) {
+      const int e = it / P2pad, sy = it % P2pad;
+      if (sy >= P2) continue;
+      const int jj = qj[e];
+      const T *w = winv + (size_t)jj * 3 * P2;
+      const T wrow = (T)xq[jj].w * w[qs[e]] * w[P2 + sy];
+      const int row = mod_pos(mbase[4 * (size_t)jj + 1] + sy, M);
+      int col = mbase[4 * (size_t)jj + 2];
+      col = col < 0 ? col + M : col;
+      long long *arow = acc + (size_t)row * Mp;
+      for (int sz = 0; sz < P2; ++sz) {
+        const double v = (double)(wrow * w[2 * P2 + sz]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
+        col = (col + 1 == M) ? 0 : col + 1;
       }
     }
     __syncthreads();
@@ -508,16 +546,20 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
 
 // ---------------------------------------------------------------------------
 // Mesh pass 3: inverse y FFT, complex-to-real z FFT and gather for one plane.
+// Work items are (queued charge, stencil row sy) in groups of P2pad lanes
+// (P2pad = 2p rounded up to a power of two); each lane sums its mesh row
+// against the z window and its derivative, the group reduces with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
-k_recip_bwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp,
+k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const T *__restrict__ winv,
+            const T *__restrict__ wind, const DevScalars *__restrict__ sc, MeshParams mp,
             const typename CplxOf<T>::type *__restrict__ tw,
             const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
-  const int wv = tid / kWave, nw = nt / kWave;
+  const int P2pad = pow2_at_least(P2);
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int x0 = blockIdx.x;
 
   T *plane = reinterpret_cast<T *>(smem);
@@ -528,9 +570,9 @@ k_recip_bwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, M
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  int *queue = reinterpret_cast<int *>(smem + off);
-  off += (size_t)nt * sizeof(int);
-  int *qn = reinterpret_cast<int *>(smem + off);
+  int *qj = reinterpret_cast<int *>(smem + off);
+  int *qs = qj + nt;
+  int *qn = qs + nt;
 
   for (int m = tid; m < M; m += nt) {
     twr[m] = tw[m].x;
@@ -581,46 +623,53 @@ k_recip_bwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, M
     __syncthreads();
     const int j = base + tid;
     if (j < nq) {
-      double t;
-      const int cx = mesh_cell(xq[j].x, mp.m_over_l, M, &t);
-      if (mod_pos(x0 - (cx - p + 1), M) < P2) queue[atomicAdd(qn, 1)] = j;
+      const int sx = mod_pos(x0 - mbase[4 * (size_t)j], M);
+      if (sx < P2) {
+        const int e = atomicAdd(qn, 1);
+        qj[e] = j;
+        qs[e] = sx;
+      }
     }
     __syncthreads();
     const int cnt = *qn;
-    for (int e = wv; e < cnt; e += nw) {
-      const int jj = queue[e];
-      const double4 c = xq[jj];
-      double tx, ty, tz;
-      const int bx = mesh_cell(c.x, mp.m_over_l, M, &tx) - p + 1;
-      const int by = mesh_cell(c.y, mp.m_over_l, M, &ty) - p + 1;
-      const int bz = mesh_cell(c.z, mp.m_over_l, M, &tz) - p + 1;
-      const int sx = mod_pos(x0 - bx, M);
-      T wval = (T)0, wder = (T)0;
-      if (lane < P2)
-        window_eval<T>(mp.win, (T)(ty - (double)(by + lane)), &wval, &wder);
-      else if (lane < 2 * P2)
-        window_eval<T>(mp.win, (T)(tz - (double)(bz + lane - P2)), &wval, &wder);
-      else if (lane == 2 * P2)
-        window_eval<T>(mp.win, (T)(tx - (double)(bx + sx)), &wval, &wder);
-      const T wx = __shfl(wval, 2 * P2, kWave), dwx = __shfl(wder, 2 * P2, kWave);
-      T A = (T)0, By = (T)0, Bz = (T)0;
-      for (int f0 = 0; f0 < P2 * P2; f0 += kWave) {
-        const int f = f0 + lane;
-        const bool act = f < P2 * P2;
-        const int sy = act ? f / P2 : 0, sz = act ? f % P2 : 0;
-        const T wy = __shfl(wval, sy, kWave), dwy = __shfl(wder, sy, kWave);
-        const T wz = __shfl(wval, P2 + sz, kWave), dwz = __shfl(wder, P2 + sz, kWave);
-        if (act) {
-          const T h = plane[mod_pos(by + sy, M) * Mp + mod_pos(bz + sz, M)];
-          A += h * wy * wz;
-          By += h * dwy * wz;
-          Bz += h * wy * dwz;
-        }
+    // whole wavefronts iterate together so that the group shuffles see every lane
+    const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
+    for (int it = tid; it < items; it += nt) {
+      const int e = it / P2pad, sy = it % P2pad;
+      const bool has = e < cnt;
+      const bool act = has && sy < P2;
+      int jj = 0, sx = 0;
+      T A = (T)0, By = (T)0, Bz = (T)0, wx = (T)0, dwx = (T)0;
+      if (has) {
+        jj = qj[e];
+        sx = qs[e];
       }
-      A = wave_sum(A);
-      By = wave_sum(By);
-      Bz = wave_sum(Bz);
-      if (lane == 0)
+      if (act) {
+        const T *w = winv + (size_t)jj * 3 * P2;
+        const T *d = wind + (size_t)jj * 3 * P2;
+        const int row = mod_pos(mbase[4 * (size_t)jj + 1] + sy, M);
+        int col = mbase[4 * (size_t)jj + 2];
+        col = col < 0 ? col + M : col;
+        const T *hrow = plane + (size_t)row * Mp;
+        T a = (T)0, b = (T)0;
+        for (int sz = 0; sz < P2; ++sz) {
+          const T h = hrow[col];
+          a += h * w[2 * P2 + sz];
+          b += h * d[2 * P2 + sz];
+          col = (col + 1 == M) ? 0 : col + 1;
+        }
+        A = w[P2 + sy] * a;
+        By = d[P2 + sy] * a;
+        Bz = w[P2 + sy] * b;
+        wx = w[sx];
+        dwx = d[sx];
+      }
+      for (int o = P2pad / 2; o >= 1; o >>= 1) {
+        A += __shfl_xor(A, o, kWave);
+        By += __shfl_xor(By, o, kWave);
+        Bz += __shfl_xor(Bz, o, kWave);
+      }
+      if (has && sy == 0)
         part[(size_t)jj * P2 + sx] = make_double4((double)(dwx * A), (double)(wx * By),
                                                   (double)(wx * Bz), (double)(wx * A));
     }
@@ -633,7 +682,7 @@ k_recip_bwd(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, M
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kPrepThreads)
 k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
-          const long long *__restrict__ freal, const double4 *__restrict__ part, int P2,
+          unsigned long long *freal, const double4 *__restrict__ part, int P2,
           double fscale, double inv2piL, double alpha, int nblk, double *blk_eg, unsigned *done,
           const double *__restrict__ epart, int nky, const unsigned long long *eacc,
           const DevScalars *sc, double *forces, double *energy, double *energy5) {
@@ -655,9 +704,12 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
         a += v.w;
       }
       const double qj = xq[j].w;
-      fx = (double)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
-      fy = (double)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
-      fz = (double)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
+      fx = (double)(long long)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
+      fy = (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
+      fz = (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
+      freal[3 * (size_t)j] = 0ull;  // leave the accumulator cleared for the next call
+      freal[3 * (size_t)j + 1] = 0ull;
+      freal[3 * (size_t)j + 2] = 0ull;
       eg = qj * a;
     }
     forces[3 * i] = fx;
@@ -702,7 +754,7 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
 // ---------------------------------------------------------------------------
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd) {
   const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
-  const size_t misc = (size_t)kPassThreads * sizeof(int) + 16;
+  const size_t misc = 2 * (size_t)kPassThreads * sizeof(int) + 16;
   const size_t acc = (size_t)m.M * m.Mp * sizeof(long long);
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
@@ -719,6 +771,7 @@ hipError_t configure_kernels(size_t max_lds) {
   e = hipFuncSetAttribute((const void *)k_recip_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_recip_x<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_recip_x<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
   if (e != hipSuccess) return e;
@@ -733,14 +786,22 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
   const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
   C *gzy = reinterpret_cast<C *>(b.gzy);
   const MeshParams &mp = cfg.mesh;
+  T *winv = reinterpret_cast<T *>(b.winv), *wind = reinterpret_cast<T *>(b.wind);
+  const int per = 6 * mp.win.p;
+  int64_t nwin = (cfg.N * per + 255) / 256;
+  const int gwin = (int)(nwin < 4096 ? nwin : 4096);
+  hipLaunchKernelGGL(k_window<T>, dim3(gwin), dim3(256), 0, st, (const double4 *)b.xq, (const DevScalars *)b.sc,
+                     mp, winv, wind, b.mbase);
   if (tm) tm->before(5, st);
-  hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, b.xq, b.sc, mp, tw, gzy);
+  hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, (const double4 *)b.xq,
+                     (const int *)b.mbase, (const T *)winv, (const DevScalars *)b.sc, mp, tw, gzy);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
   hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy, b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
-  hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, b.xq, b.sc, mp, tw,
+  hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, (const double4 *)b.xq,
+                     (const int *)b.mbase, (const T *)winv, (const T *)wind, (const DevScalars *)b.sc, mp, tw,
                      (const C *)gzy, b.part);
   if (tm) tm->after(7, st);
 }
@@ -757,14 +818,14 @@ hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, con
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
                      (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
-                     b.done, b.sc);
+                     b.cidx, b.done, b.sc);
   if (tm) tm->after(3, st);
   int grid_real = (int)((cfg.N + 3) / 4);
   grid_real = grid_real < 2048 ? grid_real : 2048;
   if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(256), 0, st, (const double4 *)b.xq, (const int *)b.ccnt,
-                     (const int *)b.cgrid, cfg.cells, cfg.L, cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda,
-                     b.sc, b.freal, b.eacc);
+                     (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L, cfg.alpha,
+                     cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.eacc);
   if (tm) tm->after(4, st);
   if (cfg.precision == 0)
     launch_mesh<double>(cfg, b, st, tm);
@@ -775,7 +836,7 @@ hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, con
   const double inv2piL = 1.0 / (2.0 * M_PI * L);
   if (tm) tm->before(8, st);
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
-                     (const double4 *)b.xq, (const long long *)b.freal, (const double4 *)b.part,
+                     (const double4 *)b.xq, b.freal, (const double4 *)b.part,
                      2 * cfg.mesh.win.p, fscale, inv2piL, cfg.alpha, nblk, b.blk_eg, b.done,
                      (const double *)b.epart, cfg.mesh.nky, (const unsigned long long *)b.eacc,
                      (const DevScalars *)b.sc, forces, energy_total, energy5);

@@ -207,23 +207,28 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.idx = (int *)pl->alloc(n * sizeof(int));
   b.slot = (int *)pl->alloc(n * sizeof(int));
   b.ccnt = (int *)pl->alloc(ncell3 * sizeof(int));
-  b.cgrid = (int *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(int));
-  b.freal = (long long *)pl->alloc(n * 3 * sizeof(long long));
+  b.cgrid = (double4 *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(double4));
+  b.cidx = (int *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(int));
+  b.freal = (unsigned long long *)pl->alloc(n * 3 * sizeof(unsigned long long));
   b.eacc = (unsigned long long *)pl->alloc(4 * sizeof(unsigned long long));
   b.gzy = pl->alloc((size_t)M * m.nky * Kc * sizeof(double2));
   b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
   b.part = (double4 *)pl->alloc(n * P2 * sizeof(double4));
   b.blk_eg = (double *)pl->alloc(nblk * sizeof(double));
+  b.winv = pl->alloc(n * 3 * P2 * sizeof(double));
+  b.wind = pl->alloc(n * 3 * P2 * sizeof(double));
+  b.mbase = (int *)pl->alloc(n * 4 * sizeof(int));
   b.atab = (double *)pl->alloc((size_t)m.nky * sizeof(double));
   b.tw64 = (double2 *)pl->alloc((size_t)M * sizeof(double2));
   b.tw32 = (float2 *)pl->alloc((size_t)M * sizeof(float2));
-  if (pl->allocations.size() != 18) {  // alloc() records successful allocations only
+  if (pl->allocations.size() != 22) {  // alloc() records successful allocations only
     set_error("device allocation failed");
     delete pl;
     return nullptr;
   }
   if (hipMemset(b.done, 0, 4 * sizeof(unsigned)) != hipSuccess ||
-      hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess) {
+      hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
+      hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess) {
     set_error("hipMemset failed");
     delete pl;
     return nullptr;
@@ -344,11 +349,12 @@ struct enuf_dpd {
   enuf_plan *plan = nullptr;  // not owned
   double *q = nullptr;        // [N]
   double *v0 = nullptr;       // [N * 3] predicted velocities
-  double *fdpd = nullptr;     // [N * 3]
+  unsigned long long *facc = nullptr;  // [N * 3] fixed-point pair + bond forces
   double *felec = nullptr;    // [N * 3]
   double *e5 = nullptr;       // [5]
   int *dcnt = nullptr;        // [ncell^3]
-  int *dgrid = nullptr;       // [ncell^3 * cap]
+  double4 *cpos = nullptr;    // [ncell^3 * cap] (x, y, z, index) per cell slot
+  double4 *cvel = nullptr;    // [ncell^3 * cap] predicted velocity per cell slot
   int *bond_start = nullptr;  // [N + 1]
   int *bond_to = nullptr;     // [2 nbonds]
   int *status = nullptr;      // [1]
@@ -421,19 +427,21 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
   d->q = (double *)d->alloc(n * sizeof(double));
   d->v0 = (double *)d->alloc(3 * n * sizeof(double));
-  d->fdpd = (double *)d->alloc(3 * n * sizeof(double));
+  d->facc = (unsigned long long *)d->alloc(3 * n * sizeof(unsigned long long));
   d->felec = (double *)d->alloc(3 * n * sizeof(double));
   d->e5 = (double *)d->alloc(5 * sizeof(double));
   d->dcnt = (int *)d->alloc(nc3 * sizeof(int));
-  d->dgrid = (int *)d->alloc(nc3 * (size_t)P.cap * sizeof(int));
+  d->cpos = (double4 *)d->alloc(nc3 * (size_t)P.cap * sizeof(double4));
+  d->cvel = (double4 *)d->alloc(nc3 * (size_t)P.cap * sizeof(double4));
   d->bond_start = (int *)d->alloc((n + 1) * sizeof(int));
   d->bond_to = (int *)d->alloc(to.size() * sizeof(int));
   d->status = (int *)d->alloc(sizeof(int));
-  if (d->allocations.size() != 10) { set_error("device allocation failed"); delete d; return nullptr; }
+  if (d->allocations.size() != 11) { set_error("device allocation failed"); delete d; return nullptr; }
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
+      hipMemset(d->facc, 0, 3 * n * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     set_error("device setup of the DPD integrator failed");
     delete d;
@@ -452,17 +460,18 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step) {
   const int64_t N = d->N;
   KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
-  hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->dgrid, d->status, d->stream, tm);
+  hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
+                                d->stream, tm);
   if (e == hipSuccess)
-    e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->dgrid, d->bond_start, d->bond_to, d->fdpd,
-                        d->stream, tm);
+    e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+                        d->facc, d->stream, tm);
   if (e == hipSuccess && d->plan) {
     enuf_plan *pl = d->plan;
     pl->stream = d->stream;
     e = launch_compute(pl->cfg, pl->buf, pos, d->q, d->felec, nullptr, d->e5, d->stream, tm);
   }
   if (e == hipSuccess)
-    e = launch_dpd_post(N, mode, d->P, d->fdpd, d->plan ? d->felec : nullptr, force, vel, d->dcnt, d->stream,
+    e = launch_dpd_post(N, mode, d->P, d->facc, d->plan ? d->felec : nullptr, force, vel, d->dcnt, d->stream,
                         tm);
   if (e != hipSuccess) {
     set_error(std::string("DPD kernel launch failed: ") + hipGetErrorString(e));
