@@ -40,6 +40,8 @@ def parse():
                     help="oracle DPD steps timed on the host for cpu_baseline (0 = skip)")
     ap.add_argument("--time-kernel", default="mesh_bwd",
                     help="kernel whose launches are event-timed for the roofline entry")
+    ap.add_argument("--serial", action="store_true",
+                    help="run each step on one stream (no overlap of pair, real-space and mesh kernels)")
     return ap.parse_args()
 
 
@@ -102,6 +104,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     d = DPD(s.L, s.q, prm, bonds=s.bonds, enuf=e, precision="fp64", device=0)
+    if a.serial:
+        d.set_concurrency(False)
     pos = torch.tensor(s.pos, dtype=torch.float64, device=dev)
     vel = torch.tensor(s.vel, dtype=torch.float64, device=dev)
     F = torch.empty_like(pos)
@@ -154,7 +158,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "DPD polyelectrolyte + salt, L=20, N=24000, Nq=1650, ENUF M=64 Kc=16 p=4",
                    "N": s.N, "Nq": s.Nq, "box": s.L, "M": e["M"], "Kc": e["Kc"], "p": e["p"],
-                   "precision": "fp64", "window": "kaiser-bessel"},
+                   "precision": "fp64", "window": "kaiser-bessel",
+                   "schedule": "serial" if a.serial else "forked streams"},
         "roofline": roofline,
     }
     if a.cpu_steps > 0:

@@ -174,6 +174,11 @@ int enuf_dpd_forces(enuf_dpd *dpd, double *pos, const double *vel, double *force
 int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_t first_step,
                  int nsteps);
 
+/* Overlap the pair forces and the real-space term with the mesh passes on two
+ * internal streams (enable = 1, the default) or run the whole step on the
+ * integrator's stream (0). */
+int enuf_dpd_set_concurrency(enuf_dpd *dpd, int enable);
+
 /* Copy (on the stream) the ENUF energy components of the last force
  * evaluation, unscaled by kappa, into the device array energy5 (as in
  * enuf_compute_components).  Without a plan all five are 0. */

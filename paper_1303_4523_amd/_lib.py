@@ -55,6 +55,8 @@ lib.enuf_dpd_forces.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
 lib.enuf_dpd_forces.restype = _int
 lib.enuf_dpd_run.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64, _int]
 lib.enuf_dpd_run.restype = _int
+lib.enuf_dpd_set_concurrency.argtypes = [_vp, _int]
+lib.enuf_dpd_set_concurrency.restype = _int
 lib.enuf_dpd_energy.argtypes = [_vp, _vp]
 lib.enuf_dpd_energy.restype = _int
 lib.enuf_dpd_status.argtypes = [_vp, ctypes.POINTER(_int)]
@@ -75,7 +77,7 @@ EXPORTED = [
     "enuf_plan_create", "enuf_destroy", "enuf_last_error", "enuf_plan_set_stream",
     "enuf_plan_set_options", "enuf_compute", "enuf_compute_components", "enuf_plan_status",
     "enuf_plan_footprint_bytes",
-    "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_forces", "enuf_dpd_run",
+    "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_set_concurrency", "enuf_dpd_forces", "enuf_dpd_run",
     "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
     "enuf_dpd_time_kernel", "enuf_dpd_kernel_time",
 ]

@@ -1,5 +1,5 @@
 // enuf_device.h -- device helpers of the ENUF kernels (gfx950): window
-// functions, wavefront reductions and the LDS-resident Stockham FFT.
+// series evaluation, wavefront reductions and the LDS-resident Stockham FFT.
 #pragma once
 
 #include "enuf_internal.h"
@@ -9,11 +9,6 @@ namespace enuf {
 // ---------------------------------------------------------------------------
 // Small math helpers
 // ---------------------------------------------------------------------------
-__device__ inline double dev_exp(double x) { return exp(x); }
-__device__ inline float dev_exp(float x) { return expf(x); }
-__device__ inline double dev_sqrt(double x) { return sqrt(x); }
-__device__ inline float dev_sqrt(float x) { return sqrtf(x); }
-
 __device__ inline int mod_pos(int a, int m) {
   int r = a % m;
   return r < 0 ? r + m : r;
@@ -31,52 +26,21 @@ __device__ inline int mesh_cell(double x, double m_over_l, int M, double *t) {
 }
 
 // ---------------------------------------------------------------------------
-// NFFT window phi(u), |u| <= p, normalised to phi(0) = 1, and its derivative.
-//
-// Kaiser-Bessel (NFFT literature):  phi(u) = p sinh(b s) / (s sinh(b p)),
-// s = sqrt(p^2 - u^2).  With e1 = exp(b (s - p)), e2 = exp(-2 b s):
-//   phi  = p e1 (1 - e2) c1 / s,        c1 = 1/(1 - exp(-2 b p)),
-//   phi' = -p u e1 c1 [b s (1 + e2) - (1 - e2)] / s^3.
-// For b s < 1/2 both closed forms lose digits, so the even power series of
-// sinh(z)/z and (z cosh z - sinh z)/z^3 (z = b s) are summed instead.
-// Gaussian:  phi(u) = exp(-u^2 / b_G),  phi' = -2 u / b_G phi.
+// Chebyshev series sum_{k<=n} c_k T_k(x) by Clenshaw's recurrence.  The mesh
+// kernels evaluate the window from per-offset series of this form (the
+// piecewise-polynomial kernel evaluation of Barnett, Magland & af Klinteberg,
+// SIAM J. Sci. Comput. 2019), fitted on the host to the window above.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline void window_eval(const WindowParams &w, T u, T *val, T *der) {
-  if (w.kind == 1) {
-    const T ib = (T)w.inv_bg;
-    T g = dev_exp(-u * u * ib);
-    *val = g;
-    *der = (T)(-2) * u * ib * g;
-    return;
+__device__ inline T clenshaw(const T *c, int n, T x) {
+  T b1 = (T)0, b2 = (T)0;
+  const T x2 = x + x;
+  for (int k = n; k >= 1; --k) {
+    const T t = c[k] + x2 * b1 - b2;
+    b2 = b1;
+    b1 = t;
   }
-  const T p = (T)w.p, b = (T)w.b;
-  T s2 = p * p - u * u;
-  s2 = s2 > (T)0 ? s2 : (T)0;
-  const T s = dev_sqrt(s2);
-  const T z = b * s;
-  if (z >= (T)0.5) {
-    const T e1 = dev_exp(b * (s - p));
-    const T e2 = dev_exp((T)(-2) * z);
-    const T c1 = (T)w.c1;
-    *val = p * e1 * ((T)1 - e2) * c1 / s;
-    *der = -p * u * e1 * c1 * (z * ((T)1 + e2) - ((T)1 - e2)) / (s2 * s);
-  } else {
-    // sinh(z)/z = sum z^{2m}/(2m+1)!            (term ratio z^2 / (2m (2m+1)))
-    // (z cosh z - sinh z)/z^3 = sum z^{2m} / ((2m+3) (2m+1)!)   (ratio z^2 / (2m (2m+3)))
-    const T z2 = z * z;
-    T a = (T)1, h = (T)(1.0 / 3.0), ta = (T)1, th = (T)(1.0 / 3.0);
-#pragma unroll
-    for (int m = 1; m <= 6; ++m) {
-      ta *= z2 / (T)((2 * m) * (2 * m + 1));
-      a += ta;
-      th *= z2 / (T)((2 * m) * (2 * m + 3));
-      h += th;
-    }
-    const T isb = (T)w.inv_sinh_bp;
-    *val = p * b * a * isb;
-    *der = -p * u * b * b * b * h * isb;
-  }
+  return c[0] + x * b1 - b2;
 }
 
 // ---------------------------------------------------------------------------

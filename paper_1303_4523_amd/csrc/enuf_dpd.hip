@@ -61,8 +61,18 @@ __device__ inline int dpd_cell_of(double x, double inv_cell, int n) {
 __global__ void __launch_bounds__(256)
 k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__restrict__ vel,
           const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
-          double4 *cvel, int *status) {
+          double4 *cvel, int *status, DpdCharges ch) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch.enabled && i == 0) {
+    ch.sc->nq = ch.stat.nq;
+    ch.sc->scale = ch.stat.scale;
+    ch.sc->inv_scale = ch.stat.inv_scale;
+    ch.sc->sum_q = ch.stat.sum_q;
+    ch.sc->sum_absq = ch.stat.sum_absq;
+    ch.sc->sum_q2 = ch.stat.sum_q2;
+    ch.eacc[0] = 0ull;
+    ch.eacc[1] = 0ull;
+  }
   if (i >= N) return;
   double r[3], v[3], f[3], w[3];
 #pragma unroll
@@ -101,27 +111,51 @@ k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__
   } else {
     atomicCAS(status, 0, kEOverflow);
   }
+  if (ch.enabled) {
+    const int j = ch.dslot[i];
+    ch.slot[i] = j;
+    if (j >= 0) {
+      const double qi = ch.q[i];
+      ch.xq[j] = make_double4(r[0], r[1], r[2], qi);
+      const CellParams &cp = ch.cells;
+      int cx = (int)(r[0] * cp.inv_cell), cy = (int)(r[1] * cp.inv_cell), cz = (int)(r[2] * cp.inv_cell);
+      cx = cx < cp.ncell ? cx : cp.ncell - 1;
+      cy = cy < cp.ncell ? cy : cp.ncell - 1;
+      cz = cz < cp.ncell ? cz : cp.ncell - 1;
+      const int c = (cx * cp.ncell + cy) * cp.ncell + cz;
+      const int sl = atomicAdd(&ch.ccnt[c], 1);
+      if (sl < cp.cap) {
+        ch.cgrid[(size_t)c * cp.cap + sl] = make_double4(r[0], r[1], r[2], qi);
+        ch.cidx[(size_t)c * cp.cap + sl] = j;
+      } else {
+        atomicCAS(&ch.sc->status, 0, kEOverflow);
+      }
+      double t;
+      const int xc = mesh_cell(r[0], ch.m_over_l, ch.M, &t);
+      const int xs = atomicAdd(&ch.xcnt[xc], 1);
+      if (xs < ch.xcap)
+        ch.xslot[(size_t)xc * ch.xcap + xs] = j;
+      else
+        atomicCAS(&ch.sc->status, 0, kEOverflow);
+    }
+  }
 }
 
 __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-__device__ inline void atomic_add_fx(unsigned long long *acc, double v) {
-  atomicAdd(acc, (unsigned long long)to_fixed(v, kRealFxScale));
-}
-
-// Four lanes per particle i split the 27 neighbour cells.  Each pair is
-// evaluated once, by the lower index (Newton's third law): the force on i is
-// summed in registers, the opposite force goes to j through an int64 atomic.
-// All sums are exact fixed point (2^-36), so the result does not depend on
-// the order in which pairs are visited.
+// Four lanes per particle i split the 27 neighbour cells; every pair is
+// evaluated from both of its particles (theta_ij = theta_ji keeps the pair
+// forces antisymmetric), so no thread writes another particle's force.  Sums
+// are exact int64 fixed point (2^-36): the result does not depend on the order
+// in which the pairs are visited.
 __global__ void __launch_bounds__(256)
 k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos,
            const double *__restrict__ v0, const int *__restrict__ dcnt,
            const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to,
-           unsigned long long *facc) {
+           double *__restrict__ fdpd) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i64 = g >> 2;
   const int quad = (int)(g & 3);
@@ -144,7 +178,7 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
     for (int s = 0; s < cnt; ++s) {
       const double4 e = cp[s];
       const int j = (int)e.w;
-      if (j <= i) continue;
+      if (j == i) continue;
       double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
       dx -= L * rint(dx * invL);
       dy -= L * rint(dy * invL);
@@ -158,21 +192,15 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
       const double vdot = (vx - vj.x) * ex + (vy - vj.y) * ey + (vz - vj.z) * ez;
       const double th = dpd_theta(P.seed, step, i, j);
       const double mag = P.a * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
-      const long long ax = to_fixed(mag * ex, kRealFxScale), ay = to_fixed(mag * ey, kRealFxScale),
-                      az = to_fixed(mag * ez, kRealFxScale);
-      fx += ax;
-      fy += ay;
-      fz += az;
-      atomicAdd(&facc[3 * (size_t)j], (unsigned long long)(-ax));
-      atomicAdd(&facc[3 * (size_t)j + 1], (unsigned long long)(-ay));
-      atomicAdd(&facc[3 * (size_t)j + 2], (unsigned long long)(-az));
+      fx += to_fixed(mag * ex, kRealFxScale);
+      fy += to_fixed(mag * ey, kRealFxScale);
+      fz += to_fixed(mag * ez, kRealFxScale);
     }
   }
-  // harmonic bonds with j > i, F_i = -K (r - r0) rhat_ij
+  // harmonic bonds of i, F_i = -K (r - r0) rhat_ij
   if (quad == 0) {
     for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
       const int j = bond_to[b];
-      if (j <= i) continue;
       double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
       dx -= L * rint(dx * invL);
       dy -= L * rint(dy * invL);
@@ -180,14 +208,9 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       if (r == 0.0) continue;
       const double mag = -P.k_bond * (r - P.r0_bond) / r;
-      const long long ax = to_fixed(mag * dx, kRealFxScale), ay = to_fixed(mag * dy, kRealFxScale),
-                      az = to_fixed(mag * dz, kRealFxScale);
-      fx += ax;
-      fy += ay;
-      fz += az;
-      atomicAdd(&facc[3 * (size_t)j], (unsigned long long)(-ax));
-      atomicAdd(&facc[3 * (size_t)j + 1], (unsigned long long)(-ay));
-      atomicAdd(&facc[3 * (size_t)j + 2], (unsigned long long)(-az));
+      fx += to_fixed(mag * dx, kRealFxScale);
+      fy += to_fixed(mag * dy, kRealFxScale);
+      fz += to_fixed(mag * dz, kRealFxScale);
     }
   }
   fx += __shfl_xor(fx, 1, kWave);
@@ -197,16 +220,16 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
   fy += __shfl_xor(fy, 2, kWave);
   fz += __shfl_xor(fz, 2, kWave);
   if (quad == 0) {
-    atomicAdd(&facc[3 * (size_t)i], (unsigned long long)fx);
-    atomicAdd(&facc[3 * (size_t)i + 1], (unsigned long long)fy);
-    atomicAdd(&facc[3 * (size_t)i + 2], (unsigned long long)fz);
+    fdpd[3 * i] = (double)fx * kRealFxInv;
+    fdpd[3 * i + 1] = (double)fy * kRealFxInv;
+    fdpd[3 * i + 2] = (double)fz * kRealFxInv;
   }
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
-// only.  Clears the pair accumulator and the cell counts for the next step.
+// only.  Clears the cell counts for the next step.
 __global__ void __launch_bounds__(256)
-k_dpd_post(int64_t N, int mode, DpdParams P, unsigned long long *facc,
+k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
            const double *__restrict__ felec, double *__restrict__ force, double *__restrict__ vel,
            int *dcnt, int ncell3) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,8 +238,7 @@ k_dpd_post(int64_t N, int mode, DpdParams P, unsigned long long *facc,
   if (i >= N) return;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double f = (double)(long long)facc[3 * i + a] * kRealFxInv;
-    facc[3 * i + a] = 0ull;
+    double f = fdpd[3 * i + a];
     if (felec) f += P.kappa * felec[3 * i + a];
     force[3 * i + a] = f;
     if (mode == 0) vel[3 * i + a] += 0.5 * P.dt * f;
@@ -225,34 +247,34 @@ k_dpd_post(int64_t N, int mode, DpdParams P, unsigned long long *facc,
 
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
                           const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
-                          int *status, hipStream_t st, KernelTimer *tm) {
+                          int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
   const int nb = (int)((N + 255) / 256);
   if (tm) tm->before(0, st);
   hipLaunchKernelGGL(k_dpd_pre, dim3(nb), dim3(256), 0, st, N, mode, P, pos, vel, force, v0, dcnt, cpos,
-                     cvel, status);
+                     cvel, status, ch);
   if (tm) tm->after(0, st);
   return hipGetLastError();
 }
 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, unsigned long long *facc,
+                           const int *bond_start, const int *bond_to, double *fdpd,
                            hipStream_t st, KernelTimer *tm) {
   const int nb = (int)((4 * N + 255) / 256);
   if (tm) tm->before(1, st);
   hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(256), 0, st, N, P, step, pos, v0, dcnt, cpos, cvel,
-                     bond_start, bond_to, facc);
+                     bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }
 
-hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, unsigned long long *facc,
+hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,
                            KernelTimer *tm) {
   const int nb = (int)((N + 255) / 256);
   const int ncell3 = P.ncell * P.ncell * P.ncell;
   if (tm) tm->before(9, st);
-  hipLaunchKernelGGL(k_dpd_post, dim3(nb), dim3(256), 0, st, N, mode, P, facc, felec, force, vel, dcnt,
+  hipLaunchKernelGGL(k_dpd_post, dim3(nb), dim3(256), 0, st, N, mode, P, fdpd, felec, force, vel, dcnt,
                      ncell3);
   if (tm) tm->after(9, st);
   return hipGetLastError();

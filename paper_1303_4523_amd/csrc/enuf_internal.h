@@ -11,6 +11,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kPrepThreads = 256;  // threads per block of the particle-parallel kernels
 constexpr int kPassThreads = 512;  // threads per block of the mesh-plane kernels
 constexpr int kMaxRadixPasses = 16;
+constexpr int kMaxChebDeg = 24;    // highest degree of the window series
 
 // Device-resident scalars produced by the preparation kernels of one compute.
 struct DevScalars {
@@ -40,8 +41,13 @@ struct WindowParams {
   double inv_bg;   // Gaussian: 1 / b_G, b_G = 2 sigma p / ((2 sigma - 1) pi)
 };
 
-// Geometry shared by the mesh kernels.
+// Geometry shared by the mesh kernels.  The window is evaluated from
+// piecewise Chebyshev series: on stencil offset s the window at
+// u = frac + p - 1 - s (frac in [0, 1)) is sum_k c_{s,k} T_k(2 frac - 1),
+// and its u-derivative a series of degree cheb_deg - 1.
 struct MeshParams {
+  int cheb_deg;    // degree of the value series (derivative: cheb_deg - 1)
+  int xcap;        // slots per x-bin of the charge binning
   int M;           // mesh points per side
   int Mp;          // padded row stride of LDS planes (elements)
   int Mz;          // padded line stride of LDS spectrum buffers (elements)
@@ -90,15 +96,16 @@ struct ComputeBuffers {
   int *ccnt;             // [ncell^3]
   double4 *cgrid;        // [ncell^3 * cap] (x, y, z, q) per cell slot
   int *cidx;             // [ncell^3 * cap] compact index per cell slot
-  unsigned long long *freal;  // [N * 3] fixed-point real-space forces per slot (zero between calls)
+  unsigned long long *freal;  // [N * 3] fixed-point real-space force per compact slot
   unsigned long long *eacc;  // [2] fixed-point E_real (whole), E_slater
   // reciprocal
   void *gzy;             // [M * nky * Kc] complex (double2 or float2)
   double *epart;         // [nky] k-space energy per ky row
   double4 *part;         // [N * 2p] gather partials (dwx A, wx By, wx Bz, wx A)
-  void *winv;            // [N * 3 * 2p] window values per charge, axis, offset (double or float)
-  void *wind;            // [N * 3 * 2p] window derivatives
-  int *mbase;            // [N * 4] first stencil index per axis
+  int *xcnt;             // [M] charges per mesh x-cell (zero between calls)
+  int *xslot;            // [M * xcap] compact indices of the charges of each x-cell
+  double *wcoef64;       // [2p (D+1) + 2p D] window series coefficients (value, then derivative)
+  float *wcoef32;
   double *blk_eg;        // [nblk] per-block sums of q * A
   // tables
   double *atab;          // [nky] exp(-pi^2 k^2/(alpha L)^2) / Phi(k/M)^2
@@ -135,6 +142,30 @@ struct KernelTimer {
     }
   }
 };
+
+// What the closing kernel does besides the electrostatic force.
+struct FinishArgs {
+  int mode = -1;                     // -1: plain ENUF evaluation (forces = F_elec)
+                                     //  0: DPD step: F = F_pair + kappa F_elec, v += dt F / 2
+                                     //  1: DPD forces only: F = F_pair + kappa F_elec
+  double kappa = 0.0, dt = 0.0;
+  const double *fdpd = nullptr;      // DPD pair + bond forces
+  double *vel = nullptr;
+  int *dcnt = nullptr;               // DPD cell counts, cleared for the next step
+  int ndcell3 = 0;
+};
+
+// The ENUF evaluation in four phases (launch_compute runs them in order on
+// one stream; the DPD step forks the real-space phase onto another stream).
+hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
+                       const double *q, hipStream_t st, KernelTimer *tm);
+hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
+                       KernelTimer *tm);
+hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
+                        KernelTimer *tm);
+hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
+                          double *energy_total, double *energy5, const FinishArgs &fa, hipStream_t st,
+                          KernelTimer *tm);
 
 hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b,
                           const double *pos, const double *q, double *forces,

@@ -3,9 +3,9 @@
 // Pipeline of enuf_compute (all on one stream):
 //   k_prep_count    count charged particles per block; clear cell counts
 //   k_prep_compact  wrap positions, compact the charges in index order, bin
-//                   them into the real-space cell grid, reduce sum q, |q|, q^2
+//                   them into the real-space cell grid and by mesh x-cell,
+//                   reduce sum q, |q|, q^2
 //   k_real          real-space pair term (eq. 31 + Slater correction eq. 27)
-//   k_window        window values and derivatives of every charge, per axis
 //   k_recip_fwd     per x-plane: window spread (transposed NFFT, eq. 14) into
 //                   an LDS plane, z real-to-complex FFT, y FFT, keep |k| < Kc
 //   k_recip_x       per ky row: x FFT, influence multiply and FP64 energy
@@ -64,14 +64,15 @@ __device__ inline void set_status(DevScalars *sc, int code) { atomicCAS(&sc->sta
 // Preparation
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kPrepThreads)
-k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, int ncell3,
-             unsigned long long *eacc) {
+k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, int ncell3, int *xcnt,
+             int M, unsigned long long *eacc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int flag = (i < N) && (q[i] != 0.0);
   const int c = __syncthreads_count(flag);
   if (threadIdx.x == 0) blk_cnt[blockIdx.x] = c;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < ncell3; k += stride) ccnt[k] = 0;
+  for (int64_t k = i; k < M; k += stride) xcnt[k] = 0;
   if (i < 2) eacc[i] = 0ull;
 }
 
@@ -79,7 +80,8 @@ __global__ void __launch_bounds__(kPrepThreads)
 k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
                double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
                double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
-               int *cidx, unsigned *done, DevScalars *sc) {
+               int *cidx, int *xcnt, int *xslot, int M, double m_over_l, int xcap, unsigned *done,
+               DevScalars *sc) {
   __shared__ int s_int[kPrepThreads / kWave];
   __shared__ int s_wcnt[kPrepThreads / kWave];
   __shared__ double s_dbl[kPrepThreads / kWave];
@@ -132,6 +134,13 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
       } else {
         set_status(sc, kEOverflow);
       }
+      double t;
+      const int xc = mesh_cell(x, m_over_l, M, &t);
+      const int xs = atomicAdd(&xcnt[xc], 1);
+      if (xs < xcap)
+        xslot[(size_t)xc * xcap + xs] = j;
+      else
+        set_status(sc, kEOverflow);
     } else {
       slot[i] = -1;
     }
@@ -238,10 +247,10 @@ __device__ inline bool cell_offset_valid(int o, int n) {
 }
 
 // One wavefront per charge j: lanes 0..53 take one of the 27 neighbour cells
-// and every other slot in it.  Each pair is evaluated once, by its lower
-// compact index (Newton's third law): the force on j is summed in registers,
-// the opposite force goes to k through an int64 atomic; energies count the
-// whole pair.  All sums are exact fixed point.
+// and every other slot in it.  The wavefront sums the forces of all pairs of j
+// (each pair is evaluated from both of its charges, so no thread writes
+// another charge's force) and the energy of the pairs with k > j.  All sums
+// are exact int64 fixed point.
 __global__ void __launch_bounds__(256)
 k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
        const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
@@ -270,7 +279,7 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
         const int *ck = cidx + (size_t)c * cp.cap;
         for (int s = par; s < cnt; s += 2) {
           const int k = ck[s];
-          if (k <= j) continue;
+          if (k == j) continue;
           const double4 cj = cg[s];
           double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
           dx -= L * rint(dx * invL);
@@ -286,16 +295,13 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
           const double qq = ci.w * cj.w;
           const double g = qq * f;
           if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
-          const long long ax = to_fixed(g * dx, kRealFxScale), ay = to_fixed(g * dy, kRealFxScale),
-                          az = to_fixed(g * dz, kRealFxScale);
-          fx += ax;
-          fy += ay;
-          fz += az;
-          atomicAdd(&freal[3 * (size_t)k], (unsigned long long)(-ax));
-          atomicAdd(&freal[3 * (size_t)k + 1], (unsigned long long)(-ay));
-          atomicAdd(&freal[3 * (size_t)k + 2], (unsigned long long)(-az));
-          ee += to_fixed(qq * u, kRealFxScale);
-          es += to_fixed(qq * us, kRealFxScale);
+          fx += to_fixed(g * dx, kRealFxScale);
+          fy += to_fixed(g * dy, kRealFxScale);
+          fz += to_fixed(g * dz, kRealFxScale);
+          if (k > j) {
+            ee += to_fixed(qq * u, kRealFxScale);
+            es += to_fixed(qq * us, kRealFxScale);
+          }
         }
       }
     }
@@ -306,9 +312,9 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
     ee = wave_sum_ll(ee);
     es = wave_sum_ll(es);
     if (lane == 0) {
-      atomicAdd(&freal[3 * (size_t)j], (unsigned long long)fx);
-      atomicAdd(&freal[3 * (size_t)j + 1], (unsigned long long)fy);
-      atomicAdd(&freal[3 * (size_t)j + 2], (unsigned long long)fz);
+      freal[3 * (size_t)j] = (unsigned long long)fx;
+      freal[3 * (size_t)j + 1] = (unsigned long long)fy;
+      freal[3 * (size_t)j + 2] = (unsigned long long)fz;
       atomicAdd(&eacc[0], (unsigned long long)ee);
       atomicAdd(&eacc[1], (unsigned long long)es);
     }
@@ -316,37 +322,12 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// Window values phi(u) and derivatives phi'(u) of every charge, for the 2p
-// stencil offsets of each axis: winv[(j * 3 + a) * 2p + s] at
-// u = M x_a / L - (b_a + s), b_a = floor(M x_a / L) - p + 1 (stored in mbase).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_window(const double4 *__restrict__ xq, const DevScalars *__restrict__ sc, MeshParams mp, T *winv,
-         T *wind, int *mbase) {
-  const int p = mp.win.p, P2 = 2 * p, per = 3 * P2;
-  const int64_t total = (int64_t)sc->nq * per;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(t / per), r = (int)(t % per), a = r / P2, s = r % P2;
-    const double4 c = xq[j];
-    const double x = a == 0 ? c.x : (a == 1 ? c.y : c.z);
-    double tt;
-    const int b = mesh_cell(x, mp.m_over_l, mp.M, &tt) - p + 1;
-    T v, d;
-    window_eval<T>(mp.win, (T)(tt - (double)(b + s)), &v, &d);
-    winv[t] = v;
-    wind[t] = d;
-    if (s == 0) mbase[4 * (size_t)j + a] = b;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Mesh pass 1: spread + z R2C FFT + y FFT for one x-plane.
-// LDS: int64 accumulator plane [M][Mp] (aliased by the T plane after
-// conversion), spectrum lines Zre/Zim [Kc][Mz], twiddles, a charge queue.
-// Work items of the spread are (queued charge, stencil row sy): each adds the
-// 2p products q wx wy[sy] wz[sz] of one mesh row.
+// Charges relevant to plane x0 are those of the 2p mesh x-cells
+// x0 - p .. x0 + p - 1; the charges of cell x0 - p + b have the plane at
+// stencil offset sx = 2p - 1 - b.  Work items are (charge, stencil row sy) in
+// groups of P2pad lanes (2p rounded up to a power of two, so that a group
+// never straddles a wavefront); lane sy evaluates the window of offset sy on
+// each axis and the group shares them with shuffles.
 // ---------------------------------------------------------------------------
 __device__ inline int pow2_at_least(int v) {
   int r = 1;
@@ -354,15 +335,61 @@ __device__ inline int pow2_at_least(int v) {
   return r;
 }
 
+struct PlaneCharges {
+  int *cnt;  // [2p + 1] prefix sums over the 2p x-cells (LDS)
+  int *cell; // [2p] x-cell of bin b (LDS)
+};
+
+// Fill the LDS prefix sums of the plane's 2p x-bins; returns the charge count.
+__device__ inline int plane_bins(int x0, int M, int p, const int *__restrict__ xcnt, int xcap, int *pre,
+                                 int *cell) {
+  const int P2 = 2 * p;
+  if (threadIdx.x < P2) {
+    const int c = mod_pos(x0 - p + (int)threadIdx.x, M);
+    const int n = xcnt[c];
+    cell[threadIdx.x] = c;
+    pre[threadIdx.x + 1] = n < xcap ? n : xcap;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pre[0] = 0;
+    for (int b = 0; b < P2; ++b) pre[b + 1] += pre[b];
+  }
+  __syncthreads();
+  return pre[P2];
+}
+
+// Offsets of charge e of the plane: x-bin b, and the compact index.
+__device__ inline int plane_charge(int e, int P2, const int *pre, const int *cell, const int *__restrict__ xslot,
+                                   int xcap, int *b_out) {
+  int b = 0;
+  while (b < P2 - 1 && e >= pre[b + 1]) ++b;
+  *b_out = b;
+  return xslot[(size_t)cell[b] * xcap + (e - pre[b])];
+}
+
+// Mesh cell and fractional offset of one coordinate.
+__device__ inline int cell_frac(double x, double m_over_l, int M, double *frac) {
+  double t;
+  const int c = mesh_cell(x, m_over_l, M, &t);
+  *frac = t - (double)c;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh pass 1: spread + z R2C FFT + y FFT for one x-plane.
+// LDS: int64 accumulator plane [M][Mp] (aliased by the T plane after
+// conversion), spectrum lines Zre/Zim [Kc][Mz], twiddles, window series.
+// ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
-k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const T *__restrict__ winv,
-            const DevScalars *__restrict__ sc, MeshParams mp,
+k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
+            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
             const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p;
+  const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p, D = mp.cheb_deg;
   const int P2pad = pow2_at_least(P2);
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const int x0 = blockIdx.x;
 
   long long *acc = reinterpret_cast<long long *>(smem);
@@ -380,51 +407,58 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  int *qj = reinterpret_cast<int *>(smem + off);
-  int *qs = qj + nt;
-  int *qn = qs + nt;
+  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][D + 1] value series
+  off += (size_t)P2 * (D + 1) * sizeof(T);
+  int *pre = reinterpret_cast<int *>(smem + off);
+  int *bcell = pre + P2 + 1;
 
   for (int m = tid; m < M; m += nt) {
     twr[m] = tw[m].x;
     twi[m] = tw[m].y;
   }
+  for (int k = tid; k < P2 * (D + 1); k += nt) cv[k] = wcoef[k];
   for (int k = tid; k < M * Mp; k += nt) acc[k] = 0;
-  const int nq = sc->nq;
   const double scale = sc->scale, inv_scale = sc->inv_scale;
-  __syncthreads();
+  const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);
 
-  for (int base = 0; base < nq; base += nt) {
-    if (tid == 0) *qn = 0;
-    __syncthreads();
-    const int j = base + tid;
-    if (j < nq) {
-      const int sx = mod_pos(x0 - mbase[4 * (size_t)j], M);
-      if (sx < P2) {
-        const int e = atomicAdd(qn, 1);
-        qj[e] = j;
-        qs[e] = sx;
+  // whole wavefronts iterate together so that the group shuffles see every lane
+  const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
+  const int gbase = lane & ~(P2pad - 1);
+  for (int it = tid; it < items; it += nt) {
+    const int e = it / P2pad, sy = it % P2pad;
+    const bool has = e < total, act = has && sy < P2;
+    T wz = (T)0, wrow = (T)0;
+    int row = 0, bz = 0;
+    if (has) {
+      int b;
+      const int j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
+      const double4 c = xq[j];
+      double fx, fy, fz;
+      cell_frac(c.x, mp.m_over_l, M, &fx);
+      const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
+      const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
+      if (act) {
+        const int sx = P2 - 1 - b;
+        const T wx = clenshaw<T>(cv + sx * (D + 1), D, (T)(2.0 * fx - 1.0));
+        const T wy = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fy - 1.0));
+        wz = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fz - 1.0));
+        wrow = (T)c.w * wx * wy;
+        row = mod_pos(cy - p + 1 + sy, M);
+        bz = cz - p + 1;
       }
     }
-    __syncthreads();
-    const int cnt = *qn;
-    for (int it = tid; it < cnt * P2pad; it += nt) {
-      const int e = it / P2pad, sy = it % P2pad;
-      if (sy >= P2) continue;
-      const int jj = qj[e];
-      const T *w = winv + (size_t)jj * 3 * P2;
-      const T wrow = (T)xq[jj].w * w[qs[e]] * w[P2 + sy];
-      const int row = mod_pos(mbase[4 * (size_t)jj + 1] + sy, M);
-      int col = mbase[4 * (size_t)jj + 2];
-      col = col < 0 ? col + M : col;
-      long long *arow = acc + (size_t)row * Mp;
-      for (int sz = 0; sz < P2; ++sz) {
-        const double v = (double)(wrow * w[2 * P2 + sz]);
+    long long *arow = acc + (size_t)row * Mp;
+    int col = bz < 0 ? bz + M : bz;
+    for (int sz = 0; sz < P2; ++sz) {
+      const T w = __shfl(wz, gbase + sz, kWave);
+      if (act) {
+        const double v = (double)(wrow * w);
         atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
         col = (col + 1 == M) ? 0 : col + 1;
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // fixed point -> T plane (in place; FP32 rows move down in chunks)
   if (sizeof(T) == 8) {
@@ -497,6 +531,7 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
   T *twi = twr + M;
   const size_t red_off = ((2 * (size_t)Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
   double *red = reinterpret_cast<double *>(smem + red_off);
+  double *at = red + kPassThreads / kWave;  // [nky] influence table
 
   int nkz = 0;
   while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
@@ -505,6 +540,7 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
     twr[m] = tw[m].x;
     twi[m] = tw[m].y;
   }
+  for (int k = tid; k < nky; k += nt) at[k] = atab[k];
   for (int id = tid; id < M * nkz; id += nt) {
     const int x = id / nkz, kz = id % nkz;
     const typename CplxOf<T>::type v = gzy[((size_t)x * nky + kyi) * Kc + kz];
@@ -514,7 +550,7 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
   __syncthreads();
   lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, false);
 
-  const double ay = atab[kyi];
+  const double ay = at[kyi];
   double e = 0.0;
   for (int id = tid; id < nkz * M; id += nt) {
     const int kz = id / M, m = id % M;
@@ -522,7 +558,7 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
     const int k2 = kx * kx + ky * ky + kz * kz;
     T hr = (T)0, hi = (T)0;
     if (kx > -Kc && kx < Kc && k2 < Kc * Kc && k2 > 0) {
-      const double c = atab[kx + Kc - 1] * ay * atab[kz + Kc - 1] / (double)k2;
+      const double c = at[kx + Kc - 1] * ay * at[kz + Kc - 1] / (double)k2;
       const double gr = (double)Xre[kz * Mz + m], gi = (double)Xim[kz * Mz + m];
       e += (kz > 0 ? 2.0 : 1.0) * c * (gr * gr + gi * gi);
       hr = (T)(c * gr);
@@ -546,20 +582,20 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
 
 // ---------------------------------------------------------------------------
 // Mesh pass 3: inverse y FFT, complex-to-real z FFT and gather for one plane.
-// Work items are (queued charge, stencil row sy) in groups of P2pad lanes
-// (P2pad = 2p rounded up to a power of two); each lane sums its mesh row
-// against the z window and its derivative, the group reduces with shuffles.
+// Each lane of a work-item group sums its mesh row against the z window and
+// its derivative (shared across the group); the group reduces with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
-k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const T *__restrict__ winv,
-            const T *__restrict__ wind, const DevScalars *__restrict__ sc, MeshParams mp,
+k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
+            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
             const typename CplxOf<T>::type *__restrict__ tw,
             const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
+  const int D = mp.cheb_deg;
   const int P2pad = pow2_at_least(P2);
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const int x0 = blockIdx.x;
 
   T *plane = reinterpret_cast<T *>(smem);
@@ -570,14 +606,17 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  int *qj = reinterpret_cast<int *>(smem + off);
-  int *qs = qj + nt;
-  int *qn = qs + nt;
+  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][D + 1] value series
+  T *cd = cv + (size_t)P2 * (D + 1);          // [P2][D] derivative series
+  off += (size_t)P2 * (2 * D + 1) * sizeof(T);
+  int *pre = reinterpret_cast<int *>(smem + off);
+  int *bcell = pre + P2 + 1;
 
   for (int m = tid; m < M; m += nt) {
     twr[m] = tw[m].x;
     twi[m] = tw[m].y;
   }
+  for (int k = tid; k < P2 * (2 * D + 1); k += nt) cv[k] = wcoef[k];
   for (int k = tid; k < 2 * Kc * Mz; k += nt) Zre[k] = (T)0;
   __syncthreads();
   for (int id = tid; id < nky * Kc; id += nt) {
@@ -614,66 +653,59 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ mbase, const
     plane[2 * c * Mp + k] = re;
     plane[(2 * c + 1) * Mp + k] = im;
   }
-  __syncthreads();
+  const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
   lds_fft<T>(plane, plane + Mp, 2 * Mp, M / 2, mp.fft, twr, twi, true);
 
-  const int nq = sc->nq;
-  for (int base = 0; base < nq; base += nt) {
-    if (tid == 0) *qn = 0;
-    __syncthreads();
-    const int j = base + tid;
-    if (j < nq) {
-      const int sx = mod_pos(x0 - mbase[4 * (size_t)j], M);
-      if (sx < P2) {
-        const int e = atomicAdd(qn, 1);
-        qj[e] = j;
-        qs[e] = sx;
-      }
-    }
-    __syncthreads();
-    const int cnt = *qn;
-    // whole wavefronts iterate together so that the group shuffles see every lane
-    const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
-    for (int it = tid; it < items; it += nt) {
-      const int e = it / P2pad, sy = it % P2pad;
-      const bool has = e < cnt;
-      const bool act = has && sy < P2;
-      int jj = 0, sx = 0;
-      T A = (T)0, By = (T)0, Bz = (T)0, wx = (T)0, dwx = (T)0;
-      if (has) {
-        jj = qj[e];
-        sx = qs[e];
-      }
+  const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
+  const int gbase = lane & ~(P2pad - 1);
+  for (int it = tid; it < items; it += nt) {
+    const int e = it / P2pad, sy = it % P2pad;
+    const bool has = e < total, act = has && sy < P2;
+    int j = 0, sx = 0, row = 0, bz = 0;
+    T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
+    if (has) {
+      int b;
+      j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
+      sx = P2 - 1 - b;
+      const double4 c = xq[j];
+      double fx, fy, fz;
+      cell_frac(c.x, mp.m_over_l, M, &fx);
+      const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
+      const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
       if (act) {
-        const T *w = winv + (size_t)jj * 3 * P2;
-        const T *d = wind + (size_t)jj * 3 * P2;
-        const int row = mod_pos(mbase[4 * (size_t)jj + 1] + sy, M);
-        int col = mbase[4 * (size_t)jj + 2];
-        col = col < 0 ? col + M : col;
-        const T *hrow = plane + (size_t)row * Mp;
-        T a = (T)0, b = (T)0;
-        for (int sz = 0; sz < P2; ++sz) {
-          const T h = hrow[col];
-          a += h * w[2 * P2 + sz];
-          b += h * d[2 * P2 + sz];
-          col = (col + 1 == M) ? 0 : col + 1;
-        }
-        A = w[P2 + sy] * a;
-        By = d[P2 + sy] * a;
-        Bz = w[P2 + sy] * b;
-        wx = w[sx];
-        dwx = d[sx];
+        const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
+        wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
+        dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
+        wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
+        dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
+        wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
+        dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
+        row = mod_pos(cy - p + 1 + sy, M);
+        bz = cz - p + 1;
       }
-      for (int o = P2pad / 2; o >= 1; o >>= 1) {
-        A += __shfl_xor(A, o, kWave);
-        By += __shfl_xor(By, o, kWave);
-        Bz += __shfl_xor(Bz, o, kWave);
-      }
-      if (has && sy == 0)
-        part[(size_t)jj * P2 + sx] = make_double4((double)(dwx * A), (double)(wx * By),
-                                                  (double)(wx * Bz), (double)(wx * A));
     }
-    __syncthreads();
+    const T *hrow = plane + (size_t)row * Mp;
+    int col = bz < 0 ? bz + M : bz;
+    T a = (T)0, bsum = (T)0;
+    for (int sz = 0; sz < P2; ++sz) {
+      const T w = __shfl(wz, gbase + sz, kWave);
+      const T d = __shfl(dwz, gbase + sz, kWave);
+      if (act) {
+        const T h = hrow[col];
+        a += h * w;
+        bsum += h * d;
+        col = (col + 1 == M) ? 0 : col + 1;
+      }
+    }
+    T A = wy * a, By = dwy * a, Bz = wy * bsum;
+    for (int o = P2pad / 2; o >= 1; o >>= 1) {
+      A += __shfl_xor(A, o, kWave);
+      By += __shfl_xor(By, o, kWave);
+      Bz += __shfl_xor(Bz, o, kWave);
+    }
+    if (has && sy == 0)
+      part[(size_t)j * P2 + sx] = make_double4((double)(dwx * A), (double)(wx * By),
+                                               (double)(wx * Bz), (double)(wx * A));
   }
 }
 
@@ -685,11 +717,20 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
           unsigned long long *freal, const double4 *__restrict__ part, int P2,
           double fscale, double inv2piL, double alpha, int nblk, double *blk_eg, unsigned *done,
           const double *__restrict__ epart, int nky, const unsigned long long *eacc,
-          const DevScalars *sc, double *forces, double *energy, double *energy5) {
+          const DevScalars *sc, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
+          double *energy, double *energy5) {
   __shared__ double s_dbl[kPrepThreads / kWave];
   __shared__ int s_last;
   const int tid = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  {
+    // cell counts are left cleared for the next evaluation (their consumers ran before)
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = i; c < ncell3; c += stride) ccnt[c] = 0;
+    for (int64_t c = i; c < M; c += stride) xcnt[c] = 0;
+    if (fa.mode >= 0)
+      for (int64_t c = i; c < fa.ndcell3; c += stride) fa.dcnt[c] = 0;
+  }
   double eg = 0.0;
   if (i < N) {
     const int j = slot[i];
@@ -707,14 +748,21 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
       fx = (double)(long long)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
       fy = (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
       fz = (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
-      freal[3 * (size_t)j] = 0ull;  // leave the accumulator cleared for the next call
-      freal[3 * (size_t)j + 1] = 0ull;
-      freal[3 * (size_t)j + 2] = 0ull;
       eg = qj * a;
     }
-    forces[3 * i] = fx;
-    forces[3 * i + 1] = fy;
-    forces[3 * i + 2] = fz;
+    if (fa.mode < 0) {
+      forces[3 * i] = fx;
+      forces[3 * i + 1] = fy;
+      forces[3 * i + 2] = fz;
+    } else {
+      const double fe[3] = {fx, fy, fz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double f = fa.fdpd[3 * i + a] + fa.kappa * fe[a];
+        forces[3 * i + a] = f;
+        if (fa.mode == 0) fa.vel[3 * i + a] += 0.5 * fa.dt * f;
+      }
+    }
   }
   eg = block_sum(eg, s_dbl);
   if (tid == 0) {
@@ -754,12 +802,14 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
 // ---------------------------------------------------------------------------
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd) {
   const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
-  const size_t misc = 2 * (size_t)kPassThreads * sizeof(int) + 16;
+  const int P2 = 2 * m.win.p;
+  const size_t misc = (size_t)P2 * (2 * m.cheb_deg + 1) * ts + (3 * (size_t)P2 + 2) * sizeof(int) + 32;
   const size_t acc = (size_t)m.M * m.Mp * sizeof(long long);
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
   *fwd = (ts == 8 ? acc + zp : acc) + tw + misc;
-  *x = ((zp + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) + 16;
+  *x = ((zp + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) +
+       (size_t)m.nky * sizeof(double) + 16;
   *bwd = (size_t)m.M * m.Mp * ts + zp + tw + misc;
 }
 
@@ -784,64 +834,88 @@ template <typename T>
 static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st, KernelTimer *tm) {
   using C = typename CplxOf<T>::type;
   const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
+  const T *wc = reinterpret_cast<const T *>(sizeof(T) == 8 ? (const void *)b.wcoef64 : (const void *)b.wcoef32);
   C *gzy = reinterpret_cast<C *>(b.gzy);
   const MeshParams &mp = cfg.mesh;
-  T *winv = reinterpret_cast<T *>(b.winv), *wind = reinterpret_cast<T *>(b.wind);
-  const int per = 6 * mp.win.p;
-  int64_t nwin = (cfg.N * per + 255) / 256;
-  const int gwin = (int)(nwin < 4096 ? nwin : 4096);
-  hipLaunchKernelGGL(k_window<T>, dim3(gwin), dim3(256), 0, st, (const double4 *)b.xq, (const DevScalars *)b.sc,
-                     mp, winv, wind, b.mbase);
   if (tm) tm->before(5, st);
   hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, (const double4 *)b.xq,
-                     (const int *)b.mbase, (const T *)winv, (const DevScalars *)b.sc, mp, tw, gzy);
+                     (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gzy);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
   hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy, b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
   hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, (const double4 *)b.xq,
-                     (const int *)b.mbase, (const T *)winv, (const T *)wind, (const DevScalars *)b.sc, mp, tw,
+                     (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw,
                      (const C *)gzy, b.part);
   if (tm) tm->after(7, st);
 }
 
-hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
-                          const double *q, double *forces, double *energy_total, double *energy5,
-                          hipStream_t st, KernelTimer *tm) {
+hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
+                       const double *q, hipStream_t st, KernelTimer *tm) {
   const int nblk = cfg.nblk;
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   if (tm) tm->before(2, st);
   hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
-                     ncell3, b.eacc);
+                     ncell3, b.xcnt, cfg.mesh.M, b.eacc);
   if (tm) tm->after(2, st);
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
                      (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
-                     b.cidx, b.done, b.sc);
+                     b.cidx, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.done, b.sc);
   if (tm) tm->after(3, st);
-  int grid_real = (int)((cfg.N + 3) / 4);
-  grid_real = grid_real < 2048 ? grid_real : 2048;
+  return hipGetLastError();
+}
+
+hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
+                       KernelTimer *tm) {
+  int64_t g = (nq_max + 3) / 4;
+  const int grid_real = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(256), 0, st, (const double4 *)b.xq, (const int *)b.ccnt,
                      (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L, cfg.alpha,
                      cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.eacc);
   if (tm) tm->after(4, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
+                        KernelTimer *tm) {
+  (void)nq_max;
   if (cfg.precision == 0)
     launch_mesh<double>(cfg, b, st, tm);
   else
     launch_mesh<float>(cfg, b, st, tm);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
+                          double *energy_total, double *energy5, const FinishArgs &fa, hipStream_t st,
+                          KernelTimer *tm) {
+  const int nblk = cfg.nblk;
+  const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   const double L = cfg.L;
   const double fscale = (double)cfg.mesh.M / (M_PI * L * L);
   const double inv2piL = 1.0 / (2.0 * M_PI * L);
-  if (tm) tm->before(8, st);
+  const int kid = fa.mode < 0 ? 8 : 9;
+  if (tm) tm->before(kid, st);
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
-                     (const double4 *)b.xq, b.freal, (const double4 *)b.part,
-                     2 * cfg.mesh.win.p, fscale, inv2piL, cfg.alpha, nblk, b.blk_eg, b.done,
-                     (const double *)b.epart, cfg.mesh.nky, (const unsigned long long *)b.eacc,
-                     (const DevScalars *)b.sc, forces, energy_total, energy5);
-  if (tm) tm->after(8, st);
+                     (const double4 *)b.xq, b.freal, (const double4 *)b.part, 2 * cfg.mesh.win.p, fscale,
+                     inv2piL, cfg.alpha, nblk, b.blk_eg, b.done, (const double *)b.epart, cfg.mesh.nky,
+                     (const unsigned long long *)b.eacc, (const DevScalars *)b.sc, b.ccnt, ncell3, b.xcnt,
+                     cfg.mesh.M, fa, forces, energy_total, energy5);
+  if (tm) tm->after(kid, st);
   return hipGetLastError();
+}
+
+hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
+                          const double *q, double *forces, double *energy_total, double *energy5,
+                          hipStream_t st, KernelTimer *tm) {
+  hipError_t e = launch_prep(cfg, b, pos, q, st, tm);
+  if (e == hipSuccess) e = launch_real(cfg, b, cfg.N, st, tm);
+  if (e == hipSuccess) e = launch_recip(cfg, b, cfg.N, st, tm);
+  if (e == hipSuccess) e = launch_combine(cfg, b, forces, energy_total, energy5, FinishArgs(), st, tm);
+  return e;
 }
 
 }  // namespace enuf

@@ -114,6 +114,113 @@ long double window_hat(const WindowParams &w, long double xi) {
   return bessel_i0(arg) * (long double)M_PI * p / std::sinh(b * p);
 }
 
+// Normalised window phi(u) (phi(0) = 1) and phi'(u) in long double, for the
+// host-side series fit.  Kaiser-Bessel: p sinh(b s)/(s sinh(b p)),
+// s = sqrt(p^2 - u^2) (an even function of s, hence entire in u); its
+// derivative -p u (b s cosh(b s) - sinh(b s)) / (s^3 sinh(b p)), summed as a
+// series for small b s.  Gaussian: exp(-u^2 / b_G).
+void window_exact(const WindowParams &w, long double u, long double *val, long double *der) {
+  if (w.kind == ENUF_WINDOW_GAUSS) {
+    const long double ib = w.inv_bg;
+    const long double g = std::exp(-u * u * ib);
+    *val = g;
+    *der = -2.0L * u * ib * g;
+    return;
+  }
+  const long double p = w.p, b = w.b;
+  const long double isb = 1.0L / std::sinh(b * p);
+  long double s2 = p * p - u * u;
+  if (s2 < 0) s2 = 0;
+  const long double s = std::sqrt(s2), z = b * s;
+  if (z > 0.5L) {
+    *val = p * std::sinh(z) / s * isb;
+    *der = -p * u * (z * std::cosh(z) - std::sinh(z)) / (s2 * s) * isb;
+  } else {
+    // sinh(z)/z = sum z^{2m}/(2m+1)!;  (z cosh z - sinh z)/z^3 = sum z^{2m}/((2m+3)(2m+1)!)
+    long double a = 1.0L, h = 1.0L / 3.0L, ta = 1.0L, th = 1.0L / 3.0L;
+    for (int k = 1; k < 20; ++k) {
+      ta *= z * z / ((2.0L * k) * (2.0L * k + 1.0L));
+      th *= z * z / ((2.0L * k) * (2.0L * k + 3.0L));
+      a += ta;
+      h += th;
+    }
+    *val = p * b * a * isb;
+    *der = -p * u * b * b * b * h * isb;
+  }
+}
+
+// Chebyshev series of the window on each of the 2p unit intervals: offset s,
+// x = 2 frac - 1, u = frac + p - 1 - s.  coef[s (D+1) + k] holds the value
+// series; coef[2p (D+1) + s D + k] the series of d phi/du.  The degree is the
+// smallest meeting the tolerance of the precision on a test grid.
+int fit_window_series(const WindowParams &w, int fp32, std::vector<long double> *coef) {
+  const int P2 = 2 * w.p;
+  const long double tol_v = fp32 ? 1e-8L : 4e-15L, tol_d = fp32 ? 1e-6L : 1e-12L;
+  int D = 4;
+  for (;; ++D) {
+    coef->assign((size_t)P2 * (2 * D + 1), 0.0L);
+    long double ev = 0, ed = 0;
+    const int n = D + 1;
+    for (int s = 0; s < P2; ++s) {
+      long double *c = coef->data() + (size_t)s * (D + 1);
+      long double *d = coef->data() + (size_t)P2 * (D + 1) + (size_t)s * D;
+      std::vector<long double> f(n), dd(D + 1, 0.0L);
+      for (int m = 0; m < n; ++m) {
+        const long double x = std::cos((long double)M_PI * (m + 0.5L) / n);
+        long double v, dv;
+        window_exact(w, x / 2 + w.p - 0.5L - s, &v, &dv);
+        f[m] = v;
+      }
+      for (int k = 0; k <= D; ++k) {
+        long double acc = 0;
+        for (int m = 0; m < n; ++m) acc += f[m] * std::cos((long double)M_PI * k * (m + 0.5L) / n);
+        c[k] = 2.0L * acc / n;
+      }
+      c[0] *= 0.5L;
+      // derivative series d/dx, then d/du = 2 d/dx
+      if (D >= 1) {
+        dd[D - 1] = 2.0L * D * c[D];
+        for (int k = D - 1; k >= 1; --k) dd[k - 1] = (k + 1 <= D ? dd[k + 1] : 0.0L) + 2.0L * k * c[k];
+        dd[0] *= 0.5L;
+      }
+      for (int k = 0; k < D; ++k) d[k] = 2.0L * dd[k];
+      for (int t = 0; t <= 256; ++t) {
+        const long double x = -1.0L + t / 128.0L;
+        long double v, dv;
+        window_exact(w, x / 2 + w.p - 0.5L - s, &v, &dv);
+        long double b1 = 0, b2 = 0;
+        for (int k = D; k >= 1; --k) { const long double tt = c[k] + 2 * x * b1 - b2; b2 = b1; b1 = tt; }
+        const long double sv = c[0] + x * b1 - b2;
+        b1 = b2 = 0;
+        for (int k = D - 1; k >= 1; --k) { const long double tt = d[k] + 2 * x * b1 - b2; b2 = b1; b1 = tt; }
+        const long double sd = D >= 1 ? d[0] + x * b1 - b2 : 0.0L;
+        ev = std::max(ev, std::fabs(sv - v));
+        ed = std::max(ed, std::fabs(sd - dv));
+      }
+    }
+    if ((ev < tol_v && ed < tol_d) || D >= kMaxChebDeg) break;
+  }
+  return D;
+}
+
+int upload_window_series(enuf_plan *pl) {
+  std::vector<long double> coef;
+  const int fp32 = pl->precision == ENUF_MIXED;
+  const int D = fit_window_series(pl->cfg.mesh.win, fp32, &coef);
+  pl->cfg.mesh.cheb_deg = D;
+  const size_t n = coef.size();
+  if (fp32) {
+    std::vector<float> h(n);
+    for (size_t k = 0; k < n; ++k) h[k] = (float)coef[k];
+    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef32, h.data(), n * sizeof(float), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  } else {
+    std::vector<double> h(n);
+    for (size_t k = 0; k < n; ++k) h[k] = (double)coef[k];
+    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef64, h.data(), n * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  }
+  return ENUF_OK;
+}
+
 int upload_tables(enuf_plan *pl) {
   const int Kc = pl->Kc, M = pl->M, nky = 2 * Kc - 1;
   const WindowParams &w = pl->cfg.mesh.win;
@@ -134,7 +241,7 @@ int upload_tables(enuf_plan *pl) {
   HIP_OR_RETURN(hipMemcpy(pl->buf.atab, atab.data(), nky * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
   HIP_OR_RETURN(hipMemcpy(pl->buf.tw64, tw64.data(), M * sizeof(double2), hipMemcpyHostToDevice), ENUF_EDEVICE);
   HIP_OR_RETURN(hipMemcpy(pl->buf.tw32, tw32.data(), M * sizeof(float2), hipMemcpyHostToDevice), ENUF_EDEVICE);
-  return ENUF_OK;
+  return upload_window_series(pl);
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -194,6 +301,9 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   c.cells.ncell = ncell;
   c.cells.cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
   c.cells.inv_cell = (double)ncell / box;
+  const double xmean = (double)N / (double)M;
+  m.xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 16.0);
+  m.cheb_deg = 1;
   mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
 
   ComputeBuffers &b = pl->buf;
@@ -215,20 +325,23 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
   b.part = (double4 *)pl->alloc(n * P2 * sizeof(double4));
   b.blk_eg = (double *)pl->alloc(nblk * sizeof(double));
-  b.winv = pl->alloc(n * 3 * P2 * sizeof(double));
-  b.wind = pl->alloc(n * 3 * P2 * sizeof(double));
-  b.mbase = (int *)pl->alloc(n * 4 * sizeof(int));
+  b.xcnt = (int *)pl->alloc((size_t)M * sizeof(int));
+  b.xslot = (int *)pl->alloc((size_t)M * (size_t)m.xcap * sizeof(int));
+  b.wcoef64 = (double *)pl->alloc(P2 * (2 * kMaxChebDeg + 1) * sizeof(double));
+  b.wcoef32 = (float *)pl->alloc(P2 * (2 * kMaxChebDeg + 1) * sizeof(float));
   b.atab = (double *)pl->alloc((size_t)m.nky * sizeof(double));
   b.tw64 = (double2 *)pl->alloc((size_t)M * sizeof(double2));
   b.tw32 = (float2 *)pl->alloc((size_t)M * sizeof(float2));
-  if (pl->allocations.size() != 22) {  // alloc() records successful allocations only
+  if (pl->allocations.size() != 23) {  // alloc() records successful allocations only
     set_error("device allocation failed");
     delete pl;
     return nullptr;
   }
   if (hipMemset(b.done, 0, 4 * sizeof(unsigned)) != hipSuccess ||
       hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
-      hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess) {
+      hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(b.ccnt, 0, ncell3 * sizeof(int)) != hipSuccess ||
+      hipMemset(b.xcnt, 0, (size_t)M * sizeof(int)) != hipSuccess) {
     set_error("hipMemset failed");
     delete pl;
     return nullptr;
@@ -237,6 +350,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     delete pl;
     return nullptr;
   }
+  mesh_lds_bytes(pl->cfg.mesh, ENUF_FP64, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
   static bool configured = false;
   if (!configured) {
     if (configure_kernels(pl->max_lds) != hipSuccess) {
@@ -270,26 +384,34 @@ int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
   if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
   if (precision != ENUF_FP64 && precision != ENUF_MIXED) { set_error("unknown precision"); return ENUF_EINVAL; }
   if (window != ENUF_WINDOW_KB && window != ENUF_WINDOW_GAUSS) { set_error("unknown window"); return ENUF_EINVAL; }
-  size_t f, x, bw;
-  mesh_lds_bytes(plan->cfg.mesh, precision, &f, &x, &bw);
-  if (f > plan->max_lds || x > plan->max_lds || bw > plan->max_lds) {
-    set_error("mesh too large for one LDS plane in this precision (need " + std::to_string(f > bw ? f : bw) +
-              " bytes, have " + std::to_string(plan->max_lds) + ")");
-    return ENUF_EINVAL;
-  }
-  const bool window_changed = window != plan->window;
+  // the stream may still read the old tables
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  const int old_prec = plan->precision, old_win = plan->window;
   plan->precision = precision;
   plan->window = window;
   plan->cfg.precision = precision;
+  plan->cfg.mesh.win = make_window(window, plan->p, plan->sigma);
+  int rc = upload_tables(plan);
+  size_t f = 0, x = 0, bw = 0;
+  if (rc == ENUF_OK) {
+    mesh_lds_bytes(plan->cfg.mesh, precision, &f, &x, &bw);
+    if (f > plan->max_lds || x > plan->max_lds || bw > plan->max_lds) {
+      set_error("mesh too large for one LDS plane in this precision (need " + std::to_string(f > bw ? f : bw) +
+                " bytes, have " + std::to_string(plan->max_lds) + ")");
+      rc = ENUF_EINVAL;
+    }
+  }
+  if (rc != ENUF_OK) {  // restore the previous, valid configuration
+    plan->precision = old_prec;
+    plan->window = old_win;
+    plan->cfg.precision = old_prec;
+    plan->cfg.mesh.win = make_window(old_win, plan->p, plan->sigma);
+    (void)upload_tables(plan);
+    return rc;
+  }
   plan->cfg.lds_fwd = f;
   plan->cfg.lds_x = x;
   plan->cfg.lds_bwd = bw;
-  if (window_changed) {
-    plan->cfg.mesh.win = make_window(window, plan->p, plan->sigma);
-    // the stream may still read the old table
-    HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
-    return upload_tables(plan);
-  }
   return ENUF_OK;
 }
 
@@ -349,7 +471,7 @@ struct enuf_dpd {
   enuf_plan *plan = nullptr;  // not owned
   double *q = nullptr;        // [N]
   double *v0 = nullptr;       // [N * 3] predicted velocities
-  unsigned long long *facc = nullptr;  // [N * 3] fixed-point pair + bond forces
+  double *fdpd = nullptr;     // [N * 3] pair + bond forces
   double *felec = nullptr;    // [N * 3]
   double *e5 = nullptr;       // [5]
   int *dcnt = nullptr;        // [ncell^3]
@@ -361,6 +483,12 @@ struct enuf_dpd {
   std::vector<void *> allocations;
   KernelTimer timer;
   std::vector<hipEvent_t> events;
+  int *dslot = nullptr;       // [N] static compact slot of each particle (-1: neutral)
+  int64_t nq = 0;
+  DpdCharges charges{};
+  hipStream_t side[2] = {nullptr, nullptr};  // forked streams (pair forces, real space)
+  int concurrent = 1;
+  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 
   void *alloc(size_t n) {
     void *ptr = nullptr;
@@ -376,6 +504,11 @@ struct enuf_dpd {
   }
   ~enuf_dpd() {
     drop_events();
+    for (int k = 0; k < 2; ++k) {
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+      if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (void *ptr : allocations) (void)hipFree(ptr);
   }
 };
@@ -427,7 +560,7 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
   d->q = (double *)d->alloc(n * sizeof(double));
   d->v0 = (double *)d->alloc(3 * n * sizeof(double));
-  d->facc = (unsigned long long *)d->alloc(3 * n * sizeof(unsigned long long));
+  d->fdpd = (double *)d->alloc(3 * n * sizeof(double));
   d->felec = (double *)d->alloc(3 * n * sizeof(double));
   d->e5 = (double *)d->alloc(5 * sizeof(double));
   d->dcnt = (int *)d->alloc(nc3 * sizeof(int));
@@ -436,14 +569,78 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   d->bond_start = (int *)d->alloc((n + 1) * sizeof(int));
   d->bond_to = (int *)d->alloc(to.size() * sizeof(int));
   d->status = (int *)d->alloc(sizeof(int));
-  if (d->allocations.size() != 11) { set_error("device allocation failed"); delete d; return nullptr; }
+  d->dslot = (int *)d->alloc(n * sizeof(int));
+  if (d->allocations.size() != 12) { set_error("device allocation failed"); delete d; return nullptr; }
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
-      hipMemset(d->facc, 0, 3 * n * sizeof(unsigned long long)) != hipSuccess ||
+
       hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     set_error("device setup of the DPD integrator failed");
+    delete d;
+    return nullptr;
+  }
+  // The charges are fixed: compact them once (index order) and precompute the
+  // plan scalars the compaction kernels would otherwise produce every step.
+  std::vector<double> hq(n);
+  if (hipMemcpy(hq.data(), d->q, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("copying the charges failed");
+    delete d;
+    return nullptr;
+  }
+  std::vector<int> hslot(n, -1);
+  DevScalars st{};
+  int nq = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (!std::isfinite(hq[i])) { set_error("non-finite charge"); delete d; return nullptr; }
+    if (hq[i] != 0.0) hslot[i] = nq++;
+    st.sum_q += hq[i];
+    st.sum_absq += std::fabs(hq[i]);
+    st.sum_q2 += hq[i] * hq[i];
+  }
+  if (std::fabs(st.sum_q) > 1e-10 * st.sum_absq) { set_error("charges are not neutral"); delete d; return nullptr; }
+  st.nq = nq;
+  int ex;
+  std::frexp(st.sum_absq + 1.0, &ex);
+  st.scale = std::ldexp(1.0, 61 - ex);
+  st.inv_scale = std::ldexp(1.0, ex - 61);
+  d->nq = nq;
+  if (hipMemcpy(d->dslot, hslot.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("uploading the charge map failed");
+    delete d;
+    return nullptr;
+  }
+  if (plan) {
+    DpdCharges &ch = d->charges;
+    ch.enabled = 1;
+    ch.dslot = d->dslot;
+    ch.q = d->q;
+    ch.xq = plan->buf.xq;
+    ch.slot = plan->buf.slot;
+    ch.ccnt = plan->buf.ccnt;
+    ch.cgrid = plan->buf.cgrid;
+    ch.cidx = plan->buf.cidx;
+    ch.cells = plan->cfg.cells;
+    ch.xcnt = plan->buf.xcnt;
+    ch.xslot = plan->buf.xslot;
+    ch.M = plan->cfg.mesh.M;
+    ch.xcap = plan->cfg.mesh.xcap;
+    ch.m_over_l = plan->cfg.mesh.m_over_l;
+    ch.sc = plan->buf.sc;
+    ch.eacc = plan->buf.eacc;
+    ch.stat = st;
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (hipStreamCreateWithFlags(&d->side[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&d->join_ev[k], hipEventDisableTiming) != hipSuccess) {
+      set_error("creating the side streams failed");
+      delete d;
+      return nullptr;
+    }
+  }
+  if (hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    set_error("creating the fork event failed");
     delete d;
     return nullptr;
   }
@@ -457,22 +654,50 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
   return ENUF_OK;
 }
 
+// One force evaluation (mode 1) or step (mode 0).  With a plan the pair
+// forces and the real-space term run on two forked streams while the mesh
+// passes run on the integrator's stream; the combine kernel joins them.
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step) {
   const int64_t N = d->N;
   KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
+  hipStream_t st = d->stream;
   hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
-                                d->stream, tm);
-  if (e == hipSuccess)
-    e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                        d->facc, d->stream, tm);
-  if (e == hipSuccess && d->plan) {
+                                d->charges, st, tm);
+  if (!d->plan) {
+    if (e == hipSuccess)
+      e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+                          d->fdpd, st, tm);
+    if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
+  } else {
     enuf_plan *pl = d->plan;
-    pl->stream = d->stream;
-    e = launch_compute(pl->cfg, pl->buf, pos, d->q, d->felec, nullptr, d->e5, d->stream, tm);
+    pl->stream = st;
+    const bool fork = d->concurrent != 0;
+    hipStream_t s0 = fork ? d->side[0] : st, s1 = fork ? d->side[1] : st;
+    if (fork) {
+      if (e == hipSuccess) e = hipEventRecord(d->fork_ev, st);
+      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(d->side[k], d->fork_ev, 0);
+    }
+    if (e == hipSuccess)
+      e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+                          d->fdpd, s0, tm);
+    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[0], s0);
+    if (e == hipSuccess) e = launch_real(pl->cfg, pl->buf, d->nq, s1, tm);
+    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[1], s1);
+    if (e == hipSuccess) e = launch_recip(pl->cfg, pl->buf, d->nq, st, tm);
+    if (fork)
+      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, d->join_ev[k], 0);
+    if (e == hipSuccess) {
+      FinishArgs fa;
+      fa.mode = mode;
+      fa.kappa = d->P.kappa;
+      fa.dt = d->P.dt;
+      fa.fdpd = d->fdpd;
+      fa.vel = vel;
+      fa.dcnt = d->dcnt;
+      fa.ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
+      e = launch_combine(pl->cfg, pl->buf, force, nullptr, d->e5, fa, st, tm);
+    }
   }
-  if (e == hipSuccess)
-    e = launch_dpd_post(N, mode, d->P, d->facc, d->plan ? d->felec : nullptr, force, vel, d->dcnt, d->stream,
-                        tm);
   if (e != hipSuccess) {
     set_error(std::string("DPD kernel launch failed: ") + hipGetErrorString(e));
     return ENUF_EDEVICE;
@@ -507,6 +732,13 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
     rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s);
     if (rc != ENUF_OK) return rc;
   }
+  return ENUF_OK;
+}
+
+int enuf_dpd_set_concurrency(enuf_dpd *d, int enable) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  d->concurrent = enable ? 1 : 0;
   return ENUF_OK;
 }
 

@@ -63,6 +63,10 @@ class DPD:
         check(lib.enuf_dpd_run(self._h, *self._state(pos, vel, force), int(first_step), int(nsteps)),
               "enuf_dpd_run")
 
+    def set_concurrency(self, enable):
+        """Overlap pair forces and real space with the mesh passes (default) or not."""
+        check(lib.enuf_dpd_set_concurrency(self._h, int(bool(enable))), "enuf_dpd_set_concurrency")
+
     def energy(self):
         """ENUF energy components of the last evaluation (unscaled by kappa)."""
         e = torch.empty(5, dtype=torch.float64, device=self.device)
