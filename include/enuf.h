@@ -73,6 +73,10 @@ typedef struct enuf_plan enuf_plan;
  *   r_cut  : real-space cutoff, 0 < r_cut <= box/2 (minimum image).
  *   lambda : Slater decay length lambda_e of eq. 26 (>= 0); 0 means point charges.
  * Allocates all device scratch on the current device.  Returns NULL on error.
+ * The mesh passes keep one x-plane in LDS; a plane too large for it (FP64 beyond
+ * M = 96 with Kc = M/4) is processed in chunks of mesh rows.  The environment
+ * variable ENUF_MAX_LDS_BYTES, read here, lowers the LDS budget per block below
+ * the device's (tuning and testing of the chunked passes).
  */
 enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma,
                             int M, int Kc, double r_cut, double lambda);

@@ -53,6 +53,10 @@ struct MeshParams {
   int Mz;          // padded line stride of LDS spectrum buffers (elements)
   int Kc;          // reciprocal cutoff: 0 < |k| < Kc
   int nky;         // 2 Kc - 1 stored ky values (ky = idx - (Kc - 1))
+  int rows;        // mesh rows (y) per LDS chunk of a plane pass; even, >= 2p when < M
+  int nchunk;      // ceil(M / rows)
+  int nslot;       // gather partials per (charge, x offset): 1, or 2 when a
+                   // charge's 2p rows can straddle two chunks
   double L;
   double m_over_l; // M / L: mesh coordinate t = x * m_over_l
   WindowParams win;
@@ -101,7 +105,7 @@ struct ComputeBuffers {
   // reciprocal
   void *gzy;             // [M * nky * Kc] complex (double2 or float2)
   double *epart;         // [nky] k-space energy per ky row
-  double4 *part;         // [N * 2p] gather partials (dwx A, wx By, wx Bz, wx A)
+  double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
   int *xcnt;             // [M] charges per mesh x-cell (zero between calls)
   int *xslot;            // [M * xcap] compact indices of the charges of each x-cell
   double *wcoef64;       // [2p (D+1) + 2p D] window series coefficients (value, then derivative)
@@ -172,8 +176,13 @@ hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b,
                           double *energy_total, double *energy5, hipStream_t stream,
                           KernelTimer *timer = nullptr);
 
-// LDS bytes the three mesh passes need for the given geometry and precision.
+// LDS bytes the three mesh passes need for the given geometry, precision and
+// m.rows.
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd);
+
+// Choose m.rows / m.nchunk / m.nslot: the fewest row chunks whose passes fit
+// in max_lds bytes.  Returns false when no chunking fits.
+bool mesh_choose_rows(MeshParams &m, int precision, size_t max_lds);
 
 // Raise the per-kernel dynamic LDS limit where needed (once per process).
 hipError_t configure_kernels(size_t max_lds);

@@ -378,9 +378,14 @@ __device__ inline int cell_frac(double x, double m_over_l, int M, double *frac) 
 
 // ---------------------------------------------------------------------------
 // Mesh pass 1: spread + z R2C FFT + y FFT for one x-plane.
-// LDS: int64 accumulator plane [M][Mp] (aliased by the T plane after
-// conversion), spectrum lines Zre/Zim [Kc][Mz], twiddles, window series.
+// The plane is processed in chunks of mp.rows mesh rows (all of it when it
+// fits): each chunk is spread into an int64 LDS accumulator, converted to T in
+// place, z-transformed and its Kc retained modes moved into the spectrum lines
+// Zre/Zim [Kc][Mz], which then take the y FFT.
+// LDS: accumulator [rows][Mp] int64, spectrum lines, twiddles, window series.
 // ---------------------------------------------------------------------------
+__device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
 k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
@@ -388,22 +393,17 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
             const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p, D = mp.cheb_deg;
+  const int R = mp.rows;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const int x0 = blockIdx.x;
 
   long long *acc = reinterpret_cast<long long *>(smem);
   T *plane = reinterpret_cast<T *>(smem);
-  const size_t plane_bytes = (size_t)M * Mp * sizeof(long long);
-  T *Zre;
-  size_t off = plane_bytes;
-  if (sizeof(T) == 8) {
-    Zre = reinterpret_cast<T *>(smem + off);
-    off += 2 * (size_t)Kc * Mz * sizeof(T);
-  } else {
-    Zre = reinterpret_cast<T *>(smem + (size_t)M * Mp * sizeof(T));
-  }
+  size_t off = align16((size_t)R * Mp * sizeof(long long));
+  T *Zre = reinterpret_cast<T *>(smem + off);
   T *Zim = Zre + (size_t)Kc * Mz;
+  off += 2 * (size_t)Kc * Mz * sizeof(T);
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
@@ -417,89 +417,100 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
     twi[m] = tw[m].y;
   }
   for (int k = tid; k < P2 * (D + 1); k += nt) cv[k] = wcoef[k];
-  for (int k = tid; k < M * Mp; k += nt) acc[k] = 0;
   const double scale = sc->scale, inv_scale = sc->inv_scale;
-  const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);
+  const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
 
   // whole wavefronts iterate together so that the group shuffles see every lane
   const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
   const int gbase = lane & ~(P2pad - 1);
-  for (int it = tid; it < items; it += nt) {
-    const int e = it / P2pad, sy = it % P2pad;
-    const bool has = e < total, act = has && sy < P2;
-    T wz = (T)0, wrow = (T)0;
-    int row = 0, bz = 0;
-    if (has) {
-      int b;
-      const int j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-      const double4 c = xq[j];
-      double fx, fy, fz;
-      cell_frac(c.x, mp.m_over_l, M, &fx);
-      const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
-      const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
-      if (act) {
-        const int sx = P2 - 1 - b;
-        const T wx = clenshaw<T>(cv + sx * (D + 1), D, (T)(2.0 * fx - 1.0));
-        const T wy = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fy - 1.0));
-        wz = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fz - 1.0));
-        wrow = (T)c.w * wx * wy;
-        row = mod_pos(cy - p + 1 + sy, M);
-        bz = cz - p + 1;
+  for (int r0 = 0; r0 < M; r0 += R) {
+    const int nr = (M - r0) < R ? (M - r0) : R;
+    for (int k = tid; k < nr * Mp; k += nt) acc[k] = 0;
+    __syncthreads();
+    for (int it = tid; it < items; it += nt) {
+      const int e = it / P2pad, sy = it % P2pad;
+      const bool has = e < total;
+      bool act = has && sy < P2, in = false;
+      T wz = (T)0, wrow = (T)0;
+      int row = 0, bz = 0;
+      if (has) {
+        int b;
+        const int j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
+        const double4 c = xq[j];
+        double fx, fy, fz;
+        cell_frac(c.x, mp.m_over_l, M, &fx);
+        const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
+        const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
+        if (act) {
+          wz = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fz - 1.0));
+          row = mod_pos(cy - p + 1 + sy, M) - r0;
+          in = (unsigned)row < (unsigned)nr;
+          if (in) {
+            const int sx = P2 - 1 - b;
+            const T wx = clenshaw<T>(cv + sx * (D + 1), D, (T)(2.0 * fx - 1.0));
+            const T wy = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fy - 1.0));
+            wrow = (T)c.w * wx * wy;
+          } else {
+            row = 0;
+          }
+          bz = cz - p + 1;
+        }
       }
-    }
-    long long *arow = acc + (size_t)row * Mp;
-    int col = bz < 0 ? bz + M : bz;
-    for (int sz = 0; sz < P2; ++sz) {
-      const T w = __shfl(wz, gbase + sz, kWave);
-      if (act) {
-        const double v = (double)(wrow * w);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
-        col = (col + 1 == M) ? 0 : col + 1;
+      long long *arow = acc + (size_t)row * Mp;
+      int col = bz < 0 ? bz + M : bz;
+      for (int sz = 0; sz < P2; ++sz) {
+        const T w = __shfl(wz, gbase + sz, kWave);
+        if (in) {
+          const double v = (double)(wrow * w);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
+          col = (col + 1 == M) ? 0 : col + 1;
+        }
       }
-    }
-  }
-  __syncthreads();
-
-  // fixed point -> T plane (in place; FP32 rows move down in chunks)
-  if (sizeof(T) == 8) {
-    for (int k = tid; k < M * Mp; k += nt) {
-      const long long v = acc[k];
-      plane[k] = (T)((double)v * inv_scale);
     }
     __syncthreads();
-  } else {
-    int R = (4 * nt) / Mp;
-    R = R < 1 ? 1 : R;
-    for (int r0 = 0; r0 < M; r0 += R) {
-      const int n = ((M - r0) < R ? (M - r0) : R) * Mp;
-      long long v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = tid + u * nt;
-        if (k < n) v[u] = acc[(size_t)r0 * Mp + k];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = tid + u * nt;
-        if (k < n) plane[(size_t)r0 * Mp + k] = (T)((double)v[u] * inv_scale);
-      }
-      __syncthreads();
-    }
-  }
 
-  // z: rows 2c (real part) and 2c+1 (imaginary part) form complex line c
-  lds_fft<T>(plane, plane + Mp, 2 * Mp, M / 2, mp.fft, twr, twi, false);
-  for (int id = tid; id < (M / 2) * Kc; id += nt) {
-    const int c = id / Kc, k = id % Kc, mk = (M - k) % M;
-    const T zr = plane[2 * c * Mp + k], zi = plane[(2 * c + 1) * Mp + k];
-    const T mr = plane[2 * c * Mp + mk], mi = plane[(2 * c + 1) * Mp + mk];
-    Zre[k * Mz + 2 * c] = (T)0.5 * (zr + mr);
-    Zim[k * Mz + 2 * c] = (T)0.5 * (zi - mi);
-    Zre[k * Mz + 2 * c + 1] = (T)0.5 * (zi + mi);
-    Zim[k * Mz + 2 * c + 1] = (T)0.5 * (mr - zr);
+    // fixed point -> T rows (in place; FP32 rows move down in groups)
+    if (sizeof(T) == 8) {
+      for (int k = tid; k < nr * Mp; k += nt) {
+        const long long v = acc[k];
+        plane[k] = (T)((double)v * inv_scale);
+      }
+      __syncthreads();
+    } else {
+      int G = (4 * nt) / Mp;
+      G = G < 1 ? 1 : G;
+      for (int g0 = 0; g0 < nr; g0 += G) {
+        const int n = ((nr - g0) < G ? (nr - g0) : G) * Mp;
+        long long v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = tid + u * nt;
+          if (k < n) v[u] = acc[(size_t)g0 * Mp + k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = tid + u * nt;
+          if (k < n) plane[(size_t)g0 * Mp + k] = (T)((double)v[u] * inv_scale);
+        }
+        __syncthreads();
+      }
+    }
+
+    // z: rows 2c (real part) and 2c+1 (imaginary part) form complex line c
+    lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, false);
+    for (int id = tid; id < (nr / 2) * Kc; id += nt) {
+      const int c = id / Kc, k = id % Kc, mk = (M - k) % M;
+      const T zr = plane[2 * c * Mp + k], zi = plane[(2 * c + 1) * Mp + k];
+      const T mr = plane[2 * c * Mp + mk], mi = plane[(2 * c + 1) * Mp + mk];
+      const int y = r0 + 2 * c;
+      Zre[k * Mz + y] = (T)0.5 * (zr + mr);
+      Zim[k * Mz + y] = (T)0.5 * (zi - mi);
+      Zre[k * Mz + y + 1] = (T)0.5 * (zi + mi);
+      Zim[k * Mz + y + 1] = (T)0.5 * (mr - zr);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // y: one complex line per kz
   lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, false);
   const int nky = mp.nky;
@@ -593,13 +604,13 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
             const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
-  const int D = mp.cheb_deg;
+  const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const int x0 = blockIdx.x;
 
-  T *plane = reinterpret_cast<T *>(smem);
-  size_t off = (size_t)M * Mp * sizeof(T);
+  T *plane = reinterpret_cast<T *>(smem);  // [rows][Mp]
+  size_t off = align16((size_t)R * Mp * sizeof(T));
   T *Zre = reinterpret_cast<T *>(smem + off);
   T *Zim = Zre + (size_t)Kc * Mz;
   off += 2 * (size_t)Kc * Mz * sizeof(T);
@@ -628,84 +639,110 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
   }
   __syncthreads();
   lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
-
-  // Hermitian z spectra of rows 2c and 2c+1 packed as H1 + i H2
-  for (int id = tid; id < (M / 2) * M; id += nt) {
-    const int c = id / M, k = id % M;
-    T re = (T)0, im = (T)0;
-    if (k < Kc) {
-      const T h1r = Zre[k * Mz + 2 * c], h1i = Zim[k * Mz + 2 * c];
-      const T h2r = Zre[k * Mz + 2 * c + 1], h2i = Zim[k * Mz + 2 * c + 1];
-      if (k == 0) {
-        re = h1r;
-        im = h2r;
-      } else {
-        re = h1r - h2i;
-        im = h1i + h2r;
-      }
-    } else if (k > M - Kc) {
-      const int kk = M - k;
-      const T h1r = Zre[kk * Mz + 2 * c], h1i = Zim[kk * Mz + 2 * c];
-      const T h2r = Zre[kk * Mz + 2 * c + 1], h2i = Zim[kk * Mz + 2 * c + 1];
-      re = h1r + h2i;
-      im = h2r - h1i;
-    }
-    plane[2 * c * Mp + k] = re;
-    plane[(2 * c + 1) * Mp + k] = im;
-  }
   const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
-  lds_fft<T>(plane, plane + Mp, 2 * Mp, M / 2, mp.fft, twr, twi, true);
 
   const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
   const int gbase = lane & ~(P2pad - 1);
-  for (int it = tid; it < items; it += nt) {
-    const int e = it / P2pad, sy = it % P2pad;
-    const bool has = e < total, act = has && sy < P2;
-    int j = 0, sx = 0, row = 0, bz = 0;
-    T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
-    if (has) {
-      int b;
-      j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-      sx = P2 - 1 - b;
-      const double4 c = xq[j];
-      double fx, fy, fz;
-      cell_frac(c.x, mp.m_over_l, M, &fx);
-      const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
-      const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
-      if (act) {
-        const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
-        wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
-        dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
-        wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
-        dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
-        wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
-        dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
-        row = mod_pos(cy - p + 1 + sy, M);
-        bz = cz - p + 1;
+  for (int r0 = 0; r0 < M; r0 += R) {
+    const int nr = (M - r0) < R ? (M - r0) : R;
+    // Hermitian z spectra of rows r0 + 2c and r0 + 2c + 1 packed as H1 + i H2
+    for (int id = tid; id < (nr / 2) * M; id += nt) {
+      const int c = id / M, k = id % M, y = r0 + 2 * c;
+      T re = (T)0, im = (T)0;
+      if (k < Kc) {
+        const T h1r = Zre[k * Mz + y], h1i = Zim[k * Mz + y];
+        const T h2r = Zre[k * Mz + y + 1], h2i = Zim[k * Mz + y + 1];
+        if (k == 0) {
+          re = h1r;
+          im = h2r;
+        } else {
+          re = h1r - h2i;
+          im = h1i + h2r;
+        }
+      } else if (k > M - Kc) {
+        const int kk = M - k;
+        const T h1r = Zre[kk * Mz + y], h1i = Zim[kk * Mz + y];
+        const T h2r = Zre[kk * Mz + y + 1], h2i = Zim[kk * Mz + y + 1];
+        re = h1r + h2i;
+        im = h2r - h1i;
+      }
+      plane[2 * c * Mp + k] = re;
+      plane[(2 * c + 1) * Mp + k] = im;
+    }
+    __syncthreads();
+    lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, true);
+
+    const int chunk = r0 / R;
+    for (int it = tid; it < items; it += nt) {
+      const int e = it / P2pad, sy = it % P2pad;
+      const bool has = e < total, act = has && sy < P2;
+      bool in = false;
+      int j = 0, sx = 0, row = 0, bz = 0, cy = 0;
+      T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
+      if (has) {
+        int b;
+        j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
+        sx = P2 - 1 - b;
+        const double4 c = xq[j];
+        double fx, fy, fz;
+        cell_frac(c.x, mp.m_over_l, M, &fx);
+        cy = cell_frac(c.y, mp.m_over_l, M, &fy);
+        const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
+        if (act) {
+          const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
+          wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
+          dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
+          wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
+          dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
+          row = mod_pos(cy - p + 1 + sy, M) - r0;
+          in = (unsigned)row < (unsigned)nr;
+          if (in) {
+            wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
+            dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
+          } else {
+            row = 0;
+          }
+          bz = cz - p + 1;
+        }
+      }
+      const T *hrow = plane + (size_t)row * Mp;
+      int col = bz < 0 ? bz + M : bz;
+      T a = (T)0, bsum = (T)0;
+      for (int sz = 0; sz < P2; ++sz) {
+        const T w = __shfl(wz, gbase + sz, kWave);
+        const T d = __shfl(dwz, gbase + sz, kWave);
+        if (in) {
+          const T h = hrow[col];
+          a += h * w;
+          bsum += h * d;
+          col = (col + 1 == M) ? 0 : col + 1;
+        }
+      }
+      T A = wy * a, By = dwy * a, Bz = wy * bsum;
+      for (int o = P2pad / 2; o >= 1; o >>= 1) {
+        A += __shfl_xor(A, o, kWave);
+        By += __shfl_xor(By, o, kWave);
+        Bz += __shfl_xor(Bz, o, kWave);
+      }
+      if (has && sy == 0) {
+        const double4 v = make_double4((double)(dwx * A), (double)(wx * By), (double)(wx * Bz),
+                                       (double)(wx * A));
+        double4 *dst = part + ((size_t)j * P2 + sx) * nslot;
+        if (nslot == 1) {
+          dst[0] = v;
+        } else {
+          // chunk of the charge's first and last stencil rows
+          const int first = mod_pos(cy - p + 1, M) / R, last = mod_pos(cy + p, M) / R;
+          if (chunk == first) {
+            dst[0] = v;
+            if (first == last) dst[1] = make_double4(0.0, 0.0, 0.0, 0.0);
+          } else if (chunk == last) {
+            dst[1] = v;
+          }
+        }
       }
     }
-    const T *hrow = plane + (size_t)row * Mp;
-    int col = bz < 0 ? bz + M : bz;
-    T a = (T)0, bsum = (T)0;
-    for (int sz = 0; sz < P2; ++sz) {
-      const T w = __shfl(wz, gbase + sz, kWave);
-      const T d = __shfl(dwz, gbase + sz, kWave);
-      if (act) {
-        const T h = hrow[col];
-        a += h * w;
-        bsum += h * d;
-        col = (col + 1 == M) ? 0 : col + 1;
-      }
-    }
-    T A = wy * a, By = dwy * a, Bz = wy * bsum;
-    for (int o = P2pad / 2; o >= 1; o >>= 1) {
-      A += __shfl_xor(A, o, kWave);
-      By += __shfl_xor(By, o, kWave);
-      Bz += __shfl_xor(Bz, o, kWave);
-    }
-    if (has && sy == 0)
-      part[(size_t)j * P2 + sx] = make_double4((double)(dwx * A), (double)(wx * By),
-                                               (double)(wx * Bz), (double)(wx * A));
+    __syncthreads();  // the next chunk overwrites the plane
   }
 }
 
@@ -714,7 +751,7 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kPrepThreads)
 k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
-          unsigned long long *freal, const double4 *__restrict__ part, int P2,
+          unsigned long long *freal, const double4 *__restrict__ part, int P2S,
           double fscale, double inv2piL, double alpha, int nblk, double *blk_eg, unsigned *done,
           const double *__restrict__ epart, int nky, const unsigned long long *eacc,
           const DevScalars *sc, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
@@ -737,8 +774,8 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (j >= 0) {
       double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
-      for (int s = 0; s < P2; ++s) {
-        const double4 v = part[(size_t)j * P2 + s];
+      for (int s = 0; s < P2S; ++s) {
+        const double4 v = part[(size_t)j * P2S + s];
         bx += v.x;
         by += v.y;
         bz += v.z;
@@ -804,13 +841,38 @@ void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, 
   const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
   const int P2 = 2 * m.win.p;
   const size_t misc = (size_t)P2 * (2 * m.cheb_deg + 1) * ts + (3 * (size_t)P2 + 2) * sizeof(int) + 32;
-  const size_t acc = (size_t)m.M * m.Mp * sizeof(long long);
+  const size_t a16 = 15;
+  const size_t acc = ((size_t)m.rows * m.Mp * sizeof(long long) + a16) & ~a16;
+  const size_t rows_t = ((size_t)m.rows * m.Mp * ts + a16) & ~a16;
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
-  *fwd = (ts == 8 ? acc + zp : acc) + tw + misc;
+  *fwd = acc + zp + tw + misc;
   *x = ((zp + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) +
        (size_t)m.nky * sizeof(double) + 16;
-  *bwd = (size_t)m.M * m.Mp * ts + zp + tw + misc;
+  *bwd = rows_t + zp + tw + misc;
+}
+
+bool mesh_choose_rows(MeshParams &m, int precision, size_t max_lds) {
+  for (int nchunk = 1; nchunk <= m.M / 2; ++nchunk) {
+    int rows = (m.M + nchunk - 1) / nchunk;
+    rows += rows & 1;
+    if (nchunk > 1 && rows < 2 * m.win.p) return false;
+    MeshParams t = m;
+    t.rows = rows;
+    t.nchunk = (m.M + rows - 1) / rows;
+    t.nslot = t.nchunk > 1 ? 2 : 1;
+    if (t.nchunk > 1 && m.M - (t.nchunk - 1) * rows < 2 * m.win.p) continue;  // keep every chunk >= 2p rows
+    size_t f, x, b;
+    mesh_lds_bytes(t, precision, &f, &x, &b);
+    if (x > max_lds) return false;
+    if (f <= max_lds && b <= max_lds) {
+      m.rows = t.rows;
+      m.nchunk = t.nchunk;
+      m.nslot = t.nslot;
+      return true;
+    }
+  }
+  return false;
 }
 
 hipError_t configure_kernels(size_t max_lds) {
@@ -900,7 +962,8 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
   const int kid = fa.mode < 0 ? 8 : 9;
   if (tm) tm->before(kid, st);
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
-                     (const double4 *)b.xq, b.freal, (const double4 *)b.part, 2 * cfg.mesh.win.p, fscale,
+                     (const double4 *)b.xq, b.freal, (const double4 *)b.part,
+                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale,
                      inv2piL, cfg.alpha, nblk, b.blk_eg, b.done, (const double *)b.epart, cfg.mesh.nky,
                      (const unsigned long long *)b.eacc, (const DevScalars *)b.sc, b.ccnt, ncell3, b.xcnt,
                      cfg.mesh.M, fa, forces, energy_total, energy5);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -68,6 +69,7 @@ struct enuf_plan {
   int p = 0, M = 0, Kc = 0;
   int precision = ENUF_FP64, window = ENUF_WINDOW_KB;
   size_t max_lds = 0;
+  int part_slots = 1;      // gather partial slots allocated per (charge, x offset)
   ComputeConfig cfg{};
   ComputeBuffers buf{};
   std::vector<void *> allocations;
@@ -284,6 +286,11 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     return nullptr;
   }
   pl->max_lds = (size_t)lds;
+  // optional lower LDS budget per block: forces the row-chunked plane passes
+  if (const char *cap = std::getenv("ENUF_MAX_LDS_BYTES")) {
+    const long long v = std::atoll(cap);
+    if (v > 0 && (size_t)v < pl->max_lds) pl->max_lds = (size_t)v;
+  }
 
   ComputeConfig &c = pl->cfg;
   c.N = N;
@@ -303,7 +310,24 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   c.cells.inv_cell = (double)ncell / box;
   const double xmean = (double)N / (double)M;
   m.xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 16.0);
-  m.cheb_deg = 1;
+  // Row chunking of the plane passes; the gather partials are sized for the
+  // largest series degree in either precision.
+  m.cheb_deg = kMaxChebDeg;
+  int part_slots = 0;
+  for (int prec = ENUF_FP64; prec <= ENUF_MIXED; ++prec) {
+    MeshParams t = m;
+    if (mesh_choose_rows(t, prec, pl->max_lds)) part_slots = t.nslot > part_slots ? t.nslot : part_slots;
+  }
+  if (part_slots == 0) {
+    set_error("mesh too large: no row chunking of the plane passes fits in " + std::to_string(pl->max_lds) +
+              " bytes of LDS");
+    delete pl;
+    return nullptr;
+  }
+  pl->part_slots = part_slots;
+  m.rows = M;
+  m.nchunk = 1;
+  m.nslot = 1;
   mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
 
   ComputeBuffers &b = pl->buf;
@@ -323,7 +347,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.eacc = (unsigned long long *)pl->alloc(4 * sizeof(unsigned long long));
   b.gzy = pl->alloc((size_t)M * m.nky * Kc * sizeof(double2));
   b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
-  b.part = (double4 *)pl->alloc(n * P2 * sizeof(double4));
+  b.part = (double4 *)pl->alloc(n * P2 * (size_t)part_slots * sizeof(double4));
   b.blk_eg = (double *)pl->alloc(nblk * sizeof(double));
   b.xcnt = (int *)pl->alloc((size_t)M * sizeof(int));
   b.xslot = (int *)pl->alloc((size_t)M * (size_t)m.xcap * sizeof(int));
@@ -350,7 +374,13 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     delete pl;
     return nullptr;
   }
-  mesh_lds_bytes(pl->cfg.mesh, ENUF_FP64, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
+  if (!mesh_choose_rows(m, ENUF_FP64, pl->max_lds) || m.nslot > pl->part_slots) {
+    // FP64 does not fit; the plan stays usable after switching to the mixed mode
+    m.rows = M;
+    m.nchunk = 1;
+    m.nslot = 1;
+  }
+  mesh_lds_bytes(m, ENUF_FP64, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
   static bool configured = false;
   if (!configured) {
     if (configure_kernels(pl->max_lds) != hipSuccess) {
@@ -393,12 +423,14 @@ int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
   plan->cfg.mesh.win = make_window(window, plan->p, plan->sigma);
   int rc = upload_tables(plan);
   size_t f = 0, x = 0, bw = 0;
+  const MeshParams old_mesh = plan->cfg.mesh;
   if (rc == ENUF_OK) {
-    mesh_lds_bytes(plan->cfg.mesh, precision, &f, &x, &bw);
-    if (f > plan->max_lds || x > plan->max_lds || bw > plan->max_lds) {
-      set_error("mesh too large for one LDS plane in this precision (need " + std::to_string(f > bw ? f : bw) +
-                " bytes, have " + std::to_string(plan->max_lds) + ")");
+    MeshParams &m = plan->cfg.mesh;
+    if (!mesh_choose_rows(m, precision, plan->max_lds) || m.nslot > plan->part_slots) {
+      set_error("mesh too large for the LDS in this precision (" + std::to_string(plan->max_lds) + " bytes)");
       rc = ENUF_EINVAL;
+    } else {
+      mesh_lds_bytes(m, precision, &f, &x, &bw);
     }
   }
   if (rc != ENUF_OK) {  // restore the previous, valid configuration
@@ -407,6 +439,9 @@ int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
     plan->cfg.precision = old_prec;
     plan->cfg.mesh.win = make_window(old_win, plan->p, plan->sigma);
     (void)upload_tables(plan);
+    plan->cfg.mesh.rows = old_mesh.rows;
+    plan->cfg.mesh.nchunk = old_mesh.nchunk;
+    plan->cfg.mesh.nslot = old_mesh.nslot;
     return rc;
   }
   plan->cfg.lds_fwd = f;

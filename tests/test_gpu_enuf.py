@@ -190,3 +190,67 @@ def test_force_is_gradient_of_gpu_energy():
             fd = -((Ep[0] + Ep[2]) - (Em[0] + Em[2])) / (2 * h)
             assert abs(fd - F0[i, a]) < 1e-5 * (1 + abs(fd))
     plan.close()
+
+
+@pytest.mark.parametrize("cap", [11000, 9400])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_row_chunked_planes_match(monkeypatch, precision, cap):
+    """A lowered LDS budget makes the plane passes work in chunks of mesh rows
+    (two partial slots per charge); the result equals the one-chunk plane to
+    rounding and still meets the oracle bar."""
+    s = wl.single_eval_small()
+    e = s.meta["enuf"]
+    whole = _plan(s.N, e, precision)
+    Fw, Ew, stw = _run(whole, s.pos, s.q)
+    fp_whole = whole.footprint_bytes
+    whole.close()
+    monkeypatch.setenv("ENUF_MAX_LDS_BYTES", str(cap))
+    print(f"case: chunked planes, precision={precision}, LDS cap {cap}", flush=True)
+    chunked = _plan(s.N, e, precision)
+    Fc, Ec, stc = _run(chunked, s.pos, s.q)
+    fp_chunked = chunked.footprint_bytes
+    chunked.close()
+    assert stw == 0 and stc == 0
+    # the second slot of the gather partials is allocated only for chunked planes
+    assert fp_chunked - fp_whole == s.N * 2 * e["p"] * 32
+    d = np.linalg.norm(Fc - Fw) / np.linalg.norm(Fw)
+    print(f"chunked vs whole plane: force rel {d:.3e}, E_recip {Ec[2]:.15e} vs {Ew[2]:.15e}")
+    assert d < (1e-12 if precision == "fp64" else 1e-6)
+    assert Ec[2] == Ew[2]   # the spread is an exact fixed-point sum; same FFT lines
+    ref = oracle.ewald(s.pos, s.q, e["L"], e["alpha"], e["Kc"], e["r_cut"], e["lam"])
+    ef, ee, _ = _errors(Fc, Ec, ref)
+    tf, te = TOL[precision]
+    assert ef <= tf and ee <= te
+
+
+_SWEEP_REF = {}
+
+
+def _sweep_ref(L):
+    if L not in _SWEEP_REF:
+        s = wl.n_sweep(L)
+        e = s.meta["enuf"]
+        _SWEEP_REF[L] = (s, oracle.ewald(s.pos, s.q, e["L"], e["alpha"], e["Kc"], e["r_cut"], e["lam"]))
+    return _SWEEP_REF[L]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("L", [15, 20, 30, 40])
+def test_n_sweep_parity(L, precision):
+    """The N sweep at density 3 with 10 % charges: L = 15 ... 40, N = 10125 ...
+    192000, M = 3.2 L, Kc = 0.8 L (L = 40 in FP64 runs the row-chunked planes),
+    every force and the energy against the full direct-Ewald oracle."""
+    s, ref = _sweep_ref(L)
+    e = s.meta["enuf"]
+    print(f"case: n_sweep L={L} N={s.N} Nq={s.Nq} M={e['M']} Kc={e['Kc']} {precision}", flush=True)
+    plan = _plan(s.N, e, precision)
+    F, E5, st = _run(plan, s.pos, s.q)
+    plan.close()
+    ef, ee, Et = _errors(F, E5, ref)
+    scale = abs(ref["E_real"]) + abs(ref["E_recip"]) + abs(ref["E_self"])
+    print(f"L={L} {precision}: force rel rms {ef:.3e}  energy rel {ee:.3e} "
+          f"(vs sum of |components| {abs(Et - ref['E']) / scale:.3e})")
+    assert st == 0
+    tf, te = TOL[precision]
+    assert ef <= tf and ee <= te
+    assert np.all(F[s.q == 0.0] == 0.0)
