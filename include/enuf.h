@@ -195,6 +195,78 @@ int enuf_dpd_status(enuf_dpd *dpd, int *status);
 /* Release the integrator (not its plan).  NULL is a no-op. */
 void enuf_dpd_destroy(enuf_dpd *dpd);
 
+/* Device bytes held by the integrator and its plan (admission control). */
+size_t enuf_dpd_footprint_bytes(const enuf_dpd *dpd);
+
+/* Lanes per particle of the pair-force kernel: 4 (default) or 8.  Results do
+ * not depend on it (exact fixed-point force sums). */
+int enuf_dpd_set_tuning(enuf_dpd *dpd, int pair_lanes);
+
+/* ------------------------------------------------------------------------
+ * Batched DPD steps: many independent systems (each an integrator with its
+ * own plan, N, box, M, Kc, charges and parameters) advanced together, one
+ * kernel launch per stage of the step for all members, the step captured
+ * once in a HIP graph and replayed.  A member's trajectory is bitwise the one
+ * enuf_dpd_run gives it alone (same kernels, same per-system arithmetic).
+ * ------------------------------------------------------------------------ */
+typedef struct enuf_batch enuf_batch;
+
+/* Create an empty batch on the current device for members of one precision
+ * (ENUF_FP64 / ENUF_MIXED).  NULL on error. */
+enuf_batch *enuf_batch_create(int precision);
+
+/* Release the batch (synchronises; members are not destroyed).  NULL is a no-op. */
+void enuf_batch_destroy(enuf_batch *batch);
+
+/* The caller's stream (NULL = null stream): a run is ordered after the work
+ * already queued on it and before work queued on it later.  Members use it as
+ * their stream while they belong to the batch. */
+int enuf_batch_set_stream(enuf_batch *batch, void *hip_stream);
+
+/* use_graph: replay one captured step (1, default) or launch eagerly (0);
+ * concurrent: in eager launches, fork the pair forces and real space onto
+ * side streams (1, default) or keep the step on one stream (0).  The captured
+ * step always uses the single-stream schedule.  Results do not depend on
+ * either option. */
+int enuf_batch_set_options(enuf_batch *batch, int use_graph, int concurrent);
+
+/*
+ * Add an integrator (with a plan of the batch's precision) and its state:
+ * device arrays pos, vel, force of N x 3 FP64, owned by the caller and kept
+ * alive while the member belongs to the batch.  force must hold the force of
+ * the current state (enuf_dpd_forces or an earlier run); the member's next
+ * step uses the random numbers of step first_step.  Returns a member id >= 0,
+ * or a negative ENUF_* code.
+ */
+int enuf_batch_add(enuf_batch *batch, enuf_dpd *dpd, double *pos, double *vel, double *force,
+                   uint64_t first_step);
+
+/* Remove a member (synchronises the batch's work first). */
+int enuf_batch_remove(enuf_batch *batch, int member_id);
+
+/* Number of members. */
+int enuf_batch_size(const enuf_batch *batch);
+
+/* Advance every member nsteps steps (enqueue-only). */
+int enuf_batch_run(enuf_batch *batch, int nsteps);
+
+/* Device bytes of the batch's tables and of all members (with their plans). */
+size_t enuf_batch_footprint_bytes(const enuf_batch *batch);
+
+/* Lanes per particle of the pair-force kernel (4 or 8) for all members.
+ * Results do not depend on it (exact fixed-point force sums). */
+int enuf_batch_set_tuning(enuf_batch *batch, int pair_lanes);
+
+/*
+ * Autotuner: time trial_steps eager steps of the current members under each
+ * launch configuration (pair lanes 4 / 8; with graphs off also forked / single
+ * stream), keep the fastest, and restore every member's state (pos, vel,
+ * force, step index) to what it was on entry.  Synchronises; allocates a
+ * temporary copy of the states.
+ * The chosen values are returned through the pointers (which may be NULL).
+ */
+int enuf_batch_autotune(enuf_batch *batch, int trial_steps, int *pair_lanes, int *concurrent);
+
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  While enabled, an integrator records
  * a pair of HIP events on its stream around each launch of one kernel of the

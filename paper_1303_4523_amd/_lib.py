@@ -67,6 +67,33 @@ lib.enuf_dpd_time_kernel.argtypes = [_vp, _int, _int]
 lib.enuf_dpd_time_kernel.restype = _int
 lib.enuf_dpd_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_int)]
 lib.enuf_dpd_kernel_time.restype = _int
+lib.enuf_dpd_footprint_bytes.argtypes = [_vp]
+lib.enuf_dpd_footprint_bytes.restype = _sz
+
+lib.enuf_batch_create.argtypes = [_int]
+lib.enuf_batch_create.restype = _vp
+lib.enuf_batch_destroy.argtypes = [_vp]
+lib.enuf_batch_destroy.restype = None
+lib.enuf_batch_set_stream.argtypes = [_vp, _vp]
+lib.enuf_batch_set_stream.restype = _int
+lib.enuf_batch_set_options.argtypes = [_vp, _int, _int]
+lib.enuf_batch_set_options.restype = _int
+lib.enuf_batch_add.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint64]
+lib.enuf_batch_add.restype = _int
+lib.enuf_batch_remove.argtypes = [_vp, _int]
+lib.enuf_batch_remove.restype = _int
+lib.enuf_batch_size.argtypes = [_vp]
+lib.enuf_batch_size.restype = _int
+lib.enuf_batch_run.argtypes = [_vp, _int]
+lib.enuf_batch_run.restype = _int
+lib.enuf_batch_footprint_bytes.argtypes = [_vp]
+lib.enuf_batch_footprint_bytes.restype = _sz
+lib.enuf_batch_set_tuning.argtypes = [_vp, _int]
+lib.enuf_batch_set_tuning.restype = _int
+lib.enuf_batch_autotune.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int)]
+lib.enuf_batch_autotune.restype = _int
+lib.enuf_dpd_set_tuning.argtypes = [_vp, _int]
+lib.enuf_dpd_set_tuning.restype = _int
 
 # Kernel ids of the timing hook (ENUF_K_* in include/enuf.h).
 KERNELS = {"dpd_pre": 0, "dpd_pair": 1, "prep_count": 2, "prep_compact": 3, "real": 4,
@@ -79,7 +106,10 @@ EXPORTED = [
     "enuf_plan_footprint_bytes",
     "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_set_concurrency", "enuf_dpd_forces", "enuf_dpd_run",
     "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
-    "enuf_dpd_time_kernel", "enuf_dpd_kernel_time",
+    "enuf_dpd_time_kernel", "enuf_dpd_kernel_time", "enuf_dpd_footprint_bytes",
+    "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
+    "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
+    "enuf_batch_set_tuning", "enuf_batch_autotune", "enuf_dpd_set_tuning",
 ]
 
 # Status codes (include/enuf.h).

@@ -1,0 +1,87 @@
+"""Batched DPD steps of many independent systems (enuf_batch_* C ABI).
+
+Each member is a DPD integrator (with its own ENUF plan) plus its device
+state tensors; one run advances all members with one kernel launch per stage
+of the step, replayed from a captured HIP graph.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import EnufError, check, lib
+from .plan import _dev_ptr, _device
+
+
+class Batch:
+    def __init__(self, precision="mixed", device=None, use_graph=True, concurrent=True):
+        self.device = _device(device)
+        self.precision = precision
+        pr = {"fp64": _lib.FP64, "mixed": _lib.MIXED}[precision]
+        with torch.cuda.device(self.device):
+            h = lib.enuf_batch_create(pr)
+        if not h:
+            raise EnufError(_lib.EINVAL, "enuf_batch_create")
+        self._h = ctypes.c_void_p(h)
+        self._members = {}   # id -> (dpd, pos, vel, force): keeps the state tensors alive
+        self.set_options(use_graph, concurrent)
+
+    def set_options(self, use_graph=True, concurrent=True):
+        check(lib.enuf_batch_set_options(self._h, int(bool(use_graph)), int(bool(concurrent))),
+              "enuf_batch_set_options")
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.enuf_batch_set_stream(self._h, ctypes.c_void_p(s)), "enuf_batch_set_stream")
+
+    def add(self, dpd, pos, vel, force, first_step):
+        """Add an integrator and its state (force must hold the current force).
+        Returns the member id."""
+        N = dpd.N
+        args = (_dev_ptr(pos, "pos", (N, 3)), _dev_ptr(vel, "vel", (N, 3)), _dev_ptr(force, "force", (N, 3)))
+        self._bind_stream()
+        mid = lib.enuf_batch_add(self._h, dpd._h, *args, int(first_step))
+        if mid < 0:
+            raise EnufError(mid, "enuf_batch_add")
+        self._members[mid] = (dpd, pos, vel, force)
+        return mid
+
+    def remove(self, member_id):
+        check(lib.enuf_batch_remove(self._h, int(member_id)), "enuf_batch_remove")
+        return self._members.pop(member_id)
+
+    def __len__(self):
+        return int(lib.enuf_batch_size(self._h))
+
+    def run(self, nsteps):
+        """Advance every member nsteps steps (ordered on the current stream)."""
+        self._bind_stream()
+        check(lib.enuf_batch_run(self._h, int(nsteps)), "enuf_batch_run")
+
+    def set_tuning(self, pair_lanes):
+        check(lib.enuf_batch_set_tuning(self._h, int(pair_lanes)), "enuf_batch_set_tuning")
+
+    def autotune(self, trial_steps=5):
+        """Pick the fastest launch configuration on the current members; their
+        states are left as they were.  Returns (pair_lanes, concurrent)."""
+        self._bind_stream()
+        lanes, conc = ctypes.c_int(0), ctypes.c_int(0)
+        check(lib.enuf_batch_autotune(self._h, int(trial_steps), ctypes.byref(lanes), ctypes.byref(conc)),
+              "enuf_batch_autotune")
+        return lanes.value, bool(conc.value)
+
+    @property
+    def footprint_bytes(self):
+        return int(lib.enuf_batch_footprint_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.enuf_batch_destroy(self._h)
+            self._h = None
+        self._members = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

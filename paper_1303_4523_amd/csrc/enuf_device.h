@@ -9,6 +9,35 @@ namespace enuf {
 // ---------------------------------------------------------------------------
 // Small math helpers
 // ---------------------------------------------------------------------------
+// Pointers to global memory.  The batched kernels read buffer addresses from
+// a member table in device memory, and a pointer loaded from memory is
+// generic (flat) unless its address space is stated.  Flat loads are counted
+// against LDS traffic too, which would serialise them behind the LDS atomics
+// and queue writes of these kernels, so the kernel bodies take global pointers.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_g(T *p) {
+  return (gptr<T>)p;
+}
+
+// Loads and stores of HIP vector types (double2/4, float2) through global
+// pointers go through their native vector representation.
+template <typename V>
+__device__ __forceinline__ V gload(gptr<const V> p) {
+  V r;
+  get_native_vector(r) = *(gptr<const typename V::Native_vec_>)p;
+  return r;
+}
+template <typename V>
+__device__ __forceinline__ V gload(gptr<V> p) {
+  return gload<V>((gptr<const V>)p);
+}
+template <typename V>
+__device__ __forceinline__ void gstore(gptr<V> p, const V &v) {
+  *(gptr<typename V::Native_vec_>)p = get_native_vector(v);
+}
+
 __device__ inline int mod_pos(int a, int m) {
   int r = a % m;
   return r < 0 ? r + m : r;
@@ -32,7 +61,7 @@ __device__ inline int mesh_cell(double x, double m_over_l, int M, double *t) {
 // SIAM J. Sci. Comput. 2019), fitted on the host to the window above.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline T clenshaw(const T *c, int n, T x) {
+__device__ __forceinline__ T clenshaw(const T *c, int n, T x) {
   T b1 = (T)0, b2 = (T)0;
   const T x2 = x + x;
   for (int k = n; k >= 1; --k) {
@@ -81,7 +110,7 @@ __device__ inline long long to_fixed(double v, double scale) {
 template <typename T> struct MaxBfly { static constexpr int value = 2; };
 
 template <typename T, int R>
-__device__ inline void dft_radix(T *xr, T *xi) {
+__device__ __forceinline__ void dft_radix(T *xr, T *xi) {
   if constexpr (R == 2) {
     T ar = xr[0], ai = xi[0];
     xr[0] = ar + xr[1]; xi[0] = ai + xi[1];
@@ -126,7 +155,7 @@ __device__ inline void dft_radix(T *xr, T *xi) {
 
 // One radix-R pass over `nlines` lines of length n, span Ns before the pass.
 template <typename T, int R>
-__device__ void stockham_pass(T *re, T *im, int ls, int nlines, int n, int Ns, const T *twr,
+__device__ __forceinline__ void stockham_pass(T *re, T *im, int ls, int nlines, int n, int Ns, const T *twr,
                               const T *twi, bool conj_in, bool conj_out) {
   const int nt = blockDim.x, tid = threadIdx.x;
   const int nb = n / R;
@@ -180,7 +209,7 @@ __device__ void stockham_pass(T *re, T *im, int ls, int nlines, int n, int Ns, c
 }
 
 template <typename T>
-__device__ void lds_fft(T *re, T *im, int ls, int nlines, const FftPlan &pl,
+__device__ __forceinline__ void lds_fft(T *re, T *im, int ls, int nlines, const FftPlan &pl,
                         const T *twr, const T *twi, bool inverse) {
   int Ns = 1;
   for (int ps = 0; ps < pl.npass; ++ps) {

@@ -34,16 +34,53 @@ struct DpdCharges {
   int M = 0, xcap = 0;
   double m_over_l = 0.0;
   DevScalars *sc = nullptr;     // plan scalars, rewritten every step
-  unsigned long long *eacc = nullptr;  // plan: real-space energy accumulators (cleared)
   DevScalars stat{};            // nq, sums and fixed-point scale of the fixed charges
 };
+
+// One member system of a batched DPD step (one launch per stage for all
+// members): the geometry and scratch of its ENUF plan, its integrator state
+// and its device step counter.  Kept in device memory; every block of a
+// batched launch reads the member its work-map entry names.
+struct BatchMember {
+  ComputeConfig cfg;
+  ComputeBuffers buf;
+  int nq;                       // charged particles (static compaction)
+  int nblk;                     // blocks of 256 particles (pre, combine)
+  int pair_blocks;              // blocks of the pair kernel at the batch's lanes per particle
+  int real_blocks;              // blocks of the real-space kernel (one wave per charge)
+  double fscale, inv2piL;       // M / (pi L^2), 1 / (2 pi L)
+  int64_t N;
+  DpdParams P;
+  double *pos, *vel, *force;    // caller-owned state
+  double *v0, *fdpd, *e5;
+  int *dcnt;
+  double4 *cpos, *cvel;
+  const int *bond_start, *bond_to;
+  int *status;
+  DpdCharges ch;
+  unsigned long long *step;     // index of the member's next step
+};
+
+// Batched launches: map[b] = (member, block of that member) for block b.
+hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st);
+// Blocks of the pair kernel for N particles at `lanes` (4 or 8) lanes per particle.
+int pair_blocks(int64_t N, int lanes);
+hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
+hipError_t launch_batch_recip(const BatchMember *mem, int precision, const int2 *fwd, int nfwd, const int2 *x,
+                              int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
+                              hipStream_t st);
+// Combine for every member, then the final energies (one block per member).
+hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *map, int nmap, int mode,
+                                hipStream_t st);
+hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hipStream_t st);
 
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
                           const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
                           int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm = nullptr);
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd,
+                           const int *bond_start, const int *bond_to, double *fdpd, int lanes,
                            hipStream_t st, KernelTimer *tm = nullptr);
 hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,

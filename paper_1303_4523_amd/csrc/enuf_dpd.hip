@@ -58,11 +58,11 @@ __device__ inline int dpd_cell_of(double x, double inv_cell, int n) {
 // Each particle is binned into a slot of its DPD cell together with its
 // position (and index) and predicted velocity, so that the pair kernel reads
 // neighbour data contiguously.
-__global__ void __launch_bounds__(256)
-k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__restrict__ vel,
-          const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
-          double4 *cvel, int *status, DpdCharges ch) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void
+dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, double *__restrict__ vel,
+             const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
+             double4 *cvel, int *status, const DpdCharges &ch, int bid) {
+  const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
   if (ch.enabled && i == 0) {
     ch.sc->nq = ch.stat.nq;
     ch.sc->scale = ch.stat.scale;
@@ -70,8 +70,6 @@ k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__
     ch.sc->sum_q = ch.stat.sum_q;
     ch.sc->sum_absq = ch.stat.sum_absq;
     ch.sc->sum_q2 = ch.stat.sum_q2;
-    ch.eacc[0] = 0ull;
-    ch.eacc[1] = 0ull;
   }
   if (i >= N) return;
   double r[3], v[3], f[3], w[3];
@@ -141,64 +139,159 @@ k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__restrict__ vel,
+          const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
+          double4 *cvel, int *status, DpdCharges ch) {
+  dpd_pre_body(N, mode, P, pos, vel, force, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
+}
+
 __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// Four lanes per particle i split the 27 neighbour cells; every pair is
-// evaluated from both of its particles (theta_ij = theta_ji keeps the pair
-// forces antisymmetric), so no thread writes another particle's force.  Sums
-// are exact int64 fixed point (2^-36): the result does not depend on the order
-// in which the pairs are visited.
-__global__ void __launch_bounds__(256)
-k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos,
-           const double *__restrict__ v0, const int *__restrict__ dcnt,
-           const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
-           const int *__restrict__ bond_start, const int *__restrict__ bond_to,
-           double *__restrict__ fdpd) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i64 = g >> 2;
-  const int quad = (int)(g & 3);
-  if (i64 >= N) return;  // whole quads leave together
-  const int i = (int)i64;
+// Q lanes per particle i (Q = 4 or 8; 64/Q particles per wavefront) split
+// the 27 neighbour cells.  Scan: each lane walks the slots of its cells and
+// the pairs with r < R_c = 1 are appended to a wavefront queue in LDS.
+// Evaluation: the whole wavefront takes the queued pairs 64 at a time (so the
+// Philox draw and the pair force run with full lanes however sparse the
+// neighbours are) and adds each pair force to i's int64 fixed-point
+// accumulator in LDS.  Every pair is evaluated from both of its particles
+// (theta_ij = theta_ji keeps the pair forces antisymmetric), so no thread
+// writes another particle's force; the fixed-point sums (2^-36) are exact, so
+// the result does not depend on the order in which pairs are visited.
+constexpr int kPairThreads = 256;
+constexpr int kPairQueue = 128;  // queued pairs per wavefront (flushed at > 64)
+
+template <int Q>
+__device__ __forceinline__ void
+dpd_pair_body(int64_t N, const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
+              gptr<const double> __restrict__ v0, gptr<const int> __restrict__ dcnt,
+              gptr<const double4> __restrict__ cpos, gptr<const double4> __restrict__ cvel,
+              gptr<const int> __restrict__ bond_start, gptr<const int> __restrict__ bond_to,
+              gptr<double> __restrict__ fdpd, int bid) {
+  constexpr int PPW = kWave / Q;
+  constexpr int NW = kPairThreads / kWave;
+  __shared__ int s_qs[NW][kPairQueue];
+  __shared__ int s_ql[NW][kPairQueue];
+  __shared__ double s_rv[NW][PPW][6];
+  __shared__ unsigned long long s_f[NW][PPW][3];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int64_t base = ((int64_t)bid * NW + w) * PPW;
+  if (base >= N) return;  // whole wavefronts leave together
+  const int lp = lane / Q, quad = lane % Q;
+  const bool has = base + lp < N;
+  const int i = (int)(base + lp);
   const double L = P.L, invL = 1.0 / L, isdt = 1.0 / sqrt(P.dt);
-  const double rx = pos[3 * i], ry = pos[3 * i + 1], rz = pos[3 * i + 2];
-  const double vx = v0[3 * i], vy = v0[3 * i + 1], vz = v0[3 * i + 2];
+  int *qs = s_qs[w], *ql = s_ql[w];
+  double rx = 0.0, ry = 0.0, rz = 0.0;
+  if (has) {
+    rx = pos[3 * i];
+    ry = pos[3 * i + 1];
+    rz = pos[3 * i + 2];
+    if (quad < 3) s_f[w][lp][quad] = 0ull;
+    if (quad == 0) {
+      s_rv[w][lp][0] = rx;
+      s_rv[w][lp][1] = ry;
+      s_rv[w][lp][2] = rz;
+      s_rv[w][lp][3] = v0[3 * i];
+      s_rv[w][lp][4] = v0[3 * i + 1];
+      s_rv[w][lp][5] = v0[3 * i + 2];
+    }
+  }
   const int n = P.ncell;
   const int cx = dpd_cell_of(rx, P.inv_cell, n), cy = dpd_cell_of(ry, P.inv_cell, n),
             cz = dpd_cell_of(rz, P.inv_cell, n);
-  long long fx = 0, fy = 0, fz = 0;
-  for (int o = quad; o < 27; o += 4) {
+  // cursor over the lane's cells o = quad, quad + Q, ... and their slots
+  int o = has ? quad : 27, s = 0, cnt = 0;
+  size_t cb = 0;
+  for (; o < 27; o += Q) {
     const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
     if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
     const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-    int cnt = dcnt[c];
+    cnt = dcnt[c];
     cnt = cnt < P.cap ? cnt : P.cap;
-    const double4 *cp = cpos + (size_t)c * P.cap;
-    for (int s = 0; s < cnt; ++s) {
-      const double4 e = cp[s];
+    cb = (size_t)c * P.cap;
+    if (cnt > 0) break;
+  }
+
+  auto flush = [&](int qn) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < qn; e += kWave) {
+      const int l = ql[e];
+      const int slot = qs[e];
+      const int ii = (int)(base + l);
+      const double4 ej = gload(cpos + slot);
+      const double4 vj = gload(cvel + slot);
+      const int j = (int)ej.w;
+      double dx = s_rv[w][l][0] - ej.x, dy = s_rv[w][l][1] - ej.y, dz = s_rv[w][l][2] - ej.z;
+      dx -= L * rint(dx * invL);
+      dy -= L * rint(dy * invL);
+      dz -= L * rint(dz * invL);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r = sqrt(r2), ir = 1.0 / r;
+      const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+      const double wr = 1.0 - r;
+      const double vdot = (s_rv[w][l][3] - vj.x) * ex + (s_rv[w][l][4] - vj.y) * ey + (s_rv[w][l][5] - vj.z) * ez;
+      const double th = dpd_theta(P.seed, step, ii, j);
+      const double mag = P.a * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
+      atomicAdd(&s_f[w][l][0], (unsigned long long)to_fixed(mag * ex, kRealFxScale));
+      atomicAdd(&s_f[w][l][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
+      atomicAdd(&s_f[w][l][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+
+  int qn = 0;  // wavefront-uniform queue length
+  while (true) {
+    const bool live = o < 27;
+    if (__ballot(live) == 0ull) break;
+    bool take = false;
+    int slot = 0;
+    if (live) {
+      const double4 e = gload(cpos + cb + s);
       const int j = (int)e.w;
-      if (j == i) continue;
       double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
       dx -= L * rint(dx * invL);
       dy -= L * rint(dy * invL);
       dz -= L * rint(dz * invL);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      if (!(r2 < 1.0) || r2 == 0.0) continue;
-      const double4 vj = cvel[(size_t)c * P.cap + s];
-      const double r = sqrt(r2), ir = 1.0 / r;
-      const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
-      const double wr = 1.0 - r;
-      const double vdot = (vx - vj.x) * ex + (vy - vj.y) * ey + (vz - vj.z) * ez;
-      const double th = dpd_theta(P.seed, step, i, j);
-      const double mag = P.a * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
-      fx += to_fixed(mag * ex, kRealFxScale);
-      fy += to_fixed(mag * ey, kRealFxScale);
-      fz += to_fixed(mag * ez, kRealFxScale);
+      take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
+      slot = (int)(cb + s);
+      if (++s >= cnt) {  // next non-empty cell of this lane
+        s = 0;
+        for (o += Q; o < 27; o += Q) {
+          const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+          if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
+          const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
+          cnt = dcnt[c];
+          cnt = cnt < P.cap ? cnt : P.cap;
+          cb = (size_t)c * P.cap;
+          if (cnt > 0) break;
+        }
+      }
+    }
+    const unsigned long long m = __ballot(take);
+    if (take) {
+      const int at = qn + (int)__popcll(m & __lanemask_lt());
+      qs[at] = slot;
+      ql[at] = lp;
+    }
+    qn += (int)__popcll(m);
+    if (qn > kPairQueue - kWave) {
+      flush(qn);
+      qn = 0;
     }
   }
+  flush(qn);
+
   // harmonic bonds of i, F_i = -K (r - r0) rhat_ij
-  if (quad == 0) {
+  if (has && quad == 0) {
+    long long fx = (long long)s_f[w][lp][0], fy = (long long)s_f[w][lp][1], fz = (long long)s_f[w][lp][2];
     for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
       const int j = bond_to[b];
       double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
@@ -212,18 +305,26 @@ k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos
       fy += to_fixed(mag * dy, kRealFxScale);
       fz += to_fixed(mag * dz, kRealFxScale);
     }
-  }
-  fx += __shfl_xor(fx, 1, kWave);
-  fy += __shfl_xor(fy, 1, kWave);
-  fz += __shfl_xor(fz, 1, kWave);
-  fx += __shfl_xor(fx, 2, kWave);
-  fy += __shfl_xor(fy, 2, kWave);
-  fz += __shfl_xor(fz, 2, kWave);
-  if (quad == 0) {
     fdpd[3 * i] = (double)fx * kRealFxInv;
     fdpd[3 * i + 1] = (double)fy * kRealFxInv;
     fdpd[3 * i + 2] = (double)fz * kRealFxInv;
   }
+}
+
+template <int Q>
+__global__ void __launch_bounds__(kPairThreads)
+k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos,
+           const double *__restrict__ v0, const int *__restrict__ dcnt,
+           const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
+           const int *__restrict__ bond_start, const int *__restrict__ bond_to,
+           double *__restrict__ fdpd) {
+  dpd_pair_body<Q>(N, P, step, to_g(pos), to_g(v0), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start),
+                   to_g(bond_to), to_g(fdpd), blockIdx.x);
+}
+
+int pair_blocks(int64_t N, int lanes) {
+  const int64_t per_block = (int64_t)(kPairThreads / lanes);
+  return (int)((N + per_block - 1) / per_block);
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -245,6 +346,49 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched DPD kernels: one launch covers every member of a batch.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+kb_dpd_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, int mode) {
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  dpd_pre_body(m.N, mode, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt, m.cpos, m.cvel, m.status, m.ch, w.y);
+}
+
+template <int Q>
+__global__ void __launch_bounds__(kPairThreads)
+kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  dpd_pair_body<Q>(m.N, m.P, *m.step, to_g(m.pos), to_g(m.v0), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
+                   to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y);
+}
+
+__global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
+  if (threadIdx.x == 0) dst[0] = value;
+}
+
+hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st) {
+  if (nmap > 0) hipLaunchKernelGGL(kb_dpd_pre, dim3(nmap), dim3(256), 0, st, mem, map, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st) {
+  if (nmap > 0) {
+    if (lanes == 8)
+      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), 0, st, mem, map);
+    else
+      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), 0, st, mem, map);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, dst, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
                           const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
                           int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
@@ -258,12 +402,16 @@ hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, 
 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd,
+                           const int *bond_start, const int *bond_to, double *fdpd, int lanes,
                            hipStream_t st, KernelTimer *tm) {
-  const int nb = (int)((4 * N + 255) / 256);
+  const int nb = pair_blocks(N, lanes);
   if (tm) tm->before(1, st);
-  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(256), 0, st, N, P, step, pos, v0, dcnt, cpos, cvel,
-                     bond_start, bond_to, fdpd);
+  if (lanes == 8)
+    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), 0, st, N, P, step, pos, v0, dcnt, cpos,
+                       cvel, bond_start, bond_to, fdpd);
+  else
+    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), 0, st, N, P, step, pos, v0, dcnt, cpos,
+                       cvel, bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }

@@ -91,7 +91,6 @@ struct ComputeBuffers {
   // preparation
   int *blk_cnt;          // [nblk]
   double *blk_sums;      // [nblk * 3]
-  unsigned *done;        // [2] last-block tickets (prep, combine)
   DevScalars *sc;
   double4 *xq;           // [N] compacted (x, y, z, q), wrapped into [0, L)
   int *idx;              // [N] particle index of compact slot j
@@ -101,7 +100,8 @@ struct ComputeBuffers {
   double4 *cgrid;        // [ncell^3 * cap] (x, y, z, q) per cell slot
   int *cidx;             // [ncell^3 * cap] compact index per cell slot
   unsigned long long *freal;  // [N * 3] fixed-point real-space force per compact slot
-  unsigned long long *eacc;  // [2] fixed-point E_real (whole), E_slater
+  unsigned long long *ereal; // [2 N] fixed-point (E_real whole, E_slater) of the pairs (j, k > j), per compact slot j
+  long long *blk_er;         // [2 nblk] per-block sums of ereal over the particles of the block
   // reciprocal
   void *gzy;             // [M * nky * Kc] complex (double2 or float2)
   double *epart;         // [nky] k-space energy per ky row

@@ -17,6 +17,7 @@
 // Accumulations that cross threads are either fixed-order reductions or exact
 // int64 fixed-point sums, so results are bitwise reproducible.
 #include "enuf_device.h"
+#include "enuf_dpd.h"
 
 namespace enuf {
 
@@ -52,6 +53,17 @@ __device__ int block_sum_int(int v, int *scratch) {
   return s;
 }
 
+__device__ long long block_sum_ll(long long v, long long *scratch) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  v = wave_sum_ll(v);
+  __syncthreads();
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  long long s = 0;
+  for (int i = 0; i < nw; ++i) s += scratch[i];
+  return s;
+}
+
 __device__ inline double wrap_coord(double x, double L) {
   double y = x - L * floor(x / L);
   if (!(y < L) || y < 0.0) y = 0.0;
@@ -59,13 +71,18 @@ __device__ inline double wrap_coord(double x, double L) {
 }
 
 __device__ inline void set_status(DevScalars *sc, int code) { atomicCAS(&sc->status, 0, code); }
+__device__ inline void set_status(gptr<DevScalars> sc, int code) {
+  int expected = 0;
+  __hip_atomic_compare_exchange_strong(&sc->status, &expected, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Preparation
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kPrepThreads)
 k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, int ncell3, int *xcnt,
-             int M, unsigned long long *eacc) {
+             int M) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int flag = (i < N) && (q[i] != 0.0);
   const int c = __syncthreads_count(flag);
@@ -73,19 +90,16 @@ k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, i
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < ncell3; k += stride) ccnt[k] = 0;
   for (int64_t k = i; k < M; k += stride) xcnt[k] = 0;
-  if (i < 2) eacc[i] = 0ull;
 }
 
 __global__ void __launch_bounds__(kPrepThreads)
 k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
                double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
                double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
-               int *cidx, int *xcnt, int *xslot, int M, double m_over_l, int xcap, unsigned *done,
-               DevScalars *sc) {
+               int *cidx, int *xcnt, int *xslot, int M, double m_over_l, int xcap, DevScalars *sc) {
   __shared__ int s_int[kPrepThreads / kWave];
   __shared__ int s_wcnt[kPrepThreads / kWave];
   __shared__ double s_dbl[kPrepThreads / kWave];
-  __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
 
@@ -153,39 +167,40 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
     blk_sums[3 * blockIdx.x] = sq;
     blk_sums[3 * blockIdx.x + 1] = sa;
     blk_sums[3 * blockIdx.x + 2] = s2;
-    __threadfence();
-    const unsigned t = atomicAdd(&done[0], 1u);
-    s_last = (t == (unsigned)nblk - 1);
   }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    double a = 0.0, b = 0.0, c = 0.0;
-    int nq = 0;
-    for (int k = tid; k < nblk; k += blockDim.x) {
-      a += blk_sums[3 * k];
-      b += blk_sums[3 * k + 1];
-      c += blk_sums[3 * k + 2];
-      nq += blk_cnt[k];
-    }
-    a = block_sum(a, s_dbl);
-    b = block_sum(b, s_dbl);
-    c = block_sum(c, s_dbl);
-    nq = block_sum_int(nq, s_int);
-    if (tid == 0) {
-      sc->nq = nq;
-      sc->sum_q = a;
-      sc->sum_absq = b;
-      sc->sum_q2 = c;
-      // Mesh values are bounded by sum |q| (the window is <= 1): choose the
-      // largest power of two keeping sum|q| * scale below 2^61.
-      int e;
-      frexp(b + 1.0, &e);
-      sc->scale = ldexp(1.0, 61 - e);
-      sc->inv_scale = ldexp(1.0, e - 61);
-      if (fabs(a) > 1e-10 * b) set_status(sc, kENonNeutral);
-      done[0] = 0u;
-    }
+}
+
+// Sums of the charges, their count and the fixed-point scale of the mesh
+// accumulator from the per-block partials of the compaction (one block).
+__global__ void __launch_bounds__(kPrepThreads)
+k_prep_finish(int nblk, const int *__restrict__ blk_cnt, const double *__restrict__ blk_sums, DevScalars *sc) {
+  __shared__ int s_int[kPrepThreads / kWave];
+  __shared__ double s_dbl[kPrepThreads / kWave];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0;
+  int nq = 0;
+  for (int k = tid; k < nblk; k += blockDim.x) {
+    a += blk_sums[3 * k];
+    b += blk_sums[3 * k + 1];
+    c += blk_sums[3 * k + 2];
+    nq += blk_cnt[k];
+  }
+  a = block_sum(a, s_dbl);
+  b = block_sum(b, s_dbl);
+  c = block_sum(c, s_dbl);
+  nq = block_sum_int(nq, s_int);
+  if (tid == 0) {
+    sc->nq = nq;
+    sc->sum_q = a;
+    sc->sum_absq = b;
+    sc->sum_q2 = c;
+    // Mesh values are bounded by sum |q| (the window is <= 1): choose the
+    // largest power of two keeping sum|q| * scale below 2^61.
+    int e;
+    frexp(b + 1.0, &e);
+    sc->scale = ldexp(1.0, 61 - e);
+    sc->inv_scale = ldexp(1.0, e - 61);
+    if (fabs(a) > 1e-10 * b) set_status(sc, kENonNeutral);
   }
 }
 
@@ -246,65 +261,126 @@ __device__ inline bool cell_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// One wavefront per charge j: lanes 0..53 take one of the 27 neighbour cells
-// and every other slot in it.  The wavefront sums the forces of all pairs of j
-// (each pair is evaluated from both of its charges, so no thread writes
-// another charge's force) and the energy of the pairs with k > j.  All sums
-// are exact int64 fixed point.
-__global__ void __launch_bounds__(256)
-k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
-       const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
-       DevScalars *sc, unsigned long long *freal, unsigned long long *eacc) {
+// One wavefront per charge j.  Scan: lanes 0..53 take one of the 27
+// neighbour cells and every other slot in it; the pairs within r_cut are
+// appended to a wavefront queue in LDS (with their minimum-image offsets).
+// Evaluation: the whole wavefront takes the queued pairs 64 at a time, so
+// the erfc / Slater terms run with full lanes however the pairs are spread
+// over the cells.  The wavefront sums the forces of all pairs of j (each pair
+// is evaluated from both of its charges, so no thread writes another charge's
+// force) and the energy of the pairs with k > j, as exact int64 fixed point;
+// the energies go to j's own slot (no shared accumulator).
+constexpr int kRealThreads = 256;
+constexpr int kRealQueue = 128;  // queued pairs per wavefront (flushed at > 64)
+
+__device__ __forceinline__ void real_flush(int qn, const double *qx, const double *qy, const double *qz,
+                                           const double *qc, const int *qk, int j, double qj, double alpha,
+                                           double lam, long long &fx,
+                                           long long &fy, long long &fz, long long &ee, long long &es,
+                                           int &err) {
   const int lane = threadIdx.x & (kWave - 1);
+  for (int e = lane; e < qn; e += kWave) {
+    const double dx = qx[e], dy = qy[e], dz = qz[e];
+    const int k = qk[e];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double u, us, f;
+    if (!real_pair(sqrt(r2), alpha, lam, &u, &us, &f)) {
+      err = kECoincident;
+      continue;
+    }
+    const double qq = qj * qc[e];
+    const double g = qq * f;
+    if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
+    fx += to_fixed(g * dx, kRealFxScale);
+    fy += to_fixed(g * dy, kRealFxScale);
+    fz += to_fixed(g * dz, kRealFxScale);
+    if (k > j) {
+      ee += to_fixed(qq * u, kRealFxScale);
+      es += to_fixed(qq * us, kRealFxScale);
+    }
+  }
+}
+
+__device__ __forceinline__ void
+real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt,
+          gptr<const double4> __restrict__ cgrid, gptr<const int> __restrict__ cidx, const CellParams &cp,
+          double L, double alpha, double rc2, double lam, gptr<DevScalars> sc, gptr<unsigned long long> freal,
+          gptr<unsigned long long> ereal, int bid, int nbid) {
+  __shared__ double s_qx[kRealThreads / kWave][kRealQueue], s_qy[kRealThreads / kWave][kRealQueue],
+      s_qz[kRealThreads / kWave][kRealQueue];
+  __shared__ double s_qc[kRealThreads / kWave][kRealQueue];
+  __shared__ int s_qk[kRealThreads / kWave][kRealQueue];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
+  double *qx = s_qx[w], *qy = s_qy[w], *qz = s_qz[w];
+  double *qc = s_qc[w];
+  int *qk = s_qk[w];
   const int nq = sc->nq;
   const double invL = 1.0 / L;
-  for (int j = blockIdx.x * wpb + threadIdx.x / kWave; j < nq; j += gridDim.x * wpb) {
-    const double4 ci = xq[j];
+  for (int j = bid * wpb + w; j < nq; j += nbid * wpb) {
+    const double4 ci = gload(xq + j);
     int cx = (int)(ci.x * cp.inv_cell), cy = (int)(ci.y * cp.inv_cell), cz = (int)(ci.z * cp.inv_cell);
     cx = cx < cp.ncell ? cx : cp.ncell - 1;
     cy = cy < cp.ncell ? cy : cp.ncell - 1;
     cz = cz < cp.ncell ? cz : cp.ncell - 1;
     long long fx = 0, fy = 0, fz = 0, ee = 0, es = 0;
     int err = 0;
+    int c = -1, cnt = 0, s = lane / 27;
     if (lane < 54) {
-      const int o = lane % 27, par = lane / 27;
+      const int o = lane % 27;
       const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
       const int n = cp.ncell;
       if (cell_offset_valid(ox, n) && cell_offset_valid(oy, n) && cell_offset_valid(oz, n)) {
-        const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-        int cnt = ccnt[c];
+        c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
+        cnt = ccnt[c];
         cnt = cnt < cp.cap ? cnt : cp.cap;
-        const double4 *cg = cgrid + (size_t)c * cp.cap;
-        const int *ck = cidx + (size_t)c * cp.cap;
-        for (int s = par; s < cnt; s += 2) {
-          const int k = ck[s];
-          if (k == j) continue;
-          const double4 cj = cg[s];
-          double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-          dx -= L * rint(dx * invL);
-          dy -= L * rint(dy * invL);
-          dz -= L * rint(dz * invL);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (!(r2 < rc2)) continue;
-          double u, us, f;
-          if (!real_pair(sqrt(r2), alpha, lam, &u, &us, &f)) {
-            err = kECoincident;
-            continue;
-          }
-          const double qq = ci.w * cj.w;
-          const double g = qq * f;
-          if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
-          fx += to_fixed(g * dx, kRealFxScale);
-          fy += to_fixed(g * dy, kRealFxScale);
-          fz += to_fixed(g * dz, kRealFxScale);
-          if (k > j) {
-            ee += to_fixed(qq * u, kRealFxScale);
-            es += to_fixed(qq * us, kRealFxScale);
-          }
-        }
       }
     }
+    const size_t cbase = (size_t)(c < 0 ? 0 : c) * cp.cap;
+    int qn = 0;  // wavefront-uniform queue length
+    while (true) {
+      const bool live = s < cnt;
+      if (__ballot(live) == 0ull) break;
+      bool take = false;
+      int k = 0;
+      double dx = 0.0, dy = 0.0, dz = 0.0, qo = 0.0;
+      if (live) {
+        k = cidx[cbase + s];
+        const double4 cj = gload(cgrid + cbase + s);
+        dx = ci.x - cj.x;
+        dy = ci.y - cj.y;
+        dz = ci.z - cj.z;
+        qo = cj.w;
+        dx -= L * rint(dx * invL);
+        dy -= L * rint(dy * invL);
+        dz -= L * rint(dz * invL);
+        take = (k != j) && (dx * dx + dy * dy + dz * dz < rc2);
+      }
+      const unsigned long long m = __ballot(take);
+      if (take) {
+        const int at = qn + (int)__popcll(m & __lanemask_lt());
+        qx[at] = dx;
+        qy[at] = dy;
+        qz[at] = dz;
+        qc[at] = qo;
+        qk[at] = k;
+      }
+      s += 2;
+      qn += (int)__popcll(m);
+      if (qn > kRealQueue - kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        real_flush(qn, qx, qy, qz, qc, qk, j, ci.w, alpha, lam, fx, fy, fz, ee, es, err);
+        __builtin_amdgcn_wave_barrier();
+        qn = 0;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    real_flush(qn, qx, qy, qz, qc, qk, j, ci.w, alpha, lam, fx, fy, fz, ee, es, err);
+    __builtin_amdgcn_wave_barrier();
     if (err) set_status(sc, err);
     fx = wave_sum_ll(fx);
     fy = wave_sum_ll(fy);
@@ -315,10 +391,18 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
       freal[3 * (size_t)j] = (unsigned long long)fx;
       freal[3 * (size_t)j + 1] = (unsigned long long)fy;
       freal[3 * (size_t)j + 2] = (unsigned long long)fz;
-      atomicAdd(&eacc[0], (unsigned long long)ee);
-      atomicAdd(&eacc[1], (unsigned long long)es);
+      ereal[2 * (size_t)j] = (unsigned long long)ee;
+      ereal[2 * (size_t)j + 1] = (unsigned long long)es;
     }
   }
+}
+
+__global__ void __launch_bounds__(kRealThreads)
+k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
+       const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
+       DevScalars *sc, unsigned long long *freal, unsigned long long *ereal) {
+  real_body(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
+            to_g(ereal), blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,7 +425,7 @@ struct PlaneCharges {
 };
 
 // Fill the LDS prefix sums of the plane's 2p x-bins; returns the charge count.
-__device__ inline int plane_bins(int x0, int M, int p, const int *__restrict__ xcnt, int xcap, int *pre,
+__device__ inline int plane_bins(int x0, int M, int p, gptr<const int> __restrict__ xcnt, int xcap, int *pre,
                                  int *cell) {
   const int P2 = 2 * p;
   if (threadIdx.x < P2) {
@@ -360,7 +444,7 @@ __device__ inline int plane_bins(int x0, int M, int p, const int *__restrict__ x
 }
 
 // Offsets of charge e of the plane: x-bin b, and the compact index.
-__device__ inline int plane_charge(int e, int P2, const int *pre, const int *cell, const int *__restrict__ xslot,
+__device__ inline int plane_charge(int e, int P2, const int *pre, const int *cell, gptr<const int> __restrict__ xslot,
                                    int xcap, int *b_out) {
   int b = 0;
   while (b < P2 - 1 && e >= pre[b + 1]) ++b;
@@ -387,16 +471,16 @@ __device__ inline int cell_frac(double x, double m_over_l, int M, double *frac) 
 __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 template <typename T>
-__global__ void __launch_bounds__(kPassThreads)
-k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
-            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
-            const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
+__device__ __forceinline__ void
+recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ xcnt,
+               gptr<const int> __restrict__ xslot, gptr<const T> __restrict__ wcoef,
+               gptr<const DevScalars> __restrict__ sc, const MeshParams &mp,
+               gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<typename CplxOf<T>::type> gzy, int x0) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p, D = mp.cheb_deg;
   const int R = mp.rows;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
-  const int x0 = blockIdx.x;
 
   long long *acc = reinterpret_cast<long long *>(smem);
   T *plane = reinterpret_cast<T *>(smem);
@@ -413,8 +497,9 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
   int *bcell = pre + P2 + 1;
 
   for (int m = tid; m < M; m += nt) {
-    twr[m] = tw[m].x;
-    twi[m] = tw[m].y;
+    const typename CplxOf<T>::type t = gload(tw + m);
+    twr[m] = t.x;
+    twi[m] = t.y;
   }
   for (int k = tid; k < P2 * (D + 1); k += nt) cv[k] = wcoef[k];
   const double scale = sc->scale, inv_scale = sc->inv_scale;
@@ -436,7 +521,7 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
       if (has) {
         int b;
         const int j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-        const double4 c = xq[j];
+        const double4 c = gload(xq + j);
         double fx, fy, fz;
         cell_frac(c.x, mp.m_over_l, M, &fx);
         const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
@@ -520,22 +605,30 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
     typename CplxOf<T>::type v;
     v.x = Zre[kz * Mz + m];
     v.y = Zim[kz * Mz + m];
-    gzy[((size_t)x0 * nky + kyi) * Kc + kz] = v;
+    gstore(gzy + ((size_t)x0 * nky + kyi) * Kc + kz, v);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
+            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
+            const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
+  recip_fwd_body<T>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Mesh pass 2: x FFT, influence multiply + energy, inverse x FFT for one ky.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kPassThreads)
-k_recip_x(MeshParams mp, const double *__restrict__ atab,
-          const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy,
-          double *epart) {
+__device__ __forceinline__ void
+recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
+             gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<typename CplxOf<T>::type> gzy,
+             gptr<double> epart, int kyi) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int kyi = blockIdx.x, ky = kyi - (Kc - 1);
+  const int ky = kyi - (Kc - 1);
   T *Xre = reinterpret_cast<T *>(smem);
   T *Xim = Xre + (size_t)Kc * Mz;
   T *twr = Xim + (size_t)Kc * Mz;
@@ -548,13 +641,14 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
   while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
 
   for (int m = tid; m < M; m += nt) {
-    twr[m] = tw[m].x;
-    twi[m] = tw[m].y;
+    const typename CplxOf<T>::type t = gload(tw + m);
+    twr[m] = t.x;
+    twi[m] = t.y;
   }
   for (int k = tid; k < nky; k += nt) at[k] = atab[k];
   for (int id = tid; id < M * nkz; id += nt) {
     const int x = id / nkz, kz = id % nkz;
-    const typename CplxOf<T>::type v = gzy[((size_t)x * nky + kyi) * Kc + kz];
+    const typename CplxOf<T>::type v = gload(gzy + ((size_t)x * nky + kyi) * Kc + kz);
     Xre[kz * Mz + x] = v.x;
     Xim[kz * Mz + x] = v.y;
   }
@@ -587,8 +681,16 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
     typename CplxOf<T>::type v;
     v.x = kz < nkz ? Xre[kz * Mz + x] : (T)0;
     v.y = kz < nkz ? Xim[kz * Mz + x] : (T)0;
-    gzy[((size_t)x * nky + kyi) * Kc + kz] = v;
+    gstore(gzy + ((size_t)x * nky + kyi) * Kc + kz, v);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_x(MeshParams mp, const double *__restrict__ atab,
+          const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy,
+          double *epart) {
+  recip_x_body<T>(mp, to_g(atab), to_g(tw), to_g(gzy), to_g(epart), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,17 +699,17 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
 // its derivative (shared across the group); the group reduces with shuffles.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kPassThreads)
-k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
-            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
-            const typename CplxOf<T>::type *__restrict__ tw,
-            const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
+__device__ __forceinline__ void
+recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ xcnt,
+               gptr<const int> __restrict__ xslot, gptr<const T> __restrict__ wcoef,
+               gptr<const DevScalars> __restrict__ sc, const MeshParams &mp,
+               gptr<const typename CplxOf<T>::type> __restrict__ tw,
+               gptr<const typename CplxOf<T>::type> __restrict__ gzy, gptr<double4> part, int x0) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
   const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
-  const int x0 = blockIdx.x;
 
   T *plane = reinterpret_cast<T *>(smem);  // [rows][Mp]
   size_t off = align16((size_t)R * Mp * sizeof(T));
@@ -624,8 +726,9 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
   int *bcell = pre + P2 + 1;
 
   for (int m = tid; m < M; m += nt) {
-    twr[m] = tw[m].x;
-    twi[m] = tw[m].y;
+    const typename CplxOf<T>::type t = gload(tw + m);
+    twr[m] = t.x;
+    twi[m] = t.y;
   }
   for (int k = tid; k < P2 * (2 * D + 1); k += nt) cv[k] = wcoef[k];
   for (int k = tid; k < 2 * Kc * Mz; k += nt) Zre[k] = (T)0;
@@ -633,7 +736,7 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
   for (int id = tid; id < nky * Kc; id += nt) {
     const int kyi = id / Kc, kz = id % Kc;
     const int m = mod_pos(kyi - (Kc - 1), M);
-    const typename CplxOf<T>::type v = gzy[((size_t)x0 * nky + kyi) * Kc + kz];
+    const typename CplxOf<T>::type v = gload(gzy + ((size_t)x0 * nky + kyi) * Kc + kz);
     Zre[kz * Mz + m] = v.x;
     Zim[kz * Mz + m] = v.y;
   }
@@ -683,7 +786,7 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
         int b;
         j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
         sx = P2 - 1 - b;
-        const double4 c = xq[j];
+        const double4 c = gload(xq + j);
         double fx, fy, fz;
         cell_frac(c.x, mp.m_over_l, M, &fx);
         cy = cell_frac(c.y, mp.m_over_l, M, &fy);
@@ -727,17 +830,17 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
       if (has && sy == 0) {
         const double4 v = make_double4((double)(dwx * A), (double)(wx * By), (double)(wx * Bz),
                                        (double)(wx * A));
-        double4 *dst = part + ((size_t)j * P2 + sx) * nslot;
+        const gptr<double4> dst = part + ((size_t)j * P2 + sx) * nslot;
         if (nslot == 1) {
-          dst[0] = v;
+          gstore(dst, v);
         } else {
           // chunk of the charge's first and last stencil rows
           const int first = mod_pos(cy - p + 1, M) / R, last = mod_pos(cy + p, M) / R;
           if (chunk == first) {
-            dst[0] = v;
-            if (first == last) dst[1] = make_double4(0.0, 0.0, 0.0, 0.0);
+            gstore(dst, v);
+            if (first == last) gstore(dst + 1, make_double4(0.0, 0.0, 0.0, 0.0));
           } else if (chunk == last) {
-            dst[1] = v;
+            gstore(dst + 1, v);
           }
         }
       }
@@ -746,42 +849,54 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
+            const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
+            const typename CplxOf<T>::type *__restrict__ tw,
+            const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
+  recip_bwd_body<T>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy), to_g(part),
+                    blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
-// Combine: forces per particle and the final energies (last block).
+// Combine: forces per particle and per-block energy partials.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kPrepThreads)
-k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
-          unsigned long long *freal, const double4 *__restrict__ part, int P2S,
-          double fscale, double inv2piL, double alpha, int nblk, double *blk_eg, unsigned *done,
-          const double *__restrict__ epart, int nky, const unsigned long long *eacc,
-          const DevScalars *sc, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
-          double *energy, double *energy5) {
+__device__ __forceinline__ void
+combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> __restrict__ xq,
+             gptr<const unsigned long long> freal, gptr<const double4> __restrict__ part, int P2S,
+             double fscale, int nblk, double *blk_eg, gptr<const unsigned long long> __restrict__ ereal,
+             long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, const FinishArgs &fa, double *forces,
+             int bid) {
   __shared__ double s_dbl[kPrepThreads / kWave];
-  __shared__ int s_last;
+  __shared__ long long s_ll[kPrepThreads / kWave];
   const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int64_t i = (int64_t)bid * blockDim.x + tid;
   {
     // cell counts are left cleared for the next evaluation (their consumers ran before)
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = (int64_t)nblk * blockDim.x;
     for (int64_t c = i; c < ncell3; c += stride) ccnt[c] = 0;
     for (int64_t c = i; c < M; c += stride) xcnt[c] = 0;
     if (fa.mode >= 0)
       for (int64_t c = i; c < fa.ndcell3; c += stride) fa.dcnt[c] = 0;
   }
   double eg = 0.0;
+  long long er = 0, esl = 0;
   if (i < N) {
     const int j = slot[i];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (j >= 0) {
+      er = (long long)ereal[2 * (size_t)j];
+      esl = (long long)ereal[2 * (size_t)j + 1];
       double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
       for (int s = 0; s < P2S; ++s) {
-        const double4 v = part[(size_t)j * P2S + s];
+        const double4 v = gload(part + (size_t)j * P2S + s);
         bx += v.x;
         by += v.y;
         bz += v.z;
         a += v.w;
       }
-      const double qj = xq[j].w;
+      const double qj = gload(xq + j).w;
       fx = (double)(long long)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
       fy = (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
       fz = (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
@@ -802,36 +917,180 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
     }
   }
   eg = block_sum(eg, s_dbl);
+  er = block_sum_ll(er, s_ll);
+  esl = block_sum_ll(esl, s_ll);
   if (tid == 0) {
-    blk_eg[blockIdx.x] = eg;
-    __threadfence();
-    const unsigned t = atomicAdd(&done[1], 1u);
-    s_last = (t == (unsigned)nblk - 1);
+    blk_eg[bid] = eg;
+    blk_er[2 * bid] = er;
+    blk_er[2 * bid + 1] = esl;
   }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    double g = 0.0, k = 0.0;
-    for (int b = tid; b < nblk; b += blockDim.x) g += blk_eg[b];
-    for (int b = tid; b < nky; b += blockDim.x) k += epart[b];
-    g = block_sum(g, s_dbl);
-    k = block_sum(k, s_dbl);
-    if (tid == 0) {
-      const double e_real = (double)(long long)eacc[0] * kRealFxInv;
-      const double e_sl = (double)(long long)eacc[1] * kRealFxInv;
-      const double e_rec = k * inv2piL;
-      const double e_self = -alpha * 0.56418958354775628695 * sc->sum_q2;  // 1/sqrt(pi)
-      if (energy) energy[0] = e_real + e_rec + e_self;
-      if (energy5) {
-        energy5[0] = e_real;
-        energy5[1] = e_sl;
-        energy5[2] = e_rec;
-        energy5[3] = e_self;
-        energy5[4] = g * inv2piL;
-      }
-      done[1] = 0u;
+}
+
+// Final energies of one evaluation from the per-block partials of the combine
+// kernel and the per-ky k-space sums (one block; a separate launch, so the
+// partials of every combine block are visible without a device-wide fence).
+__device__ __forceinline__ void finish_body(int nblk, const double *__restrict__ blk_eg,
+                                            const long long *__restrict__ blk_er,
+                                            const double *__restrict__ epart, int nky,
+                                            const DevScalars *__restrict__ sc, double alpha, double inv2piL,
+                                            double *energy, double *energy5, unsigned long long *step) {
+  __shared__ double s_dbl[kPrepThreads / kWave];
+  __shared__ long long s_ll[kPrepThreads / kWave];
+  const int tid = threadIdx.x;
+  double g = 0.0, k = 0.0;
+  long long tr = 0, ts = 0;
+  for (int b = tid; b < nblk; b += blockDim.x) {
+    g += blk_eg[b];
+    tr += blk_er[2 * b];
+    ts += blk_er[2 * b + 1];
+  }
+  for (int b = tid; b < nky; b += blockDim.x) k += epart[b];
+  g = block_sum(g, s_dbl);
+  k = block_sum(k, s_dbl);
+  tr = block_sum_ll(tr, s_ll);
+  ts = block_sum_ll(ts, s_ll);
+  if (tid == 0) {
+    const double e_real = (double)tr * kRealFxInv;
+    const double e_sl = (double)ts * kRealFxInv;
+    const double e_rec = k * inv2piL;
+    const double e_self = -alpha * 0.56418958354775628695 * sc->sum_q2;  // 1/sqrt(pi)
+    if (energy) energy[0] = e_real + e_rec + e_self;
+    if (energy5) {
+      energy5[0] = e_real;
+      energy5[1] = e_sl;
+      energy5[2] = e_rec;
+      energy5[3] = e_self;
+      energy5[4] = g * inv2piL;
     }
+    if (step) step[0] += 1ull;
   }
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+k_finish(int nblk, const double *__restrict__ blk_eg, const long long *__restrict__ blk_er,
+         const double *__restrict__ epart, int nky, const DevScalars *__restrict__ sc, double alpha,
+         double inv2piL, double *energy, double *energy5) {
+  finish_body(nblk, blk_eg, blk_er, epart, nky, sc, alpha, inv2piL, energy, energy5, nullptr);
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
+          const unsigned long long *freal, const double4 *__restrict__ part, int P2S, double fscale, int nblk,
+          double *blk_eg, const unsigned long long *__restrict__ ereal, long long *blk_er, int *ccnt, int ncell3,
+          int *xcnt, int M, FinishArgs fa, double *forces) {
+  combine_body(N, to_g(slot), to_g(xq), to_g(freal), to_g(part), P2S, fscale, nblk, blk_eg, to_g(ereal), blk_er,
+               ccnt, ncell3, xcnt, M, fa, forces, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels: one launch covers every member of a batch; block b works
+// on block map[b].y of member map[b].x with that member's geometry and buffers.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kRealThreads)
+kb_real(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  real_body(to_g(m.buf.xq), to_g(m.buf.ccnt), to_g(m.buf.cgrid), to_g(m.buf.cidx), m.cfg.cells, m.cfg.L,
+            m.cfg.alpha, m.cfg.r_cut * m.cfg.r_cut, m.cfg.lambda, to_g(m.buf.sc), to_g(m.buf.freal),
+            to_g(m.buf.ereal), w.y, m.real_blocks);
+}
+
+template <typename T> struct MemberTables;
+template <> struct MemberTables<double> {
+  static __device__ const double *wcoef(const ComputeBuffers &b) { return b.wcoef64; }
+  static __device__ const double2 *tw(const ComputeBuffers &b) { return b.tw64; }
+};
+template <> struct MemberTables<float> {
+  static __device__ const float *wcoef(const ComputeBuffers &b) { return b.wcoef32; }
+  static __device__ const float2 *tw(const ComputeBuffers &b) { return b.tw32; }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+kb_recip_fwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  using C = typename CplxOf<T>::type;
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  recip_fwd_body<T>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
+                    to_g(m.buf.sc), m.cfg.mesh, to_g(MemberTables<T>::tw(m.buf)),
+                    to_g(reinterpret_cast<C *>(m.buf.gzy)), w.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+kb_recip_x(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  using C = typename CplxOf<T>::type;
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  recip_x_body<T>(m.cfg.mesh, to_g(m.buf.atab), to_g(MemberTables<T>::tw(m.buf)),
+                  to_g(reinterpret_cast<C *>(m.buf.gzy)), to_g(m.buf.epart), w.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPassThreads)
+kb_recip_bwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  using C = typename CplxOf<T>::type;
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  recip_bwd_body<T>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
+                    to_g(m.buf.sc), m.cfg.mesh, to_g(MemberTables<T>::tw(m.buf)),
+                    to_g(reinterpret_cast<const C *>(m.buf.gzy)), to_g(m.buf.part), w.y);
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+kb_combine(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, int mode) {
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  FinishArgs fa;
+  fa.mode = mode;
+  fa.kappa = m.P.kappa;
+  fa.dt = m.P.dt;
+  fa.fdpd = m.fdpd;
+  fa.vel = m.vel;
+  fa.dcnt = m.dcnt;
+  fa.ndcell3 = m.P.ncell * m.P.ncell * m.P.ncell;
+  const int nc = m.cfg.cells.ncell;
+  combine_body(m.N, to_g(m.buf.slot), to_g(m.buf.xq), to_g(m.buf.freal), to_g(m.buf.part),
+               2 * m.cfg.mesh.win.p * m.cfg.mesh.nslot, m.fscale, m.nblk, m.buf.blk_eg, to_g(m.buf.ereal),
+               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M, fa, m.force, w.y);
+}
+
+__global__ void __launch_bounds__(kPrepThreads)
+kb_finish(const BatchMember *__restrict__ mem, int mode) {
+  const BatchMember &m = mem[blockIdx.x];
+  finish_body(m.nblk, m.buf.blk_eg, m.buf.blk_er, m.buf.epart, m.cfg.mesh.nky, m.buf.sc, m.cfg.alpha, m.inv2piL,
+              nullptr, m.e5, mode == 0 ? m.step : nullptr);
+}
+
+hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st) {
+  if (nmap > 0) hipLaunchKernelGGL(kb_real, dim3(nmap), dim3(kRealThreads), 0, st, mem, map);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void launch_batch_mesh(const BatchMember *mem, const int2 *fwd, int nfwd, const int2 *x, int nx,
+                              const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
+                              hipStream_t st) {
+  if (nfwd > 0) hipLaunchKernelGGL(kb_recip_fwd<T>, dim3(nfwd), dim3(kPassThreads), lds_fwd, st, mem, fwd);
+  if (nx > 0) hipLaunchKernelGGL(kb_recip_x<T>, dim3(nx), dim3(kPassThreads), lds_x, st, mem, x);
+  if (nbwd > 0) hipLaunchKernelGGL(kb_recip_bwd<T>, dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem, bwd);
+}
+
+hipError_t launch_batch_recip(const BatchMember *mem, int precision, const int2 *fwd, int nfwd, const int2 *x,
+                              int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
+                              hipStream_t st) {
+  if (precision == 0)
+    launch_batch_mesh<double>(mem, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+  else
+    launch_batch_mesh<float>(mem, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *map, int nmap, int mode,
+                                hipStream_t st) {
+  if (nmap > 0) hipLaunchKernelGGL(kb_combine, dim3(nmap), dim3(kPrepThreads), 0, st, mem, map, mode);
+  if (nmem > 0) hipLaunchKernelGGL(kb_finish, dim3(nmem), dim3(kPrepThreads), 0, st, mem, mode);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -889,7 +1148,16 @@ hipError_t configure_kernels(size_t max_lds) {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_recip_bwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_recip_bwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  e = hipFuncSetAttribute((const void *)k_recip_bwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (e != hipSuccess) return e;
+  const void *batched[] = {(const void *)kb_recip_fwd<double>, (const void *)kb_recip_fwd<float>,
+                           (const void *)kb_recip_x<double>,   (const void *)kb_recip_x<float>,
+                           (const void *)kb_recip_bwd<double>, (const void *)kb_recip_bwd<float>};
+  for (const void *f : batched) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
@@ -919,12 +1187,14 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   if (tm) tm->before(2, st);
   hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
-                     ncell3, b.xcnt, cfg.mesh.M, b.eacc);
+                     ncell3, b.xcnt, cfg.mesh.M);
   if (tm) tm->after(2, st);
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
                      (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
-                     b.cidx, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.done, b.sc);
+                     b.cidx, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.sc);
+  hipLaunchKernelGGL(k_prep_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const int *)b.blk_cnt,
+                     (const double *)b.blk_sums, b.sc);
   if (tm) tm->after(3, st);
   return hipGetLastError();
 }
@@ -934,9 +1204,9 @@ hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_
   int64_t g = (nq_max + 3) / 4;
   const int grid_real = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   if (tm) tm->before(4, st);
-  hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(256), 0, st, (const double4 *)b.xq, (const int *)b.ccnt,
-                     (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L, cfg.alpha,
-                     cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.eacc);
+  hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(kRealThreads), 0, st, (const double4 *)b.xq,
+                     (const int *)b.ccnt, (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L,
+                     cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal);
   if (tm) tm->after(4, st);
   return hipGetLastError();
 }
@@ -962,11 +1232,12 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
   const int kid = fa.mode < 0 ? 8 : 9;
   if (tm) tm->before(kid, st);
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
-                     (const double4 *)b.xq, b.freal, (const double4 *)b.part,
-                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale,
-                     inv2piL, cfg.alpha, nblk, b.blk_eg, b.done, (const double *)b.epart, cfg.mesh.nky,
-                     (const unsigned long long *)b.eacc, (const DevScalars *)b.sc, b.ccnt, ncell3, b.xcnt,
-                     cfg.mesh.M, fa, forces, energy_total, energy5);
+                     (const double4 *)b.xq, (const unsigned long long *)b.freal, (const double4 *)b.part,
+                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, nblk, b.blk_eg,
+                     (const unsigned long long *)b.ereal, b.blk_er, b.ccnt, ncell3, b.xcnt, cfg.mesh.M, fa, forces);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
+                     (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky, (const DevScalars *)b.sc,
+                     cfg.alpha, inv2piL, energy_total, energy5);
   if (tm) tm->after(kid, st);
   return hipGetLastError();
 }

@@ -2,6 +2,8 @@
 // and influence tables, FFT factorisation, device buffers and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -335,7 +337,6 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   const size_t P2 = 2 * (size_t)p;
   b.blk_cnt = (int *)pl->alloc(nblk * sizeof(int));
   b.blk_sums = (double *)pl->alloc(nblk * 3 * sizeof(double));
-  b.done = (unsigned *)pl->alloc(4 * sizeof(unsigned));
   b.sc = (DevScalars *)pl->alloc(sizeof(DevScalars));
   b.xq = (double4 *)pl->alloc(n * sizeof(double4));
   b.idx = (int *)pl->alloc(n * sizeof(int));
@@ -344,7 +345,8 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.cgrid = (double4 *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(double4));
   b.cidx = (int *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(int));
   b.freal = (unsigned long long *)pl->alloc(n * 3 * sizeof(unsigned long long));
-  b.eacc = (unsigned long long *)pl->alloc(4 * sizeof(unsigned long long));
+  b.ereal = (unsigned long long *)pl->alloc(n * 2 * sizeof(unsigned long long));
+  b.blk_er = (long long *)pl->alloc(nblk * 2 * sizeof(long long));
   b.gzy = pl->alloc((size_t)M * m.nky * Kc * sizeof(double2));
   b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
   b.part = (double4 *)pl->alloc(n * P2 * (size_t)part_slots * sizeof(double4));
@@ -361,8 +363,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     delete pl;
     return nullptr;
   }
-  if (hipMemset(b.done, 0, 4 * sizeof(unsigned)) != hipSuccess ||
-      hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
+  if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
       hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(b.ccnt, 0, ncell3 * sizeof(int)) != hipSuccess ||
       hipMemset(b.xcnt, 0, (size_t)M * sizeof(int)) != hipSuccess) {
@@ -524,12 +525,16 @@ struct enuf_dpd {
   hipStream_t side[2] = {nullptr, nullptr};  // forked streams (pair forces, real space)
   int concurrent = 1;
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+  unsigned long long *step_ctr = nullptr;  // [1] next step index when stepped in a batch
+  int pair_lanes = 4;                      // lanes per particle of the pair kernel (4 or 8)
+  size_t bytes = 0;
 
   void *alloc(size_t n) {
     void *ptr = nullptr;
     if (n == 0) n = 16;
     if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
     allocations.push_back(ptr);
+    bytes += n;
     return ptr;
   }
   void drop_events() {
@@ -605,7 +610,8 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   d->bond_to = (int *)d->alloc(to.size() * sizeof(int));
   d->status = (int *)d->alloc(sizeof(int));
   d->dslot = (int *)d->alloc(n * sizeof(int));
-  if (d->allocations.size() != 12) { set_error("device allocation failed"); delete d; return nullptr; }
+  d->step_ctr = (unsigned long long *)d->alloc(sizeof(unsigned long long));
+  if (d->allocations.size() != 13) { set_error("device allocation failed"); delete d; return nullptr; }
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -663,7 +669,6 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
     ch.xcap = plan->cfg.mesh.xcap;
     ch.m_over_l = plan->cfg.mesh.m_over_l;
     ch.sc = plan->buf.sc;
-    ch.eacc = plan->buf.eacc;
     ch.stat = st;
   }
   for (int k = 0; k < 2; ++k) {
@@ -701,7 +706,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
   if (!d->plan) {
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, st, tm);
+                          d->fdpd, d->pair_lanes, st, tm);
     if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
   } else {
     enuf_plan *pl = d->plan;
@@ -714,7 +719,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
     }
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, s0, tm);
+                          d->fdpd, d->pair_lanes, s0, tm);
     if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[0], s0);
     if (e == hipSuccess) e = launch_real(pl->cfg, pl->buf, d->nq, s1, tm);
     if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[1], s1);
@@ -842,6 +847,459 @@ void enuf_dpd_destroy(enuf_dpd *d) {
   if (!d) return;
   (void)hipStreamSynchronize(d->stream);
   delete d;
+}
+
+size_t enuf_dpd_footprint_bytes(const enuf_dpd *d) {
+  if (!d) return 0;
+  return d->bytes + (d->plan ? d->plan->bytes : 0);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched DPD steps: one launch per stage for every member of the batch.
+// ---------------------------------------------------------------------------
+struct enuf_batch {
+  struct Member {
+    int id;
+    enuf_dpd *d;
+    double *pos, *vel, *force;
+  };
+  int device = 0;
+  int precision = ENUF_MIXED;
+  hipStream_t stream = nullptr;   // the caller's stream: runs are ordered after its work and before its later work
+  hipStream_t own = nullptr;      // the batch's stream (graph capture needs a non-null stream)
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+  hipEvent_t in_ev = nullptr, out_ev = nullptr;
+  int concurrent = 1;
+  int use_graph = 1;
+  int pair_lanes = 4;
+  std::vector<Member> members;
+  int next_id = 0;
+  // device copies of the member table and the work maps (rebuilt when the
+  // membership changes), staged through pinned host buffers
+  BatchMember *dmem = nullptr;
+  int2 *dmap = nullptr;
+  size_t mem_cap = 0, map_cap = 0;
+  BatchMember *hmem = nullptr;
+  int2 *hmap = nullptr;
+  int off[8] = {0};  // map offsets: pre, pair, real, fwd, x, bwd, comb, end
+  int nmem = 0;      // members in the device table
+  size_t lds_fwd = 0, lds_x = 0, lds_bwd = 0;
+  bool dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~enuf_batch() {
+    drop_graph();
+    for (int k = 0; k < 2; ++k) {
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+      if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (in_ev) (void)hipEventDestroy(in_ev);
+    if (out_ev) (void)hipEventDestroy(out_ev);
+    if (own) (void)hipStreamDestroy(own);
+    if (dmem) (void)hipFree(dmem);
+    if (dmap) (void)hipFree(dmap);
+    if (hmem) (void)hipHostFree(hmem);
+    if (hmap) (void)hipHostFree(hmap);
+  }
+};
+
+namespace {
+
+BatchMember member_view(const enuf_batch::Member &mb, int pair_lanes) {
+  const enuf_dpd *d = mb.d;
+  const enuf_plan *pl = d->plan;
+  BatchMember m{};
+  m.cfg = pl->cfg;
+  m.buf = pl->buf;
+  m.nq = (int)d->nq;
+  m.nblk = pl->cfg.nblk;
+  m.pair_blocks = pair_blocks(d->N, pair_lanes);
+  const int64_t g = (d->nq + 3) / 4;
+  m.real_blocks = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
+  m.fscale = (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
+  m.inv2piL = 1.0 / (2.0 * M_PI * pl->cfg.L);
+  m.N = d->N;
+  m.P = d->P;
+  m.pos = mb.pos;
+  m.vel = mb.vel;
+  m.force = mb.force;
+  m.v0 = d->v0;
+  m.fdpd = d->fdpd;
+  m.e5 = d->e5;
+  m.dcnt = d->dcnt;
+  m.cpos = d->cpos;
+  m.cvel = d->cvel;
+  m.bond_start = d->bond_start;
+  m.bond_to = d->bond_to;
+  m.status = d->status;
+  m.ch = d->charges;
+  m.step = d->step_ctr;
+  return m;
+}
+
+// Member table and work maps.  Members are ordered by decreasing N so that
+// the blocks of the largest systems are dispatched first in every stage.
+int batch_rebuild(enuf_batch *b) {
+  std::vector<int> order(b->members.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->members[x].d->N > b->members[y].d->N; });
+  std::vector<BatchMember> mem;
+  std::vector<int2> map[7];
+  size_t lf = 0, lx = 0, lb = 0;
+  for (int k : order) {
+    const BatchMember m = member_view(b->members[k], b->pair_lanes);
+    const int id = (int)mem.size();
+    mem.push_back(m);
+    const int counts[7] = {m.nblk, m.pair_blocks, m.real_blocks, m.cfg.mesh.M, m.cfg.mesh.nky, m.cfg.mesh.M, m.nblk};
+    for (int s = 0; s < 7; ++s)
+      for (int i = 0; i < counts[s]; ++i) map[s].push_back(make_int2(id, i));
+    lf = std::max(lf, m.cfg.lds_fwd);
+    lx = std::max(lx, m.cfg.lds_x);
+    lb = std::max(lb, m.cfg.lds_bwd);
+  }
+  size_t nmap = 0;
+  for (int s = 0; s < 7; ++s) {
+    b->off[s] = (int)nmap;
+    nmap += map[s].size();
+  }
+  b->off[7] = (int)nmap;
+  // the previous table may still be read by queued work
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  if (mem.size() > b->mem_cap) {
+    const size_t cap = std::max<size_t>(mem.size(), 2 * b->mem_cap);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->hmem) (void)hipHostFree(b->hmem);
+    b->dmem = nullptr;
+    b->hmem = nullptr;
+    b->mem_cap = 0;
+    HIP_OR_RETURN(hipMalloc(&b->dmem, cap * sizeof(BatchMember)), ENUF_ENOMEM);
+    HIP_OR_RETURN(hipHostMalloc((void **)&b->hmem, cap * sizeof(BatchMember), hipHostMallocDefault), ENUF_ENOMEM);
+    b->mem_cap = cap;
+  }
+  if (nmap > b->map_cap) {
+    const size_t cap = std::max<size_t>(nmap, 2 * b->map_cap);
+    if (b->dmap) (void)hipFree(b->dmap);
+    if (b->hmap) (void)hipHostFree(b->hmap);
+    b->dmap = nullptr;
+    b->hmap = nullptr;
+    b->map_cap = 0;
+    HIP_OR_RETURN(hipMalloc(&b->dmap, cap * sizeof(int2)), ENUF_ENOMEM);
+    HIP_OR_RETURN(hipHostMalloc((void **)&b->hmap, cap * sizeof(int2), hipHostMallocDefault), ENUF_ENOMEM);
+    b->map_cap = cap;
+  }
+  if (!mem.empty()) {
+    std::memcpy(b->hmem, mem.data(), mem.size() * sizeof(BatchMember));
+    for (int s = 0; s < 7; ++s)
+      if (!map[s].empty()) std::memcpy(b->hmap + b->off[s], map[s].data(), map[s].size() * sizeof(int2));
+    HIP_OR_RETURN(hipMemcpyAsync(b->dmem, b->hmem, mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice,
+                                 b->own), ENUF_EDEVICE);
+    HIP_OR_RETURN(hipMemcpyAsync(b->dmap, b->hmap, nmap * sizeof(int2), hipMemcpyHostToDevice, b->own),
+                  ENUF_EDEVICE);
+  }
+  b->nmem = (int)mem.size();
+  b->lds_fwd = lf;
+  b->lds_x = lx;
+  b->lds_bwd = lb;
+  b->drop_graph();
+  b->dirty = false;
+  return ENUF_OK;
+}
+
+// One step of every member: pre on the batch stream; pair forces and real
+// space forked onto two side streams (fork = true) or kept on the batch
+// stream; the mesh passes on the batch stream; the combine joins them.
+hipError_t batch_step(enuf_batch *b, bool fork) {
+  const int *o = b->off;
+  const int2 *mp = b->dmap;
+  hipStream_t st = b->own;
+  hipStream_t s0 = fork ? b->side[0] : st, s1 = fork ? b->side[1] : st;
+  hipError_t e = launch_batch_pre(b->dmem, mp + o[0], o[1] - o[0], 0, st);
+  if (fork) {
+    if (e == hipSuccess) e = hipEventRecord(b->fork_ev, st);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
+  }
+  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], b->pair_lanes, s0);
+  if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[0], s0);
+  if (e == hipSuccess) e = launch_batch_real(b->dmem, mp + o[2], o[3] - o[2], s1);
+  if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
+  if (e == hipSuccess)
+    e = launch_batch_recip(b->dmem, b->precision, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4], mp + o[5],
+                           o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st);
+  if (fork)
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->join_ev[k], 0);
+  if (e == hipSuccess) e = launch_batch_combine(b->dmem, b->nmem, mp + o[6], o[7] - o[6], 0, st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+enuf_batch *enuf_batch_create(int precision) {
+  g_last_error.clear();
+  if (precision != ENUF_FP64 && precision != ENUF_MIXED) { set_error("unknown precision"); return nullptr; }
+  enuf_batch *b = new enuf_batch();
+  b->precision = precision;
+  if (hipGetDevice(&b->device) != hipSuccess) { set_error("hipGetDevice failed"); delete b; return nullptr; }
+  for (int k = 0; k < 2; ++k) {
+    if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming) != hipSuccess) {
+      set_error("creating the side streams failed");
+      delete b;
+      return nullptr;
+    }
+  }
+  if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) != hipSuccess) {
+    set_error("creating the batch stream or events failed");
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+void enuf_batch_destroy(enuf_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->own);
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+int enuf_batch_set_stream(enuf_batch *b, void *hip_stream) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
+  b->stream = (hipStream_t)hip_stream;
+  for (auto &mb : b->members) {
+    mb.d->stream = b->stream;
+    mb.d->plan->stream = b->stream;
+  }
+  b->drop_graph();
+  return ENUF_OK;
+}
+
+int enuf_batch_set_options(enuf_batch *b, int use_graph, int concurrent) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  b->use_graph = use_graph ? 1 : 0;
+  b->concurrent = concurrent ? 1 : 0;
+  b->drop_graph();
+  return ENUF_OK;
+}
+
+int enuf_batch_add(enuf_batch *b, enuf_dpd *d, double *pos, double *vel, double *force, uint64_t first_step) {
+  if (!b || !d) { set_error("NULL batch or integrator"); return ENUF_EINVAL; }
+  if (!pos || !vel || !force) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  if (!d->plan) { set_error("batched integrators need an ENUF plan"); return ENUF_EINVAL; }
+  if (d->plan->precision != b->precision) { set_error("integrator precision differs from the batch's"); return ENUF_EINVAL; }
+  if (d->device != b->device || d->plan->device != b->device) { set_error("integrator on another device"); return ENUF_EINVAL; }
+  const ComputeConfig &cf = d->plan->cfg;
+  if (cf.lds_fwd > d->plan->max_lds || cf.lds_bwd > d->plan->max_lds || cf.lds_x > d->plan->max_lds) {
+    set_error("mesh too large for the LDS in this precision");
+    return ENUF_EINVAL;
+  }
+  for (const auto &mb : b->members)
+    if (mb.d == d) { set_error("integrator is already a member"); return ENUF_EINVAL; }
+  // the member's own stream may still be working on it
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  d->stream = b->stream;
+  d->plan->stream = b->stream;
+  HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, b->stream), ENUF_EDEVICE);
+  enuf_batch::Member mb{b->next_id++, d, pos, vel, force};
+  b->members.push_back(mb);
+  b->dirty = true;
+  return mb.id;
+}
+
+int enuf_batch_remove(enuf_batch *b, int id) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  for (size_t k = 0; k < b->members.size(); ++k) {
+    if (b->members[k].id == id) {
+      HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+      HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
+      b->members.erase(b->members.begin() + (long)k);
+      b->dirty = true;
+      return ENUF_OK;
+    }
+  }
+  set_error("no member with this id");
+  return ENUF_EINVAL;
+}
+
+int enuf_batch_size(const enuf_batch *b) { return b ? (int)b->members.size() : 0; }
+
+int enuf_batch_run(enuf_batch *b, int nsteps) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
+  if (b->members.empty() || nsteps == 0) return ENUF_OK;
+  int dev = -1;
+  HIP_OR_RETURN(hipGetDevice(&dev), ENUF_EDEVICE);
+  if (dev != b->device) { set_error("the batch's device is not current"); return ENUF_EINVAL; }
+  if (b->dirty) {
+    const int rc = batch_rebuild(b);
+    if (rc != ENUF_OK) return rc;
+  }
+  // The captured step is the single-stream schedule: no cross-stream event
+  // record / wait inside a capture.
+  if (b->use_graph && !b->exec) {
+    HIP_OR_RETURN(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), ENUF_EDEVICE);
+    const hipError_t e = batch_step(b, false);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->own, &g);
+    if (e != hipSuccess || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      set_error(std::string("capturing the batched step failed: ") + hipGetErrorString(e != hipSuccess ? e : ec));
+      return ENUF_EDEVICE;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->drop_graph();
+      set_error("instantiating the batched step graph failed");
+      return ENUF_EDEVICE;
+    }
+  }
+  // order after the caller's stream, run on the batch stream, order the
+  // caller's later work after the run
+  HIP_OR_RETURN(hipEventRecord(b->in_ev, b->stream), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipStreamWaitEvent(b->own, b->in_ev, 0), ENUF_EDEVICE);
+  for (int s = 0; s < nsteps; ++s) {
+    const hipError_t e = b->use_graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0);
+    if (e != hipSuccess) {
+      set_error(std::string("batched step launch failed: ") + hipGetErrorString(e));
+      return ENUF_EDEVICE;
+    }
+  }
+  HIP_OR_RETURN(hipEventRecord(b->out_ev, b->own), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipStreamWaitEvent(b->stream, b->out_ev, 0), ENUF_EDEVICE);
+  return ENUF_OK;
+}
+
+int enuf_batch_set_tuning(enuf_batch *b, int pair_lanes) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if (pair_lanes != 4 && pair_lanes != 8) { set_error("pair_lanes must be 4 or 8"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  b->pair_lanes = pair_lanes;
+  b->dirty = true;
+  return ENUF_OK;
+}
+
+int enuf_batch_autotune(enuf_batch *b, int trial_steps, int *pair_lanes, int *concurrent) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if (trial_steps < 1 || trial_steps > 10000) { set_error("trial_steps must be in [1, 10000]"); return ENUF_EINVAL; }
+  if (b->members.empty()) { set_error("empty batch"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
+  // snapshot of every member's state, restored before each trial and at the end
+  struct Snap {
+    double *buf = nullptr;
+    unsigned long long step = 0;
+  };
+  std::vector<Snap> snap(b->members.size());
+  auto release = [&]() {
+    for (auto &sn : snap)
+      if (sn.buf) (void)hipFree(sn.buf);
+  };
+  for (size_t k = 0; k < snap.size(); ++k) {
+    const auto &mb = b->members[k];
+    const size_t n3 = 3 * (size_t)mb.d->N;
+    if (hipMalloc(&snap[k].buf, 3 * n3 * sizeof(double)) != hipSuccess ||
+        hipMemcpy(snap[k].buf, mb.pos, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(snap[k].buf + n3, mb.vel, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(snap[k].buf + 2 * n3, mb.force, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(&snap[k].step, mb.d->step_ctr, sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess) {
+      release();
+      set_error("autotune: snapshot of the member state failed");
+      return ENUF_ENOMEM;
+    }
+  }
+  auto restore = [&]() -> bool {
+    for (size_t k = 0; k < snap.size(); ++k) {
+      const auto &mb = b->members[k];
+      const size_t n3 = 3 * (size_t)mb.d->N;
+      if (hipMemcpy(mb.pos, snap[k].buf, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+          hipMemcpy(mb.vel, snap[k].buf + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+          hipMemcpy(mb.force, snap[k].buf + 2 * n3, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
+          hipMemcpy(mb.d->step_ctr, &snap[k].step, sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    }
+    return hipDeviceSynchronize() == hipSuccess;
+  };
+  // Trials launch eagerly (no graph is captured or destroyed while tuning);
+  // with graphs on, the forked schedule is not a candidate (a graph holds
+  // the single-stream step).
+  const int old_lanes = b->pair_lanes, old_conc = b->concurrent, old_graph = b->use_graph;
+  b->use_graph = 0;
+  b->drop_graph();
+  double best = 1e300;
+  int best_lanes = old_lanes, best_conc = old_conc;
+  for (int lanes : {4, 8}) {
+    for (int conc : {1, 0}) {
+      if (old_graph && conc) continue;
+      b->pair_lanes = lanes;
+      b->concurrent = conc;
+      b->dirty = true;
+      if (!restore()) {
+        release();
+        set_error("autotune: restoring the member state failed");
+        return ENUF_EDEVICE;
+      }
+      int rc = enuf_batch_run(b, 1);  // builds the tables, warms up
+      if (rc == ENUF_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = ENUF_EDEVICE;
+      const auto t0 = std::chrono::steady_clock::now();
+      if (rc == ENUF_OK) rc = enuf_batch_run(b, trial_steps);
+      if (rc == ENUF_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = ENUF_EDEVICE;
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rc != ENUF_OK) {
+        release();
+        b->use_graph = old_graph;
+        return rc;
+      }
+      if (dt < best) {
+        best = dt;
+        best_lanes = lanes;
+        best_conc = conc;
+      }
+    }
+  }
+  const bool ok = restore();
+  release();
+  b->pair_lanes = best_lanes;
+  b->concurrent = best_conc;
+  b->use_graph = old_graph;
+  b->dirty = true;
+  if (!ok) { set_error("autotune: restoring the member state failed"); return ENUF_EDEVICE; }
+  if (pair_lanes) *pair_lanes = best_lanes;
+  if (concurrent) *concurrent = best_conc;
+  return ENUF_OK;
+}
+
+int enuf_dpd_set_tuning(enuf_dpd *d, int pair_lanes) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  if (pair_lanes != 4 && pair_lanes != 8) { set_error("pair_lanes must be 4 or 8"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  d->pair_lanes = pair_lanes;
+  return ENUF_OK;
+}
+
+size_t enuf_batch_footprint_bytes(const enuf_batch *b) {
+  if (!b) return 0;
+  size_t t = b->mem_cap * sizeof(BatchMember) + b->map_cap * sizeof(int2);
+  for (const auto &mb : b->members) t += enuf_dpd_footprint_bytes(mb.d);
+  return t;
 }
 
 }  // extern "C"

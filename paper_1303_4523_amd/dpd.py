@@ -67,6 +67,10 @@ class DPD:
         """Overlap pair forces and real space with the mesh passes (default) or not."""
         check(lib.enuf_dpd_set_concurrency(self._h, int(bool(enable))), "enuf_dpd_set_concurrency")
 
+    def set_tuning(self, pair_lanes):
+        """Lanes per particle of the pair-force kernel (4 or 8)."""
+        check(lib.enuf_dpd_set_tuning(self._h, int(pair_lanes)), "enuf_dpd_set_tuning")
+
     def energy(self):
         """ENUF energy components of the last evaluation (unscaled by kappa)."""
         e = torch.empty(5, dtype=torch.float64, device=self.device)
@@ -84,6 +88,11 @@ class DPD:
         ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
         check(lib.enuf_dpd_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)), "enuf_dpd_kernel_time")
         return ms.value, n.value
+
+    @property
+    def footprint_bytes(self):
+        """Device bytes of the integrator and its plan."""
+        return int(lib.enuf_dpd_footprint_bytes(self._h))
 
     def status(self):
         st = ctypes.c_int(0)

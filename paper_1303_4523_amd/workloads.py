@@ -155,3 +155,47 @@ def n_sweep(L):
     s.meta["enuf"] = enuf_params(float(L))
     s.meta["name"] = f"N-sweep L={L} N={n} Nq={2 * (nq // 2)}"
     return s
+
+
+def mesh_size(n):
+    """Smallest even 2^a 3^b 5^c that is >= n (an FFT-friendly mesh)."""
+    m = max(2, int(math.ceil(n - 1e-9)))
+    while True:
+        k = m
+        for r in (2, 3, 5):
+            while k % r == 0:
+                k //= r
+        if k == 1 and m % 2 == 0:
+            return m
+        m += 1
+
+
+DPD_DEFAULTS = dict(a=25.0, gamma=4.5, sigma=3.0, dt=0.03, lam=0.65, k_bond=4.0, r0_bond=0.7,
+                    kappa=BJERRUM_COUPLING / (4.0 * math.pi))
+
+
+def replica(s, n_min=3000, n_max=48000, seed_base=BASE_SEED + 4):
+    """Replica s of the batched workload: N log-uniform in [n_min, n_max] at
+    density 3 (L = (N/3)^(1/3)); one 50-bead chain with charge fraction
+    f = (0.1, 0.25, 0.5, 1.0)[s mod 4] and its +1 counterions; z:1 salt with
+    z = (1, 2, 3)[(s div 4) mod 3] (0.1 cations per unit volume at +z and z
+    times as many -1 anions); M = smallest even 2^a 3^b 5^c >= 3.2 L,
+    Kc = min(floor(0.8 L), floor(M / 4))."""
+    seed = seed_base + 1000 * s
+    rng = _rng(seed)
+    n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+    L = (n / 3.0) ** (1.0 / 3.0)
+    f = (0.1, 0.25, 0.5, 1.0)[s % 4]
+    z = (1, 2, 3)[(s // 4) % 3]
+    sysm = polyelectrolyte(L, 3.0, 50, f, 0.1, z, seed + 1)
+    M = mesh_size(3.2 * L)
+    Kc = min(int(math.floor(0.8 * L + 1e-9)), M // 4)
+    sysm.meta["enuf"] = enuf_params(L, M=M, Kc=Kc)
+    sysm.meta["dpd"] = dict(DPD_DEFAULTS, L=L, seed=seed)
+    sysm.meta["name"] = f"replica {s}: N={sysm.N} L={L:.3f} f={f} z={z} M={M} Kc={Kc}"
+    return sysm
+
+
+def batched_replicas(nsys=64):
+    """The batched workload: nsys independent polyelectrolyte replicas."""
+    return [replica(s) for s in range(nsys)]

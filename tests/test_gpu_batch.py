@@ -1,0 +1,195 @@
+"""Batched DPD steps (one launch per stage for many systems) against the
+single-system path and the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4523_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device=DEV).contiguous()
+
+
+def _replicas(ids, n_max=9000):
+    return [wl.replica(s, n_max=n_max) for s in ids]
+
+
+def _member(s, precision="mixed", first_step=1):
+    """Integrator, state tensors and initial forces of one replica."""
+    from paper_1303_4523_amd.dpd import DPD
+    d = DPD(s.L, s.q, s.meta["dpd"], bonds=s.bonds, enuf=s.meta["enuf"], precision=precision, device=0)
+    pos, vel = _t(s.pos), _t(s.vel)
+    F = torch.empty_like(pos)
+    d.forces(pos, vel, F, step=first_step - 1)
+    return d, pos, vel, F
+
+
+def _alone(s, nsteps, precision="mixed", first_step=1):
+    d, pos, vel, F = _member(s, precision, first_step)
+    d.run(pos, vel, F, first_step, nsteps)
+    st = d.status()
+    e5 = d.energy().cpu().numpy()
+    out = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), e5)
+    d.close()
+    assert st == 0
+    return out
+
+
+def _same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("use_graph,concurrent", [(True, True), (False, True), (True, False)])
+def test_batch_equals_each_system_alone(use_graph, concurrent):
+    """Six uneven replicas (valency 1-3, charge fraction 0.1-1, different M
+    and Kc) stepped together: every member's state is bitwise the one it gets
+    when stepped alone."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([0, 1, 2, 3, 5, 10])
+    print("case: batch of", [r.meta["name"] for r in reps], f"graph={use_graph} concurrent={concurrent}",
+          flush=True)
+    b = Batch("mixed", device=0, use_graph=use_graph, concurrent=concurrent)
+    members = []
+    for s in reps:
+        d, pos, vel, F = _member(s)
+        b.add(d, pos, vel, F, first_step=1)
+        members.append((d, pos, vel, F))
+    assert len(b) == len(reps)
+    b.run(4)
+    torch.cuda.synchronize()
+    for s, (d, pos, vel, F) in zip(reps, members):
+        got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy())
+        assert d.status() == 0
+        ref = _alone(s, 4)
+        assert _same(got, ref), s.meta["name"]
+    b.close()
+    for d, *_ in members:
+        d.close()
+
+
+def test_graph_replays_match_eager_steps():
+    """Each replay of the captured step, with host reads and synchronisation
+    between replays, equals the eager launch sequence."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([4, 7, 9])
+    runs = {}
+    for use_graph in (True, False):
+        b = Batch("mixed", device=0, use_graph=use_graph)
+        mem = [_member(s) for s in reps]
+        for d, pos, vel, F in mem:
+            b.add(d, pos, vel, F, first_step=1)
+        snaps = []
+        for step in range(5):
+            b.run(1)
+            torch.cuda.synchronize()
+            snaps.append([p.cpu().numpy() for _, p, _, _ in mem] + [F.cpu().numpy() for *_, F in mem])
+            _ = torch.zeros(1000, device=DEV).sum().item()   # unrelated eager work between replays
+        runs[use_graph] = snaps
+        b.close()
+        for d, *_ in mem:
+            d.close()
+    for a, c in zip(runs[True], runs[False]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, c))
+
+
+def test_membership_changes_between_runs():
+    """Members join with their own step index and leave; the others continue
+    as if alone."""
+    from paper_1303_4523_amd.batch import Batch
+    r0, r1, r2 = _replicas([0, 6, 8])
+    b = Batch("mixed", device=0)
+    m0 = _member(r0)
+    m1 = _member(r1)
+    i0 = b.add(*m0, first_step=1)
+    i1 = b.add(*m1, first_step=1)
+    b.run(2)
+    m2 = _member(r2, first_step=5)
+    b.add(*m2, first_step=5)
+    b.run(1)
+    b.remove(i0)
+    b.run(2)
+    torch.cuda.synchronize()
+    got0 = tuple(t.cpu().numpy() for t in m0[1:])
+    got1 = tuple(t.cpu().numpy() for t in m1[1:])
+    got2 = tuple(t.cpu().numpy() for t in m2[1:])
+    assert _same(got0, _alone(r0, 3)[:3])
+    assert _same(got1, _alone(r1, 5)[:3])
+    assert _same(got2, _alone(r2, 3, first_step=5)[:3])
+    b.close()
+    for m in (m0, m1, m2):
+        m[0].close()
+    assert i1 != i0
+
+
+def test_mixed_member_against_oracle():
+    """A replica with z = 3 salt in the mixed mode: forces at step 0 and the
+    state after three steps against the FP64 oracle (mixed bar 5e-4)."""
+    s = wl.replica(8, n_max=6000)
+    e, dp = s.meta["enuf"], s.meta["dpd"]
+    print("case:", s.meta["name"], flush=True)
+    d, pos, vel, F = _member(s, "mixed", first_step=1)
+    F0 = F.cpu().numpy()
+    from paper_1303_4523_amd.batch import Batch
+    b = Batch("mixed", device=0)
+    b.add(d, pos, vel, F, first_step=1)
+    b.run(3)
+    torch.cuda.synchronize()
+    gp, gF = pos.cpu().numpy(), F.cpu().numpy()
+    assert d.status() == 0
+    b.close()
+    d.close()
+    P = dict(dp, alpha=e["alpha"], r_cut=e["r_cut"], lambda_e=e["lam"], Kc=e["Kc"], use_elec=1)
+    Fo, _ = oracle.dpd_forces(s.pos, s.vel, s.q, s.bonds, P, seed=dp["seed"], step=0)
+    err0 = np.linalg.norm(F0 - Fo) / np.linalg.norm(Fo)
+    op, ov = s.pos.copy(), s.vel.copy()
+    for k in range(1, 4):
+        op, ov, Fo, _ = oracle.dpd_step(op, ov, Fo, s.q, s.bonds, P, seed=dp["seed"], step=k)
+    ddp = gp - op
+    ddp -= s.L * np.round(ddp / s.L)
+    err3 = np.linalg.norm(gF - Fo) / np.linalg.norm(Fo)
+    print(f"mixed member: step-0 force rel {err0:.3e}, after 3 steps force rel {err3:.3e}, "
+          f"max |dr| {np.abs(ddp).max():.3e}")
+    assert err0 < 5e-4 and err3 < 5e-4
+    assert np.abs(ddp).max() < 1e-5
+
+
+def test_autotune_restores_state_and_keeps_results():
+    """The autotuner times the launch configurations on the members and leaves
+    their states as they were; the tuned run equals the untuned one."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([2, 5, 11])
+    b = Batch("mixed", device=0)
+    mem = [_member(s) for s in reps]
+    for m in mem:
+        b.add(*m, first_step=1)
+    before = [[t.cpu().numpy() for t in m[1:]] for m in mem]
+    lanes, conc = b.autotune(2)
+    print(f"case: autotune -> pair lanes {lanes}, concurrent {conc}", flush=True)
+    assert lanes in (4, 8)
+    after = [[t.cpu().numpy() for t in m[1:]] for m in mem]
+    assert all(np.array_equal(x, y) for a, c in zip(before, after) for x, y in zip(a, c))
+    b.run(3)
+    torch.cuda.synchronize()
+    for s, m in zip(reps, mem):
+        assert _same(tuple(t.cpu().numpy() for t in m[1:]), _alone(s, 3)[:3])
+    b.close()
+    for m in mem:
+        m[0].close()
+
+
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_pair_lanes_do_not_change_results(lanes):
+    """Four or eight lanes per particle in the pair kernel: same bits."""
+    s = wl.replica(3, n_max=9000)
+    d, pos, vel, F = _member(s, "fp64")
+    d.set_tuning(lanes)
+    d.run(pos, vel, F, 1, 3)
+    got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy())
+    d.close()
+    assert _same(got, _alone(s, 3, precision="fp64")[:3])
