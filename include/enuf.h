@@ -198,6 +198,12 @@ void enuf_dpd_destroy(enuf_dpd *dpd);
 /* Device bytes held by the integrator and its plan (admission control). */
 size_t enuf_dpd_footprint_bytes(const enuf_dpd *dpd);
 
+/* Device bytes enuf_plan_create (on the current device) and enuf_dpd_create
+ * would allocate for these sizes, without allocating: admission control
+ * before a system is created.  0 for invalid sizes. */
+size_t enuf_plan_footprint_estimate(int64_t N, double box, int p, int M, int Kc, double r_cut);
+size_t enuf_dpd_footprint_estimate(int64_t N, double box, int64_t nbonds);
+
 /* Lanes per particle of the pair-force kernel: 4 (default) or 8.  Results do
  * not depend on it (exact fixed-point force sums). */
 int enuf_dpd_set_tuning(enuf_dpd *dpd, int pair_lanes);

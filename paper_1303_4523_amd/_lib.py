@@ -69,6 +69,10 @@ lib.enuf_dpd_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_
 lib.enuf_dpd_kernel_time.restype = _int
 lib.enuf_dpd_footprint_bytes.argtypes = [_vp]
 lib.enuf_dpd_footprint_bytes.restype = _sz
+lib.enuf_plan_footprint_estimate.argtypes = [_i64, _dbl, _int, _int, _int, _dbl]
+lib.enuf_plan_footprint_estimate.restype = _sz
+lib.enuf_dpd_footprint_estimate.argtypes = [_i64, _dbl, _i64]
+lib.enuf_dpd_footprint_estimate.restype = _sz
 
 lib.enuf_batch_create.argtypes = [_int]
 lib.enuf_batch_create.restype = _vp
@@ -110,6 +114,7 @@ EXPORTED = [
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_batch_set_tuning", "enuf_batch_autotune", "enuf_dpd_set_tuning",
+    "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate",
 ]
 
 # Status codes (include/enuf.h).

@@ -3,11 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -63,6 +67,18 @@ bool factor_235(int n, FftPlan *pl) {
 
 }  // namespace
 
+namespace {
+
+size_t arena_slot(size_t n) { return ((n == 0 ? 16 : n) + 255) & ~(size_t)255; }
+
+size_t arena_bytes(const size_t *sizes, int n) {
+  size_t t = 0;
+  for (int k = 0; k < n; ++k) t += arena_slot(sizes[k]);
+  return t;
+}
+
+}  // namespace
+
 struct enuf_plan {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -77,13 +93,20 @@ struct enuf_plan {
   std::vector<void *> allocations;
   size_t bytes = 0;
 
-  void *alloc(size_t n) {
-    void *ptr = nullptr;
-    if (n == 0) n = 16;
-    if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
-    allocations.push_back(ptr);
-    bytes += n;
-    return ptr;
+  // All buffers in one device allocation (one hipMalloc / hipFree per
+  // object), each at a 256-byte aligned offset.  False on failure.
+  bool alloc_arena(const size_t *sizes, int n, void **ptrs) {
+    const size_t total = arena_bytes(sizes, n);
+    void *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) return false;
+    allocations.push_back(base);
+    bytes += total;
+    size_t off = 0;
+    for (int k = 0; k < n; ++k) {
+      ptrs[k] = (char *)base + off;
+      off += arena_slot(sizes[k]);
+    }
+    return true;
   }
   ~enuf_plan() {
     for (void *ptr : allocations) (void)hipFree(ptr);
@@ -207,10 +230,31 @@ int fit_window_series(const WindowParams &w, int fp32, std::vector<long double> 
   return D;
 }
 
+// The fits depend only on the window (kind, p, shape) and the precision:
+// they are computed once per process and reused by every plan.
+int cached_window_series(const WindowParams &w, int fp32, std::vector<long double> *coef) {
+  struct Fit {
+    int D;
+    std::vector<long double> coef;
+  };
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, double, double, int>, Fit> cache;
+  const auto key = std::make_tuple(w.kind, w.p, w.b, w.inv_bg, fp32);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    Fit f;
+    f.D = fit_window_series(w, fp32, &f.coef);
+    it = cache.emplace(key, std::move(f)).first;
+  }
+  *coef = it->second.coef;
+  return it->second.D;
+}
+
 int upload_window_series(enuf_plan *pl) {
   std::vector<long double> coef;
   const int fp32 = pl->precision == ENUF_MIXED;
-  const int D = fit_window_series(pl->cfg.mesh.win, fp32, &coef);
+  const int D = cached_window_series(pl->cfg.mesh.win, fp32, &coef);
   pl->cfg.mesh.cheb_deg = D;
   const size_t n = coef.size();
   if (fp32) {
@@ -252,6 +296,82 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
 
+namespace {
+
+// Geometry that fixes the plan's buffer sizes.
+struct PlanGeom {
+  int ncell = 1, cap = 1, xcap = 1, part_slots = 0, nblk = 1;
+};
+
+// Returns false when no row chunking of the plane passes fits in max_lds.
+bool plan_geometry(int64_t N, double box, int p, int M, int Kc, double r_cut, size_t max_lds, PlanGeom *g) {
+  int ncell = (int)std::floor(box / r_cut);
+  ncell = ncell < 1 ? 1 : (ncell > 1024 ? 1024 : ncell);
+  const double mean = (double)N / ((double)ncell * ncell * ncell);
+  g->ncell = ncell;
+  g->cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+  const double xmean = (double)N / (double)M;
+  g->xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 16.0);
+  g->nblk = (int)((N + kPrepThreads - 1) / kPrepThreads);
+  // the gather partials are sized for the largest series degree in either precision
+  MeshParams m{};
+  m.M = M; m.Mp = M + 1; m.Mz = M + 1; m.Kc = Kc; m.nky = 2 * Kc - 1;
+  m.win.p = p;
+  m.cheb_deg = kMaxChebDeg;
+  g->part_slots = 0;
+  for (int prec = ENUF_FP64; prec <= ENUF_MIXED; ++prec) {
+    MeshParams t = m;
+    if (mesh_choose_rows(t, prec, max_lds)) g->part_slots = t.nslot > g->part_slots ? t.nslot : g->part_slots;
+  }
+  return g->part_slots > 0;
+}
+
+constexpr int kPlanBuffers = 23;
+
+// Bytes of every device buffer of a plan, in allocation order.
+std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int Kc, const PlanGeom &g) {
+  const size_t n = (size_t)N, nblk = (size_t)g.nblk, P2 = 2 * (size_t)p, nky = 2 * (size_t)Kc - 1;
+  const size_t ncell3 = (size_t)g.ncell * g.ncell * g.ncell, cap = (size_t)g.cap;
+  return {nblk * sizeof(int),                                 // blk_cnt
+          nblk * 3 * sizeof(double),                          // blk_sums
+          sizeof(DevScalars),                                 // sc
+          n * sizeof(double4),                                // xq
+          n * sizeof(int),                                    // idx
+          n * sizeof(int),                                    // slot
+          ncell3 * sizeof(int),                               // ccnt
+          ncell3 * cap * sizeof(double4),                     // cgrid
+          ncell3 * cap * sizeof(int),                         // cidx
+          n * 3 * sizeof(unsigned long long),                 // freal
+          n * 2 * sizeof(unsigned long long),                 // ereal
+          nblk * 2 * sizeof(long long),                       // blk_er
+          (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzy
+          nky * sizeof(double),                               // epart
+          n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
+          nblk * sizeof(double),                              // blk_eg
+          (size_t)M * sizeof(int),                            // xcnt
+          (size_t)M * (size_t)g.xcap * sizeof(int),           // xslot
+          P2 * (2 * kMaxChebDeg + 1) * sizeof(double),        // wcoef64
+          P2 * (2 * kMaxChebDeg + 1) * sizeof(float),         // wcoef32
+          nky * sizeof(double),                               // atab
+          (size_t)M * sizeof(double2),                        // tw64
+          (size_t)M * sizeof(float2)};                        // tw32
+}
+
+// LDS bytes per block the plans of this device may use: the device's limit,
+// or the lower value of ENUF_MAX_LDS_BYTES.  0 if the device cannot be queried.
+size_t lds_budget(int device) {
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return 0;
+  size_t v = (size_t)lds;
+  if (const char *cap = std::getenv("ENUF_MAX_LDS_BYTES")) {
+    const long long c = std::atoll(cap);
+    if (c > 0 && (size_t)c < v) v = (size_t)c;
+  }
+  return v;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *enuf_last_error(void) { return g_last_error.c_str(); }
@@ -281,17 +401,11 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     delete pl;
     return nullptr;
   }
-  int lds = 0;
-  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) != hipSuccess) {
+  pl->max_lds = lds_budget(pl->device);
+  if (pl->max_lds == 0) {
     set_error("hipDeviceGetAttribute failed");
     delete pl;
     return nullptr;
-  }
-  pl->max_lds = (size_t)lds;
-  // optional lower LDS budget per block: forces the row-chunked plane passes
-  if (const char *cap = std::getenv("ENUF_MAX_LDS_BYTES")) {
-    const long long v = std::atoll(cap);
-    if (v > 0 && (size_t)v < pl->max_lds) pl->max_lds = (size_t)v;
   }
 
   ComputeConfig &c = pl->cfg;
@@ -304,65 +418,57 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.L = box; m.m_over_l = (double)M / box;
   m.win = make_window(ENUF_WINDOW_KB, p, sigma);
   m.fft = fp;
-  int ncell = (int)std::floor(box / r_cut);
-  ncell = ncell < 1 ? 1 : (ncell > 1024 ? 1024 : ncell);
-  const double mean = (double)N / ((double)ncell * ncell * ncell);
-  c.cells.ncell = ncell;
-  c.cells.cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
-  c.cells.inv_cell = (double)ncell / box;
-  const double xmean = (double)N / (double)M;
-  m.xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 16.0);
-  // Row chunking of the plane passes; the gather partials are sized for the
-  // largest series degree in either precision.
-  m.cheb_deg = kMaxChebDeg;
-  int part_slots = 0;
-  for (int prec = ENUF_FP64; prec <= ENUF_MIXED; ++prec) {
-    MeshParams t = m;
-    if (mesh_choose_rows(t, prec, pl->max_lds)) part_slots = t.nslot > part_slots ? t.nslot : part_slots;
-  }
-  if (part_slots == 0) {
+  PlanGeom g;
+  if (!plan_geometry(N, box, p, M, Kc, r_cut, pl->max_lds, &g)) {
     set_error("mesh too large: no row chunking of the plane passes fits in " + std::to_string(pl->max_lds) +
               " bytes of LDS");
     delete pl;
     return nullptr;
   }
-  pl->part_slots = part_slots;
+  const int ncell = g.ncell;
+  c.cells.ncell = ncell;
+  c.cells.cap = g.cap;
+  c.cells.inv_cell = (double)ncell / box;
+  m.xcap = g.xcap;
+  pl->part_slots = g.part_slots;
+  m.cheb_deg = kMaxChebDeg;
   m.rows = M;
   m.nchunk = 1;
   m.nslot = 1;
   mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
 
   ComputeBuffers &b = pl->buf;
-  const size_t nblk = c.nblk, n = (size_t)N, ncell3 = (size_t)ncell * ncell * ncell;
-  const size_t P2 = 2 * (size_t)p;
-  b.blk_cnt = (int *)pl->alloc(nblk * sizeof(int));
-  b.blk_sums = (double *)pl->alloc(nblk * 3 * sizeof(double));
-  b.sc = (DevScalars *)pl->alloc(sizeof(DevScalars));
-  b.xq = (double4 *)pl->alloc(n * sizeof(double4));
-  b.idx = (int *)pl->alloc(n * sizeof(int));
-  b.slot = (int *)pl->alloc(n * sizeof(int));
-  b.ccnt = (int *)pl->alloc(ncell3 * sizeof(int));
-  b.cgrid = (double4 *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(double4));
-  b.cidx = (int *)pl->alloc(ncell3 * (size_t)c.cells.cap * sizeof(int));
-  b.freal = (unsigned long long *)pl->alloc(n * 3 * sizeof(unsigned long long));
-  b.ereal = (unsigned long long *)pl->alloc(n * 2 * sizeof(unsigned long long));
-  b.blk_er = (long long *)pl->alloc(nblk * 2 * sizeof(long long));
-  b.gzy = pl->alloc((size_t)M * m.nky * Kc * sizeof(double2));
-  b.epart = (double *)pl->alloc((size_t)m.nky * sizeof(double));
-  b.part = (double4 *)pl->alloc(n * P2 * (size_t)part_slots * sizeof(double4));
-  b.blk_eg = (double *)pl->alloc(nblk * sizeof(double));
-  b.xcnt = (int *)pl->alloc((size_t)M * sizeof(int));
-  b.xslot = (int *)pl->alloc((size_t)M * (size_t)m.xcap * sizeof(int));
-  b.wcoef64 = (double *)pl->alloc(P2 * (2 * kMaxChebDeg + 1) * sizeof(double));
-  b.wcoef32 = (float *)pl->alloc(P2 * (2 * kMaxChebDeg + 1) * sizeof(float));
-  b.atab = (double *)pl->alloc((size_t)m.nky * sizeof(double));
-  b.tw64 = (double2 *)pl->alloc((size_t)M * sizeof(double2));
-  b.tw32 = (float2 *)pl->alloc((size_t)M * sizeof(float2));
-  if (pl->allocations.size() != 23) {  // alloc() records successful allocations only
+  const size_t n = (size_t)N, ncell3 = (size_t)ncell * ncell * ncell;
+  const std::array<size_t, kPlanBuffers> sz = plan_buffer_bytes(N, p, M, Kc, g);
+  void *ptr[kPlanBuffers];
+  if (!pl->alloc_arena(sz.data(), kPlanBuffers, ptr)) {
     set_error("device allocation failed");
     delete pl;
     return nullptr;
   }
+  b.blk_cnt = (int *)ptr[0];
+  b.blk_sums = (double *)ptr[1];
+  b.sc = (DevScalars *)ptr[2];
+  b.xq = (double4 *)ptr[3];
+  b.idx = (int *)ptr[4];
+  b.slot = (int *)ptr[5];
+  b.ccnt = (int *)ptr[6];
+  b.cgrid = (double4 *)ptr[7];
+  b.cidx = (int *)ptr[8];
+  b.freal = (unsigned long long *)ptr[9];
+  b.ereal = (unsigned long long *)ptr[10];
+  b.blk_er = (long long *)ptr[11];
+  b.gzy = ptr[12];
+  b.epart = (double *)ptr[13];
+  b.part = (double4 *)ptr[14];
+  b.blk_eg = (double *)ptr[15];
+  b.xcnt = (int *)ptr[16];
+  b.xslot = (int *)ptr[17];
+  b.wcoef64 = (double *)ptr[18];
+  b.wcoef32 = (float *)ptr[19];
+  b.atab = (double *)ptr[20];
+  b.tw64 = (double2 *)ptr[21];
+  b.tw32 = (float2 *)ptr[22];
   if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
       hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(b.ccnt, 0, ncell3 * sizeof(int)) != hipSuccess ||
@@ -391,7 +497,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     }
     configured = true;
   }
-  if (hipDeviceSynchronize() != hipSuccess) {
+  if (hipStreamSynchronize(nullptr) != hipSuccess) {
     set_error("device synchronisation after plan setup failed");
     delete pl;
     return nullptr;
@@ -499,6 +605,40 @@ size_t enuf_plan_footprint_bytes(const enuf_plan *plan) { return plan ? plan->by
 // ---------------------------------------------------------------------------
 // DPD integrator
 // ---------------------------------------------------------------------------
+namespace {
+
+// DPD cell grid: cells per side (edge box / nc >= R_c = 1) and slots per cell.
+void dpd_geometry(int64_t N, double box, int *nc_out, int *cap_out) {
+  int nc = (int)std::floor(box);
+  nc = nc < 1 ? 1 : (nc > 1024 ? 1024 : nc);
+  const double mean = (double)N / ((double)nc * nc * nc);
+  *nc_out = nc;
+  *cap_out = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+}
+
+constexpr int kDpdBuffers = 12;
+
+// Bytes of every device buffer of a DPD integrator, in allocation order.
+std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t nbonds) {
+  int nc, cap;
+  dpd_geometry(N, box, &nc, &cap);
+  const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
+  return {n * sizeof(double),                                        // q
+          3 * n * sizeof(double),                                    // v0
+          3 * n * sizeof(double),                                    // fdpd
+          5 * sizeof(double),                                        // e5
+          nc3 * sizeof(int),                                         // dcnt
+          nc3 * (size_t)cap * sizeof(double4),                       // cpos
+          nc3 * (size_t)cap * sizeof(double4),                       // cvel
+          (n + 1) * sizeof(int),                                     // bond_start
+          (size_t)(2 * nbonds > 0 ? 2 * nbonds : 1) * sizeof(int),   // bond_to
+          sizeof(int),                                               // status
+          n * sizeof(int),                                           // dslot
+          sizeof(unsigned long long)};                               // step_ctr
+}
+
+}  // namespace
+
 struct enuf_dpd {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -508,7 +648,6 @@ struct enuf_dpd {
   double *q = nullptr;        // [N]
   double *v0 = nullptr;       // [N * 3] predicted velocities
   double *fdpd = nullptr;     // [N * 3] pair + bond forces
-  double *felec = nullptr;    // [N * 3]
   double *e5 = nullptr;       // [5]
   int *dcnt = nullptr;        // [ncell^3]
   double4 *cpos = nullptr;    // [ncell^3 * cap] (x, y, z, index) per cell slot
@@ -529,13 +668,20 @@ struct enuf_dpd {
   int pair_lanes = 4;                      // lanes per particle of the pair kernel (4 or 8)
   size_t bytes = 0;
 
-  void *alloc(size_t n) {
-    void *ptr = nullptr;
-    if (n == 0) n = 16;
-    if (hipMalloc(&ptr, n) != hipSuccess) return nullptr;
-    allocations.push_back(ptr);
-    bytes += n;
-    return ptr;
+  // All buffers in one device allocation (one hipMalloc / hipFree per
+  // object), each at a 256-byte aligned offset.  False on failure.
+  bool alloc_arena(const size_t *sizes, int n, void **ptrs) {
+    const size_t total = arena_bytes(sizes, n);
+    void *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) return false;
+    allocations.push_back(base);
+    bytes += total;
+    size_t off = 0;
+    for (int k = 0; k < n; ++k) {
+      ptrs[k] = (char *)base + off;
+      off += arena_slot(sizes[k]);
+    }
+    return true;
   }
   void drop_events() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -591,33 +737,33 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   DpdParams &P = d->P;
   P.L = box; P.a = prm->a; P.gamma = prm->gamma; P.sigma = prm->sigma; P.dt = prm->dt; P.lam = prm->lam;
   P.k_bond = prm->k_bond; P.r0_bond = prm->r0_bond; P.kappa = prm->kappa; P.seed = prm->seed;
-  int nc = (int)std::floor(box);  // cell edge box / nc >= 1 = R_c
-  nc = nc < 1 ? 1 : (nc > 1024 ? 1024 : nc);
+  int nc, cap;
+  dpd_geometry(N, box, &nc, &cap);
   P.ncell = nc;
-  const double mean = (double)N / ((double)nc * nc * nc);
-  P.cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
+  P.cap = cap;
   P.inv_cell = (double)nc / box;
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
-  d->q = (double *)d->alloc(n * sizeof(double));
-  d->v0 = (double *)d->alloc(3 * n * sizeof(double));
-  d->fdpd = (double *)d->alloc(3 * n * sizeof(double));
-  d->felec = (double *)d->alloc(3 * n * sizeof(double));
-  d->e5 = (double *)d->alloc(5 * sizeof(double));
-  d->dcnt = (int *)d->alloc(nc3 * sizeof(int));
-  d->cpos = (double4 *)d->alloc(nc3 * (size_t)P.cap * sizeof(double4));
-  d->cvel = (double4 *)d->alloc(nc3 * (size_t)P.cap * sizeof(double4));
-  d->bond_start = (int *)d->alloc((n + 1) * sizeof(int));
-  d->bond_to = (int *)d->alloc(to.size() * sizeof(int));
-  d->status = (int *)d->alloc(sizeof(int));
-  d->dslot = (int *)d->alloc(n * sizeof(int));
-  d->step_ctr = (unsigned long long *)d->alloc(sizeof(unsigned long long));
-  if (d->allocations.size() != 13) { set_error("device allocation failed"); delete d; return nullptr; }
+  const std::array<size_t, kDpdBuffers> sz = dpd_buffer_bytes(N, box, nbonds);
+  void *ptr[kDpdBuffers];
+  if (!d->alloc_arena(sz.data(), kDpdBuffers, ptr)) { set_error("device allocation failed"); delete d; return nullptr; }
+  d->q = (double *)ptr[0];
+  d->v0 = (double *)ptr[1];
+  d->fdpd = (double *)ptr[2];
+  d->e5 = (double *)ptr[3];
+  d->dcnt = (int *)ptr[4];
+  d->cpos = (double4 *)ptr[5];
+  d->cvel = (double4 *)ptr[6];
+  d->bond_start = (int *)ptr[7];
+  d->bond_to = (int *)ptr[8];
+  d->status = (int *)ptr[9];
+  d->dslot = (int *)ptr[10];
+  d->step_ctr = (unsigned long long *)ptr[11];
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
 
-      hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
     set_error("device setup of the DPD integrator failed");
     delete d;
     return nullptr;
@@ -852,6 +998,23 @@ void enuf_dpd_destroy(enuf_dpd *d) {
 size_t enuf_dpd_footprint_bytes(const enuf_dpd *d) {
   if (!d) return 0;
   return d->bytes + (d->plan ? d->plan->bytes : 0);
+}
+
+size_t enuf_plan_footprint_estimate(int64_t N, double box, int p, int M, int Kc, double r_cut) {
+  if (N < 1 || !finite_pos(box) || p < 1 || M < 4 || Kc < 1 || !finite_pos(r_cut)) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const size_t lds = lds_budget(dev);
+  PlanGeom g;
+  if (lds == 0 || !plan_geometry(N, box, p, M, Kc, r_cut, lds, &g)) return 0;
+  const auto sz = plan_buffer_bytes(N, p, M, Kc, g);
+  return arena_bytes(sz.data(), kPlanBuffers);
+}
+
+size_t enuf_dpd_footprint_estimate(int64_t N, double box, int64_t nbonds) {
+  if (N < 1 || !finite_pos(box) || nbonds < 0) return 0;
+  const auto sz = dpd_buffer_bytes(N, box, nbonds);
+  return arena_bytes(sz.data(), kDpdBuffers);
 }
 
 }  // extern "C"

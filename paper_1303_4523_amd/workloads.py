@@ -199,3 +199,31 @@ def replica(s, n_min=3000, n_max=48000, seed_base=BASE_SEED + 4):
 def batched_replicas(nsys=64):
     """The batched workload: nsys independent polyelectrolyte replicas."""
     return [replica(s) for s in range(nsys)]
+
+
+def serving_request(r, n_min=3000, n_max=200000, seed_base=BASE_SEED + 5):
+    """Request r of the serving stream: N log-uniform in [n_min, n_max] at
+    density 3, a fraction c ~ U[0.05, 1] of the beads charged as
+    n = round(c N / (1 + z)) cations at +z and z n anions at -1 (neutral),
+    z uniform in {1, 2, 3}; no bonds; M = smallest even 2^a 3^b 5^c >= 3.2 L,
+    Kc = min(floor(0.8 L), floor(M / 4))."""
+    seed = seed_base + 1000 * r
+    rng = _rng(seed)
+    n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+    L = (n / 3.0) ** (1.0 / 3.0)
+    c = rng.uniform(0.05, 1.0)
+    z = int(rng.integers(1, 4))
+    n_cat = int(round(c * n / (1 + z)))
+    s = electrolyte(L, n, n_cat, z * n_cat, seed + 1, z_plus=float(z), z_minus=-1.0, with_velocities=True)
+    M = mesh_size(3.2 * L)
+    Kc = min(int(math.floor(0.8 * L + 1e-9)), M // 4)
+    s.meta["enuf"] = enuf_params(L, M=M, Kc=Kc)
+    s.meta["dpd"] = dict(DPD_DEFAULTS, L=L, seed=seed)
+    s.meta["name"] = f"request {r}: N={n} L={L:.3f} c={c:.3f} z={z} M={M} Kc={Kc}"
+    return s
+
+
+def poisson_arrivals(n, rate, seed=BASE_SEED + 6):
+    """n arrival times (seconds) of a Poisson stream with the given rate."""
+    rng = _rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

@@ -193,3 +193,54 @@ def test_pair_lanes_do_not_change_results(lanes):
     got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy())
     d.close()
     assert _same(got, _alone(s, 3, precision="fp64")[:3])
+
+
+def _requests(ids, n_max=12000, steps=10, rate=None):
+    from paper_1303_4523_amd.serving import Request
+    t = wl.poisson_arrivals(len(ids), rate) if rate else np.zeros(len(ids))
+    return [Request(rid=r, arrival=float(a), system=wl.serving_request(r, n_max=n_max), steps=steps)
+            for r, a in zip(ids, t)]
+
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    """Requests of different N, charge fraction and valency arriving over time
+    are served with continuous batching; each result is bitwise the one the
+    request gets when its system is stepped alone."""
+    from paper_1303_4523_amd.serving import Server, latency_stats
+    reqs = _requests(range(8), rate=400.0)
+    print("case: serving", [r.system.meta["name"] for r in reqs], flush=True)
+    srv = Server(hbm_budget=8 << 30, precision="mixed", device=0, keep_state=True)
+    res = srv.serve(reqs)
+    srv.close()
+    assert len(res) == len(reqs) and all(r.status == 0 for r in res)
+    st = latency_stats(res)
+    print(f"serving: {st}, peak members {srv.peak_members}")
+    for r in res:
+        s = reqs[r.rid].system
+        alone = _alone(s, 10)
+        assert _same(r.state, alone[:3]), s.meta["name"]
+        assert np.array_equal(r.energy5, alone[3])
+
+
+def test_serving_admission_respects_the_budget():
+    """With a budget that holds only a few systems, admission waits for memory
+    (first come, first served) and the resident footprint never exceeds it;
+    the estimate equals the footprint the created system holds."""
+    from paper_1303_4523_amd.serving import Server, footprint_estimate
+    reqs = _requests(range(6), n_max=9000, steps=4)
+    est = [footprint_estimate(r.system) for r in reqs]
+    budget = int(2.5 * max(est))
+    srv = Server(hbm_budget=budget, precision="mixed", device=0)
+    res = srv.serve(reqs)
+    srv.close()
+    print(f"case: budget {budget} B, peak used {srv.peak_used} B, peak members {srv.peak_members}", flush=True)
+    assert all(r.status == 0 for r in res) and len(res) == len(reqs)
+    assert srv.peak_used <= budget
+    assert srv.peak_members < len(reqs)
+    by_id = {r.rid: r for r in res}
+    assert all(by_id[i].footprint == est[i] for i in range(len(reqs)))
+    # a request larger than the whole budget is rejected, not queued forever
+    srv2 = Server(hbm_budget=min(est) // 2, precision="mixed", device=0)
+    res2 = srv2.serve(reqs[:1])
+    srv2.close()
+    assert res2[0].status == -1 and res2[0].steps == 0
