@@ -14,6 +14,7 @@ struct DpdParams {
   int ncell;                        // DPD cells per side (edge >= R_c = 1)
   int cap;                          // slots per cell
   double inv_cell;
+  int group4, group8;               // cells per wavefront group of the pair kernel at 4 / 8 lanes per particle
 };
 
 // Charges of a DPD system are fixed, so their compaction into an ENUF plan is
@@ -64,8 +65,12 @@ struct BatchMember {
 // Batched launches: map[b] = (member, block of that member) for block b.
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
 hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st);
-// Blocks of the pair kernel for N particles at `lanes` (4 or 8) lanes per particle.
-int pair_blocks(int64_t N, int lanes);
+// Cells per wavefront group of the pair kernel: about 3/4 of the 64/lanes
+// particles a wavefront takes per round, at the mean cell occupancy.
+int pair_group_cells(double cell_mean, int lanes);
+// Blocks of the pair kernel at `lanes` (4 or 8) lanes per particle; a multiple
+// of 8 (whole rounds over the XCDs).
+int pair_blocks(const DpdParams &P, int lanes);
 hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, const int2 *fwd, int nfwd, const int2 *x,
                               int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,

@@ -150,8 +150,13 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// Q lanes per particle i (Q = 4 or 8; 64/Q particles per wavefront) split
-// the 27 neighbour cells.  Scan: each lane walks the slots of its cells and
+// Pair forces in cell order.  A wavefront takes a group of consecutive DPD
+// cells (z fastest) and their particles, 64/Q at a time with Q = 4 or 8 lanes
+// per particle; the particles of one wavefront are neighbours, so they read
+// the same neighbour cells.  Blocks are mapped so that each of the 8 XCDs
+// (which take the blocks of a launch round-robin) works on one contiguous
+// slab of cells, keeping its L2 working set to that slab and its halo.
+// Scan: each lane walks the slots of its share of the 27 neighbour cells and
 // the pairs with r < R_c = 1 are appended to a wavefront queue in LDS.
 // Evaluation: the whole wavefront takes the queued pairs 64 at a time (so the
 // Philox draw and the pair force run with full lanes however sparse the
@@ -160,69 +165,53 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
 // (theta_ij = theta_ji keeps the pair forces antisymmetric), so no thread
 // writes another particle's force; the fixed-point sums (2^-36) are exact, so
 // the result does not depend on the order in which pairs are visited.
+// Particles beyond a full cell's capacity (reported as ENUF_EOVERFLOW by the
+// binning) get no force.
 constexpr int kPairThreads = 256;
 constexpr int kPairQueue = 128;  // queued pairs per wavefront (flushed at > 64)
+constexpr int kXcds = 8;         // MI355X: blocks of a launch are dealt round-robin to 8 XCDs
 
 template <int Q>
 __device__ __forceinline__ void
-dpd_pair_body(int64_t N, const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
-              gptr<const double> __restrict__ v0, gptr<const int> __restrict__ dcnt,
-              gptr<const double4> __restrict__ cpos, gptr<const double4> __restrict__ cvel,
-              gptr<const int> __restrict__ bond_start, gptr<const int> __restrict__ bond_to,
-              gptr<double> __restrict__ fdpd, int bid) {
+dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
+              gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
+              gptr<const double4> __restrict__ cvel, gptr<const int> __restrict__ bond_start,
+              gptr<const int> __restrict__ bond_to, gptr<double> __restrict__ fdpd, int pb, int nb) {
   constexpr int PPW = kWave / Q;
   constexpr int NW = kPairThreads / kWave;
   __shared__ int s_qs[NW][kPairQueue];
   __shared__ int s_ql[NW][kPairQueue];
   __shared__ double s_rv[NW][PPW][6];
+  __shared__ int s_id[NW][PPW];
   __shared__ unsigned long long s_f[NW][PPW][3];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int64_t base = ((int64_t)bid * NW + w) * PPW;
-  if (base >= N) return;  // whole wavefronts leave together
+  const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
+  const int n = P.ncell, cap = P.cap;
+  const int G = Q == 8 ? P.group8 : P.group4;
+  const int64_t nc3 = (int64_t)n * n * n;
+  const int64_t c0 = ((int64_t)lb * NW + w) * G;
+  if (c0 >= nc3) return;  // whole wavefronts leave together
+  const int ng = (int)((nc3 - c0) < G ? (nc3 - c0) : G);
+  int total = 0;
+  for (int k = 0; k < ng; ++k) {
+    const int ck = dcnt[c0 + k];
+    total += ck < cap ? ck : cap;
+  }
   const int lp = lane / Q, quad = lane % Q;
-  const bool has = base + lp < N;
-  const int i = (int)(base + lp);
   const double L = P.L, invL = 1.0 / L, isdt = 1.0 / sqrt(P.dt);
   int *qs = s_qs[w], *ql = s_ql[w];
-  double rx = 0.0, ry = 0.0, rz = 0.0;
-  if (has) {
-    rx = pos[3 * i];
-    ry = pos[3 * i + 1];
-    rz = pos[3 * i + 2];
-    if (quad < 3) s_f[w][lp][quad] = 0ull;
-    if (quad == 0) {
-      s_rv[w][lp][0] = rx;
-      s_rv[w][lp][1] = ry;
-      s_rv[w][lp][2] = rz;
-      s_rv[w][lp][3] = v0[3 * i];
-      s_rv[w][lp][4] = v0[3 * i + 1];
-      s_rv[w][lp][5] = v0[3 * i + 2];
-    }
-  }
-  const int n = P.ncell;
-  const int cx = dpd_cell_of(rx, P.inv_cell, n), cy = dpd_cell_of(ry, P.inv_cell, n),
-            cz = dpd_cell_of(rz, P.inv_cell, n);
-  // cursor over the lane's cells o = quad, quad + Q, ... and their slots
-  int o = has ? quad : 27, s = 0, cnt = 0;
-  size_t cb = 0;
-  for (; o < 27; o += Q) {
-    const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-    if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
-    const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-    cnt = dcnt[c];
-    cnt = cnt < P.cap ? cnt : P.cap;
-    cb = (size_t)c * P.cap;
-    if (cnt > 0) break;
-  }
 
-  auto flush = [&](int qn) {
+  auto wave_sync = []() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  auto flush = [&](int qn) {
+    wave_sync();
     for (int e = lane; e < qn; e += kWave) {
       const int l = ql[e];
       const int slot = qs[e];
-      const int ii = (int)(base + l);
+      const int ii = s_id[w][l];
       const double4 ej = gload(cpos + slot);
       const double4 vj = gload(cvel + slot);
       const int j = (int)ej.w;
@@ -241,90 +230,145 @@ dpd_pair_body(int64_t N, const DpdParams &P, uint64_t step, gptr<const double> _
       atomicAdd(&s_f[w][l][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
       atomicAdd(&s_f[w][l][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();
   };
 
-  int qn = 0;  // wavefront-uniform queue length
-  while (true) {
-    const bool live = o < 27;
-    if (__ballot(live) == 0ull) break;
-    bool take = false;
-    int slot = 0;
-    if (live) {
-      const double4 e = gload(cpos + cb + s);
-      const int j = (int)e.w;
-      double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
-      dx -= L * rint(dx * invL);
-      dy -= L * rint(dy * invL);
-      dz -= L * rint(dz * invL);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
-      slot = (int)(cb + s);
-      if (++s >= cnt) {  // next non-empty cell of this lane
-        s = 0;
-        for (o += Q; o < 27; o += Q) {
-          const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-          if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
-          const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-          cnt = dcnt[c];
-          cnt = cnt < P.cap ? cnt : P.cap;
-          cb = (size_t)c * P.cap;
-          if (cnt > 0) break;
-        }
+  for (int r0 = 0; r0 < total; r0 += PPW) {
+    // particle r0 + lp of the group: cell ci, slot sl
+    const int pidx = r0 + lp;
+    const bool has = pidx < total;
+    int ci = 0, own = 0, i = -1;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (has) {
+      int k = 0, rem = pidx;
+      for (; k < ng - 1; ++k) {
+        int ck = dcnt[c0 + k];
+        ck = ck < cap ? ck : cap;
+        if (rem < ck) break;
+        rem -= ck;
+      }
+      ci = (int)(c0 + k);
+      own = ci * cap + rem;
+      const double4 e = gload(cpos + own);
+      rx = e.x;
+      ry = e.y;
+      rz = e.z;
+      i = (int)e.w;
+      if (quad < 3) s_f[w][lp][quad] = 0ull;
+      if (quad == 0) {
+        const double4 v = gload(cvel + own);
+        s_rv[w][lp][0] = rx;
+        s_rv[w][lp][1] = ry;
+        s_rv[w][lp][2] = rz;
+        s_rv[w][lp][3] = v.x;
+        s_rv[w][lp][4] = v.y;
+        s_rv[w][lp][5] = v.z;
+        s_id[w][lp] = i;
       }
     }
-    const unsigned long long m = __ballot(take);
-    if (take) {
-      const int at = qn + (int)__popcll(m & __lanemask_lt());
-      qs[at] = slot;
-      ql[at] = lp;
+    const int cx = ci / (n * n), cy = (ci / n) % n, cz = ci % n;
+    // cursor over the lane's cells o = quad, quad + Q, ... and their slots
+    int o = has ? quad : 27, s = 0, cnt = 0;
+    size_t cb = 0;
+    for (; o < 27; o += Q) {
+      const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+      if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
+      const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
+      cnt = dcnt[c];
+      cnt = cnt < cap ? cnt : cap;
+      cb = (size_t)c * cap;
+      if (cnt > 0) break;
     }
-    qn += (int)__popcll(m);
-    if (qn > kPairQueue - kWave) {
-      flush(qn);
-      qn = 0;
+    int qn = 0;  // wavefront-uniform queue length
+    while (true) {
+      const bool live = o < 27;
+      if (__ballot(live) == 0ull) break;
+      bool take = false;
+      int slot = 0;
+      if (live) {
+        const double4 e = gload(cpos + cb + s);
+        const int j = (int)e.w;
+        double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
+        dx -= L * rint(dx * invL);
+        dy -= L * rint(dy * invL);
+        dz -= L * rint(dz * invL);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
+        slot = (int)(cb + s);
+        if (++s >= cnt) {  // next non-empty cell of this lane
+          s = 0;
+          for (o += Q; o < 27; o += Q) {
+            const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+            if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
+            const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
+            cnt = dcnt[c];
+            cnt = cnt < cap ? cnt : cap;
+            cb = (size_t)c * cap;
+            if (cnt > 0) break;
+          }
+        }
+      }
+      const unsigned long long m = __ballot(take);
+      if (take) {
+        const int at = qn + (int)__popcll(m & __lanemask_lt());
+        qs[at] = slot;
+        ql[at] = lp;
+      }
+      qn += (int)__popcll(m);
+      if (qn > kPairQueue - kWave) {
+        flush(qn);
+        qn = 0;
+      }
     }
-  }
-  flush(qn);
+    flush(qn);
 
-  // harmonic bonds of i, F_i = -K (r - r0) rhat_ij
-  if (has && quad == 0) {
-    long long fx = (long long)s_f[w][lp][0], fy = (long long)s_f[w][lp][1], fz = (long long)s_f[w][lp][2];
-    for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
-      const int j = bond_to[b];
-      double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
-      dx -= L * rint(dx * invL);
-      dy -= L * rint(dy * invL);
-      dz -= L * rint(dz * invL);
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      if (r == 0.0) continue;
-      const double mag = -P.k_bond * (r - P.r0_bond) / r;
-      fx += to_fixed(mag * dx, kRealFxScale);
-      fy += to_fixed(mag * dy, kRealFxScale);
-      fz += to_fixed(mag * dz, kRealFxScale);
+    // harmonic bonds of i, F_i = -K (r - r0) rhat_ij
+    if (has && quad == 0) {
+      long long fx = (long long)s_f[w][lp][0], fy = (long long)s_f[w][lp][1], fz = (long long)s_f[w][lp][2];
+      for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
+        const int j = bond_to[b];
+        double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
+        dx -= L * rint(dx * invL);
+        dy -= L * rint(dy * invL);
+        dz -= L * rint(dz * invL);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r == 0.0) continue;
+        const double mag = -P.k_bond * (r - P.r0_bond) / r;
+        fx += to_fixed(mag * dx, kRealFxScale);
+        fy += to_fixed(mag * dy, kRealFxScale);
+        fz += to_fixed(mag * dz, kRealFxScale);
+      }
+      fdpd[3 * i] = (double)fx * kRealFxInv;
+      fdpd[3 * i + 1] = (double)fy * kRealFxInv;
+      fdpd[3 * i + 2] = (double)fz * kRealFxInv;
     }
-    fdpd[3 * i] = (double)fx * kRealFxInv;
-    fdpd[3 * i + 1] = (double)fy * kRealFxInv;
-    fdpd[3 * i + 2] = (double)fz * kRealFxInv;
+    wave_sync();  // the next round reuses the LDS rows of this one
   }
 }
 
 template <int Q>
 __global__ void __launch_bounds__(kPairThreads)
-k_dpd_pair(int64_t N, DpdParams P, uint64_t step, const double *__restrict__ pos,
-           const double *__restrict__ v0, const int *__restrict__ dcnt,
+k_dpd_pair(DpdParams P, uint64_t step, const double *__restrict__ pos, const int *__restrict__ dcnt,
            const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
-           const int *__restrict__ bond_start, const int *__restrict__ bond_to,
-           double *__restrict__ fdpd) {
-  dpd_pair_body<Q>(N, P, step, to_g(pos), to_g(v0), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start),
-                   to_g(bond_to), to_g(fdpd), blockIdx.x);
+           const int *__restrict__ bond_start, const int *__restrict__ bond_to, double *__restrict__ fdpd) {
+  dpd_pair_body<Q>(P, step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start), to_g(bond_to),
+                   to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
-int pair_blocks(int64_t N, int lanes) {
-  const int64_t per_block = (int64_t)(kPairThreads / lanes);
-  return (int)((N + per_block - 1) / per_block);
+int pair_group_cells(double cell_mean, int lanes) {
+  const double per_round = 0.75 * (double)(kWave / lanes);
+  int g = (int)(per_round / (cell_mean > 0.0 ? cell_mean : 1.0));
+  return g < 1 ? 1 : (g > 64 ? 64 : g);
+}
+
+int pair_blocks(const DpdParams &P, int lanes) {
+  const int64_t G = lanes == 8 ? P.group8 : P.group4;
+  const int64_t nc3 = (int64_t)P.ncell * P.ncell * P.ncell;
+  const int64_t waves = (nc3 + G - 1) / G;
+  const int64_t nw = kPairThreads / kWave;
+  int64_t blocks = (waves + nw - 1) / nw;
+  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+  return (int)blocks;
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -361,8 +405,8 @@ __global__ void __launch_bounds__(kPairThreads)
 kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pair_body<Q>(m.N, m.P, *m.step, to_g(m.pos), to_g(m.v0), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
-                   to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y);
+  dpd_pair_body<Q>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel), to_g(m.bond_start),
+                   to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
@@ -404,14 +448,16 @@ hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const d
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
                            const int *bond_start, const int *bond_to, double *fdpd, int lanes,
                            hipStream_t st, KernelTimer *tm) {
-  const int nb = pair_blocks(N, lanes);
+  (void)N;
+  (void)v0;
+  const int nb = pair_blocks(P, lanes);
   if (tm) tm->before(1, st);
   if (lanes == 8)
-    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), 0, st, N, P, step, pos, v0, dcnt, cpos,
-                       cvel, bond_start, bond_to, fdpd);
+    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), 0, st, P, step, pos, dcnt, cpos, cvel,
+                       bond_start, bond_to, fdpd);
   else
-    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), 0, st, N, P, step, pos, v0, dcnt, cpos,
-                       cvel, bond_start, bond_to, fdpd);
+    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), 0, st, P, step, pos, dcnt, cpos, cvel,
+                       bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }

@@ -742,6 +742,9 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   P.ncell = nc;
   P.cap = cap;
   P.inv_cell = (double)nc / box;
+  const double cell_mean = (double)N / ((double)nc * nc * nc);
+  P.group4 = pair_group_cells(cell_mean, 4);
+  P.group8 = pair_group_cells(cell_mean, 8);
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
   const std::array<size_t, kDpdBuffers> sz = dpd_buffer_bytes(N, box, nbonds);
   void *ptr[kDpdBuffers];
@@ -1087,7 +1090,7 @@ BatchMember member_view(const enuf_batch::Member &mb, int pair_lanes) {
   m.buf = pl->buf;
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
-  m.pair_blocks = pair_blocks(d->N, pair_lanes);
+  m.pair_blocks = pair_blocks(d->P, pair_lanes);
   const int64_t g = (d->nq + 3) / 4;
   m.real_blocks = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   m.fscale = (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
