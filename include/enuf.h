@@ -93,6 +93,17 @@ int enuf_plan_set_stream(enuf_plan *plan, void *hip_stream);
 /* Choose the precision mode (ENUF_FP64 / ENUF_MIXED) and window (ENUF_WINDOW_*). */
 int enuf_plan_set_options(enuf_plan *plan, int precision, int window);
 
+/* Forces of the reciprocal sum.
+ *   ENUF_FORCE_GRADIENT (default): the exact gradient of the NFFT energy -- one
+ *     inverse transform, gathered with the window's gradient.
+ *   ENUF_FORCE_IK: ik-differentiation (eq. 24-25) -- the three fields i k_t h
+ *     transformed back and gathered with the window; conserves total momentum
+ *     to rounding.  energy5[4] (the gathered-potential check) is 0 in this mode.
+ * Returns ENUF_EINVAL if the mesh does not fit the LDS in this mode. */
+#define ENUF_FORCE_GRADIENT 0
+#define ENUF_FORCE_IK       1
+int enuf_plan_set_force_mode(enuf_plan *plan, int mode);
+
 /*
  * Energy and forces (eq. 16, 18, 22-25, 27, 31).
  *   pos    : N x 3 row-major FP64 positions; any real values, wrapped into [0, box)

@@ -38,6 +38,8 @@ lib.enuf_plan_status.argtypes = [_vp, ctypes.POINTER(_int)]
 lib.enuf_plan_status.restype = _int
 lib.enuf_plan_footprint_bytes.argtypes = [_vp]
 lib.enuf_plan_footprint_bytes.restype = _sz
+lib.enuf_plan_set_force_mode.argtypes = [_vp, _int]
+lib.enuf_plan_set_force_mode.restype = _int
 
 
 
@@ -114,7 +116,7 @@ EXPORTED = [
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_batch_set_tuning", "enuf_batch_autotune", "enuf_dpd_set_tuning",
-    "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate",
+    "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
 ]
 
 # Status codes (include/enuf.h).
@@ -125,6 +127,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
                 ECOINCIDENT: "ECOINCIDENT", EOVERFLOW: "EOVERFLOW"}
 FP64, MIXED = 0, 1
 WINDOW_KB, WINDOW_GAUSS = 0, 1
+FORCE_GRADIENT, FORCE_IK = 0, 1
 
 
 class EnufError(RuntimeError):

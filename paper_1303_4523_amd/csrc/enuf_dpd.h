@@ -72,9 +72,9 @@ int pair_group_cells(double cell_mean, int lanes);
 // of 8 (whole rounds over the XCDs).
 int pair_blocks(const DpdParams &P, int lanes);
 hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
-hipError_t launch_batch_recip(const BatchMember *mem, int precision, const int2 *fwd, int nfwd, const int2 *x,
-                              int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
-                              hipStream_t st);
+hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
+                              const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
+                              size_t lds_bwd, hipStream_t st);
 // Combine for every member, then the final energies (one block per member).
 hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *map, int nmap, int mode,
                                 hipStream_t st);

@@ -57,6 +57,7 @@ struct MeshParams {
   int nchunk;      // ceil(M / rows)
   int nslot;       // gather partials per (charge, x offset): 1, or 2 when a
                    // charge's 2p rows can straddle two chunks
+  int ik;          // forces: 0 window gradient, 1 ik-differentiation (eq. 24-25)
   double L;
   double m_over_l; // M / L: mesh coordinate t = x * m_over_l
   WindowParams win;
@@ -104,6 +105,7 @@ struct ComputeBuffers {
   long long *blk_er;         // [2 nblk] per-block sums of ereal over the particles of the block
   // reciprocal
   void *gzy;             // [M * nky * Kc] complex (double2 or float2)
+  void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
   double *epart;         // [nky] k-space energy per ky row
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
   int *xcnt;             // [M] charges per mesh x-cell (zero between calls)

@@ -624,16 +624,17 @@ template <typename T>
 __device__ __forceinline__ void
 recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
              gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<typename CplxOf<T>::type> gzy,
-             gptr<double> epart, int kyi) {
+             gptr<typename CplxOf<T>::type> gzx, gptr<double> epart, int kyi) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int ky = kyi - (Kc - 1);
-  T *Xre = reinterpret_cast<T *>(smem);
-  T *Xim = Xre + (size_t)Kc * Mz;
-  T *twr = Xim + (size_t)Kc * Mz;
+  const int nset = mp.ik ? 2 : 1;  // ik: also i kx h, for the x component of the field
+  T *Xre = reinterpret_cast<T *>(smem);  // [nset Kc][Mz]: lines of h, then of i kx h
+  T *Xim = Xre + (size_t)nset * Kc * Mz;
+  T *twr = Xim + (size_t)nset * Kc * Mz;
   T *twi = twr + M;
-  const size_t red_off = ((2 * (size_t)Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
+  const size_t red_off = ((2 * (size_t)nset * Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
   double *red = reinterpret_cast<double *>(smem + red_off);
   double *at = red + kPassThreads / kWave;  // [nky] influence table
 
@@ -671,17 +672,25 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
     }
     Xre[kz * Mz + m] = hr;
     Xim[kz * Mz + m] = hi;
+    if (nset == 2) {  // i kx (hr + i hi)
+      Xre[(Kc + kz) * Mz + m] = -(T)kx * hi;
+      Xim[(Kc + kz) * Mz + m] = (T)kx * hr;
+    }
   }
   e = block_sum(e, red);
   if (tid == 0) epart[kyi] = e;
   __syncthreads();
-  lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, true);
-  for (int id = tid; id < M * Kc; id += nt) {
-    const int x = id / Kc, kz = id % Kc;
-    typename CplxOf<T>::type v;
-    v.x = kz < nkz ? Xre[kz * Mz + x] : (T)0;
-    v.y = kz < nkz ? Xim[kz * Mz + x] : (T)0;
-    gstore(gzy + ((size_t)x * nky + kyi) * Kc + kz, v);
+  for (int set = 0; set < nset; ++set) {
+    T *re = Xre + (size_t)set * Kc * Mz, *im = Xim + (size_t)set * Kc * Mz;
+    lds_fft<T>(re, im, Mz, nkz, mp.fft, twr, twi, true);
+    gptr<typename CplxOf<T>::type> dst = set == 0 ? gzy : gzx;
+    for (int id = tid; id < M * Kc; id += nt) {
+      const int x = id / Kc, kz = id % Kc;
+      typename CplxOf<T>::type v;
+      v.x = kz < nkz ? re[kz * Mz + x] : (T)0;
+      v.y = kz < nkz ? im[kz * Mz + x] : (T)0;
+      gstore(dst + ((size_t)x * nky + kyi) * Kc + kz, v);
+    }
   }
 }
 
@@ -689,8 +698,8 @@ template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
 k_recip_x(MeshParams mp, const double *__restrict__ atab,
           const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy,
-          double *epart) {
-  recip_x_body<T>(mp, to_g(atab), to_g(tw), to_g(gzy), to_g(epart), blockIdx.x);
+          typename CplxOf<T>::type *gzx, double *epart) {
+  recip_x_body<T>(mp, to_g(atab), to_g(tw), to_g(gzy), to_g(gzx), to_g(epart), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,13 +707,14 @@ k_recip_x(MeshParams mp, const double *__restrict__ atab,
 // Each lane of a work-item group sums its mesh row against the z window and
 // its derivative (shared across the group); the group reduces with shuffles.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool IK>
 __device__ __forceinline__ void
 recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ xcnt,
                gptr<const int> __restrict__ xslot, gptr<const T> __restrict__ wcoef,
                gptr<const DevScalars> __restrict__ sc, const MeshParams &mp,
                gptr<const typename CplxOf<T>::type> __restrict__ tw,
-               gptr<const typename CplxOf<T>::type> __restrict__ gzy, gptr<double4> part, int x0) {
+               gptr<const typename CplxOf<T>::type> __restrict__ gzy,
+               gptr<const typename CplxOf<T>::type> __restrict__ gzx, gptr<double4> part, int x0) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
   const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
@@ -731,132 +741,162 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
     twi[m] = t.y;
   }
   for (int k = tid; k < P2 * (2 * D + 1); k += nt) cv[k] = wcoef[k];
-  for (int k = tid; k < 2 * Kc * Mz; k += nt) Zre[k] = (T)0;
-  __syncthreads();
-  for (int id = tid; id < nky * Kc; id += nt) {
-    const int kyi = id / Kc, kz = id % Kc;
-    const int m = mod_pos(kyi - (Kc - 1), M);
-    const typename CplxOf<T>::type v = gload(gzy + ((size_t)x0 * nky + kyi) * Kc + kz);
-    Zre[kz * Mz + m] = v.x;
-    Zim[kz * Mz + m] = v.y;
-  }
-  __syncthreads();
-  lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
   const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
-
   const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
   const int gbase = lane & ~(P2pad - 1);
-  for (int r0 = 0; r0 < M; r0 += R) {
-    const int nr = (M - r0) < R ? (M - r0) : R;
-    // Hermitian z spectra of rows r0 + 2c and r0 + 2c + 1 packed as H1 + i H2
-    for (int id = tid; id < (nr / 2) * M; id += nt) {
-      const int c = id / M, k = id % M, y = r0 + 2 * c;
-      T re = (T)0, im = (T)0;
-      if (k < Kc) {
-        const T h1r = Zre[k * Mz + y], h1i = Zim[k * Mz + y];
-        const T h2r = Zre[k * Mz + y + 1], h2i = Zim[k * Mz + y + 1];
-        if (k == 0) {
-          re = h1r;
-          im = h2r;
-        } else {
-          re = h1r - h2i;
-          im = h1i + h2r;
-        }
-      } else if (k > M - Kc) {
-        const int kk = M - k;
-        const T h1r = Zre[kk * Mz + y], h1i = Zim[kk * Mz + y];
-        const T h2r = Zre[kk * Mz + y + 1], h2i = Zim[kk * Mz + y + 1];
-        re = h1r + h2i;
-        im = h2r - h1i;
+  // Gradient forces: one field h, gathered with the window and its gradient.
+  // ik forces (eq. 24-25): the three fields i k_t h, gathered with the window.
+  constexpr int ncomp = IK ? 3 : 1;
+#pragma unroll 1
+  for (int comp = 0; comp < ncomp; ++comp) {
+    for (int k = tid; k < 2 * Kc * Mz; k += nt) Zre[k] = (T)0;
+    __syncthreads();
+    gptr<const typename CplxOf<T>::type> src = (IK && comp == 0) ? gzx : gzy;
+    for (int id = tid; id < nky * Kc; id += nt) {
+      const int kyi = id / Kc, kz = id % Kc;
+      const int m = mod_pos(kyi - (Kc - 1), M);
+      typename CplxOf<T>::type v = gload(src + ((size_t)x0 * nky + kyi) * Kc + kz);
+      if (IK && comp > 0) {  // times i ky or i kz
+        const T k = (T)(comp == 1 ? kyi - (Kc - 1) : kz);
+        const T re = -k * v.y, im = k * v.x;
+        v.x = re;
+        v.y = im;
       }
-      plane[2 * c * Mp + k] = re;
-      plane[(2 * c + 1) * Mp + k] = im;
+      Zre[kz * Mz + m] = v.x;
+      Zim[kz * Mz + m] = v.y;
     }
     __syncthreads();
-    lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, true);
+    lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
 
-    const int chunk = r0 / R;
-    for (int it = tid; it < items; it += nt) {
-      const int e = it / P2pad, sy = it % P2pad;
-      const bool has = e < total, act = has && sy < P2;
-      bool in = false;
-      int j = 0, sx = 0, row = 0, bz = 0, cy = 0;
-      T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
-      if (has) {
-        int b;
-        j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-        sx = P2 - 1 - b;
-        const double4 c = gload(xq + j);
-        double fx, fy, fz;
-        cell_frac(c.x, mp.m_over_l, M, &fx);
-        cy = cell_frac(c.y, mp.m_over_l, M, &fy);
-        const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
-        if (act) {
-          const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
-          wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
-          dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
-          wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
-          dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
-          row = mod_pos(cy - p + 1 + sy, M) - r0;
-          in = (unsigned)row < (unsigned)nr;
-          if (in) {
-            wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
-            dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
+    for (int r0 = 0; r0 < M; r0 += R) {
+      const int nr = (M - r0) < R ? (M - r0) : R;
+      // Hermitian z spectra of rows r0 + 2c and r0 + 2c + 1 packed as H1 + i H2
+      for (int id = tid; id < (nr / 2) * M; id += nt) {
+        const int c = id / M, k = id % M, y = r0 + 2 * c;
+        T re = (T)0, im = (T)0;
+        if (k < Kc) {
+          const T h1r = Zre[k * Mz + y], h1i = Zim[k * Mz + y];
+          const T h2r = Zre[k * Mz + y + 1], h2i = Zim[k * Mz + y + 1];
+          if (k == 0) {
+            re = h1r;
+            im = h2r;
           } else {
-            row = 0;
+            re = h1r - h2i;
+            im = h1i + h2r;
           }
-          bz = cz - p + 1;
+        } else if (k > M - Kc) {
+          const int kk = M - k;
+          const T h1r = Zre[kk * Mz + y], h1i = Zim[kk * Mz + y];
+          const T h2r = Zre[kk * Mz + y + 1], h2i = Zim[kk * Mz + y + 1];
+          re = h1r + h2i;
+          im = h2r - h1i;
         }
+        plane[2 * c * Mp + k] = re;
+        plane[(2 * c + 1) * Mp + k] = im;
       }
-      const T *hrow = plane + (size_t)row * Mp;
-      int col = bz < 0 ? bz + M : bz;
-      T a = (T)0, bsum = (T)0;
-      for (int sz = 0; sz < P2; ++sz) {
-        const T w = __shfl(wz, gbase + sz, kWave);
-        const T d = __shfl(dwz, gbase + sz, kWave);
-        if (in) {
-          const T h = hrow[col];
-          a += h * w;
-          bsum += h * d;
-          col = (col + 1 == M) ? 0 : col + 1;
+      __syncthreads();
+      lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, true);
+
+      const int chunk = r0 / R;
+      for (int it = tid; it < items; it += nt) {
+        const int e = it / P2pad, sy = it % P2pad;
+        const bool has = e < total, act = has && sy < P2;
+        bool in = false;
+        int j = 0, sx = 0, row = 0, bz = 0, cy = 0;
+        T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
+        if (has) {
+          int b;
+          j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
+          sx = P2 - 1 - b;
+          const double4 c = gload(xq + j);
+          double fx, fy, fz;
+          cell_frac(c.x, mp.m_over_l, M, &fx);
+          cy = cell_frac(c.y, mp.m_over_l, M, &fy);
+          const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
+          if (act) {
+            const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
+            wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
+            wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
+            if (!IK) {
+              dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
+              dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
+            }
+            row = mod_pos(cy - p + 1 + sy, M) - r0;
+            in = (unsigned)row < (unsigned)nr;
+            if (in) {
+              wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
+              if (!IK) dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
+            } else {
+              row = 0;
+            }
+            bz = cz - p + 1;
+          }
         }
-      }
-      T A = wy * a, By = dwy * a, Bz = wy * bsum;
-      for (int o = P2pad / 2; o >= 1; o >>= 1) {
-        A += __shfl_xor(A, o, kWave);
-        By += __shfl_xor(By, o, kWave);
-        Bz += __shfl_xor(Bz, o, kWave);
-      }
-      if (has && sy == 0) {
-        const double4 v = make_double4((double)(dwx * A), (double)(wx * By), (double)(wx * Bz),
-                                       (double)(wx * A));
-        const gptr<double4> dst = part + ((size_t)j * P2 + sx) * nslot;
-        if (nslot == 1) {
-          gstore(dst, v);
-        } else {
-          // chunk of the charge's first and last stencil rows
-          const int first = mod_pos(cy - p + 1, M) / R, last = mod_pos(cy + p, M) / R;
-          if (chunk == first) {
-            gstore(dst, v);
-            if (first == last) gstore(dst + 1, make_double4(0.0, 0.0, 0.0, 0.0));
-          } else if (chunk == last) {
-            gstore(dst + 1, v);
+        const T *hrow = plane + (size_t)row * Mp;
+        int col = bz < 0 ? bz + M : bz;
+        T a = (T)0, bsum = (T)0;
+        for (int sz = 0; sz < P2; ++sz) {
+          const T w = __shfl(wz, gbase + sz, kWave);
+          const T d = __shfl(dwz, gbase + sz, kWave);
+          if (in) {
+            const T h = hrow[col];
+            a += h * w;
+            bsum += h * d;
+            col = (col + 1 == M) ? 0 : col + 1;
+          }
+        }
+        T A = wy * a, By = dwy * a, Bz = wy * bsum;
+        for (int o = P2pad / 2; o >= 1; o >>= 1) {
+          A += __shfl_xor(A, o, kWave);
+          By += __shfl_xor(By, o, kWave);
+          Bz += __shfl_xor(Bz, o, kWave);
+        }
+        if (has && sy == 0) {
+          // the chunk of the charge's first stencil row writes slot 0 (and
+          // clears slot 1 when all its rows are in that chunk); the chunk of
+          // its last row writes slot 1
+          int slot = 0;
+          bool write = true, clear1 = false;
+          if (nslot > 1) {
+            const int first = mod_pos(cy - p + 1, M) / R, last = mod_pos(cy + p, M) / R;
+            write = chunk == first || chunk == last;
+            slot = chunk == first ? 0 : 1;
+            clear1 = chunk == first && first == last;
+          }
+          if (write) {
+            const gptr<double4> dst = part + ((size_t)j * P2 + sx) * nslot;
+            if (!IK) {
+              gstore(dst + slot, make_double4((double)(dwx * A), (double)(wx * By), (double)(wx * Bz),
+                                              (double)(wx * A)));
+              if (clear1) gstore(dst + 1, make_double4(0.0, 0.0, 0.0, 0.0));
+            } else {
+              // component comp of the field; the potential entry stays zero
+              const gptr<double> d = (gptr<double>)(dst + slot);
+              d[comp] = (double)(wx * A);
+              if (comp == 0) d[3] = 0.0;
+              if (clear1) {
+                const gptr<double> d1 = (gptr<double>)(dst + 1);
+                d1[comp] = 0.0;
+                if (comp == 0) d1[3] = 0.0;
+              }
+            }
           }
         }
       }
+      __syncthreads();  // the next chunk overwrites the plane
     }
-    __syncthreads();  // the next chunk overwrites the plane
   }
 }
 
-template <typename T>
+template <typename T, bool IK>
 __global__ void __launch_bounds__(kPassThreads)
 k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
             const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
             const typename CplxOf<T>::type *__restrict__ tw,
-            const typename CplxOf<T>::type *__restrict__ gzy, double4 *part) {
-  recip_bwd_body<T>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy), to_g(part),
-                    blockIdx.x);
+            const typename CplxOf<T>::type *__restrict__ gzy, const typename CplxOf<T>::type *__restrict__ gzx,
+            double4 *part) {
+  recip_bwd_body<T, IK>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy),
+                        to_g(gzx), to_g(part), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1023,18 +1063,20 @@ kb_recip_x(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
   recip_x_body<T>(m.cfg.mesh, to_g(m.buf.atab), to_g(MemberTables<T>::tw(m.buf)),
-                  to_g(reinterpret_cast<C *>(m.buf.gzy)), to_g(m.buf.epart), w.y);
+                  to_g(reinterpret_cast<C *>(m.buf.gzy)), to_g(reinterpret_cast<C *>(m.buf.gzx)), to_g(m.buf.epart),
+                  w.y);
 }
 
-template <typename T>
+template <typename T, bool IK>
 __global__ void __launch_bounds__(kPassThreads)
 kb_recip_bwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   using C = typename CplxOf<T>::type;
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  recip_bwd_body<T>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
+  recip_bwd_body<T, IK>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
                     to_g(m.buf.sc), m.cfg.mesh, to_g(MemberTables<T>::tw(m.buf)),
-                    to_g(reinterpret_cast<const C *>(m.buf.gzy)), to_g(m.buf.part), w.y);
+                    to_g(reinterpret_cast<const C *>(m.buf.gzy)), to_g(reinterpret_cast<const C *>(m.buf.gzx)),
+                    to_g(m.buf.part), w.y);
 }
 
 __global__ void __launch_bounds__(kPrepThreads)
@@ -1068,21 +1110,28 @@ hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, 
 }
 
 template <typename T>
-static void launch_batch_mesh(const BatchMember *mem, const int2 *fwd, int nfwd, const int2 *x, int nx,
+static void launch_batch_mesh(const BatchMember *mem, int ik, const int2 *fwd, int nfwd, const int2 *x, int nx,
                               const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
                               hipStream_t st) {
   if (nfwd > 0) hipLaunchKernelGGL(kb_recip_fwd<T>, dim3(nfwd), dim3(kPassThreads), lds_fwd, st, mem, fwd);
   if (nx > 0) hipLaunchKernelGGL(kb_recip_x<T>, dim3(nx), dim3(kPassThreads), lds_x, st, mem, x);
-  if (nbwd > 0) hipLaunchKernelGGL(kb_recip_bwd<T>, dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem, bwd);
+  if (nbwd > 0) {
+    if (ik)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, true>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
+                         bwd);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, false>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
+                         bwd);
+  }
 }
 
-hipError_t launch_batch_recip(const BatchMember *mem, int precision, const int2 *fwd, int nfwd, const int2 *x,
-                              int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
-                              hipStream_t st) {
+hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
+                              const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
+                              size_t lds_bwd, hipStream_t st) {
   if (precision == 0)
-    launch_batch_mesh<double>(mem, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+    launch_batch_mesh<double>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
   else
-    launch_batch_mesh<float>(mem, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+    launch_batch_mesh<float>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
   return hipGetLastError();
 }
 
@@ -1106,7 +1155,7 @@ void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, 
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
   *fwd = acc + zp + tw + misc;
-  *x = ((zp + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) +
+  *x = ((zp * (m.ik ? 2 : 1) + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) +
        (size_t)m.nky * sizeof(double) + 16;
   *bwd = rows_t + zp + tw + misc;
 }
@@ -1146,15 +1195,15 @@ hipError_t configure_kernels(size_t max_lds) {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_recip_x<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_recip_bwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_recip_bwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  if (e != hipSuccess) return e;
-  const void *batched[] = {(const void *)kb_recip_fwd<double>, (const void *)kb_recip_fwd<float>,
-                           (const void *)kb_recip_x<double>,   (const void *)kb_recip_x<float>,
-                           (const void *)kb_recip_bwd<double>, (const void *)kb_recip_bwd<float>};
-  for (const void *f : batched) {
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  const void *more[] = {(const void *)k_recip_bwd<double, false>,  (const void *)k_recip_bwd<float, false>,
+                        (const void *)k_recip_bwd<double, true>,   (const void *)k_recip_bwd<float, true>,
+                        (const void *)kb_recip_fwd<double>,        (const void *)kb_recip_fwd<float>,
+                        (const void *)kb_recip_x<double>,          (const void *)kb_recip_x<float>,
+                        (const void *)kb_recip_bwd<double, false>, (const void *)kb_recip_bwd<float, false>,
+                        (const void *)kb_recip_bwd<double, true>,  (const void *)kb_recip_bwd<float, true>};
+  const void *const *batched = more;
+  for (size_t k = 0; k < sizeof(more) / sizeof(more[0]); ++k) {
+    e = hipFuncSetAttribute(batched[k], hipFuncAttributeMaxDynamicSharedMemorySize, v);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1172,12 +1221,18 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
                      (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gzy);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
-  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy, b.epart);
+  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy,
+                     reinterpret_cast<C *>(b.gzx), b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
-  hipLaunchKernelGGL(k_recip_bwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st, (const double4 *)b.xq,
-                     (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw,
-                     (const C *)gzy, b.part);
+  if (mp.ik)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, true>), dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st,
+                       (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
+                       (const DevScalars *)b.sc, mp, tw, (const C *)gzy, (const C *)b.gzx, b.part);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, false>), dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st,
+                       (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
+                       (const DevScalars *)b.sc, mp, tw, (const C *)gzy, (const C *)b.gzx, b.part);
   if (tm) tm->after(7, st);
 }
 
@@ -1227,7 +1282,7 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
   const int nblk = cfg.nblk;
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   const double L = cfg.L;
-  const double fscale = (double)cfg.mesh.M / (M_PI * L * L);
+  const double fscale = cfg.mesh.ik ? 2.0 / (L * L) : (double)cfg.mesh.M / (M_PI * L * L);
   const double inv2piL = 1.0 / (2.0 * M_PI * L);
   const int kid = fa.mode < 0 ? 8 : 9;
   if (tm) tm->before(kid, st);

@@ -326,7 +326,7 @@ bool plan_geometry(int64_t N, double box, int p, int M, int Kc, double r_cut, si
   return g->part_slots > 0;
 }
 
-constexpr int kPlanBuffers = 23;
+constexpr int kPlanBuffers = 24;
 
 // Bytes of every device buffer of a plan, in allocation order.
 std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int Kc, const PlanGeom &g) {
@@ -345,6 +345,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           n * 2 * sizeof(unsigned long long),                 // ereal
           nblk * 2 * sizeof(long long),                       // blk_er
           (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzy
+          (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzx
           nky * sizeof(double),                               // epart
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
@@ -459,16 +460,17 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.ereal = (unsigned long long *)ptr[10];
   b.blk_er = (long long *)ptr[11];
   b.gzy = ptr[12];
-  b.epart = (double *)ptr[13];
-  b.part = (double4 *)ptr[14];
-  b.blk_eg = (double *)ptr[15];
-  b.xcnt = (int *)ptr[16];
-  b.xslot = (int *)ptr[17];
-  b.wcoef64 = (double *)ptr[18];
-  b.wcoef32 = (float *)ptr[19];
-  b.atab = (double *)ptr[20];
-  b.tw64 = (double2 *)ptr[21];
-  b.tw32 = (float2 *)ptr[22];
+  b.gzx = ptr[13];
+  b.epart = (double *)ptr[14];
+  b.part = (double4 *)ptr[15];
+  b.blk_eg = (double *)ptr[16];
+  b.xcnt = (int *)ptr[17];
+  b.xslot = (int *)ptr[18];
+  b.wcoef64 = (double *)ptr[19];
+  b.wcoef32 = (float *)ptr[20];
+  b.atab = (double *)ptr[21];
+  b.tw64 = (double2 *)ptr[22];
+  b.tw32 = (float2 *)ptr[23];
   if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
       hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(b.ccnt, 0, ncell3 * sizeof(int)) != hipSuccess ||
@@ -551,6 +553,25 @@ int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
     plan->cfg.mesh.nslot = old_mesh.nslot;
     return rc;
   }
+  plan->cfg.lds_fwd = f;
+  plan->cfg.lds_x = x;
+  plan->cfg.lds_bwd = bw;
+  return ENUF_OK;
+}
+
+int enuf_plan_set_force_mode(enuf_plan *plan, int mode) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  if (mode != ENUF_FORCE_GRADIENT && mode != ENUF_FORCE_IK) { set_error("unknown force mode"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  MeshParams m = plan->cfg.mesh;
+  m.ik = mode == ENUF_FORCE_IK ? 1 : 0;
+  if (!mesh_choose_rows(m, plan->precision, plan->max_lds) || m.nslot > plan->part_slots) {
+    set_error("mesh too large for the LDS with this force mode and precision");
+    return ENUF_EINVAL;
+  }
+  size_t f = 0, x = 0, bw = 0;
+  mesh_lds_bytes(m, plan->precision, &f, &x, &bw);
+  plan->cfg.mesh = m;
   plan->cfg.lds_fwd = f;
   plan->cfg.lds_x = x;
   plan->cfg.lds_bwd = bw;
@@ -1041,6 +1062,7 @@ struct enuf_batch {
   int concurrent = 1;
   int use_graph = 1;
   int pair_lanes = 4;
+  int ik = -1;       // force mode of the members (all alike; -1 while empty)
   std::vector<Member> members;
   int next_id = 0;
   // device copies of the member table and the work maps (rebuilt when the
@@ -1093,7 +1115,7 @@ BatchMember member_view(const enuf_batch::Member &mb, int pair_lanes) {
   m.pair_blocks = pair_blocks(d->P, pair_lanes);
   const int64_t g = (d->nq + 3) / 4;
   m.real_blocks = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
-  m.fscale = (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
+  m.fscale = pl->cfg.mesh.ik ? 2.0 / (pl->cfg.L * pl->cfg.L) : (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
   m.inv2piL = 1.0 / (2.0 * M_PI * pl->cfg.L);
   m.N = d->N;
   m.P = d->P;
@@ -1201,8 +1223,8 @@ hipError_t batch_step(enuf_batch *b, bool fork) {
   if (e == hipSuccess) e = launch_batch_real(b->dmem, mp + o[2], o[3] - o[2], s1);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
   if (e == hipSuccess)
-    e = launch_batch_recip(b->dmem, b->precision, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4], mp + o[5],
-                           o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st);
+    e = launch_batch_recip(b->dmem, b->precision, b->ik, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4],
+                           mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st);
   if (fork)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->join_ev[k], 0);
   if (e == hipSuccess) e = launch_batch_combine(b->dmem, b->nmem, mp + o[6], o[7] - o[6], 0, st);
@@ -1280,6 +1302,10 @@ int enuf_batch_add(enuf_batch *b, enuf_dpd *d, double *pos, double *vel, double 
   }
   for (const auto &mb : b->members)
     if (mb.d == d) { set_error("integrator is already a member"); return ENUF_EINVAL; }
+  if (!b->members.empty() && cf.mesh.ik != b->ik) {
+    set_error("integrator force mode differs from the other members'");
+    return ENUF_EINVAL;
+  }
   // the member's own stream may still be working on it
   HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
   d->stream = b->stream;
@@ -1287,6 +1313,7 @@ int enuf_batch_add(enuf_batch *b, enuf_dpd *d, double *pos, double *vel, double 
   HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, b->stream), ENUF_EDEVICE);
   enuf_batch::Member mb{b->next_id++, d, pos, vel, force};
   b->members.push_back(mb);
+  b->ik = cf.mesh.ik;
   b->dirty = true;
   return mb.id;
 }

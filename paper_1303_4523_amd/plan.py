@@ -50,6 +50,12 @@ class Plan:
         check(lib.enuf_plan_set_options(self._h, pr, wi), "enuf_plan_set_options")
         self.precision, self.window = precision, window
 
+    def set_force_mode(self, mode="gradient"):
+        """'gradient' (exact gradient of the NFFT energy) or 'ik' (eq. 24-25)."""
+        m = {"gradient": _lib.FORCE_GRADIENT, "ik": _lib.FORCE_IK}[mode]
+        check(lib.enuf_plan_set_force_mode(self._h, m), "enuf_plan_set_force_mode")
+        self.force_mode = mode
+
     def _bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.enuf_plan_set_stream(self._h, ctypes.c_void_p(s)), "enuf_plan_set_stream")
