@@ -15,6 +15,9 @@ Contents
 * ``dpd_forces`` / ``dpd_step``: the modified velocity-Verlet DPD step of
   Table 2 with the pair forces of eq. 2-7, harmonic bonds and the
   electrostatic force above.
+* ``pair_histogram`` / ``chain_rg2``: the pair-distance histogram by class
+  behind the radial distribution functions (Sec. 5) and the radius of
+  gyration of a chain (Sec. 6).
 * ``philox4x32_10`` / ``theta``: the counter-based generator that supplies
   the random variable theta_ij (``philox4x64_10`` is kept and pinned too).
 * ``nfft_mirror``: a NumPy re-statement of the NFFT reciprocal path (window
@@ -40,7 +43,9 @@ class _DPDParams(ctypes.Structure):
                 ("k_bond", ctypes.c_double), ("r0_bond", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("r_cut", ctypes.c_double), ("lambda_e", ctypes.c_double),
-                ("Kc", ctypes.c_int), ("use_elec", ctypes.c_int)]
+                ("Kc", ctypes.c_int), ("use_elec", ctypes.c_int),
+                ("nspec", ctypes.c_int), ("species", ctypes.c_void_p),
+                ("atab", ctypes.c_double * 16)]
 
 
 def _load():
@@ -57,6 +62,10 @@ def _load():
     lib.oracle_real.restype = ctypes.c_int
     lib.oracle_recip.argtypes = [i64, ip, ip, d, d, ctypes.c_int, i64, ip, ip, ip]
     lib.oracle_recip.restype = ctypes.c_int
+    lib.oracle_pair_histogram.argtypes = [i64, ip, i64, ip, ip, ctypes.c_int, d, d, ctypes.c_int, ip]
+    lib.oracle_pair_histogram.restype = ctypes.c_int
+    lib.oracle_chain_rg2.argtypes = [i64, ip, ctypes.c_int, ctypes.c_int, ip, d, ip]
+    lib.oracle_chain_rg2.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_self.argtypes = [i64, ip, d]
@@ -186,11 +195,25 @@ def theta(seed, step, i, j):
 
 
 def _params(p):
-    return _DPDParams(L=p["L"], a=p["a"], gamma=p["gamma"], sigma=p["sigma"], dt=p["dt"],
-                      lam=p["lam"], k_bond=p["k_bond"], r0_bond=p["r0_bond"],
-                      kappa=p.get("kappa", 0.0), alpha=p.get("alpha", 1.0),
-                      r_cut=p.get("r_cut", 1.0), lambda_e=p.get("lambda_e", 0.0),
-                      Kc=int(p.get("Kc", 1)), use_elec=int(p.get("use_elec", 0)))
+    """ctypes parameters; with p["species"] (int per particle) and p["a_table"]
+    (nspec x nspec) the conservative amplitude is a_{s_i s_j}.  Returns the
+    structure and the species array it points to (keep both alive)."""
+    P = _DPDParams(L=p["L"], a=p["a"], gamma=p["gamma"], sigma=p["sigma"], dt=p["dt"],
+                   lam=p["lam"], k_bond=p["k_bond"], r0_bond=p["r0_bond"],
+                   kappa=p.get("kappa", 0.0), alpha=p.get("alpha", 1.0),
+                   r_cut=p.get("r_cut", 1.0), lambda_e=p.get("lambda_e", 0.0),
+                   Kc=int(p.get("Kc", 1)), use_elec=int(p.get("use_elec", 0)))
+    sp = None
+    if p.get("species") is not None:
+        sp = np.ascontiguousarray(np.asarray(p["species"], dtype=np.int32))
+        tab = np.asarray(p["a_table"], dtype=np.float64)
+        ns = tab.shape[0]
+        P.nspec = ns
+        P.species = sp.ctypes.data
+        for a in range(ns):
+            for b in range(ns):
+                P.atab[4 * a + b] = tab[a, b]
+    return P, sp
 
 
 def dpd_forces(pos, vel, q, bonds, params, seed, step):
@@ -203,7 +226,7 @@ def dpd_forces(pos, vel, q, bonds, params, seed, step):
     b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int64).reshape(-1, 2))
     F = np.zeros_like(pos)
     E = np.zeros(1)
-    P = _params(params)
+    P, _sp = _params(params)
     st = lib.oracle_dpd_forces(len(q), _ptr(pos), _ptr(vel), _ptr(q), len(b), _ptr(b),
                                ctypes.byref(P), seed, step, _ptr(F), _ptr(E))
     _check(st, "oracle_dpd_forces")
@@ -220,8 +243,35 @@ def dpd_step(pos, vel, F, q, bonds, params, seed, step):
     q = _f64(q)
     b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int64).reshape(-1, 2))
     E = np.zeros(1)
-    P = _params(params)
+    P, _sp = _params(params)
     st = lib.oracle_dpd_step(len(q), _ptr(pos), _ptr(vel), _ptr(F), _ptr(q), len(b), _ptr(b),
                              ctypes.byref(P), seed, step, _ptr(E))
     _check(st, "oracle_dpd_step")
     return pos, vel, F, float(E[0])
+
+
+def pair_histogram(pos, sel, cls, ncls, L, r_max, nbins):
+    """Counts of unordered selected pairs by (class_lo, class_hi, bin of r);
+    returns a (ncls, ncls, nbins) uint64 array (only lo <= hi filled)."""
+    lib = _load()
+    pos = _f64(pos, (-1, 3))
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    cls = np.ascontiguousarray(np.asarray(cls, dtype=np.int32))
+    h = np.zeros((ncls, ncls, nbins), dtype=np.uint64)
+    st = lib.oracle_pair_histogram(len(pos), _ptr(pos), len(sel), _ptr(sel), _ptr(cls), int(ncls), float(L),
+                                   float(r_max), int(nbins), _ptr(h))
+    _check(st, "oracle_pair_histogram")
+    return h
+
+
+def chain_rg2(pos, beads, L):
+    """Squared radius of gyration of each chain; beads is (nchains, len)."""
+    lib = _load()
+    pos = _f64(pos, (-1, 3))
+    b = np.ascontiguousarray(np.asarray(beads, dtype=np.int64))
+    if b.ndim == 1:
+        b = b[None, :]
+    out = np.zeros(b.shape[0])
+    st = lib.oracle_chain_rg2(len(pos), _ptr(pos), b.shape[0], b.shape[1], _ptr(b), float(L), _ptr(out))
+    _check(st, "oracle_chain_rg2")
+    return out

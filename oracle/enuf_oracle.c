@@ -472,6 +472,9 @@ typedef struct {
     double lambda_e;
     int Kc;
     int use_elec;      /* 0: no electrostatics */
+    int nspec;         /* species (0 or 1: every pair uses a) */
+    const int *species;/* [n] species of each particle, in [0, nspec) (nspec > 1) */
+    double atab[16];   /* a_ij = atab[4 s_i + s_j], symmetric, nspec <= 4 (Sec. 2) */
 } oracle_dpd_params;
 
 /*
@@ -487,6 +490,12 @@ int oracle_dpd_forces(int64_t n, const double *pos, const double *vel, const dou
                       uint64_t seed, uint64_t step, double *F, double *E_elec)
 {
     if (n < 1 || !P || !(P->L > 0.0) || !(P->dt > 0.0)) return OR_EINVAL;
+    const int typed = P->nspec > 1;
+    if (typed) {
+        if (P->nspec > 4 || !P->species) return OR_EINVAL;
+        for (int64_t i = 0; i < n; ++i)
+            if (P->species[i] < 0 || P->species[i] >= P->nspec) return OR_EINVAL;
+    }
     const double L = P->L, isdt = 1.0 / sqrt(P->dt);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -503,7 +512,9 @@ int oracle_dpd_forces(int64_t n, const double *pos, const double *vel, const dou
             double vdot = (vel[3 * i] - vel[3 * j]) * e[0] + (vel[3 * i + 1] - vel[3 * j + 1]) * e[1]
                           + (vel[3 * i + 2] - vel[3 * j + 2]) * e[2];
             double th = oracle_theta(seed, step, i, j);
-            double mag = P->a * wr - P->gamma * wr * wr * vdot + P->sigma * wr * th * isdt;
+            /* eq. 3: the conservative amplitude of the pair's two species */
+            double aij = typed ? P->atab[4 * P->species[i] + P->species[j]] : P->a;
+            double mag = aij * wr - P->gamma * wr * wr * vdot + P->sigma * wr * th * isdt;
             fx += mag * e[0];
             fy += mag * e[1];
             fz += mag * e[2];
@@ -570,4 +581,91 @@ int oracle_dpd_step(int64_t n, double *pos, double *vel, double *F, const double
         for (int64_t i = 0; i < 3 * n; ++i) vel[i] += 0.5 * dt * F[i];
     free(v0);
     return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Structure observables (Sec. 5: radial distribution functions;        */
+/* Sec. 6: radius of gyration of a chain)                               */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Pair-distance histogram by class.  Every unordered pair {sel[a], sel[b]},
+ * a < b, of the nsel selected particles is counted once, at the minimum-image
+ * distance r, into hist[(c_lo * ncls + c_hi) * nbins + k] (c_lo <= c_hi the
+ * pair's classes) for the bin k with (k w)^2 <= r^2 < ((k + 1) w)^2,
+ * w = r_max / nbins; pairs beyond the last edge are not counted.  hist is
+ * accumulated (not cleared).  The bin is decided on r^2 against the squared
+ * edges (k w)(k w), so it does not depend on how a square root rounds.
+ */
+int oracle_pair_histogram(int64_t n, const double *pos, int64_t nsel, const int64_t *sel,
+                          const int *cls, int ncls, double L, double r_max, int nbins,
+                          uint64_t *hist)
+{
+    if (n < 0 || nsel < 0 || ncls < 1 || nbins < 1 || !(L > 0.0) || !(r_max > 0.0)) return OR_EINVAL;
+    for (int64_t a = 0; a < nsel; ++a)
+        if (sel[a] < 0 || sel[a] >= n || cls[a] < 0 || cls[a] >= ncls) return OR_EINVAL;
+    const double w = r_max / nbins;
+    double *edge = (double *)malloc(sizeof(double) * (size_t)(nbins + 1));
+    if (!edge) return OR_ENOMEM;
+    for (int k = 0; k <= nbins; ++k) {
+        double e = (double)k * w;
+        edge[k] = e * e;
+    }
+    for (int64_t a = 0; a < nsel; ++a) {
+        for (int64_t b = a + 1; b < nsel; ++b) {
+            double d[3];
+            min_image(&pos[3 * sel[b]], &pos[3 * sel[a]], L, d);
+            double r2 = d[0] * d[0] + d[1] * d[1];
+            r2 = r2 + d[2] * d[2];
+            if (!(r2 < edge[nbins])) continue;
+            int k = (int)(sqrt(r2) / w);
+            if (k > nbins - 1) k = nbins - 1;
+            while (k > 0 && edge[k] > r2) --k;
+            while (k < nbins - 1 && edge[k + 1] <= r2) ++k;
+            int lo = cls[a] < cls[b] ? cls[a] : cls[b];
+            int hi = cls[a] < cls[b] ? cls[b] : cls[a];
+            hist[((size_t)lo * ncls + hi) * nbins + k] += 1;
+        }
+    }
+    free(edge);
+    return OR_OK;
+}
+
+/*
+ * Squared radius of gyration of nchains chains of len beads each; chain c is
+ * beads[c * len .. c * len + len - 1] in bond order.  The chain is unwrapped
+ * by following the minimum image from each bead to the next (bonds shorter
+ * than L / 2), then Rg^2 = (1/len) sum_k |u_k - u_cm|^2 with u_cm the mean of
+ * the unwrapped beads.  out[c] receives Rg^2.
+ */
+int oracle_chain_rg2(int64_t n, const double *pos, int nchains, int len, const int64_t *beads,
+                     double L, double *out)
+{
+    if (nchains < 0 || len < 1 || !(L > 0.0)) return OR_EINVAL;
+    double *u = (double *)malloc(sizeof(double) * 3 * (size_t)len);
+    if (!u) return OR_ENOMEM;
+    for (int c = 0; c < nchains; ++c) {
+        const int64_t *bd = beads + (size_t)c * len;
+        for (int k = 0; k < len; ++k)
+            if (bd[k] < 0 || bd[k] >= n) { free(u); return OR_EINVAL; }
+        for (int a = 0; a < 3; ++a) u[a] = pos[3 * bd[0] + a];
+        for (int k = 1; k < len; ++k) {
+            double d[3];
+            min_image(&pos[3 * bd[k]], &pos[3 * bd[k - 1]], L, d);
+            for (int a = 0; a < 3; ++a) u[3 * k + a] = u[3 * (k - 1) + a] + d[a];
+        }
+        double cm[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < len; ++k)
+            for (int a = 0; a < 3; ++a) cm[a] += u[3 * k + a];
+        for (int a = 0; a < 3; ++a) cm[a] /= len;
+        double s = 0.0;
+        for (int k = 0; k < len; ++k)
+            for (int a = 0; a < 3; ++a) {
+                double v = u[3 * k + a] - cm[a];
+                s += v * v;
+            }
+        out[c] = s / len;
+    }
+    free(u);
+    return OR_OK;
 }

@@ -146,3 +146,40 @@ def test_step_follows_table2_order():
     assert np.abs(p1 - pr).max() < 1e-13
     assert np.abs(F1 - Fr).max() < 1e-9 * np.abs(Fr).max()
     assert np.abs(v1 - (vh + 0.5 * dt * Fr)).max() < 1e-12
+
+
+def test_species_amplitudes_hand_computed():
+    """eq. 3 with species-dependent amplitudes (a_ij = a_ii + 2.05 chi, Sec. 2):
+    three beads on a line at x = 0, 0.5, 0.9 of species 0, 1, 2 with
+    a_01 = 10, a_02 = 20, a_12 = 30 and no dissipation or noise.  Worked by
+    hand: F_0 = -10 (0.5) - 20 (0.1) = -7, F_1 = 10 (0.5) - 30 (0.6) = -13,
+    F_2 = 20 (0.1) + 30 (0.6) = 20 along x."""
+    L = 10.0
+    pos = np.array([[1.0, 2.0, 2.0], [1.5, 2.0, 2.0], [1.9, 2.0, 2.0]])
+    tab = np.array([[1.0, 10.0, 20.0], [10.0, 2.0, 30.0], [20.0, 30.0, 3.0]])
+    P = dict(BASE, L=L, gamma=0.0, sigma=0.0, k_bond=0.0, species=[0, 1, 2], a_table=tab)
+    F, _ = oracle.dpd_forces(pos, np.zeros((3, 3)), np.zeros(3), np.zeros((0, 2)), P, seed=1, step=0)
+    assert np.allclose(F[:, 0], [-7.0, -13.0, 20.0], rtol=0, atol=1e-12)
+    assert np.all(F[:, 1:] == 0.0)
+
+
+def test_species_reduce_to_one_amplitude():
+    """A table whose every entry is a gives the single-species forces bit for
+    bit, and relabelling the species with the table permuted alike changes
+    nothing (the force depends on the pair's amplitude only)."""
+    pos, vel, q, bonds = _dpd_box(200, 5.0, 3, chain=10)
+    P = dict(BASE, L=5.0)
+    F1, _ = oracle.dpd_forces(pos, vel, q, bonds, P, seed=5, step=2)
+    sp = (np.arange(200) % 3).astype(np.int32)
+    F2, _ = oracle.dpd_forces(pos, vel, q, bonds, dict(P, species=sp, a_table=np.full((3, 3), 25.0)),
+                              seed=5, step=2)
+    assert np.array_equal(F1, F2)
+    tab = np.array([[25.0, 27.0, 31.0], [27.0, 26.0, 29.0], [31.0, 29.0, 24.0]])
+    F3, _ = oracle.dpd_forces(pos, vel, q, bonds, dict(P, species=sp, a_table=tab), seed=5, step=2)
+    perm = np.array([2, 0, 1])           # old species s becomes perm[s]
+    tab2 = np.empty_like(tab)
+    tab2[np.ix_(perm, perm)] = tab
+    F4, _ = oracle.dpd_forces(pos, vel, q, bonds, dict(P, species=perm[sp], a_table=tab2), seed=5, step=2)
+    assert np.array_equal(F3, F4)
+    assert not np.allclose(F1, F3)
+    assert np.abs(F3.sum(0)).max() < 1e-10 * np.abs(F3).max()
