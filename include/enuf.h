@@ -189,6 +189,18 @@ int enuf_dpd_forces(enuf_dpd *dpd, double *pos, const double *vel, double *force
 int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_t first_step,
                  int nsteps);
 
+/* Species-dependent conservative amplitudes (eq. 3; Sec. 2 sets
+ * a_ij = a_ii + 2.05 chi_ij between species).
+ *   nspecies : 1..4.  With 1, a_table[0] replaces params->a for every pair.
+ *   species  : HOST pointer to N ints in [0, nspecies), copied (ignored when
+ *              nspecies = 1).
+ *   a_table  : HOST pointer to the nspecies x nspecies row-major amplitudes;
+ *              must be symmetric (a_ij = a_ji keeps the pair force antisymmetric).
+ * The dissipative and random forces keep one gamma and sigma.  Synchronises
+ * the integrator's stream.  ENUF_EINVAL if the integrator is a member of a
+ * batch (set the species before enuf_batch_add), or on a bad argument. */
+int enuf_dpd_set_species(enuf_dpd *dpd, int nspecies, const int *species, const double *a_table);
+
 /* Overlap the pair forces and the real-space term with the mesh passes on two
  * internal streams (enable = 1, the default) or run the whole step on the
  * integrator's stream (0). */
@@ -237,7 +249,9 @@ void enuf_batch_destroy(enuf_batch *batch);
 
 /* The caller's stream (NULL = null stream): a run is ordered after the work
  * already queued on it and before work queued on it later.  Members use it as
- * their stream while they belong to the batch. */
+ * their stream while they belong to the batch.  Binding the stream the batch
+ * already uses does nothing; another stream first synchronises the batch's
+ * work and drops its captured graph. */
 int enuf_batch_set_stream(enuf_batch *batch, void *hip_stream);
 
 /* use_graph: replay one captured step (1, default) or launch eagerly (0);
@@ -304,6 +318,42 @@ int enuf_batch_autotune(enuf_batch *batch, int trial_steps, int *pair_lanes, int
 /* kernel = ENUF_K_* to start timing it (resets the totals), -1 to stop. */
 int enuf_dpd_time_kernel(enuf_dpd *dpd, int kernel, int max_launches);
 int enuf_dpd_kernel_time(enuf_dpd *dpd, double *total_ms, int *launches);
+
+/* ------------------------------------------------------------------------
+ * Structure observables, sampled on the device between steps (enqueued on
+ * hip_stream; NULL = null stream).  All pointers are DEVICE pointers.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Pair-distance histogram by class, the counts behind the radial distribution
+ * functions g_ab(r) of Sec. 5.  Every unordered pair {sel[a], sel[b]}, a < b,
+ * of the nsel selected particles is counted once, at its minimum-image distance
+ * r in the cubic box, into
+ *     hist[(c_lo * ncls + c_hi) * nbins + k],  c_lo = min(cls[a], cls[b]), c_hi = max,
+ * for the bin k with (k w)^2 <= r^2 < ((k + 1) w)^2, w = r_max / nbins; pairs
+ * beyond the last edge are not counted.  hist (ncls * ncls * nbins uint64) is
+ * accumulated, not cleared, so that successive samples add up.  The bin is
+ * decided in FP64 on r^2 against the squared edges, without fused
+ * multiply-adds, so the counts are those of a plain IEEE evaluation.
+ *   pos  : N x 3 FP64 positions; sel: nsel int64 indices; cls: nsel int32 classes.
+ * Entries with an index outside [0, n) or a class outside [0, ncls) are skipped.
+ * ENUF_EINVAL: ncls * ncls * nbins > 12288, nsel > 65535 * 256, box or r_max
+ * not finite and positive, NULL buffers.  Normalisation to g(r) is the
+ * caller's: g_ab = counts / (pairs_ab * shell volume / box^3 * samples).
+ */
+int enuf_pair_histogram(const double *pos, int64_t n, int64_t nsel, const int64_t *sel, const int *cls, int ncls,
+                        double box, double r_max, int nbins, unsigned long long *hist, void *hip_stream);
+
+/*
+ * Squared radius of gyration of nchains chains of len beads (Sec. 6).  Chain c
+ * is beads[c * len .. c * len + len - 1] (int64) in bond order; it is unwrapped
+ * by the minimum image of each bond vector (bonds shorter than box / 2), and
+ * out[c] = (1/len) sum_k |u_k - u_cm|^2 with u_cm the mean unwrapped position.
+ * A chain with a bead index outside [0, n) gets NaN.  Write to out + s * nchains
+ * to keep sample s of a trajectory on the device.
+ */
+int enuf_chain_rg2(const double *pos, int64_t n, int nchains, int len, const int64_t *beads, double box, double *out,
+                   void *hip_stream);
 
 #ifdef __cplusplus
 }

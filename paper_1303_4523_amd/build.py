@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libenuf.so")
-SOURCES = ["enuf_kernels.hip", "enuf_dpd.hip", "enuf_runtime.cpp"]
+SOURCES = ["enuf_kernels.hip", "enuf_dpd.hip", "enuf_observables.hip", "enuf_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

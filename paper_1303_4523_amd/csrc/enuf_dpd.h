@@ -15,6 +15,9 @@ struct DpdParams {
   int cap;                          // slots per cell
   double inv_cell;
   int group4, group8;               // cells per wavefront group of the pair kernel at 4 / 8 lanes per particle
+  int nspec;                        // > 1: the conservative amplitude depends on the pair's species
+  const int *species;               // [N] species of each particle (device; read when nspec > 1)
+  double atab[16];                  // a_ij = atab[4 s_i + s_j], symmetric (nspec <= 4)
 };
 
 // Charges of a DPD system are fixed, so their compaction into an ENUF plan is

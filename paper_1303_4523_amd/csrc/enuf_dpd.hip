@@ -105,7 +105,8 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
   const int s = atomicAdd(&dcnt[cell], 1);
   if (s < P.cap) {
     cpos[(size_t)cell * P.cap + s] = make_double4(r[0], r[1], r[2], (double)i);
-    cvel[(size_t)cell * P.cap + s] = make_double4(w[0], w[1], w[2], 0.0);
+    const double sp = P.nspec > 1 ? (double)P.species[i] : 0.0;
+    cvel[(size_t)cell * P.cap + s] = make_double4(w[0], w[1], w[2], sp);
   } else {
     atomicCAS(status, 0, kEOverflow);
   }
@@ -164,7 +165,9 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
 // accumulator in LDS.  Every pair is evaluated from both of its particles
 // (theta_ij = theta_ji keeps the pair forces antisymmetric), so no thread
 // writes another particle's force; the fixed-point sums (2^-36) are exact, so
-// the result does not depend on the order in which pairs are visited.
+// the result does not depend on the order in which pairs are visited.  With
+// species, the cell slot's predicted velocity carries the species in w and
+// the amplitude a_ij is read from the symmetric table in the parameters.
 // Particles beyond a full cell's capacity (reported as ENUF_EOVERFLOW by the
 // binning) get no force.
 constexpr int kPairThreads = 256;
@@ -183,6 +186,7 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
   __shared__ int s_ql[NW][kPairQueue];
   __shared__ double s_rv[NW][PPW][6];
   __shared__ int s_id[NW][PPW];
+  __shared__ int s_sp[NW][PPW];
   __shared__ unsigned long long s_f[NW][PPW][3];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
@@ -225,7 +229,8 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       const double wr = 1.0 - r;
       const double vdot = (s_rv[w][l][3] - vj.x) * ex + (s_rv[w][l][4] - vj.y) * ey + (s_rv[w][l][5] - vj.z) * ez;
       const double th = dpd_theta(P.seed, step, ii, j);
-      const double mag = P.a * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
+      const double aij = P.nspec > 1 ? P.atab[4 * s_sp[w][l] + (int)vj.w] : P.a;
+      const double mag = aij * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
       atomicAdd(&s_f[w][l][0], (unsigned long long)to_fixed(mag * ex, kRealFxScale));
       atomicAdd(&s_f[w][l][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
       atomicAdd(&s_f[w][l][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
@@ -264,6 +269,7 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
         s_rv[w][lp][4] = v.y;
         s_rv[w][lp][5] = v.z;
         s_id[w][lp] = i;
+        s_sp[w][lp] = (int)v.w;
       }
     }
     const int cx = ci / (n * n), cy = (ci / n) % n, cz = ci % n;

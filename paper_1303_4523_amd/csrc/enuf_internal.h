@@ -189,4 +189,14 @@ bool mesh_choose_rows(MeshParams &m, int precision, size_t max_lds);
 // Raise the per-kernel dynamic LDS limit where needed (once per process).
 hipError_t configure_kernels(size_t max_lds);
 
+// Structure observables (enuf_observables.hip).  Pair-distance histogram by
+// class: at most kHistMaxBins = classes^2 x bins counters (LDS-resident).
+constexpr int kHistMaxBins = 12288;
+constexpr int64_t kHistMaxSel = (int64_t)65535 * 256;
+hipError_t launch_pair_histogram(const double *pos, int64_t n, int64_t nsel, const int64_t *sel, const int *cls,
+                                 int ncls, double box, double r_max, int nbins, unsigned long long *hist,
+                                 hipStream_t st);
+hipError_t launch_chain_rg2(const double *pos, int64_t n, int nchains, int len, const int64_t *beads, double box,
+                            double *out, hipStream_t st);
+
 }  // namespace enuf

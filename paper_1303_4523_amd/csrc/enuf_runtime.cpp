@@ -637,7 +637,7 @@ void dpd_geometry(int64_t N, double box, int *nc_out, int *cap_out) {
   *cap_out = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
 }
 
-constexpr int kDpdBuffers = 12;
+constexpr int kDpdBuffers = 13;
 
 // Bytes of every device buffer of a DPD integrator, in allocation order.
 std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t nbonds) {
@@ -655,7 +655,8 @@ std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t 
           (size_t)(2 * nbonds > 0 ? 2 * nbonds : 1) * sizeof(int),   // bond_to
           sizeof(int),                                               // status
           n * sizeof(int),                                           // dslot
-          sizeof(unsigned long long)};                               // step_ctr
+          sizeof(unsigned long long),                                // step_ctr
+          n * sizeof(int)};                                          // species
 }
 
 }  // namespace
@@ -687,6 +688,8 @@ struct enuf_dpd {
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
   unsigned long long *step_ctr = nullptr;  // [1] next step index when stepped in a batch
   int pair_lanes = 4;                      // lanes per particle of the pair kernel (4 or 8)
+  int *species = nullptr;                  // [N] species of each particle (read when P.nspec > 1)
+  int batches = 0;                         // batches this integrator is a member of
   size_t bytes = 0;
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
@@ -782,12 +785,16 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   d->status = (int *)ptr[9];
   d->dslot = (int *)ptr[10];
   d->step_ctr = (unsigned long long *)ptr[11];
+  d->species = (int *)ptr[12];
+  P.nspec = 0;
+  P.species = d->species;
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
 
-      hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+      hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipMemset(d->species, 0, n * sizeof(int)) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess) {
     set_error("device setup of the DPD integrator failed");
     delete d;
     return nullptr;
@@ -1264,11 +1271,13 @@ void enuf_batch_destroy(enuf_batch *b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->own);
   (void)hipStreamSynchronize(b->stream);
+  for (auto &mb : b->members) --mb.d->batches;
   delete b;
 }
 
 int enuf_batch_set_stream(enuf_batch *b, void *hip_stream) {
   if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if ((hipStream_t)hip_stream == b->stream) return ENUF_OK;  // keeps the captured graph
   HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
   HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
   b->stream = (hipStream_t)hip_stream;
@@ -1313,6 +1322,7 @@ int enuf_batch_add(enuf_batch *b, enuf_dpd *d, double *pos, double *vel, double 
   HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, b->stream), ENUF_EDEVICE);
   enuf_batch::Member mb{b->next_id++, d, pos, vel, force};
   b->members.push_back(mb);
+  ++d->batches;
   b->ik = cf.mesh.ik;
   b->dirty = true;
   return mb.id;
@@ -1324,6 +1334,7 @@ int enuf_batch_remove(enuf_batch *b, int id) {
     if (b->members[k].id == id) {
       HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
       HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
+      --b->members[k].d->batches;
       b->members.erase(b->members.begin() + (long)k);
       b->dirty = true;
       return ENUF_OK;
@@ -1488,11 +1499,66 @@ int enuf_dpd_set_tuning(enuf_dpd *d, int pair_lanes) {
   return ENUF_OK;
 }
 
+int enuf_dpd_set_species(enuf_dpd *d, int nspecies, const int *species, const double *a_table) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  if (nspecies < 1 || nspecies > 4) { set_error("nspecies must be in [1, 4]"); return ENUF_EINVAL; }
+  if (!a_table || (nspecies > 1 && !species)) { set_error("NULL species or amplitude table"); return ENUF_EINVAL; }
+  if (d->batches > 0) { set_error("the integrator is a member of a batch"); return ENUF_EINVAL; }
+  for (int s = 0; s < nspecies; ++s)
+    for (int t = 0; t < nspecies; ++t) {
+      const double v = a_table[s * nspecies + t];
+      if (!std::isfinite(v)) { set_error("non-finite amplitude"); return ENUF_EINVAL; }
+      if (v != a_table[t * nspecies + s]) { set_error("the amplitude table must be symmetric"); return ENUF_EINVAL; }
+    }
+  const size_t n = (size_t)d->N;
+  if (nspecies > 1)
+    for (size_t i = 0; i < n; ++i)
+      if (species[i] < 0 || species[i] >= nspecies) { set_error("species out of range"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  DpdParams &P = d->P;
+  if (nspecies == 1) {
+    P.a = a_table[0];
+    P.nspec = 0;
+    return ENUF_OK;
+  }
+  HIP_OR_RETURN(hipMemcpy(d->species, species, n * sizeof(int), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  for (int k = 0; k < 16; ++k) P.atab[k] = 0.0;
+  for (int s = 0; s < nspecies; ++s)
+    for (int t = 0; t < nspecies; ++t) P.atab[4 * s + t] = a_table[s * nspecies + t];
+  P.nspec = nspecies;
+  return ENUF_OK;
+}
+
 size_t enuf_batch_footprint_bytes(const enuf_batch *b) {
   if (!b) return 0;
   size_t t = b->mem_cap * sizeof(BatchMember) + b->map_cap * sizeof(int2);
   for (const auto &mb : b->members) t += enuf_dpd_footprint_bytes(mb.d);
   return t;
+}
+
+int enuf_pair_histogram(const double *pos, int64_t n, int64_t nsel, const int64_t *sel, const int *cls, int ncls,
+                        double box, double r_max, int nbins, unsigned long long *hist, void *hip_stream) {
+  if (n < 0 || nsel < 0 || ncls < 1 || nbins < 1) { set_error("invalid sizes"); return ENUF_EINVAL; }
+  if ((int64_t)ncls * ncls * nbins > kHistMaxBins) { set_error("classes^2 x bins exceeds 12288"); return ENUF_EINVAL; }
+  if (nsel > kHistMaxSel) { set_error("too many selected particles"); return ENUF_EINVAL; }
+  if (!(std::isfinite(box) && box > 0.0) || !(std::isfinite(r_max) && r_max > 0.0)) {
+    set_error("box and r_max must be finite and > 0");
+    return ENUF_EINVAL;
+  }
+  if (!hist || (nsel > 0 && (!pos || !sel || !cls))) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(launch_pair_histogram(pos, n, nsel, sel, cls, ncls, box, r_max, nbins, hist,
+                                      (hipStream_t)hip_stream),
+                ENUF_EDEVICE);
+  return ENUF_OK;
+}
+
+int enuf_chain_rg2(const double *pos, int64_t n, int nchains, int len, const int64_t *beads, double box, double *out,
+                   void *hip_stream) {
+  if (n < 0 || nchains < 0 || len < 1) { set_error("invalid sizes"); return ENUF_EINVAL; }
+  if (!(std::isfinite(box) && box > 0.0)) { set_error("box must be finite and > 0"); return ENUF_EINVAL; }
+  if (nchains > 0 && (!pos || !beads || !out)) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(launch_chain_rg2(pos, n, nchains, len, beads, box, out, (hipStream_t)hip_stream), ENUF_EDEVICE);
+  return ENUF_OK;
 }
 
 }  // extern "C"

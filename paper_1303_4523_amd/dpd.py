@@ -71,6 +71,21 @@ class DPD:
         """Lanes per particle of the pair-force kernel (4 or 8)."""
         check(lib.enuf_dpd_set_tuning(self._h, int(pair_lanes)), "enuf_dpd_set_tuning")
 
+    def set_species(self, species, a_table):
+        """Species-dependent conservative amplitudes a_ij (eq. 3): species is
+        an int per particle in [0, nspecies), a_table the symmetric
+        nspecies x nspecies amplitudes (nspecies <= 4).  Set before the
+        integrator joins a batch."""
+        tab = np.ascontiguousarray(np.asarray(a_table, dtype=np.float64))
+        ns = int(tab.shape[0])
+        if tab.shape != (ns, ns):
+            raise ValueError("a_table must be square")
+        sp = np.ascontiguousarray(np.asarray(species, dtype=np.int32).reshape(-1))
+        if ns > 1 and sp.shape[0] != self.N:
+            raise ValueError("one species per particle")
+        check(lib.enuf_dpd_set_species(self._h, ns, sp.ctypes.data_as(ctypes.c_void_p),
+                                       tab.ctypes.data_as(ctypes.c_void_p)), "enuf_dpd_set_species")
+
     def energy(self):
         """ENUF energy components of the last evaluation (unscaled by kappa)."""
         e = torch.empty(5, dtype=torch.float64, device=self.device)
