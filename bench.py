@@ -132,6 +132,7 @@ def batched(nsteps, dev):
     mem = []
     for s in reps:
         d = DPD(s.L, s.q, s.meta["dpd"], bonds=s.bonds, enuf=s.meta["enuf"], precision="mixed", device=dev)
+        d.plan.set_parts(1)   # the batch fills the device
         pos, vel, F = _state(s, dev)
         d.forces(pos, vel, F, step=0)
         mem.append((d, pos, vel, F))

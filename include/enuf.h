@@ -81,6 +81,21 @@ typedef struct enuf_plan enuf_plan;
 enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma,
                             int M, int Kc, double r_cut, double lambda);
 
+/*
+ * Work-groups per mesh plane in the spread and gather passes (1 .. the value
+ * the plan was created with).  Each work-group takes the plane's charges with
+ * compact index j = part (mod parts), spreads them into its own plane and
+ * transforms it; the partial spectra are rounded to fixed point and summed
+ * exactly, so results are reproducible for a given number of parts (and
+ * differ between part counts only in the last bits).  The default fills the
+ * device with one system: parts = min(8, 256 / M) (ENUF_MESH_PARTS, read at
+ * plan creation, overrides it).  Systems stepped together in a batch already
+ * fill the device: 1 part per plane avoids the repeated transforms there.
+ * A batch reads the value when its membership changes.  Synchronises the
+ * plan's stream.  ENUF_EINVAL outside the allowed range.
+ */
+int enuf_plan_set_parts(enuf_plan *plan, int parts);
+
 /* Release the plan and its device memory.  Synchronises the plan's stream.  NULL is a no-op. */
 void enuf_destroy(enuf_plan *plan);
 
@@ -236,7 +251,8 @@ int enuf_dpd_set_tuning(enuf_dpd *dpd, int pair_lanes);
  * own plan, N, box, M, Kc, charges and parameters) advanced together, one
  * kernel launch per stage of the step for all members, the step captured
  * once in a HIP graph and replayed.  A member's trajectory is bitwise the one
- * enuf_dpd_run gives it alone (same kernels, same per-system arithmetic).
+ * enuf_dpd_run gives it alone (same kernels, same per-system arithmetic, and
+ * the same enuf_plan_set_parts setting).
  * ------------------------------------------------------------------------ */
 typedef struct enuf_batch enuf_batch;
 

@@ -100,6 +100,8 @@ lib.enuf_batch_autotune.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POIN
 lib.enuf_batch_autotune.restype = _int
 lib.enuf_dpd_set_tuning.argtypes = [_vp, _int]
 lib.enuf_dpd_set_tuning.restype = _int
+lib.enuf_plan_set_parts.argtypes = [_vp, _int]
+lib.enuf_plan_set_parts.restype = _int
 lib.enuf_dpd_set_species.argtypes = [_vp, _int, _vp, _vp]
 lib.enuf_dpd_set_species.restype = _int
 lib.enuf_pair_histogram.argtypes = [_vp, _i64, _i64, _vp, _vp, _int, _dbl, _dbl, _int, _vp, _vp]
@@ -123,7 +125,7 @@ EXPORTED = [
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_batch_set_tuning", "enuf_batch_autotune", "enuf_dpd_set_tuning",
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
-    "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2",
+    "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",
 ]
 
 # Status codes (include/enuf.h).

@@ -60,16 +60,33 @@ __device__ inline int mesh_cell(double x, double m_over_l, int M, double *t) {
 // piecewise-polynomial kernel evaluation of Barnett, Magland & af Klinteberg,
 // SIAM J. Sci. Comput. 2019), fitted on the host to the window above.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T clenshaw(const T *c, int n, T x) {
-  T b1 = (T)0, b2 = (T)0;
-  const T x2 = x + x;
-  for (int k = n; k >= 1; --k) {
-    const T t = c[k] + x2 * b1 - b2;
-    b2 = b1;
-    b1 = t;
+// NS Chebyshev series of one degree n evaluated together: series i has
+// coefficients c[i][0..n] and argument x[i].  One loop advances every
+// recurrence, so their coefficient loads and multiply-adds interleave (a loop
+// per series would wait on each load in turn).
+template <typename T, int NS>
+__device__ __forceinline__ void clenshaw_n(const T *const (&c)[NS], const T (&x)[NS], int n, T (&out)[NS]) {
+  T b1[NS], b2[NS], x2[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    b1[i] = (T)0;
+    b2[i] = (T)0;
+    x2[i] = x[i] + x[i];
   }
-  return c[0] + x * b1 - b2;
+#pragma unroll 4
+  for (int k = n; k >= 1; --k) {
+    T ck[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) ck[i] = c[i][k];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const T t = ck[i] + x2[i] * b1[i] - b2[i];
+      b2[i] = b1[i];
+      b1[i] = t;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) out[i] = c[i][0] + x[i] * b1[i] - b2[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -105,9 +122,9 @@ __device__ inline long long to_fixed(double v, double scale) {
 // thread.  inverse: the unnormalised inverse via conj(FFT(conj(x))).
 // All threads of the block must call this function.
 // ---------------------------------------------------------------------------
-// Butterflies per thread per sweep: bounded so that the register arrays of a
-// radix-5 pass stay small.
-template <typename T> struct MaxBfly { static constexpr int value = 2; };
+// Butterflies per thread per sweep.  One: a radix-8 butterfly already holds
+// 16 values, and the mesh kernels run at the edge of their register budget.
+template <typename T, int R> struct MaxBfly { static constexpr int value = 1; };
 
 template <typename T, int R>
 __device__ __forceinline__ void dft_radix(T *xr, T *xi) {
@@ -125,6 +142,24 @@ __device__ __forceinline__ void dft_radix(T *xr, T *xi) {
     xr[2] = t0r - t2r; xi[2] = t0i - t2i;
     xr[1] = t1r + t3r; xi[1] = t1i + t3i;
     xr[3] = t1r - t3r; xi[3] = t1i - t3i;
+  } else if constexpr (R == 8) {
+    // two 4-point DFTs of the even and odd elements, then e^{-2 pi i k/8} on the odd ones
+    T er[4] = {xr[0], xr[2], xr[4], xr[6]}, ei[4] = {xi[0], xi[2], xi[4], xi[6]};
+    T orr[4] = {xr[1], xr[3], xr[5], xr[7]}, oi[4] = {xi[1], xi[3], xi[5], xi[7]};
+    dft_radix<T, 4>(er, ei);
+    dft_radix<T, 4>(orr, oi);
+    const T h = (T)0.70710678118654752440;
+    const T t1r = h * (orr[1] + oi[1]), t1i = h * (oi[1] - orr[1]);   // (1 - i)/sqrt2
+    const T t2r = oi[2], t2i = -orr[2];                                // -i
+    const T t3r = h * (oi[3] - orr[3]), t3i = -h * (orr[3] + oi[3]);   // -(1 + i)/sqrt2
+    xr[0] = er[0] + orr[0]; xi[0] = ei[0] + oi[0];
+    xr[4] = er[0] - orr[0]; xi[4] = ei[0] - oi[0];
+    xr[1] = er[1] + t1r; xi[1] = ei[1] + t1i;
+    xr[5] = er[1] - t1r; xi[5] = ei[1] - t1i;
+    xr[2] = er[2] + t2r; xi[2] = ei[2] + t2i;
+    xr[6] = er[2] - t2r; xi[6] = ei[2] - t2i;
+    xr[3] = er[3] + t3r; xi[3] = ei[3] + t3i;
+    xr[7] = er[3] - t3r; xi[7] = ei[3] - t3i;
   } else if constexpr (R == 3) {
     const T c = (T)(-0.5), s = (T)(-0.86602540378443864676);  // e^{-2 pi i/3}
     T tr = xr[1] + xr[2], ti = xi[1] + xi[2];
@@ -154,24 +189,35 @@ __device__ __forceinline__ void dft_radix(T *xr, T *xi) {
 }
 
 // One radix-R pass over `nlines` lines of length n, span Ns before the pass.
+// Thread t takes butterfly j = t mod (n/R) of lines t div (n/R), + lpb, ...
+// (lpb lines per sweep): its index arithmetic and its R - 1 twiddles are the
+// same for every line, so they are computed once per pass, not per butterfly.
 template <typename T, int R>
 __device__ __forceinline__ void stockham_pass(T *re, T *im, int ls, int nlines, int n, int Ns, const T *twr,
                               const T *twi, bool conj_in, bool conj_out) {
   const int nt = blockDim.x, tid = threadIdx.x;
-  const int nb = n / R;
+  const int nb = n / R;                 // butterflies per line (<= n / 2 < blockDim.x)
   const int tstep = n / (Ns * R);
-  constexpr int kMaxBfly = MaxBfly<T>::value;
-  int lg = (kMaxBfly * nt) / nb;  // whole lines per sweep
-  if (lg < 1) lg = 1;
-  for (int l0 = 0; l0 < nlines; l0 += lg) {
-    const int lines = (nlines - l0) < lg ? (nlines - l0) : lg;
-    const int total = lines * nb;
+  const int lpb = nt / nb;              // lines per sweep step
+  const int lrow = tid / nb, j = tid - lrow * nb;
+  const bool active = lrow < lpb;
+  const int k = j % Ns;
+  const int ob = (j / Ns) * Ns * R + k;  // output offset of the butterfly within its line
+  T wr[R], wi[R];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int ti = k * r * tstep;
+    wr[r] = twr[ti];
+    wi[r] = twi[ti];
+  }
+  constexpr int kMaxBfly = MaxBfly<T, R>::value;
+  for (int l0 = 0; l0 < nlines; l0 += lpb * kMaxBfly) {
     T vr[kMaxBfly][R], vi[kMaxBfly][R];
 #pragma unroll
     for (int q = 0; q < kMaxBfly; ++q) {
-      const int id = tid + q * nt;
-      if (id < total) {
-        const int base = (l0 + id / nb) * ls + id % nb;
+      const int line = l0 + lrow + q * lpb;
+      if (active && line < nlines) {
+        const int base = line * ls + j;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           vr[q][r] = re[base + r * nb];
@@ -183,24 +229,20 @@ __device__ __forceinline__ void stockham_pass(T *re, T *im, int ls, int nlines, 
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kMaxBfly; ++q) {
-      const int id = tid + q * nt;
-      if (id < total) {
-        const int line = l0 + id / nb, j = id % nb;
-        const int k = j % Ns;
+      const int line = l0 + lrow + q * lpb;
+      if (active && line < nlines) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const int ti = k * r * tstep;
-          const T wr = twr[ti], wi = twi[ti];
           const T xr = vr[q][r], xi = vi[q][r];
-          vr[q][r] = xr * wr - xi * wi;
-          vi[q][r] = xr * wi + xi * wr;
+          vr[q][r] = xr * wr[r] - xi * wi[r];
+          vi[q][r] = xr * wi[r] + xi * wr[r];
         }
         dft_radix<T, R>(vr[q], vi[q]);
-        const int ob = line * ls + (j / Ns) * Ns * R + k;
+        const int o = line * ls + ob;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          re[ob + r * Ns] = vr[q][r];
-          im[ob + r * Ns] = conj_out ? -vi[q][r] : vi[q][r];
+          re[o + r * Ns] = vr[q][r];
+          im[o + r * Ns] = conj_out ? -vi[q][r] : vi[q][r];
         }
       }
     }
@@ -208,9 +250,34 @@ __device__ __forceinline__ void stockham_pass(T *re, T *im, int ls, int nlines, 
   }
 }
 
+// Passes of a length-N transform with radices fixed at compile time: the
+// index arithmetic of every pass folds to constants.
+template <typename T, bool INV, int N, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_passes(T *re, T *im, int ls, int nlines, const T *twr, const T *twi) {
+  constexpr bool first = NS == 1, last = sizeof...(Rest) == 0;
+  stockham_pass<T, R>(re, im, ls, nlines, N, NS, twr, twi, INV && first, INV && last);
+  if constexpr (!last) fft_passes<T, INV, N, NS * R, Rest...>(re, im, ls, nlines, twr, twi);
+}
+
+template <typename T, int N, int... Rs>
+__device__ __forceinline__ void fft_fixed(T *re, T *im, int ls, int nlines, const T *twr, const T *twi,
+                                          bool inverse) {
+  if (inverse)
+    fft_passes<T, true, N, 1, Rs...>(re, im, ls, nlines, twr, twi);
+  else
+    fft_passes<T, false, N, 1, Rs...>(re, im, ls, nlines, twr, twi);
+}
+
 template <typename T>
 __device__ __forceinline__ void lds_fft(T *re, T *im, int ls, int nlines, const FftPlan &pl,
                         const T *twr, const T *twi, bool inverse) {
+  // power-of-two meshes take fixed radix-8 sequences; other lengths the plan's
+  switch (pl.n) {
+    case 32: fft_fixed<T, 32, 8, 4>(re, im, ls, nlines, twr, twi, inverse); return;
+    case 64: fft_fixed<T, 64, 8, 8>(re, im, ls, nlines, twr, twi, inverse); return;
+    case 128: fft_fixed<T, 128, 8, 4, 4>(re, im, ls, nlines, twr, twi, inverse); return;
+    default: break;
+  }
   int Ns = 1;
   for (int ps = 0; ps < pl.npass; ++ps) {
     const int R = pl.radix[ps];
@@ -219,6 +286,7 @@ __device__ __forceinline__ void lds_fft(T *re, T *im, int ls, int nlines, const 
       case 2: stockham_pass<T, 2>(re, im, ls, nlines, pl.n, Ns, twr, twi, ci, co); break;
       case 3: stockham_pass<T, 3>(re, im, ls, nlines, pl.n, Ns, twr, twi, ci, co); break;
       case 4: stockham_pass<T, 4>(re, im, ls, nlines, pl.n, Ns, twr, twi, ci, co); break;
+      case 8: stockham_pass<T, 8>(re, im, ls, nlines, pl.n, Ns, twr, twi, ci, co); break;
       default: stockham_pass<T, 5>(re, im, ls, nlines, pl.n, Ns, twr, twi, ci, co); break;
     }
     Ns *= R;

@@ -12,6 +12,8 @@ constexpr int kPrepThreads = 256;  // threads per block of the particle-parallel
 constexpr int kPassThreads = 512;  // threads per block of the mesh-plane kernels
 constexpr int kMaxRadixPasses = 16;
 constexpr int kMaxChebDeg = 24;    // highest degree of the window series
+constexpr int kStage = 512;        // most charges of a plane staged in LDS at a time by the mesh passes
+constexpr int kMaxParts = 8;       // most work-groups per plane in the spread and gather passes
 
 // Device-resident scalars produced by the preparation kernels of one compute.
 struct DevScalars {
@@ -24,7 +26,7 @@ struct DevScalars {
   double sum_q2;
 };
 
-// Mixed-radix factorisation of an FFT length, radices in {2, 3, 4, 5}.
+// Mixed-radix factorisation of an FFT length, radices in {2, 3, 4, 5, 8}.
 struct FftPlan {
   int n;
   int npass;
@@ -44,7 +46,9 @@ struct WindowParams {
 // Geometry shared by the mesh kernels.  The window is evaluated from
 // piecewise Chebyshev series: on stencil offset s the window at
 // u = frac + p - 1 - s (frac in [0, 1)) is sum_k c_{s,k} T_k(2 frac - 1),
-// and its u-derivative a series of degree cheb_deg - 1.
+// and its u-derivative a series of degree cheb_deg - 1.  Table layout:
+// [2p][cheb_deg + 1] value series, then [2p][cheb_deg + 1] derivative series
+// (last coefficient 0), so that both kinds evaluate in one recurrence.
 struct MeshParams {
   int cheb_deg;    // degree of the value series (derivative: cheb_deg - 1)
   int xcap;        // slots per x-bin of the charge binning
@@ -58,11 +62,22 @@ struct MeshParams {
   int nslot;       // gather partials per (charge, x offset): 1, or 2 when a
                    // charge's 2p rows can straddle two chunks
   int ik;          // forces: 0 window gradient, 1 ik-differentiation (eq. 24-25)
+  int stage;       // charges of a plane staged in LDS at a time (<= kStage)
+  int parts;       // work-groups per plane in the spread and gather passes, each
+                   // taking a contiguous share of the plane's charges (<= kMaxParts)
+  double gscale_f; // fixed-point scale of the partial spectra, relative to the
+                   // spread's scale: 2^-(3 ceil(log2 2p) + 3)
   double L;
   double m_over_l; // M / L: mesh coordinate t = x * m_over_l
   WindowParams win;
   FftPlan fft;
 };
+
+// Byte offset of the field spectrum h within the gzy buffer (after the
+// fixed-point partial spectra of the plane parts).
+__host__ __device__ inline size_t spectrum_h_offset(const MeshParams &m) {
+  return (size_t)m.parts * m.M * m.nky * m.Kc * 16;
+}
 
 // Real-space cell grid of the charges (cell edge >= r_cut).
 struct CellParams {
@@ -104,7 +119,9 @@ struct ComputeBuffers {
   unsigned long long *ereal; // [2 N] fixed-point (E_real whole, E_slater) of the pairs (j, k > j), per compact slot j
   long long *blk_er;         // [2 nblk] per-block sums of ereal over the particles of the block
   // reciprocal
-  void *gzy;             // [M * nky * Kc] complex (double2 or float2)
+  void *gzy;             // [(parts + 1) * M * nky * Kc] 16-byte entries: the partial spectra
+                         // G[part][x][ky][kz] as fixed-point int64 pairs, then the field
+                         // spectrum h[x][ky][kz] as complex T (double2 or float2)
   void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
   double *epart;         // [nky] k-space energy per ky row
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)

@@ -452,6 +452,34 @@ __device__ inline int plane_charge(int e, int P2, const int *pre, const int *cel
   return xslot[(size_t)cell[b] * xcap + (e - pre[b])];
 }
 
+// Stage in LDS those of the plane's charges e0 .. e0 + cnt - 1 that belong to
+// this work-group's share of the plane (compact index j with j mod parts ==
+// part): position and charge, compact index and x-bin.  Returns how many.
+// The share depends on the charges only, not on the order in which the
+// binning stored them, so the partial spectra are reproducible; the staged
+// order does not matter (the spread sums exactly, the gather is per charge).
+// The loads of all staged charges are in flight together, so the spread and
+// gather loops that follow read only LDS.
+__device__ inline int stage_plane_charges(int e0, int cnt, int P2, const int *pre, const int *cell,
+                                          gptr<const int> __restrict__ xslot, int xcap,
+                                          gptr<const double4> __restrict__ xq, int part, int parts, double4 *s_c,
+                                          int *s_jb, int *s_n) {
+  if (threadIdx.x == 0) *s_n = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    int b;
+    const int j = plane_charge(e0 + e, P2, pre, cell, xslot, xcap, &b);
+    if (j % parts == part) {
+      const int k = atomicAdd(s_n, 1);
+      s_c[k] = gload(xq + j);
+      s_jb[2 * k] = j;
+      s_jb[2 * k + 1] = b;
+    }
+  }
+  __syncthreads();
+  return *s_n;
+}
+
 // Mesh cell and fractional offset of one coordinate.
 __device__ inline int cell_frac(double x, double m_over_l, int M, double *frac) {
   double t;
@@ -475,7 +503,7 @@ __device__ __forceinline__ void
 recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ xcnt,
                gptr<const int> __restrict__ xslot, gptr<const T> __restrict__ wcoef,
                gptr<const DevScalars> __restrict__ sc, const MeshParams &mp,
-               gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<typename CplxOf<T>::type> gzy, int x0) {
+               gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<longlong2> gfx, int x0, int part) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p, D = mp.cheb_deg;
   const int R = mp.rows;
@@ -491,68 +519,86 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][D + 1] value series
-  off += (size_t)P2 * (D + 1) * sizeof(T);
+  // series at an odd stride Ds, so that the 2p offsets read by a wavefront fall in distinct banks
+  const int Ds = (D + 1) | 1;
+  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][Ds] value series
+  off += (size_t)P2 * Ds * sizeof(T);
   int *pre = reinterpret_cast<int *>(smem + off);
   int *bcell = pre + P2 + 1;
+  off = (off + (size_t)(2 * P2 + 1) * sizeof(int) + 31) & ~(size_t)31;
+  double4 *s_c = reinterpret_cast<double4 *>(smem + off);  // [stage] staged charges
+  int *s_jb = reinterpret_cast<int *>(s_c + mp.stage);      // [stage][2] compact index, x-bin
+  int *s_n = s_jb + 2 * mp.stage;                            // staged count
 
   for (int m = tid; m < M; m += nt) {
     const typename CplxOf<T>::type t = gload(tw + m);
     twr[m] = t.x;
     twi[m] = t.y;
   }
-  for (int k = tid; k < P2 * (D + 1); k += nt) cv[k] = wcoef[k];
+  for (int k = tid; k < P2 * (D + 1); k += nt) cv[(k / (D + 1)) * Ds + k % (D + 1)] = wcoef[k];
   const double scale = sc->scale, inv_scale = sc->inv_scale;
   const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
 
-  // whole wavefronts iterate together so that the group shuffles see every lane
-  const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
   const int gbase = lane & ~(P2pad - 1);
   for (int r0 = 0; r0 < M; r0 += R) {
     const int nr = (M - r0) < R ? (M - r0) : R;
     for (int k = tid; k < nr * Mp; k += nt) acc[k] = 0;
     __syncthreads();
+    for (int e0 = 0; e0 < total; e0 += mp.stage) {
+    const int cnt = stage_plane_charges(e0, (total - e0) < mp.stage ? (total - e0) : mp.stage, P2, pre, bcell,
+                                        xslot, mp.xcap, xq, part, mp.parts, s_c, s_jb, s_n);
+    // whole wavefronts iterate together so that the group shuffles see every lane
+    const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
     for (int it = tid; it < items; it += nt) {
       const int e = it / P2pad, sy = it % P2pad;
-      const bool has = e < total;
+      const bool has = e < cnt;
       bool act = has && sy < P2, in = false;
       T wz = (T)0, wrow = (T)0;
       int row = 0, bz = 0;
       if (has) {
-        int b;
-        const int j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-        const double4 c = gload(xq + j);
+        const int b = s_jb[2 * e + 1];
+        const double4 c = s_c[e];
         double fx, fy, fz;
         cell_frac(c.x, mp.m_over_l, M, &fx);
         const int cy = cell_frac(c.y, mp.m_over_l, M, &fy);
         const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
         if (act) {
-          wz = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fz - 1.0));
+          const int sx = P2 - 1 - b;
+          const T *const ser[3] = {cv + sy * Ds, cv + sx * Ds, cv + sy * Ds};
+          const T arg[3] = {(T)(2.0 * fz - 1.0), (T)(2.0 * fx - 1.0), (T)(2.0 * fy - 1.0)};
+          T w3[3];
+          clenshaw_n<T, 3>(ser, arg, D, w3);
+          wz = w3[0];
           row = mod_pos(cy - p + 1 + sy, M) - r0;
           in = (unsigned)row < (unsigned)nr;
-          if (in) {
-            const int sx = P2 - 1 - b;
-            const T wx = clenshaw<T>(cv + sx * (D + 1), D, (T)(2.0 * fx - 1.0));
-            const T wy = clenshaw<T>(cv + sy * (D + 1), D, (T)(2.0 * fy - 1.0));
-            wrow = (T)c.w * wx * wy;
-          } else {
+          if (in)
+            wrow = (T)c.w * w3[1] * w3[2];
+          else
             row = 0;
-          }
           bz = cz - p + 1;
         }
       }
       long long *arow = acc + (size_t)row * Mp;
       int col = bz < 0 ? bz + M : bz;
-      for (int sz = 0; sz < P2; ++sz) {
-        const T w = __shfl(wz, gbase + sz, kWave);
+      // eight stencil points at a time, so that their shuffles are in flight together
+      for (int sz0 = 0; sz0 < P2; sz0 += 8) {
+        T w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = __shfl(wz, gbase + sz0 + u, kWave);
         if (in) {
-          const double v = (double)(wrow * w);
-          atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
-          col = (col + 1 == M) ? 0 : col + 1;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (sz0 + u < P2) {
+              const double v = (double)(wrow * w[u]);
+              atomicAdd(reinterpret_cast<unsigned long long *>(&arow[col]), (unsigned long long)to_fixed(v, scale));
+              col = (col + 1 == M) ? 0 : col + 1;
+            }
+          }
         }
       }
     }
-    __syncthreads();
+    __syncthreads();  // before the next batch is staged, and before the conversion
+    }
 
     // fixed point -> T rows (in place; FP32 rows move down in groups)
     if (sizeof(T) == 8) {
@@ -598,14 +644,15 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   }
   // y: one complex line per kz
   lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, false);
+  // the partial spectrum in fixed point: the parts of a plane then add exactly,
+  // so the sum does not depend on how the charges were shared out
   const int nky = mp.nky;
+  const double gs = scale * mp.gscale_f;
+  gptr<longlong2> dst = gfx + ((size_t)part * M + x0) * nky * Kc;
   for (int id = tid; id < nky * Kc; id += nt) {
     const int kyi = id / Kc, kz = id % Kc;
     const int m = mod_pos(kyi - (Kc - 1), M);
-    typename CplxOf<T>::type v;
-    v.x = Zre[kz * Mz + m];
-    v.y = Zim[kz * Mz + m];
-    gstore(gzy + ((size_t)x0 * nky + kyi) * Kc + kz, v);
+    gstore(dst + id, make_longlong2(to_fixed((double)Zre[kz * Mz + m], gs), to_fixed((double)Zim[kz * Mz + m], gs)));
   }
 }
 
@@ -613,8 +660,9 @@ template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
 k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const int *__restrict__ xslot,
             const T *__restrict__ wcoef, const DevScalars *__restrict__ sc, MeshParams mp,
-            const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy) {
-  recip_fwd_body<T>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy), blockIdx.x);
+            const typename CplxOf<T>::type *__restrict__ tw, longlong2 *gfx) {
+  recip_fwd_body<T>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gfx),
+                    blockIdx.x % mp.M, blockIdx.x / mp.M);
 }
 
 // ---------------------------------------------------------------------------
@@ -623,7 +671,8 @@ k_recip_fwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
 template <typename T>
 __device__ __forceinline__ void
 recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
-             gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<typename CplxOf<T>::type> gzy,
+             gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<const DevScalars> __restrict__ sc,
+             gptr<const longlong2> __restrict__ gfx, gptr<typename CplxOf<T>::type> gzy,
              gptr<typename CplxOf<T>::type> gzx, gptr<double> epart, int kyi) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky;
@@ -647,11 +696,20 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
     twi[m] = t.y;
   }
   for (int k = tid; k < nky; k += nt) at[k] = atab[k];
+  // sum of the plane parts' fixed-point spectra (exact), then back to T
+  const double ig = sc->inv_scale / mp.gscale_f;
+  const size_t pstride = (size_t)M * nky * Kc;
   for (int id = tid; id < M * nkz; id += nt) {
     const int x = id / nkz, kz = id % nkz;
-    const typename CplxOf<T>::type v = gload(gzy + ((size_t)x * nky + kyi) * Kc + kz);
-    Xre[kz * Mz + x] = v.x;
-    Xim[kz * Mz + x] = v.y;
+    const size_t at0 = ((size_t)x * nky + kyi) * Kc + kz;
+    long long vr = 0, vi = 0;
+    for (int pt = 0; pt < mp.parts; ++pt) {
+      const longlong2 v = gload(gfx + pt * pstride + at0);
+      vr += v.x;
+      vi += v.y;
+    }
+    Xre[kz * Mz + x] = (T)((double)vr * ig);
+    Xim[kz * Mz + x] = (T)((double)vi * ig);
   }
   __syncthreads();
   lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, false);
@@ -697,9 +755,10 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
 k_recip_x(MeshParams mp, const double *__restrict__ atab,
-          const typename CplxOf<T>::type *__restrict__ tw, typename CplxOf<T>::type *gzy,
-          typename CplxOf<T>::type *gzx, double *epart) {
-  recip_x_body<T>(mp, to_g(atab), to_g(tw), to_g(gzy), to_g(gzx), to_g(epart), blockIdx.x);
+          const typename CplxOf<T>::type *__restrict__ tw, const DevScalars *__restrict__ sc,
+          const longlong2 *__restrict__ gfx, typename CplxOf<T>::type *gzy, typename CplxOf<T>::type *gzx,
+          double *epart) {
+  recip_x_body<T>(mp, to_g(atab), to_g(tw), to_g(sc), to_g(gfx), to_g(gzy), to_g(gzx), to_g(epart), blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,7 +773,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
                gptr<const DevScalars> __restrict__ sc, const MeshParams &mp,
                gptr<const typename CplxOf<T>::type> __restrict__ tw,
                gptr<const typename CplxOf<T>::type> __restrict__ gzy,
-               gptr<const typename CplxOf<T>::type> __restrict__ gzx, gptr<double4> part, int x0) {
+               gptr<const typename CplxOf<T>::type> __restrict__ gzx, gptr<double4> part, int x0, int wpart) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
   const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
@@ -729,20 +788,25 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   T *twr = reinterpret_cast<T *>(smem + off);
   T *twi = twr + M;
   off += 2 * (size_t)M * sizeof(T);
-  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][D + 1] value series
-  T *cd = cv + (size_t)P2 * (D + 1);          // [P2][D] derivative series
-  off += (size_t)P2 * (2 * D + 1) * sizeof(T);
+  // series at an odd stride Ds, so that the 2p offsets read by a wavefront fall in distinct banks
+  const int Ds = (D + 1) | 1;
+  T *cv = reinterpret_cast<T *>(smem + off);  // [P2][Ds] value series
+  T *cd = cv + (size_t)P2 * Ds;               // [P2][Ds] derivative series
+  off += (size_t)P2 * 2 * Ds * sizeof(T);
   int *pre = reinterpret_cast<int *>(smem + off);
   int *bcell = pre + P2 + 1;
+  off = (off + (size_t)(2 * P2 + 1) * sizeof(int) + 31) & ~(size_t)31;
+  double4 *s_c = reinterpret_cast<double4 *>(smem + off);  // [stage] staged charges
+  int *s_jb = reinterpret_cast<int *>(s_c + mp.stage);      // [stage][2] compact index, x-bin
+  int *s_n = s_jb + 2 * mp.stage;                            // staged count
 
   for (int m = tid; m < M; m += nt) {
     const typename CplxOf<T>::type t = gload(tw + m);
     twr[m] = t.x;
     twi[m] = t.y;
   }
-  for (int k = tid; k < P2 * (2 * D + 1); k += nt) cv[k] = wcoef[k];
+  for (int k = tid; k < 2 * P2 * (D + 1); k += nt) cv[(k / (D + 1)) * Ds + k % (D + 1)] = wcoef[k];
   const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
-  const int items = ((total * P2pad + kWave - 1) / kWave) * kWave;
   const int gbase = lane & ~(P2pad - 1);
   // Gradient forces: one field h, gathered with the window and its gradient.
   // ik forces (eq. 24-25): the three fields i k_t h, gathered with the window.
@@ -798,36 +862,53 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
       lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, true);
 
       const int chunk = r0 / R;
+      for (int e0 = 0; e0 < total; e0 += mp.stage) {
+      const int cnt = stage_plane_charges(e0, (total - e0) < mp.stage ? (total - e0) : mp.stage, P2, pre, bcell,
+                                          xslot, mp.xcap, xq, wpart, mp.parts, s_c, s_jb, s_n);
+      const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
       for (int it = tid; it < items; it += nt) {
         const int e = it / P2pad, sy = it % P2pad;
-        const bool has = e < total, act = has && sy < P2;
+        const bool has = e < cnt, act = has && sy < P2;
         bool in = false;
         int j = 0, sx = 0, row = 0, bz = 0, cy = 0;
         T wz = (T)0, dwz = (T)0, wy = (T)0, dwy = (T)0, wx = (T)0, dwx = (T)0;
         if (has) {
-          int b;
-          j = plane_charge(e, P2, pre, bcell, xslot, mp.xcap, &b);
-          sx = P2 - 1 - b;
-          const double4 c = gload(xq + j);
+          j = s_jb[2 * e];
+          sx = P2 - 1 - s_jb[2 * e + 1];
+          const double4 c = s_c[e];
           double fx, fy, fz;
           cell_frac(c.x, mp.m_over_l, M, &fx);
           cy = cell_frac(c.y, mp.m_over_l, M, &fy);
           const int cz = cell_frac(c.z, mp.m_over_l, M, &fz);
           if (act) {
             const T ux = (T)(2.0 * fx - 1.0), uy = (T)(2.0 * fy - 1.0), uz = (T)(2.0 * fz - 1.0);
-            wz = clenshaw<T>(cv + sy * (D + 1), D, uz);
-            wx = clenshaw<T>(cv + sx * (D + 1), D, ux);
-            if (!IK) {
-              dwz = clenshaw<T>(cd + sy * D, D - 1, uz);
-              dwx = clenshaw<T>(cd + sx * D, D - 1, ux);
+            if (IK) {
+              const T *const ser[3] = {cv + sy * Ds, cv + sx * Ds, cv + sy * Ds};
+              const T arg[3] = {uz, ux, uy};
+              T o[3];
+              clenshaw_n<T, 3>(ser, arg, D, o);
+              wz = o[0];
+              wx = o[1];
+              wy = o[2];
+            } else {
+              const T *const ser[6] = {cv + sy * Ds, cd + sy * Ds, cv + sx * Ds,
+                                       cd + sx * Ds, cv + sy * Ds, cd + sy * Ds};
+              const T arg[6] = {uz, uz, ux, ux, uy, uy};
+              T o[6];
+              clenshaw_n<T, 6>(ser, arg, D, o);
+              wz = o[0];
+              dwz = o[1];
+              wx = o[2];
+              dwx = o[3];
+              wy = o[4];
+              dwy = o[5];
             }
             row = mod_pos(cy - p + 1 + sy, M) - r0;
             in = (unsigned)row < (unsigned)nr;
-            if (in) {
-              wy = clenshaw<T>(cv + sy * (D + 1), D, uy);
-              if (!IK) dwy = clenshaw<T>(cd + sy * D, D - 1, uy);
-            } else {
+            if (!in) {
               row = 0;
+              wy = (T)0;
+              dwy = (T)0;
             }
             bz = cz - p + 1;
           }
@@ -835,14 +916,30 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
         const T *hrow = plane + (size_t)row * Mp;
         int col = bz < 0 ? bz + M : bz;
         T a = (T)0, bsum = (T)0;
-        for (int sz = 0; sz < P2; ++sz) {
-          const T w = __shfl(wz, gbase + sz, kWave);
-          const T d = __shfl(dwz, gbase + sz, kWave);
+        // eight stencil points at a time: shuffles and row loads in flight together
+        for (int sz0 = 0; sz0 < P2; sz0 += 8) {
+          T w[8], d[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            w[u] = __shfl(wz, gbase + sz0 + u, kWave);
+            d[u] = IK ? (T)0 : __shfl(dwz, gbase + sz0 + u, kWave);
+          }
           if (in) {
-            const T h = hrow[col];
-            a += h * w;
-            bsum += h * d;
-            col = (col + 1 == M) ? 0 : col + 1;
+            T h[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int c = col + u;
+              h[u] = sz0 + u < P2 ? hrow[c >= M ? c - M : c] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (sz0 + u < P2) {
+                a += h[u] * w[u];
+                bsum += h[u] * d[u];
+              }
+            }
+            col += 8;
+            col = col >= M ? col - M : col;
           }
         }
         T A = wy * a, By = dwy * a, Bz = wy * bsum;
@@ -883,6 +980,8 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
           }
         }
       }
+      __syncthreads();  // the next batch restages the charges
+      }
       __syncthreads();  // the next chunk overwrites the plane
     }
   }
@@ -896,7 +995,7 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
             const typename CplxOf<T>::type *__restrict__ gzy, const typename CplxOf<T>::type *__restrict__ gzx,
             double4 *part) {
   recip_bwd_body<T, IK>(to_g(xq), to_g(xcnt), to_g(xslot), to_g(wcoef), to_g(sc), mp, to_g(tw), to_g(gzy),
-                        to_g(gzx), to_g(part), blockIdx.x);
+                        to_g(gzx), to_g(part), blockIdx.x % mp.M, blockIdx.x / mp.M);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,7 +1152,7 @@ kb_recip_fwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) 
   const BatchMember &m = mem[w.x];
   recip_fwd_body<T>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
                     to_g(m.buf.sc), m.cfg.mesh, to_g(MemberTables<T>::tw(m.buf)),
-                    to_g(reinterpret_cast<C *>(m.buf.gzy)), w.y);
+                    to_g(reinterpret_cast<longlong2 *>(m.buf.gzy)), w.y % m.cfg.mesh.M, w.y / m.cfg.mesh.M);
 }
 
 template <typename T>
@@ -1062,9 +1161,10 @@ kb_recip_x(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   using C = typename CplxOf<T>::type;
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  recip_x_body<T>(m.cfg.mesh, to_g(m.buf.atab), to_g(MemberTables<T>::tw(m.buf)),
-                  to_g(reinterpret_cast<C *>(m.buf.gzy)), to_g(reinterpret_cast<C *>(m.buf.gzx)), to_g(m.buf.epart),
-                  w.y);
+  recip_x_body<T>(m.cfg.mesh, to_g(m.buf.atab), to_g(MemberTables<T>::tw(m.buf)), to_g(m.buf.sc),
+                  to_g(reinterpret_cast<const longlong2 *>(m.buf.gzy)),
+                  to_g(reinterpret_cast<C *>((char *)m.buf.gzy + spectrum_h_offset(m.cfg.mesh))),
+                  to_g(reinterpret_cast<C *>(m.buf.gzx)), to_g(m.buf.epart), w.y);
 }
 
 template <typename T, bool IK>
@@ -1075,8 +1175,9 @@ kb_recip_bwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) 
   const BatchMember &m = mem[w.x];
   recip_bwd_body<T, IK>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
                     to_g(m.buf.sc), m.cfg.mesh, to_g(MemberTables<T>::tw(m.buf)),
-                    to_g(reinterpret_cast<const C *>(m.buf.gzy)), to_g(reinterpret_cast<const C *>(m.buf.gzx)),
-                    to_g(m.buf.part), w.y);
+                    to_g(reinterpret_cast<const C *>((const char *)m.buf.gzy + spectrum_h_offset(m.cfg.mesh))),
+                    to_g(reinterpret_cast<const C *>(m.buf.gzx)), to_g(m.buf.part), w.y % m.cfg.mesh.M,
+                    w.y / m.cfg.mesh.M);
 }
 
 __global__ void __launch_bounds__(kPrepThreads)
@@ -1148,7 +1249,8 @@ hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *ma
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd) {
   const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
   const int P2 = 2 * m.win.p;
-  const size_t misc = (size_t)P2 * (2 * m.cheb_deg + 1) * ts + (3 * (size_t)P2 + 2) * sizeof(int) + 32;
+  const size_t misc = (size_t)P2 * 2 * ((m.cheb_deg + 1) | 1) * ts + (3 * (size_t)P2 + 2) * sizeof(int) + 32 +
+                      (size_t)m.stage * (sizeof(double4) + 2 * sizeof(int)) + 48;
   const size_t a16 = 15;
   const size_t acc = ((size_t)m.rows * m.Mp * sizeof(long long) + a16) & ~a16;
   const size_t rows_t = ((size_t)m.rows * m.Mp * ts + a16) & ~a16;
@@ -1170,14 +1272,19 @@ bool mesh_choose_rows(MeshParams &m, int precision, size_t max_lds) {
     t.nchunk = (m.M + rows - 1) / rows;
     t.nslot = t.nchunk > 1 ? 2 : 1;
     if (t.nchunk > 1 && m.M - (t.nchunk - 1) * rows < 2 * m.win.p) continue;  // keep every chunk >= 2p rows
-    size_t f, x, b;
-    mesh_lds_bytes(t, precision, &f, &x, &b);
-    if (x > max_lds) return false;
-    if (f <= max_lds && b <= max_lds) {
-      m.rows = t.rows;
-      m.nchunk = t.nchunk;
-      m.nslot = t.nslot;
-      return true;
+    // the largest charge stage that fits beside these rows
+    for (int stage = kStage; stage >= 32; stage /= 2) {
+      t.stage = stage;
+      size_t f, x, b;
+      mesh_lds_bytes(t, precision, &f, &x, &b);
+      if (x > max_lds) return false;
+      if (f <= max_lds && b <= max_lds) {
+        m.rows = t.rows;
+        m.nchunk = t.nchunk;
+        m.nslot = t.nslot;
+        m.stage = t.stage;
+        return true;
+      }
     }
   }
   return false;
@@ -1214,25 +1321,27 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
   using C = typename CplxOf<T>::type;
   const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
   const T *wc = reinterpret_cast<const T *>(sizeof(T) == 8 ? (const void *)b.wcoef64 : (const void *)b.wcoef32);
-  C *gzy = reinterpret_cast<C *>(b.gzy);
   const MeshParams &mp = cfg.mesh;
+  longlong2 *gfx = reinterpret_cast<longlong2 *>(b.gzy);  // partial spectra of the plane parts
+  C *gh = reinterpret_cast<C *>((char *)b.gzy + spectrum_h_offset(mp));  // field spectrum
+  const int nplane = mp.M * mp.parts;
   if (tm) tm->before(5, st);
-  hipLaunchKernelGGL(k_recip_fwd<T>, dim3(mp.M), dim3(kPassThreads), cfg.lds_fwd, st, (const double4 *)b.xq,
-                     (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gzy);
+  hipLaunchKernelGGL(k_recip_fwd<T>, dim3(nplane), dim3(kPassThreads), cfg.lds_fwd, st, (const double4 *)b.xq,
+                     (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gfx);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
-  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw, gzy,
-                     reinterpret_cast<C *>(b.gzx), b.epart);
+  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw,
+                     (const DevScalars *)b.sc, (const longlong2 *)gfx, gh, reinterpret_cast<C *>(b.gzx), b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
   if (mp.ik)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, true>), dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, true>), dim3(nplane), dim3(kPassThreads), cfg.lds_bwd, st,
                        (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
-                       (const DevScalars *)b.sc, mp, tw, (const C *)gzy, (const C *)b.gzx, b.part);
+                       (const DevScalars *)b.sc, mp, tw, (const C *)gh, (const C *)b.gzx, b.part);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, false>), dim3(mp.M), dim3(kPassThreads), cfg.lds_bwd, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, false>), dim3(nplane), dim3(kPassThreads), cfg.lds_bwd, st,
                        (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
-                       (const DevScalars *)b.sc, mp, tw, (const C *)gzy, (const C *)b.gzx, b.part);
+                       (const DevScalars *)b.sc, mp, tw, (const C *)gh, (const C *)b.gzx, b.part);
   if (tm) tm->after(7, st);
 }
 

@@ -53,8 +53,8 @@ bool factor_235(int n, FftPlan *pl) {
   pl->n = n;
   pl->npass = 0;
   int m = n;
-  const int order[4] = {4, 2, 3, 5};
-  for (int oi = 0; oi < 4; ++oi) {
+  const int order[5] = {8, 4, 2, 3, 5};  // fewest passes first: each pass is an LDS round trip
+  for (int oi = 0; oi < 5; ++oi) {
     const int r = order[oi];
     while (m % r == 0) {
       if (pl->npass >= kMaxRadixPasses) return false;
@@ -88,6 +88,7 @@ struct enuf_plan {
   int precision = ENUF_FP64, window = ENUF_WINDOW_KB;
   size_t max_lds = 0;
   int part_slots = 1;      // gather partial slots allocated per (charge, x offset)
+  int max_parts = 1;       // partial spectra the spectrum buffer holds (plane parts)
   ComputeConfig cfg{};
   ComputeBuffers buf{};
   std::vector<void *> allocations;
@@ -254,8 +255,17 @@ int cached_window_series(const WindowParams &w, int fp32, std::vector<long doubl
 int upload_window_series(enuf_plan *pl) {
   std::vector<long double> coef;
   const int fp32 = pl->precision == ENUF_MIXED;
-  const int D = cached_window_series(pl->cfg.mesh.win, fp32, &coef);
+  std::vector<long double> fit;
+  const int D = cached_window_series(pl->cfg.mesh.win, fp32, &fit);
   pl->cfg.mesh.cheb_deg = D;
+  // device layout: value series and derivative series both at stride D + 1
+  const int P2 = 2 * pl->cfg.mesh.win.p;
+  coef.assign((size_t)P2 * 2 * (D + 1), 0.0L);
+  for (int s = 0; s < P2; ++s) {
+    for (int k = 0; k <= D; ++k) coef[(size_t)s * (D + 1) + k] = fit[(size_t)s * (D + 1) + k];
+    for (int k = 0; k < D; ++k)
+      coef[(size_t)(P2 + s) * (D + 1) + k] = fit[(size_t)P2 * (D + 1) + (size_t)s * D + k];
+  }
   const size_t n = coef.size();
   if (fp32) {
     std::vector<float> h(n);
@@ -293,6 +303,25 @@ int upload_tables(enuf_plan *pl) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Work-groups per plane of the spread and gather passes: enough planes x
+// parts to give every CU of the device a work-group (256 CUs), at most kMaxParts.
+// ENUF_MESH_PARTS (1..8) overrides the choice (tuning and testing).
+int mesh_parts(int M) {
+  if (const char *v = std::getenv("ENUF_MESH_PARTS")) {
+    const int n = std::atoi(v);
+    if (n >= 1) return std::min(kMaxParts, n);
+  }
+  return std::max(1, std::min(kMaxParts, 256 / M));
+}
+
+// Fixed-point scale of the partial spectra relative to the spread's: the
+// spectrum of a plane is bounded by sum |q| (2p)^3, and up to 8 parts add.
+double mesh_gscale_factor(int p) {
+  int e = 0;
+  while ((1 << e) < 2 * p) ++e;
+  return std::ldexp(1.0, -(3 * e + 3));
+}
 
 }  // namespace
 
@@ -344,15 +373,15 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           n * 3 * sizeof(unsigned long long),                 // freal
           n * 2 * sizeof(unsigned long long),                 // ereal
           nblk * 2 * sizeof(long long),                       // blk_er
-          (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzy
+          (size_t)(mesh_parts(M) + 1) * M * nky * (size_t)Kc * 16,  // gzy: partial spectra + field
           (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzx
           nky * sizeof(double),                               // epart
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
           (size_t)M * sizeof(int),                            // xcnt
           (size_t)M * (size_t)g.xcap * sizeof(int),           // xslot
-          P2 * (2 * kMaxChebDeg + 1) * sizeof(double),        // wcoef64
-          P2 * (2 * kMaxChebDeg + 1) * sizeof(float),         // wcoef32
+          P2 * (2 * kMaxChebDeg + 2) * sizeof(double),        // wcoef64
+          P2 * (2 * kMaxChebDeg + 2) * sizeof(float),         // wcoef32
           nky * sizeof(double),                               // atab
           (size_t)M * sizeof(double2),                        // tw64
           (size_t)M * sizeof(float2)};                        // tw32
@@ -419,6 +448,9 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.L = box; m.m_over_l = (double)M / box;
   m.win = make_window(ENUF_WINDOW_KB, p, sigma);
   m.fft = fp;
+  m.parts = mesh_parts(M);
+  pl->max_parts = m.parts;  // the spectrum buffer holds this many partial spectra
+  m.gscale_f = mesh_gscale_factor(p);
   PlanGeom g;
   if (!plan_geometry(N, box, p, M, Kc, r_cut, pl->max_lds, &g)) {
     set_error("mesh too large: no row chunking of the plane passes fits in " + std::to_string(pl->max_lds) +
@@ -436,6 +468,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.rows = M;
   m.nchunk = 1;
   m.nslot = 1;
+  m.stage = kStage;
   mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
 
   ComputeBuffers &b = pl->buf;
@@ -488,6 +521,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
     m.rows = M;
     m.nchunk = 1;
     m.nslot = 1;
+    m.stage = kStage;
   }
   mesh_lds_bytes(m, ENUF_FP64, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
   static bool configured = false;
@@ -551,11 +585,23 @@ int enuf_plan_set_options(enuf_plan *plan, int precision, int window) {
     plan->cfg.mesh.rows = old_mesh.rows;
     plan->cfg.mesh.nchunk = old_mesh.nchunk;
     plan->cfg.mesh.nslot = old_mesh.nslot;
+    plan->cfg.mesh.stage = old_mesh.stage;
     return rc;
   }
   plan->cfg.lds_fwd = f;
   plan->cfg.lds_x = x;
   plan->cfg.lds_bwd = bw;
+  return ENUF_OK;
+}
+
+int enuf_plan_set_parts(enuf_plan *plan, int parts) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  if (parts < 1 || parts > plan->max_parts) {
+    set_error("parts must be in [1, " + std::to_string(plan->max_parts) + "]");
+    return ENUF_EINVAL;
+  }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  plan->cfg.mesh.parts = parts;
   return ENUF_OK;
 }
 
@@ -1157,7 +1203,8 @@ int batch_rebuild(enuf_batch *b) {
     const BatchMember m = member_view(b->members[k], b->pair_lanes);
     const int id = (int)mem.size();
     mem.push_back(m);
-    const int counts[7] = {m.nblk, m.pair_blocks, m.real_blocks, m.cfg.mesh.M, m.cfg.mesh.nky, m.cfg.mesh.M, m.nblk};
+    const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;  // work-groups of the spread and gather passes
+    const int counts[7] = {m.nblk, m.pair_blocks, m.real_blocks, planes, m.cfg.mesh.nky, planes, m.nblk};
     for (int s = 0; s < 7; ++s)
       for (int i = 0; i < counts[s]; ++i) map[s].push_back(make_int2(id, i));
     lf = std::max(lf, m.cfg.lds_fwd);

@@ -56,6 +56,12 @@ class Plan:
         check(lib.enuf_plan_set_force_mode(self._h, m), "enuf_plan_set_force_mode")
         self.force_mode = mode
 
+    def set_parts(self, parts):
+        """Work-groups per mesh plane in the spread and gather passes (1 up
+        to the creation default min(8, 256 / M)); 1 for systems stepped in a
+        batch, which already fills the device."""
+        check(lib.enuf_plan_set_parts(self._h, int(parts)), "enuf_plan_set_parts")
+
     def _bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.enuf_plan_set_stream(self._h, ctypes.c_void_p(s)), "enuf_plan_set_stream")

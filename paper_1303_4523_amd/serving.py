@@ -8,8 +8,10 @@ stage of the step advances all members together.  Requests that arrive while
 others run are admitted at the next step boundary, first come first served,
 as long as the HBM footprint of the new system (estimated without allocating)
 fits in the budget next to the resident ones; finished members leave at step
-boundaries and free their memory.  A member's trajectory is bitwise the one
-it gets alone (each member keeps its own step counter and random stream).
+boundaries and free their memory.  Members use one work-group per mesh plane
+(the batch fills the device), and a member's trajectory is bitwise the one
+it gets alone with that setting (each member keeps its own step counter and
+random stream).
 
 Reported per request: arrival, admission and completion times (latency =
 completion - arrival), the final ENUF energy components and the device
@@ -100,6 +102,7 @@ class Server:
         m.req = req
         m.dpd = DPD(s.L, s.q, s.meta["dpd"], bonds=s.bonds, enuf=s.meta["enuf"], precision=self.precision,
                     device=self.device)
+        m.dpd.plan.set_parts(1)   # the batch fills the device
         m.pos = torch.tensor(s.pos, dtype=torch.float64, device=self.device)
         m.vel = torch.tensor(s.vel, dtype=torch.float64, device=self.device)
         m.force = torch.empty_like(m.pos)

@@ -97,6 +97,7 @@ def polyelectrolyte_rg(fractions=FRACTIONS, L=15.0, replicas=1, steps=50000, equ
             members = []
             for s in systems:
                 d = DPD(s.L, s.q, s.meta["dpd"], bonds=s.bonds, enuf=e, precision=precision, device=dev)
+                d.plan.set_parts(1)   # the batch fills the device
                 d.set_species(s.meta["species"], s.meta["a_table"])
                 pos, vel, force = _state(s, dev)
                 d.forces(pos, vel, force, step=0)

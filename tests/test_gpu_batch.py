@@ -20,18 +20,22 @@ def _replicas(ids, n_max=9000):
     return [wl.replica(s, n_max=n_max) for s in ids]
 
 
-def _member(s, precision="mixed", first_step=1):
-    """Integrator, state tensors and initial forces of one replica."""
+def _member(s, precision="mixed", first_step=1, parts=None):
+    """Integrator, state tensors and initial forces of one replica; parts:
+    work-groups per mesh plane (None: the plan's default; 1: as the serving
+    loop sets)."""
     from paper_1303_4523_amd.dpd import DPD
     d = DPD(s.L, s.q, s.meta["dpd"], bonds=s.bonds, enuf=s.meta["enuf"], precision=precision, device=0)
+    if parts is not None:
+        d.plan.set_parts(parts)
     pos, vel = _t(s.pos), _t(s.vel)
     F = torch.empty_like(pos)
     d.forces(pos, vel, F, step=first_step - 1)
     return d, pos, vel, F
 
 
-def _alone(s, nsteps, precision="mixed", first_step=1):
-    d, pos, vel, F = _member(s, precision, first_step)
+def _alone(s, nsteps, precision="mixed", first_step=1, parts=None):
+    d, pos, vel, F = _member(s, precision, first_step, parts)
     d.run(pos, vel, F, first_step, nsteps)
     st = d.status()
     e5 = d.energy().cpu().numpy()
@@ -217,7 +221,7 @@ def test_serving_results_equal_alone_and_in_the_mix():
     print(f"serving: {st}, peak members {srv.peak_members}")
     for r in res:
         s = reqs[r.rid].system
-        alone = _alone(s, 10)
+        alone = _alone(s, 10, parts=1)
         assert _same(r.state, alone[:3]), s.meta["name"]
         assert np.array_equal(r.energy5, alone[3])
 

@@ -192,12 +192,19 @@ def test_force_is_gradient_of_gpu_energy():
     plan.close()
 
 
-@pytest.mark.parametrize("cap", [11000, 9400])
+# LDS budgets (bytes) that force 2 and 4 row chunks at M = 32 (FP64) and 2 (mixed),
+# with the charge stage shrunk to what fits beside the rows
+CHUNK_CAPS = {"fp64": (13000, 11000), "mixed": (11000, 9400)}
+
+
+@pytest.mark.parametrize("which", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_row_chunked_planes_match(monkeypatch, precision, cap):
+def test_row_chunked_planes_match(monkeypatch, precision, which):
     """A lowered LDS budget makes the plane passes work in chunks of mesh rows
-    (two partial slots per charge); the result equals the one-chunk plane to
-    rounding and still meets the oracle bar."""
+    (two partial slots per charge) and stage the plane's charges in smaller
+    batches; the result equals the one-chunk plane to rounding and still
+    meets the oracle bar."""
+    cap = CHUNK_CAPS[precision][which]
     s = wl.single_eval_small()
     e = s.meta["enuf"]
     whole = _plan(s.N, e, precision)
