@@ -273,57 +273,70 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       }
     }
     const int cx = ci / (n * n), cy = (ci / n) % n, cz = ci % n;
-    // cursor over the lane's cells o = quad, quad + Q, ... and their slots
-    int o = has ? quad : 27, s = 0, cnt = 0;
-    size_t cb = 0;
-    for (; o < 27; o += Q) {
+    // The lane's share of the 27 neighbour cells (o = quad, quad + Q, ...):
+    // their counts are loaded together up front, and the lane's candidates
+    // t = 0 .. T-1 (cell by cell, slot by slot) are then fetched kB at a time,
+    // so that kB loads are in flight instead of one.
+    constexpr int KC = (27 + Q - 1) / Q;
+    constexpr int kB = 4;
+    int cb[KC], cnk[KC], pre[KC];
+    int T = 0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int o = quad + k * Q;
       const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-      if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
-      const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-      cnt = dcnt[c];
-      cnt = cnt < cap ? cnt : cap;
-      cb = (size_t)c * cap;
-      if (cnt > 0) break;
+      const bool ok = has && o < 27 && dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) &&
+                      dpd_offset_valid(oz, n);
+      const int c = ok ? (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n) : 0;
+      int ck = ok ? dcnt[c] : 0;
+      cnk[k] = ck < cap ? ck : cap;
+      cb[k] = c * cap;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      pre[k] = T;
+      T += cnk[k];
     }
     int qn = 0;  // wavefront-uniform queue length
-    while (true) {
-      const bool live = o < 27;
-      if (__ballot(live) == 0ull) break;
-      bool take = false;
-      int slot = 0;
-      if (live) {
-        const double4 e = gload(cpos + cb + s);
-        const int j = (int)e.w;
-        double dx = rx - e.x, dy = ry - e.y, dz = rz - e.z;
-        dx -= L * rint(dx * invL);
-        dy -= L * rint(dy * invL);
-        dz -= L * rint(dz * invL);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
-        slot = (int)(cb + s);
-        if (++s >= cnt) {  // next non-empty cell of this lane
-          s = 0;
-          for (o += Q; o < 27; o += Q) {
-            const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-            if (!(dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) && dpd_offset_valid(oz, n))) continue;
-            const int c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n);
-            cnt = dcnt[c];
-            cnt = cnt < cap ? cnt : cap;
-            cb = (size_t)c * cap;
-            if (cnt > 0) break;
-          }
+    for (int t0 = 0;; t0 += kB) {
+      if (__ballot(t0 < T) == 0ull) break;
+      int slot[kB];
+      double4 e[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int t = t0 + u;
+        int sl = -1;
+#pragma unroll
+        for (int k = 0; k < KC; ++k)
+          if (t >= pre[k] && t < pre[k] + cnk[k]) sl = cb[k] + (t - pre[k]);
+        slot[u] = sl;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u)
+        if (slot[u] >= 0) e[u] = gload(cpos + slot[u]);
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        bool take = false;
+        if (slot[u] >= 0) {
+          const int j = (int)e[u].w;
+          double dx = rx - e[u].x, dy = ry - e[u].y, dz = rz - e[u].z;
+          dx -= L * rint(dx * invL);
+          dy -= L * rint(dy * invL);
+          dz -= L * rint(dz * invL);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
         }
-      }
-      const unsigned long long m = __ballot(take);
-      if (take) {
-        const int at = qn + (int)__popcll(m & __lanemask_lt());
-        qs[at] = slot;
-        ql[at] = lp;
-      }
-      qn += (int)__popcll(m);
-      if (qn > kPairQueue - kWave) {
-        flush(qn);
-        qn = 0;
+        const unsigned long long m = __ballot(take);
+        if (take) {
+          const int at = qn + (int)__popcll(m & __lanemask_lt());
+          qs[at] = slot[u];
+          ql[at] = lp;
+        }
+        qn += (int)__popcll(m);
+        if (qn > kPairQueue - kWave) {
+          flush(qn);
+          qn = 0;
+        }
       }
     }
     flush(qn);
