@@ -14,7 +14,9 @@ struct DpdParams {
   int ncell;                        // DPD cells per side (edge >= R_c = 1)
   int cap;                          // slots per cell
   double inv_cell;
-  int group4, group8;               // cells per wavefront group of the pair kernel at 4 / 8 lanes per particle
+  int seg_cells, nseg, seg_whole;   // pair kernel: cells per column segment, segments per column,
+                                    // 1 when a segment is a whole column (no z halo)
+  int pair_stage;                   // particles the pair kernel stages in LDS per segment
   int nspec;                        // > 1: the conservative amplitude depends on the pair's species
   const int *species;               // [N] species of each particle (device; read when nspec > 1)
   double atab[16];                  // a_ij = atab[4 s_i + s_j], symmetric (nspec <= 4)
@@ -68,11 +70,15 @@ struct BatchMember {
 // Batched launches: map[b] = (member, block of that member) for block b.
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
 hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st);
-// Cells per wavefront group of the pair kernel: about 3/4 of the 64/lanes
-// particles a wavefront takes per round, at the mean cell occupancy.
-int pair_group_cells(double cell_mean, int lanes);
-// Blocks of the pair kernel at `lanes` (4 or 8) lanes per particle; a multiple
-// of 8 (whole rounds over the XCDs).
+// Column segments of the pair kernel for a grid of n cells per side.
+void pair_segments(int n, int *seg_cells, int *nseg, int *whole);
+// Dynamic LDS bytes of the pair kernel (its staged particles).
+size_t pair_lds_bytes(const DpdParams &P);
+constexpr int kPairStage = 768;   // particles staged per segment (52 KB of LDS)
+// Allow the pair kernels the dynamic LDS of their staged particles.
+hipError_t configure_pair_kernels(size_t lds_bytes);
+// Blocks of the pair kernel (one per column segment), a multiple of 8 (whole
+// rounds over the XCDs); the same at 4 and 8 lanes per particle.
 int pair_blocks(const DpdParams &P, int lanes);
 hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,

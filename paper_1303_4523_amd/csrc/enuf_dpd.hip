@@ -72,6 +72,9 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     ch.sc->sum_q2 = ch.stat.sum_q2;
   }
   if (i >= N) return;
+  // the static compaction slot and charge are loaded with the state
+  const int j = ch.enabled ? ch.dslot[i] : -1;
+  const double qi = j >= 0 ? ch.q[i] : 0.0;
   double r[3], v[3], f[3], w[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -102,7 +105,25 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
   const int n = P.ncell;
   const int cell = (dpd_cell_of(r[0], P.inv_cell, n) * n + dpd_cell_of(r[1], P.inv_cell, n)) * n +
                    dpd_cell_of(r[2], P.inv_cell, n);
+  // cells of a charge: real-space grid and mesh x-bin
+  int c = 0, xc = 0;
+  if (j >= 0) {
+    const CellParams &cp = ch.cells;
+    int cx = (int)(r[0] * cp.inv_cell), cy = (int)(r[1] * cp.inv_cell), cz = (int)(r[2] * cp.inv_cell);
+    cx = cx < cp.ncell ? cx : cp.ncell - 1;
+    cy = cy < cp.ncell ? cy : cp.ncell - 1;
+    cz = cz < cp.ncell ? cz : cp.ncell - 1;
+    c = (cx * cp.ncell + cy) * cp.ncell + cz;
+    double t;
+    xc = mesh_cell(r[0], ch.m_over_l, ch.M, &t);
+  }
+  // the slot claims are independent: all are in flight together
   const int s = atomicAdd(&dcnt[cell], 1);
+  int sl = 0, xs = 0;
+  if (j >= 0) {
+    sl = atomicAdd(&ch.ccnt[c], 1);
+    xs = atomicAdd(&ch.xcnt[xc], 1);
+  }
   if (s < P.cap) {
     cpos[(size_t)cell * P.cap + s] = make_double4(r[0], r[1], r[2], (double)i);
     const double sp = P.nspec > 1 ? (double)P.species[i] : 0.0;
@@ -111,27 +132,16 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     atomicCAS(status, 0, kEOverflow);
   }
   if (ch.enabled) {
-    const int j = ch.dslot[i];
     ch.slot[i] = j;
     if (j >= 0) {
-      const double qi = ch.q[i];
       ch.xq[j] = make_double4(r[0], r[1], r[2], qi);
       const CellParams &cp = ch.cells;
-      int cx = (int)(r[0] * cp.inv_cell), cy = (int)(r[1] * cp.inv_cell), cz = (int)(r[2] * cp.inv_cell);
-      cx = cx < cp.ncell ? cx : cp.ncell - 1;
-      cy = cy < cp.ncell ? cy : cp.ncell - 1;
-      cz = cz < cp.ncell ? cz : cp.ncell - 1;
-      const int c = (cx * cp.ncell + cy) * cp.ncell + cz;
-      const int sl = atomicAdd(&ch.ccnt[c], 1);
       if (sl < cp.cap) {
         ch.cgrid[(size_t)c * cp.cap + sl] = make_double4(r[0], r[1], r[2], qi);
         ch.cidx[(size_t)c * cp.cap + sl] = j;
       } else {
         atomicCAS(&ch.sc->status, 0, kEOverflow);
       }
-      double t;
-      const int xc = mesh_cell(r[0], ch.m_over_l, ch.M, &t);
-      const int xs = atomicAdd(&ch.xcnt[xc], 1);
       if (xs < ch.xcap)
         ch.xslot[(size_t)xc * ch.xcap + xs] = j;
       else
@@ -151,59 +161,79 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// Pair forces in cell order.  A wavefront takes a group of consecutive DPD
-// cells (z fastest) and their particles, 64/Q at a time with Q = 4 or 8 lanes
-// per particle; the particles of one wavefront are neighbours, so they read
-// the same neighbour cells.  Blocks are mapped so that each of the 8 XCDs
-// (which take the blocks of a launch round-robin) works on one contiguous
-// slab of cells, keeping its L2 working set to that slab and its halo.
-// Scan: each lane walks the slots of its share of the 27 neighbour cells and
-// the pairs with r < R_c = 1 are appended to a wavefront queue in LDS.
-// Evaluation: the whole wavefront takes the queued pairs 64 at a time (so the
-// Philox draw and the pair force run with full lanes however sparse the
-// neighbours are) and adds each pair force to i's int64 fixed-point
-// accumulator in LDS.  Every pair is evaluated from both of its particles
-// (theta_ij = theta_ji keeps the pair forces antisymmetric), so no thread
-// writes another particle's force; the fixed-point sums (2^-36) are exact, so
-// the result does not depend on the order in which pairs are visited.  With
-// species, the cell slot's predicted velocity carries the species in w and
-// the amplitude a_ij is read from the symmetric table in the parameters.
-// Particles beyond a full cell's capacity (reported as ENUF_EOVERFLOW by the
-// binning) get no force.
+// Pair forces by column segment.  A block takes a segment of seg_cells
+// consecutive cells of one z-column of the DPD cell grid (the whole column
+// when it has at most kSegWhole cells).  It first stages in LDS every
+// particle of the 9 neighbouring columns over the segment's z-range plus one
+// cell on each side (the whole column: no halo): the cell counts are read and
+// prefix-summed, then positions and predicted velocities are copied with all
+// loads in flight together.  The segment's own particles form one contiguous
+// range of the staged set; each wavefront takes 64/Q of them at a time with Q
+// = 4 or 8 lanes per particle.
+// Scan: each lane walks the staged particles of its share of the particle's
+// 27 neighbour cells (LDS reads, kB at a time) and appends the pairs with
+// r < R_c = 1 to a wavefront queue in LDS.  Evaluation: the whole wavefront
+// takes the queued pairs 64 at a time (so the Philox draw and the pair force
+// run with full lanes however sparse the neighbours are) and adds each pair
+// force to i's int64 fixed-point accumulator in LDS.  Every pair is evaluated
+// from both of its particles (theta_ij = theta_ji keeps the pair forces
+// antisymmetric), so no thread writes another particle's force; the
+// fixed-point sums (2^-36) are exact, so the result does not depend on the
+// order in which pairs are visited.  With species, the cell slot's predicted
+// velocity carries the species in w and the amplitude a_ij is read from the
+// symmetric table in the parameters.  A segment whose neighbourhood holds
+// more than kPairStage particles (dense cells) runs the same algorithm with
+// the candidates read from global memory instead.  Blocks are mapped so that
+// each of the 8 XCDs (which take the blocks of a launch round-robin) works on
+// one contiguous slab of columns.  Particles beyond a full cell's capacity
+// (reported as ENUF_EOVERFLOW by the binning) get no force.
 constexpr int kPairThreads = 256;
-constexpr int kPairQueue = 128;  // queued pairs per wavefront (flushed at > 64)
-constexpr int kXcds = 8;         // MI355X: blocks of a launch are dealt round-robin to 8 XCDs
+constexpr int kPairQueue = 128;   // queued pairs per wavefront (flushed at > 64)
+constexpr int kXcds = 8;          // MI355X: blocks of a launch are dealt round-robin to 8 XCDs
+constexpr int kPairCells = 256;   // staged cells: 9 columns x at most 28 z-cells
+constexpr int kSegWhole = 24;     // columns of at most this many cells are one segment
+constexpr int kSegCells = 16;     // segment length of longer columns
 
+// Per-wavefront LDS of the pair evaluation: the pair queue and the rows of
+// the particles of the current round.
 template <int Q>
+struct PairScratch {
+  static constexpr int PPW = kWave / Q;
+  static constexpr int NW = kPairThreads / kWave;
+  int qs[NW][kPairQueue];
+  int ql[NW][kPairQueue];
+  double rv[NW][PPW][6];
+  int id[NW][PPW];
+  int sp[NW][PPW];
+  unsigned long long f[NW][PPW][3];
+};
+
+template <int Q, bool STAGED>
 __device__ __forceinline__ void
-dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
-              gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
-              gptr<const double4> __restrict__ cvel, gptr<const int> __restrict__ bond_start,
-              gptr<const int> __restrict__ bond_to, gptr<double> __restrict__ fdpd, int pb, int nb) {
+dpd_pair_segment(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
+                 gptr<const double4> __restrict__ cpos, gptr<const double4> __restrict__ cvel,
+                 gptr<const int> __restrict__ bond_start, gptr<const int> __restrict__ bond_to,
+                 gptr<double> __restrict__ fdpd, PairScratch<Q> &sh, const int *s_cnt, const int *s_off,
+                 const int *s_gcell, const double4 *s_pos, const double4 *s_vel, const int *s_pc, int Sz, int zlo,
+                 int zhi) {
   constexpr int PPW = kWave / Q;
   constexpr int NW = kPairThreads / kWave;
-  __shared__ int s_qs[NW][kPairQueue];
-  __shared__ int s_ql[NW][kPairQueue];
-  __shared__ double s_rv[NW][PPW][6];
-  __shared__ int s_id[NW][PPW];
-  __shared__ int s_sp[NW][PPW];
-  __shared__ unsigned long long s_f[NW][PPW][3];
+  auto &s_qs = sh.qs;
+  auto &s_ql = sh.ql;
+  auto &s_rv = sh.rv;
+  auto &s_id = sh.id;
+  auto &s_sp = sh.sp;
+  auto &s_f = sh.f;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
   const int n = P.ncell, cap = P.cap;
-  const int G = Q == 8 ? P.group8 : P.group4;
-  const int64_t nc3 = (int64_t)n * n * n;
-  const int64_t c0 = ((int64_t)lb * NW + w) * G;
-  if (c0 >= nc3) return;  // whole wavefronts leave together
-  const int ng = (int)((nc3 - c0) < G ? (nc3 - c0) : G);
-  int total = 0;
-  for (int k = 0; k < ng; ++k) {
-    const int ck = dcnt[c0 + k];
-    total += ck < cap ? ck : cap;
-  }
   const int lp = lane / Q, quad = lane % Q;
   const double L = P.L, invL = 1.0 / L, isdt = 1.0 / sqrt(P.dt);
   int *qs = s_qs[w], *ql = s_ql[w];
+  const bool whole = P.seg_whole != 0;
+  // staged index of particle s of staged cell k (STAGED) or its global slot
+  auto where = [&](int k, int sl) { return STAGED ? s_off[k] + sl : s_gcell[k] * cap + sl; };
+  auto cand = [&](int q) -> double4 { return STAGED ? s_pos[q] : gload(cpos + q); };
+  auto cvel_of = [&](int q) -> double4 { return STAGED ? s_vel[q] : gload(cvel + q); };
 
   auto wave_sync = []() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -214,10 +244,10 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
     wave_sync();
     for (int e = lane; e < qn; e += kWave) {
       const int l = ql[e];
-      const int slot = qs[e];
+      const int q = qs[e];
       const int ii = s_id[w][l];
-      const double4 ej = gload(cpos + slot);
-      const double4 vj = gload(cvel + slot);
+      const double4 ej = cand(q);
+      const double4 vj = cvel_of(q);
       const int j = (int)ej.w;
       double dx = s_rv[w][l][0] - ej.x, dy = s_rv[w][l][1] - ej.y, dz = s_rv[w][l][2] - ej.z;
       dx -= L * rint(dx * invL);
@@ -238,30 +268,32 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
     wave_sync();
   };
 
-  for (int r0 = 0; r0 < total; r0 += PPW) {
-    // particle r0 + lp of the group: cell ci, slot sl
+  // own particles: staged cells 4 Sz + zlo .. 4 Sz + zhi - 1 (column (0, 0)), contiguous
+  const int own0 = 4 * Sz;
+  const int plo = s_off[own0 + zlo], phi = s_off[own0 + zhi];
+  for (int r0 = plo + w * PPW; r0 < phi; r0 += NW * PPW) {
     const int pidx = r0 + lp;
-    const bool has = pidx < total;
-    int ci = 0, own = 0, i = -1;
+    const bool has = pidx < phi;
+    int zi = 0, i = -1;
     double rx = 0.0, ry = 0.0, rz = 0.0;
     if (has) {
-      int k = 0, rem = pidx;
-      for (; k < ng - 1; ++k) {
-        int ck = dcnt[c0 + k];
-        ck = ck < cap ? ck : cap;
-        if (rem < ck) break;
-        rem -= ck;
+      int k;
+      if (STAGED) {
+        k = s_pc[pidx];
+      } else {
+        k = own0 + zlo;
+        while (k < own0 + zhi - 1 && pidx >= s_off[k + 1]) ++k;
       }
-      ci = (int)(c0 + k);
-      own = ci * cap + rem;
-      const double4 e = gload(cpos + own);
+      zi = k - own0;
+      const int q = where(k, pidx - s_off[k]);
+      const double4 e = cand(q);
       rx = e.x;
       ry = e.y;
       rz = e.z;
       i = (int)e.w;
       if (quad < 3) s_f[w][lp][quad] = 0ull;
       if (quad == 0) {
-        const double4 v = gload(cvel + own);
+        const double4 v = cvel_of(q);
         s_rv[w][lp][0] = rx;
         s_rv[w][lp][1] = ry;
         s_rv[w][lp][2] = rz;
@@ -272,11 +304,9 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
         s_sp[w][lp] = (int)v.w;
       }
     }
-    const int cx = ci / (n * n), cy = (ci / n) % n, cz = ci % n;
-    // The lane's share of the 27 neighbour cells (o = quad, quad + Q, ...):
-    // their counts are loaded together up front, and the lane's candidates
-    // t = 0 .. T-1 (cell by cell, slot by slot) are then fetched kB at a time,
-    // so that kB loads are in flight instead of one.
+    // The lane's share of the 27 neighbour cells (o = quad, quad + Q, ...),
+    // as staged cells; its candidates t = 0 .. T-1 (cell by cell, slot by
+    // slot) are read kB at a time.
     constexpr int KC = (27 + Q - 1) / Q;
     constexpr int kB = 4;
     int cb[KC], cnk[KC], pre[KC];
@@ -287,10 +317,11 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
       const bool ok = has && o < 27 && dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) &&
                       dpd_offset_valid(oz, n);
-      const int c = ok ? (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + mod_pos(cz + oz, n) : 0;
-      int ck = ok ? dcnt[c] : 0;
-      cnk[k] = ck < cap ? ck : cap;
-      cb[k] = c * cap;
+      int z = zi + oz;
+      if (whole) z = z < 0 ? z + Sz : (z >= Sz ? z - Sz : z);
+      const int kc = ((ox + 1) * 3 + (oy + 1)) * Sz + z;
+      cnk[k] = ok ? s_cnt[kc] : 0;
+      cb[k] = ok ? where(kc, 0) : 0;
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -313,7 +344,7 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u)
-        if (slot[u] >= 0) e[u] = gload(cpos + slot[u]);
+        if (slot[u] >= 0) e[u] = cand(slot[u]);
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         bool take = false;
@@ -366,6 +397,88 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
 }
 
 template <int Q>
+__device__ __forceinline__ void
+dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
+              gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
+              gptr<const double4> __restrict__ cvel, gptr<const int> __restrict__ bond_start,
+              gptr<const int> __restrict__ bond_to, gptr<double> __restrict__ fdpd, int pb, int nb) {
+  extern __shared__ __align__(16) unsigned char pair_smem[];
+  __shared__ PairScratch<Q> sh;
+  __shared__ int s_cnt[kPairCells], s_off[kPairCells + 1], s_gcell[kPairCells];
+  __shared__ int s_wsum[kPairThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
+  const int n = P.ncell, cap = P.cap;
+  const int col = lb / P.nseg, seg = lb % P.nseg;
+  if (col >= n * n) return;  // whole block leaves together
+  const int cx = col / n, cy = col % n;
+  const bool whole = P.seg_whole != 0;
+  const int z0 = seg * P.seg_cells;
+  const int zn = (n - z0) < P.seg_cells ? (n - z0) : P.seg_cells;  // own cells of the segment
+  const int Sz = whole ? n : P.seg_cells + 2;                         // staged z-cells per column
+  const int zlo = whole ? 0 : 1, zhi = zlo + zn;
+  const int ncells = 9 * Sz;
+  // counts of the staged cells (invalid aliasing columns of tiny grids count 0)
+  for (int k = threadIdx.x; k < ncells; k += kPairThreads) {
+    const int c9 = k / Sz, zs = k % Sz;
+    const int ox = c9 / 3 - 1, oy = c9 % 3 - 1;
+    int c = 0, cnt = 0;
+    if (dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n)) {
+      const int z = whole ? zs : mod_pos(z0 - 1 + zs, n);
+      c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + z;
+      cnt = dcnt[c];
+      cnt = cnt < cap ? cnt : cap;
+    }
+    s_cnt[k] = cnt;
+    s_gcell[k] = c;
+  }
+  __syncthreads();
+  // exclusive prefix sum over at most 256 cells: one per thread, wavefront scans
+  {
+    const int k = threadIdx.x;
+    const int v = k < ncells ? s_cnt[k] : 0;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) s_wsum[w] = x;
+    __syncthreads();
+    int base = 0;
+    for (int q = 0; q < w; ++q) base += s_wsum[q];
+    if (k < ncells) s_off[k] = base + x - v;
+    if (k == ncells - 1) s_off[ncells] = base + x;
+    __syncthreads();
+  }
+  const int S = s_off[ncells];
+  const int stage_cap = P.pair_stage;
+  double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
+  double4 *s_vel = s_pos + stage_cap;
+  int *s_pc = reinterpret_cast<int *>(s_vel + stage_cap);
+  if (S <= stage_cap) {
+    // copy the staged particles: particle p of staged cell k (binary search over the offsets)
+    for (int p = threadIdx.x; p < S; p += kPairThreads) {
+      int lo = 0, hi = ncells;  // s_off[lo] <= p < s_off[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= p) lo = mid; else hi = mid;
+      }
+      const int g = s_gcell[lo] * cap + (p - s_off[lo]);
+      s_pos[p] = gload(cpos + g);
+      s_vel[p] = gload(cvel + g);
+      s_pc[p] = lo;
+    }
+    __syncthreads();
+    dpd_pair_segment<Q, true>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
+                              s_pos, s_vel, s_pc, Sz, zlo, zhi);
+  } else {
+    dpd_pair_segment<Q, false>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
+                               s_pos, s_vel, s_pc, Sz, zlo, zhi);
+  }
+}
+
+template <int Q>
 __global__ void __launch_bounds__(kPairThreads)
 k_dpd_pair(DpdParams P, uint64_t step, const double *__restrict__ pos, const int *__restrict__ dcnt,
            const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
@@ -374,20 +487,27 @@ k_dpd_pair(DpdParams P, uint64_t step, const double *__restrict__ pos, const int
                    to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
-int pair_group_cells(double cell_mean, int lanes) {
-  const double per_round = 0.75 * (double)(kWave / lanes);
-  int g = (int)(per_round / (cell_mean > 0.0 ? cell_mean : 1.0));
-  return g < 1 ? 1 : (g > 64 ? 64 : g);
+void pair_segments(int n, int *seg_cells, int *nseg, int *whole) {
+  if (n <= kSegWhole) {
+    *seg_cells = n;
+    *nseg = 1;
+    *whole = 1;
+  } else {
+    *seg_cells = kSegCells;
+    *nseg = (n + kSegCells - 1) / kSegCells;
+    *whole = 0;
+  }
 }
 
 int pair_blocks(const DpdParams &P, int lanes) {
-  const int64_t G = lanes == 8 ? P.group8 : P.group4;
-  const int64_t nc3 = (int64_t)P.ncell * P.ncell * P.ncell;
-  const int64_t waves = (nc3 + G - 1) / G;
-  const int64_t nw = kPairThreads / kWave;
-  int64_t blocks = (waves + nw - 1) / nw;
+  (void)lanes;
+  int64_t blocks = (int64_t)P.ncell * P.ncell * P.nseg;
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   return (int)blocks;
+}
+
+size_t pair_lds_bytes(const DpdParams &P) {
+  return (size_t)P.pair_stage * (2 * sizeof(double4) + sizeof(int));
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -432,6 +552,20 @@ __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
   if (threadIdx.x == 0) dst[0] = value;
 }
 
+// every member stages kPairStage particles
+constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + sizeof(int));
+
+hipError_t configure_pair_kernels(size_t lds_bytes) {
+  const int v = (int)(lds_bytes > kPairLdsBytes ? lds_bytes : kPairLdsBytes);
+  const void *k[] = {(const void *)k_dpd_pair<4>, (const void *)k_dpd_pair<8>, (const void *)kb_dpd_pair<4>,
+                     (const void *)kb_dpd_pair<8>};
+  for (const void *f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st) {
   if (nmap > 0) hipLaunchKernelGGL(kb_dpd_pre, dim3(nmap), dim3(256), 0, st, mem, map, mode);
   return hipGetLastError();
@@ -440,9 +574,9 @@ hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, i
 hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st) {
   if (nmap > 0) {
     if (lanes == 8)
-      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), 0, st, mem, map);
+      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
     else
-      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), 0, st, mem, map);
+      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
   }
   return hipGetLastError();
 }
@@ -472,10 +606,10 @@ hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const d
   const int nb = pair_blocks(P, lanes);
   if (tm) tm->before(1, st);
   if (lanes == 8)
-    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), 0, st, P, step, pos, dcnt, cpos, cvel,
+    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos, cvel,
                        bond_start, bond_to, fdpd);
   else
-    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), 0, st, P, step, pos, dcnt, cpos, cvel,
+    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos, cvel,
                        bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();

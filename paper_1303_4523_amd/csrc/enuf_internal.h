@@ -176,6 +176,7 @@ struct FinishArgs {
   double *vel = nullptr;
   int *dcnt = nullptr;               // DPD cell counts, cleared for the next step
   int ndcell3 = 0;
+  int energies = 1;                  // 0: skip the energy reduction (a step whose energies no one reads)
 };
 
 // The ENUF evaluation in four phases (launch_compute runs them in order on

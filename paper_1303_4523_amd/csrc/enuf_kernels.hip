@@ -1022,12 +1022,22 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
   double eg = 0.0;
   long long er = 0, esl = 0;
   if (i < N) {
+    // the pair forces and velocities do not depend on the slot: loaded with it
+    double fp[3] = {0.0, 0.0, 0.0}, vv[3] = {0.0, 0.0, 0.0};
+    if (fa.mode >= 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        fp[a] = fa.fdpd[3 * i + a];
+        if (fa.mode == 0) vv[a] = fa.vel[3 * i + a];
+      }
+    }
     const int j = slot[i];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (j >= 0) {
       er = (long long)ereal[2 * (size_t)j];
       esl = (long long)ereal[2 * (size_t)j + 1];
       double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
+#pragma unroll 8
       for (int s = 0; s < P2S; ++s) {
         const double4 v = gload(part + (size_t)j * P2S + s);
         bx += v.x;
@@ -1049,9 +1059,9 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
       const double fe[3] = {fx, fy, fz};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double f = fa.fdpd[3 * i + a] + fa.kappa * fe[a];
+        const double f = fp[a] + fa.kappa * fe[a];
         forces[3 * i + a] = f;
-        if (fa.mode == 0) fa.vel[3 * i + a] += 0.5 * fa.dt * f;
+        if (fa.mode == 0) fa.vel[3 * i + a] = vv[a] + 0.5 * fa.dt * f;
       }
     }
   }
@@ -1147,7 +1157,6 @@ template <> struct MemberTables<float> {
 template <typename T>
 __global__ void __launch_bounds__(kPassThreads)
 kb_recip_fwd(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
-  using C = typename CplxOf<T>::type;
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
   recip_fwd_body<T>(to_g(m.buf.xq), to_g(m.buf.xcnt), to_g(m.buf.xslot), to_g(MemberTables<T>::wcoef(m.buf)),
@@ -1399,9 +1408,10 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
                      (const double4 *)b.xq, (const unsigned long long *)b.freal, (const double4 *)b.part,
                      2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, nblk, b.blk_eg,
                      (const unsigned long long *)b.ereal, b.blk_er, b.ccnt, ncell3, b.xcnt, cfg.mesh.M, fa, forces);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
-                     (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky, (const DevScalars *)b.sc,
-                     cfg.alpha, inv2piL, energy_total, energy5);
+  if (fa.energies)
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
+                       (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky,
+                       (const DevScalars *)b.sc, cfg.alpha, inv2piL, energy_total, energy5);
   if (tm) tm->after(kid, st);
   return hipGetLastError();
 }

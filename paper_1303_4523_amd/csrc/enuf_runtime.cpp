@@ -812,9 +812,13 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   P.ncell = nc;
   P.cap = cap;
   P.inv_cell = (double)nc / box;
-  const double cell_mean = (double)N / ((double)nc * nc * nc);
-  P.group4 = pair_group_cells(cell_mean, 4);
-  P.group8 = pair_group_cells(cell_mean, 8);
+  pair_segments(nc, &P.seg_cells, &P.nseg, &P.seg_whole);
+  P.pair_stage = kPairStage;
+  if (configure_pair_kernels(pair_lds_bytes(P)) != hipSuccess) {
+    set_error("configuring the pair kernels failed");
+    delete d;
+    return nullptr;
+  }
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
   const std::array<size_t, kDpdBuffers> sz = dpd_buffer_bytes(N, box, nbonds);
   void *ptr[kDpdBuffers];
@@ -920,7 +924,10 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
 // One force evaluation (mode 1) or step (mode 0).  With a plan the pair
 // forces and the real-space term run on two forked streams while the mesh
 // passes run on the integrator's stream; the combine kernel joins them.
-static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step) {
+// energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
+// reports the last one; steps inside a run other than its last skip it).
+static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step,
+                    bool energies = true) {
   const int64_t N = d->N;
   KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
   hipStream_t st = d->stream;
@@ -958,6 +965,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
       fa.vel = vel;
       fa.dcnt = d->dcnt;
       fa.ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
+      fa.energies = energies ? 1 : 0;
       e = launch_combine(pl->cfg, pl->buf, force, nullptr, d->e5, fa, st, tm);
     }
   }
@@ -992,7 +1000,7 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
   if (rc != ENUF_OK) return rc;
   if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
   for (int s = 0; s < nsteps; ++s) {
-    rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s);
+    rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s, s == nsteps - 1);
     if (rc != ENUF_OK) return rc;
   }
   return ENUF_OK;
