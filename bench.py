@@ -62,7 +62,24 @@ def parse():
                     help="run each step on one stream (no overlap of pair, real-space and mesh kernels)")
     ap.add_argument("--batched-steps", type=int, default=200, help="steps of the 64-replica batch (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=150, help="requests of the serving stream (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 512 MiB device-to-device five times (scale of the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: 512 MiB read and 512 MiB written per launch."""
+    import torch
+    torch.cuda.set_device(0)
+    n = 64 << 20
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8}), flush=True)
 
 
 def kernel_model(name, s, e):
@@ -218,6 +235,9 @@ def serving(nreq, dev):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return 0
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported; this build runs on a single GPU "
               "(independent systems shard trivially, see DESIGN.md)", file=sys.stderr)

@@ -242,7 +242,7 @@ size_t enuf_dpd_footprint_bytes(const enuf_dpd *dpd);
 size_t enuf_plan_footprint_estimate(int64_t N, double box, int p, int M, int Kc, double r_cut);
 size_t enuf_dpd_footprint_estimate(int64_t N, double box, int64_t nbonds);
 
-/* Lanes per particle of the pair-force kernel: 4 (default) or 8.  Results do
+/* Lanes per particle of the pair-force kernel: 4 or 8 (default).  Results do
  * not depend on it (exact fixed-point force sums). */
 int enuf_dpd_set_tuning(enuf_dpd *dpd, int pair_lanes);
 

@@ -74,7 +74,7 @@ hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, 
 void pair_segments(int n, int *seg_cells, int *nseg, int *whole);
 // Dynamic LDS bytes of the pair kernel (its staged particles).
 size_t pair_lds_bytes(const DpdParams &P);
-constexpr int kPairStage = 768;   // particles staged per segment (52 KB of LDS)
+constexpr int kPairStage = 768;   // particles staged per segment (30 KB of LDS)
 // Allow the pair kernels the dynamic LDS of their staged particles.
 hipError_t configure_pair_kernels(size_t lds_bytes);
 // Blocks of the pair kernel (one per column segment), a multiple of 8 (whole

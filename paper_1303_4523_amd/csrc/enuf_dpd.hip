@@ -166,8 +166,9 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
 // when it has at most kSegWhole cells).  It first stages in LDS every
 // particle of the 9 neighbouring columns over the segment's z-range plus one
 // cell on each side (the whole column: no halo): the cell counts are read and
-// prefix-summed, then positions and predicted velocities are copied with all
-// loads in flight together.  The segment's own particles form one contiguous
+// prefix-summed, then the positions are copied with all loads in flight
+// together (predicted velocities are read from global memory by the pair
+// evaluation, which keeps the block small enough for three per CU).  The segment's own particles form one contiguous
 // range of the staged set; each wavefront takes 64/Q of them at a time with Q
 // = 4 or 8 lanes per particle.
 // Scan: each lane walks the staged particles of its share of the particle's
@@ -214,7 +215,7 @@ dpd_pair_segment(const DpdParams &P, uint64_t step, gptr<const double> __restric
                  gptr<const double4> __restrict__ cpos, gptr<const double4> __restrict__ cvel,
                  gptr<const int> __restrict__ bond_start, gptr<const int> __restrict__ bond_to,
                  gptr<double> __restrict__ fdpd, PairScratch<Q> &sh, const int *s_cnt, const int *s_off,
-                 const int *s_gcell, const double4 *s_pos, const double4 *s_vel, const int *s_pc, int Sz, int zlo,
+                 const int *s_gcell, const double4 *s_pos, const int *s_gs, const int *s_pc, int Sz, int zlo,
                  int zhi) {
   constexpr int PPW = kWave / Q;
   constexpr int NW = kPairThreads / kWave;
@@ -233,7 +234,7 @@ dpd_pair_segment(const DpdParams &P, uint64_t step, gptr<const double> __restric
   // staged index of particle s of staged cell k (STAGED) or its global slot
   auto where = [&](int k, int sl) { return STAGED ? s_off[k] + sl : s_gcell[k] * cap + sl; };
   auto cand = [&](int q) -> double4 { return STAGED ? s_pos[q] : gload(cpos + q); };
-  auto cvel_of = [&](int q) -> double4 { return STAGED ? s_vel[q] : gload(cvel + q); };
+  auto cvel_of = [&](int q) -> double4 { return gload(cvel + (STAGED ? s_gs[q] : q)); };
 
   auto wave_sync = []() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -454,8 +455,8 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
   const int S = s_off[ncells];
   const int stage_cap = P.pair_stage;
   double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
-  double4 *s_vel = s_pos + stage_cap;
-  int *s_pc = reinterpret_cast<int *>(s_vel + stage_cap);
+  int *s_gs = reinterpret_cast<int *>(s_pos + stage_cap);  // global slot of each staged particle
+  int *s_pc = s_gs + stage_cap;                             // its staged cell
   if (S <= stage_cap) {
     // copy the staged particles: particle p of staged cell k (binary search over the offsets)
     for (int p = threadIdx.x; p < S; p += kPairThreads) {
@@ -466,15 +467,15 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       }
       const int g = s_gcell[lo] * cap + (p - s_off[lo]);
       s_pos[p] = gload(cpos + g);
-      s_vel[p] = gload(cvel + g);
+      s_gs[p] = g;
       s_pc[p] = lo;
     }
     __syncthreads();
     dpd_pair_segment<Q, true>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
-                              s_pos, s_vel, s_pc, Sz, zlo, zhi);
+                              s_pos, s_gs, s_pc, Sz, zlo, zhi);
   } else {
     dpd_pair_segment<Q, false>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
-                               s_pos, s_vel, s_pc, Sz, zlo, zhi);
+                               s_pos, s_gs, s_pc, Sz, zlo, zhi);
   }
 }
 
@@ -507,7 +508,7 @@ int pair_blocks(const DpdParams &P, int lanes) {
 }
 
 size_t pair_lds_bytes(const DpdParams &P) {
-  return (size_t)P.pair_stage * (2 * sizeof(double4) + sizeof(int));
+  return (size_t)P.pair_stage * (sizeof(double4) + 2 * sizeof(int));
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -553,7 +554,7 @@ __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
 }
 
 // every member stages kPairStage particles
-constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + sizeof(int));
+constexpr size_t kPairLdsBytes = (size_t)kPairStage * (sizeof(double4) + 2 * sizeof(int));
 
 hipError_t configure_pair_kernels(size_t lds_bytes) {
   const int v = (int)(lds_bytes > kPairLdsBytes ? lds_bytes : kPairLdsBytes);

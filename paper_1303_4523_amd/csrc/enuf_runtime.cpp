@@ -733,7 +733,7 @@ struct enuf_dpd {
   int concurrent = 1;
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
   unsigned long long *step_ctr = nullptr;  // [1] next step index when stepped in a batch
-  int pair_lanes = 4;                      // lanes per particle of the pair kernel (4 or 8)
+  int pair_lanes = 8;                      // lanes per particle of the pair kernel (4 or 8)
   int *species = nullptr;                  // [N] species of each particle (read when P.nspec > 1)
   int batches = 0;                         // batches this integrator is a member of
   size_t bytes = 0;
