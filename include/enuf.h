@@ -87,9 +87,11 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
  * compact index j = part (mod parts), spreads them into its own plane and
  * transforms it; the partial spectra are rounded to fixed point and summed
  * exactly, so results are reproducible for a given number of parts (and
- * differ between part counts only in the last bits).  The default fills the
- * device with one system: parts = min(8, 256 / M) (ENUF_MESH_PARTS, read at
- * plan creation, overrides it).  Systems stepped together in a batch already
+ * differ between part counts only in the last bits).  The default spreads
+ * one system's mesh passes over about half the device, leaving the rest to
+ * the pair and real-space kernels that run beside them: parts = min(8, 128 / M)
+ * (ENUF_MESH_PARTS, read at plan creation, overrides it).  The x pass takes
+ * min(Kc, 64 / (2 Kc - 1)) work-groups per ky row (ENUF_X_SPLIT overrides it).  Systems stepped together in a batch already
  * fill the device: 1 part per plane avoids the repeated transforms there.
  * A batch reads the value when its membership changes.  Synchronises the
  * plan's stream.  ENUF_EINVAL outside the allowed range.

@@ -54,6 +54,24 @@ __device__ inline int mesh_cell(double x, double m_over_l, int M, double *t) {
   return c;
 }
 
+// q = a / b and *rem = a % b for 0 <= a < 2^22 and 1 <= b < 2^11, from a
+// single-precision reciprocal inv_b = 1/b: the estimate a * inv_b is within
+// 0.5 of a/b, so its floor is off by at most one and is corrected (a few
+// instructions instead of an integer division).
+__device__ __forceinline__ int fdivmod(int a, int b, float inv_b, int *rem) {
+  int q = (int)((float)a * inv_b);
+  int r = a - q * b;
+  if (r < 0) {
+    --q;
+    r += b;
+  } else if (r >= b) {
+    ++q;
+    r -= b;
+  }
+  *rem = r;
+  return q;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev series sum_{k<=n} c_k T_k(x) by Clenshaw's recurrence.  The mesh
 // kernels evaluate the window from per-offset series of this form (the

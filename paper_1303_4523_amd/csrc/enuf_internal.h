@@ -65,6 +65,7 @@ struct MeshParams {
   int stage;       // charges of a plane staged in LDS at a time (<= kStage)
   int parts;       // work-groups per plane in the spread and gather passes, each
                    // taking a contiguous share of the plane's charges (<= kMaxParts)
+  int xsplit;      // work-groups per ky row in the x pass, each a contiguous range of kz
   double gscale_f; // fixed-point scale of the partial spectra, relative to the
                    // spread's scale: 2^-(3 ceil(log2 2p) + 3)
   double L;
@@ -123,7 +124,7 @@ struct ComputeBuffers {
                          // G[part][x][ky][kz] as fixed-point int64 pairs, then the field
                          // spectrum h[x][ky][kz] as complex T (double2 or float2)
   void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
-  double *epart;         // [nky] k-space energy per ky row
+  double *epart;         // [nky * xsplit] k-space energy per (ky row, kz range)
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
   int *xcnt;             // [M] charges per mesh x-cell (zero between calls)
   int *xslot;            // [M * xcap] compact indices of the charges of each x-cell

@@ -509,6 +509,7 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   const int R = mp.rows;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+  const float inv_kc = 1.0f / (float)Kc;
 
   long long *acc = reinterpret_cast<long long *>(smem);
   T *plane = reinterpret_cast<T *>(smem);
@@ -631,7 +632,8 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
     // z: rows 2c (real part) and 2c+1 (imaginary part) form complex line c
     lds_fft<T>(plane, plane + Mp, 2 * Mp, nr / 2, mp.fft, twr, twi, false);
     for (int id = tid; id < (nr / 2) * Kc; id += nt) {
-      const int c = id / Kc, k = id % Kc, mk = (M - k) % M;
+      int k;
+      const int c = fdivmod(id, Kc, inv_kc, &k), mk = k == 0 ? 0 : M - k;
       const T zr = plane[2 * c * Mp + k], zi = plane[(2 * c + 1) * Mp + k];
       const T mr = plane[2 * c * Mp + mk], mi = plane[(2 * c + 1) * Mp + mk];
       const int y = r0 + 2 * c;
@@ -650,7 +652,8 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   const double gs = scale * mp.gscale_f;
   gptr<longlong2> dst = gfx + ((size_t)part * M + x0) * nky * Kc;
   for (int id = tid; id < nky * Kc; id += nt) {
-    const int kyi = id / Kc, kz = id % Kc;
+    int kz;
+    const int kyi = fdivmod(id, Kc, inv_kc, &kz);
     const int m = mod_pos(kyi - (Kc - 1), M);
     gstore(dst + id, make_longlong2(to_fixed((double)Zre[kz * Mz + m], gs), to_fixed((double)Zim[kz * Mz + m], gs)));
   }
@@ -673,10 +676,13 @@ __device__ __forceinline__ void
 recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
              gptr<const typename CplxOf<T>::type> __restrict__ tw, gptr<const DevScalars> __restrict__ sc,
              gptr<const longlong2> __restrict__ gfx, gptr<typename CplxOf<T>::type> gzy,
-             gptr<typename CplxOf<T>::type> gzx, gptr<double> epart, int kyi) {
+             gptr<typename CplxOf<T>::type> gzx, gptr<double> epart, int blk) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky;
   const int tid = threadIdx.x, nt = blockDim.x;
+  // ky row and this work-group's range of kz lines
+  const int kyi = blk % nky, xs = blk / nky;
+  const int kz_lo = (int)((long long)Kc * xs / mp.xsplit), kz_hi = (int)((long long)Kc * (xs + 1) / mp.xsplit);
   const int ky = kyi - (Kc - 1);
   const int nset = mp.ik ? 2 : 1;  // ik: also i kx h, for the x component of the field
   T *Xre = reinterpret_cast<T *>(smem);  // [nset Kc][Mz]: lines of h, then of i kx h
@@ -687,8 +693,13 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   double *red = reinterpret_cast<double *>(smem + red_off);
   double *at = red + kPassThreads / kWave;  // [nky] influence table
 
-  int nkz = 0;
+  int nkz = 0;  // lines kz < nkz hold modes of the sphere
   while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
+  const int l1 = nkz < kz_hi ? nkz : kz_hi;
+  const int nl = l1 > kz_lo ? l1 - kz_lo : 0;  // transformed lines of this work-group
+  const int nw = kz_hi - kz_lo;                 // stored lines (zero beyond nkz)
+  const float inv_nl = 1.0f / (float)(nl > 0 ? nl : 1), inv_m = 1.0f / (float)M,
+              inv_nw = 1.0f / (float)(nw > 0 ? nw : 1);
 
   for (int m = tid; m < M; m += nt) {
     const typename CplxOf<T>::type t = gload(tw + m);
@@ -699,8 +710,10 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   // sum of the plane parts' fixed-point spectra (exact), then back to T
   const double ig = sc->inv_scale / mp.gscale_f;
   const size_t pstride = (size_t)M * nky * Kc;
-  for (int id = tid; id < M * nkz; id += nt) {
-    const int x = id / nkz, kz = id % nkz;
+  for (int id = tid; id < M * nl; id += nt) {
+    int kz;
+    const int x = fdivmod(id, nl, inv_nl, &kz);
+    kz += kz_lo;
     const size_t at0 = ((size_t)x * nky + kyi) * Kc + kz;
     long long vr = 0, vi = 0;
     for (int pt = 0; pt < mp.parts; ++pt) {
@@ -712,12 +725,13 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
     Xim[kz * Mz + x] = (T)((double)vi * ig);
   }
   __syncthreads();
-  lds_fft<T>(Xre, Xim, Mz, nkz, mp.fft, twr, twi, false);
+  lds_fft<T>(Xre + (size_t)kz_lo * Mz, Xim + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, false);
 
   const double ay = at[kyi];
   double e = 0.0;
-  for (int id = tid; id < nkz * M; id += nt) {
-    const int kz = id / M, m = id % M;
+  for (int id = tid; id < nl * M; id += nt) {
+    int m;
+    const int kz = kz_lo + fdivmod(id, M, inv_m, &m);
     const int kx = m < M / 2 ? m : m - M;
     const int k2 = kx * kx + ky * ky + kz * kz;
     T hr = (T)0, hi = (T)0;
@@ -736,14 +750,16 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
     }
   }
   e = block_sum(e, red);
-  if (tid == 0) epart[kyi] = e;
+  if (tid == 0) epart[blk] = e;
   __syncthreads();
   for (int set = 0; set < nset; ++set) {
     T *re = Xre + (size_t)set * Kc * Mz, *im = Xim + (size_t)set * Kc * Mz;
-    lds_fft<T>(re, im, Mz, nkz, mp.fft, twr, twi, true);
+    lds_fft<T>(re + (size_t)kz_lo * Mz, im + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, true);
     gptr<typename CplxOf<T>::type> dst = set == 0 ? gzy : gzx;
-    for (int id = tid; id < M * Kc; id += nt) {
-      const int x = id / Kc, kz = id % Kc;
+    for (int id = tid; id < M * nw; id += nt) {
+      int kz;
+      const int x = fdivmod(id, nw, inv_nw, &kz);
+      kz += kz_lo;
       typename CplxOf<T>::type v;
       v.x = kz < nkz ? re[kz * Mz + x] : (T)0;
       v.y = kz < nkz ? im[kz * Mz + x] : (T)0;
@@ -779,6 +795,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
   const int P2pad = pow2_at_least(P2);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
+  const float inv_kc = 1.0f / (float)Kc, inv_m = 1.0f / (float)M;
 
   T *plane = reinterpret_cast<T *>(smem);  // [rows][Mp]
   size_t off = align16((size_t)R * Mp * sizeof(T));
@@ -817,7 +834,8 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
     __syncthreads();
     gptr<const typename CplxOf<T>::type> src = (IK && comp == 0) ? gzx : gzy;
     for (int id = tid; id < nky * Kc; id += nt) {
-      const int kyi = id / Kc, kz = id % Kc;
+      int kz;
+      const int kyi = fdivmod(id, Kc, inv_kc, &kz);
       const int m = mod_pos(kyi - (Kc - 1), M);
       typename CplxOf<T>::type v = gload(src + ((size_t)x0 * nky + kyi) * Kc + kz);
       if (IK && comp > 0) {  // times i ky or i kz
@@ -836,7 +854,8 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
       const int nr = (M - r0) < R ? (M - r0) : R;
       // Hermitian z spectra of rows r0 + 2c and r0 + 2c + 1 packed as H1 + i H2
       for (int id = tid; id < (nr / 2) * M; id += nt) {
-        const int c = id / M, k = id % M, y = r0 + 2 * c;
+        int k;
+        const int c = fdivmod(id, M, inv_m, &k), y = r0 + 2 * c;
         T re = (T)0, im = (T)0;
         if (k < Kc) {
           const T h1r = Zre[k * Mz + y], h1i = Zim[k * Mz + y];
@@ -1076,7 +1095,7 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
 }
 
 // Final energies of one evaluation from the per-block partials of the combine
-// kernel and the per-ky k-space sums (one block; a separate launch, so the
+// kernel and the k-space sums per (ky row, kz range) (one block; a separate launch, so the
 // partials of every combine block are visible without a device-wide fence).
 __device__ __forceinline__ void finish_body(int nblk, const double *__restrict__ blk_eg,
                                             const long long *__restrict__ blk_er,
@@ -1210,7 +1229,8 @@ kb_combine(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, in
 __global__ void __launch_bounds__(kPrepThreads)
 kb_finish(const BatchMember *__restrict__ mem, int mode) {
   const BatchMember &m = mem[blockIdx.x];
-  finish_body(m.nblk, m.buf.blk_eg, m.buf.blk_er, m.buf.epart, m.cfg.mesh.nky, m.buf.sc, m.cfg.alpha, m.inv2piL,
+  finish_body(m.nblk, m.buf.blk_eg, m.buf.blk_er, m.buf.epart, m.cfg.mesh.nky * m.cfg.mesh.xsplit, m.buf.sc,
+              m.cfg.alpha, m.inv2piL,
               nullptr, m.e5, mode == 0 ? m.step : nullptr);
 }
 
@@ -1339,7 +1359,7 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
                      (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gfx);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
-  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw,
+  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky * mp.xsplit), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw,
                      (const DevScalars *)b.sc, (const longlong2 *)gfx, gh, reinterpret_cast<C *>(b.gzx), b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
@@ -1410,7 +1430,7 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
                      (const unsigned long long *)b.ereal, b.blk_er, b.ccnt, ncell3, b.xcnt, cfg.mesh.M, fa, forces);
   if (fa.energies)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
-                       (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky,
+                       (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky * cfg.mesh.xsplit,
                        (const DevScalars *)b.sc, cfg.alpha, inv2piL, energy_total, energy5);
   if (tm) tm->after(kid, st);
   return hipGetLastError();

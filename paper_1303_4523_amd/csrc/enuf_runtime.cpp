@@ -304,15 +304,26 @@ int upload_tables(enuf_plan *pl) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Work-groups per plane of the spread and gather passes: enough planes x
-// parts to give every CU of the device a work-group (256 CUs), at most kMaxParts.
+// Work-groups per plane of the spread and gather passes: about 128 planes x
+// parts, half the CUs of the device, which leaves the other half to the pair
+// and real-space kernels that run beside the mesh passes; at most kMaxParts.
 // ENUF_MESH_PARTS (1..8) overrides the choice (tuning and testing).
 int mesh_parts(int M) {
   if (const char *v = std::getenv("ENUF_MESH_PARTS")) {
     const int n = std::atoi(v);
     if (n >= 1) return std::min(kMaxParts, n);
   }
-  return std::max(1, std::min(kMaxParts, 256 / M));
+  return std::max(1, std::min(kMaxParts, 128 / M));
+}
+
+// Work-groups per ky row of the x pass: about 64 in all, each a range of kz
+// lines.  ENUF_X_SPLIT (1..Kc) overrides the choice (tuning and testing).
+int mesh_xsplit(int Kc, int nky) {
+  if (const char *v = std::getenv("ENUF_X_SPLIT")) {
+    const int n = std::atoi(v);
+    if (n >= 1) return std::min(Kc, n);
+  }
+  return std::max(1, std::min(Kc, 64 / nky));
 }
 
 // Fixed-point scale of the partial spectra relative to the spread's: the
@@ -375,7 +386,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           nblk * 2 * sizeof(long long),                       // blk_er
           (size_t)(mesh_parts(M) + 1) * M * nky * (size_t)Kc * 16,  // gzy: partial spectra + field
           (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzx
-          nky * sizeof(double),                               // epart
+          nky * (size_t)Kc * sizeof(double),                  // epart (x-pass splits <= Kc)
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
           (size_t)M * sizeof(int),                            // xcnt
@@ -450,6 +461,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.fft = fp;
   m.parts = mesh_parts(M);
   pl->max_parts = m.parts;  // the spectrum buffer holds this many partial spectra
+  m.xsplit = mesh_xsplit(Kc, m.nky);
   m.gscale_f = mesh_gscale_factor(p);
   PlanGeom g;
   if (!plan_geometry(N, box, p, M, Kc, r_cut, pl->max_lds, &g)) {
@@ -1212,7 +1224,8 @@ int batch_rebuild(enuf_batch *b) {
     const int id = (int)mem.size();
     mem.push_back(m);
     const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;  // work-groups of the spread and gather passes
-    const int counts[7] = {m.nblk, m.pair_blocks, m.real_blocks, planes, m.cfg.mesh.nky, planes, m.nblk};
+    const int counts[7] = {m.nblk,  m.pair_blocks, m.real_blocks, planes, m.cfg.mesh.nky * m.cfg.mesh.xsplit,
+                           planes, m.nblk};
     for (int s = 0; s < 7; ++s)
       for (int i = 0; i < counts[s]; ++i) map[s].push_back(make_int2(id, i));
     lf = std::max(lf, m.cfg.lds_fwd);

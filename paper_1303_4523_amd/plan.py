@@ -58,7 +58,7 @@ class Plan:
 
     def set_parts(self, parts):
         """Work-groups per mesh plane in the spread and gather passes (1 up
-        to the creation default min(8, 256 / M)); 1 for systems stepped in a
+        to the creation default min(8, 128 / M)); 1 for systems stepped in a
         batch, which already fills the device."""
         check(lib.enuf_plan_set_parts(self._h, int(parts)), "enuf_plan_set_parts")
 
