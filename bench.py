@@ -54,8 +54,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=10,
-                    help="oracle DPD steps timed on the host for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=200,
+                    help="at most this many oracle DPD steps timed on the host for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="stop the cpu_baseline sample after the step that passes this many seconds")
     ap.add_argument("--time-kernel", default="dpd_pair",
                     help="kernel whose launches are event-timed for the roofline entry")
     ap.add_argument("--serial", action="store_true",
@@ -116,14 +118,16 @@ def measured_traffic(kernel):
     return float(mb.group(1))
 
 
-def cpu_baseline(s, prm, e, nsteps):
+def cpu_baseline(s, prm, e, max_steps, seconds):
     import oracle
     P = dict(prm, alpha=e["alpha"], r_cut=e["r_cut"], lambda_e=e["lam"], Kc=e["Kc"], use_elec=1)
     F, _ = oracle.dpd_forces(s.pos, s.vel, s.q, s.bonds, P, seed=prm["seed"], step=0)
     pos, vel = s.pos.copy(), s.vel.copy()
     t0 = time.perf_counter()
-    for k in range(1, nsteps + 1):
-        pos, vel, F, _ = oracle.dpd_step(pos, vel, F, s.q, s.bonds, P, seed=prm["seed"], step=k)
+    nsteps = 0
+    while nsteps < max_steps and (nsteps == 0 or time.perf_counter() - t0 < seconds):
+        nsteps += 1
+        pos, vel, F, _ = oracle.dpd_step(pos, vel, F, s.q, s.bonds, P, seed=prm["seed"], step=nsteps)
     dt = time.perf_counter() - t0
     return {"value": s.N * nsteps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
             "kind": "oracle",
@@ -240,7 +244,7 @@ def main():
         return 0
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} is not supported; this build runs on a single GPU "
-              "(independent systems shard trivially, see DESIGN.md)", file=sys.stderr)
+              "(independent systems would run one process per GPU)", file=sys.stderr)
         return 2
     import torch
 
@@ -313,7 +317,7 @@ def main():
         "roofline": roofline,
     }
     if a.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(s, prm, e, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(s, prm, e, a.cpu_steps, a.cpu_seconds)
     if a.batched_steps > 0:
         out["batched"] = batched(a.batched_steps, dev)
     if a.serving_requests > 0:

@@ -1,6 +1,6 @@
 """GPU parity of enuf_compute against the FP64 CPU oracle (direct Ewald).
 
-Bars (BASELINE the benchmark spec): relative force RMS <= 1e-5 and relative energy
+Bars: relative force RMS <= 1e-5 and relative energy
 <= 1e-6 for the FP64 path; <= 5e-4 and <= 1e-4 for the mixed path.
 """
 import math
