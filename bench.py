@@ -160,7 +160,6 @@ def batched(nsteps, dev):
     b = Batch("mixed", device=dev)
     for m in mem:
         b.add(*m, first_step=1)
-    lanes, _ = b.autotune(5)
     b.run(10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -189,7 +188,7 @@ def batched(nsteps, dev):
     return {"workload": "64 replicas, N log-uniform 3000-48000 (sum %d), f 0.1-1, valency 1-3, own M/Kc" % N,
             "precision": "mixed", "steps": nsteps, "ms_per_step": dt / nsteps * 1e3,
             "particle_steps_per_s": value, "plain_fp64_particle_steps_per_s": plain,
-            "speedup_vs_plain_fp64": value / plain, "pair_lanes": lanes, "status": status}
+            "speedup_vs_plain_fp64": value / plain, "status": status}
 
 
 def serving(nreq, dev):
@@ -313,7 +312,7 @@ def main():
         "config": {"workload": "DPD polyelectrolyte + salt, L=20, N=24000, Nq=1650, ENUF M=64 Kc=16 p=4",
                    "N": s.N, "Nq": s.Nq, "box": s.L, "M": e["M"], "Kc": e["Kc"], "p": e["p"],
                    "precision": "fp64", "window": "kaiser-bessel",
-                   "schedule": "serial" if a.serial else "forked streams"},
+                   "schedule": "serial" if a.serial else "forked stream"},
         "roofline": roofline,
     }
     if a.cpu_steps > 0:

@@ -187,6 +187,9 @@ typedef struct {
  *            Not owned; it must outlive the integrator.
  *   q      : DEVICE pointer to N charges, copied at creation (charges are fixed).
  *   bonds  : HOST pointer to nbonds (i, j) index pairs (int64), copied.
+ * The cell grid has floor(box) cells per side and
+ * ceil(m + 6 sqrt(m) + 16) slots per cell (m = N / cells); creation fails if
+ * that exceeds 128 (about 70 particles per unit volume).
  * Returns NULL on error (enuf_last_error).  Allocates device scratch.
  */
 enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *params, enuf_plan *plan,
@@ -218,9 +221,10 @@ int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_
  * batch (set the species before enuf_batch_add), or on a bad argument. */
 int enuf_dpd_set_species(enuf_dpd *dpd, int nspecies, const int *species, const double *a_table);
 
-/* Overlap the pair forces and the real-space term with the mesh passes on two
- * internal streams (enable = 1, the default) or run the whole step on the
- * integrator's stream (0). */
+/* Overlap the pair forces and the real-space term (one after the other, on an
+ * internal stream) with the mesh passes on the integrator's stream
+ * (enable = 1, the default), or run the whole step on the integrator's
+ * stream (0).  Results are the same either way. */
 int enuf_dpd_set_concurrency(enuf_dpd *dpd, int enable);
 
 /* Copy (on the stream) the ENUF energy components of the last force
@@ -243,10 +247,6 @@ size_t enuf_dpd_footprint_bytes(const enuf_dpd *dpd);
  * before a system is created.  0 for invalid sizes. */
 size_t enuf_plan_footprint_estimate(int64_t N, double box, int p, int M, int Kc, double r_cut);
 size_t enuf_dpd_footprint_estimate(int64_t N, double box, int64_t nbonds);
-
-/* Lanes per particle of the pair-force kernel: 4 or 8 (default).  Results do
- * not depend on it (exact fixed-point force sums). */
-int enuf_dpd_set_tuning(enuf_dpd *dpd, int pair_lanes);
 
 /* ------------------------------------------------------------------------
  * Batched DPD steps: many independent systems (each an integrator with its
@@ -302,19 +302,7 @@ int enuf_batch_run(enuf_batch *batch, int nsteps);
 /* Device bytes of the batch's tables and of all members (with their plans). */
 size_t enuf_batch_footprint_bytes(const enuf_batch *batch);
 
-/* Lanes per particle of the pair-force kernel (4 or 8) for all members.
- * Results do not depend on it (exact fixed-point force sums). */
-int enuf_batch_set_tuning(enuf_batch *batch, int pair_lanes);
 
-/*
- * Autotuner: time trial_steps eager steps of the current members under each
- * launch configuration (pair lanes 4 / 8; with graphs off also forked / single
- * stream), keep the fastest, and restore every member's state (pos, vel,
- * force, step index) to what it was on entry.  Synchronises; allocates a
- * temporary copy of the states.
- * The chosen values are returned through the pointers (which may be NULL).
- */
-int enuf_batch_autotune(enuf_batch *batch, int trial_steps, int *pair_lanes, int *concurrent);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support).  While enabled, an integrator records

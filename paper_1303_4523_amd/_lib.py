@@ -94,12 +94,6 @@ lib.enuf_batch_run.argtypes = [_vp, _int]
 lib.enuf_batch_run.restype = _int
 lib.enuf_batch_footprint_bytes.argtypes = [_vp]
 lib.enuf_batch_footprint_bytes.restype = _sz
-lib.enuf_batch_set_tuning.argtypes = [_vp, _int]
-lib.enuf_batch_set_tuning.restype = _int
-lib.enuf_batch_autotune.argtypes = [_vp, _int, ctypes.POINTER(_int), ctypes.POINTER(_int)]
-lib.enuf_batch_autotune.restype = _int
-lib.enuf_dpd_set_tuning.argtypes = [_vp, _int]
-lib.enuf_dpd_set_tuning.restype = _int
 lib.enuf_plan_set_parts.argtypes = [_vp, _int]
 lib.enuf_plan_set_parts.restype = _int
 lib.enuf_dpd_set_species.argtypes = [_vp, _int, _vp, _vp]
@@ -123,7 +117,6 @@ EXPORTED = [
     "enuf_dpd_time_kernel", "enuf_dpd_kernel_time", "enuf_dpd_footprint_bytes",
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
-    "enuf_batch_set_tuning", "enuf_batch_autotune", "enuf_dpd_set_tuning",
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
     "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",
 ]

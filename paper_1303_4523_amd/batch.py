@@ -58,18 +58,6 @@ class Batch:
         self._bind_stream()
         check(lib.enuf_batch_run(self._h, int(nsteps)), "enuf_batch_run")
 
-    def set_tuning(self, pair_lanes):
-        check(lib.enuf_batch_set_tuning(self._h, int(pair_lanes)), "enuf_batch_set_tuning")
-
-    def autotune(self, trial_steps=5):
-        """Pick the fastest launch configuration on the current members; their
-        states are left as they were.  Returns (pair_lanes, concurrent)."""
-        self._bind_stream()
-        lanes, conc = ctypes.c_int(0), ctypes.c_int(0)
-        check(lib.enuf_batch_autotune(self._h, int(trial_steps), ctypes.byref(lanes), ctypes.byref(conc)),
-              "enuf_batch_autotune")
-        return lanes.value, bool(conc.value)
-
     @property
     def footprint_bytes(self):
         return int(lib.enuf_batch_footprint_bytes(self._h))

@@ -14,8 +14,7 @@ struct DpdParams {
   int ncell;                        // DPD cells per side (edge >= R_c = 1)
   int cap;                          // slots per cell
   double inv_cell;
-  int seg_cells, nseg, seg_whole;   // pair kernel: cells per column segment, segments per column,
-                                    // 1 when a segment is a whole column (no z halo)
+  int seg_cells, nseg;              // pair kernel: cells per column segment, segments per column
   int pair_stage;                   // particles the pair kernel stages in LDS per segment
   int nspec;                        // > 1: the conservative amplitude depends on the pair's species
   const int *species;               // [N] species of each particle (device; read when nspec > 1)
@@ -52,7 +51,7 @@ struct BatchMember {
   ComputeBuffers buf;
   int nq;                       // charged particles (static compaction)
   int nblk;                     // blocks of 256 particles (pre, combine)
-  int pair_blocks;              // blocks of the pair kernel at the batch's lanes per particle
+  int pair_blocks;              // blocks of the pair kernel
   int real_blocks;              // blocks of the real-space kernel (one wave per charge)
   double fscale, inv2piL;       // M / (pi L^2), 1 / (2 pi L)
   int64_t N;
@@ -69,17 +68,19 @@ struct BatchMember {
 
 // Batched launches: map[b] = (member, block of that member) for block b.
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
-hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st);
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
 // Column segments of the pair kernel for a grid of n cells per side.
-void pair_segments(int n, int *seg_cells, int *nseg, int *whole);
+void pair_segments(int n, int *seg_cells, int *nseg);
 // Dynamic LDS bytes of the pair kernel (its staged particles).
 size_t pair_lds_bytes(const DpdParams &P);
-constexpr int kPairStage = 768;   // particles staged per segment (30 KB of LDS)
+constexpr int kPairStage = 384;   // particles staged per segment (30 KB of LDS)
+constexpr int kPairStageMax = 1024;  // largest stage the kernel's tables allow
+constexpr int kPairOwn = 128;     // own particles of a chunk (LDS force accumulators); cell capacity limit
 // Allow the pair kernels the dynamic LDS of their staged particles.
 hipError_t configure_pair_kernels(size_t lds_bytes);
 // Blocks of the pair kernel (one per column segment), a multiple of 8 (whole
-// rounds over the XCDs); the same at 4 and 8 lanes per particle.
-int pair_blocks(const DpdParams &P, int lanes);
+// rounds over the XCDs).
+int pair_blocks(const DpdParams &P);
 hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
                               const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
@@ -94,8 +95,8 @@ hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, 
                           int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm = nullptr);
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd, int lanes,
-                           hipStream_t st, KernelTimer *tm = nullptr);
+                           const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
+                           KernelTimer *tm = nullptr);
 hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,
                            KernelTimer *tm = nullptr);

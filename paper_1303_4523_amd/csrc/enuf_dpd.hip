@@ -161,224 +161,361 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// Pair forces by column segment.  A block takes a segment of seg_cells
-// consecutive cells of one z-column of the DPD cell grid (the whole column
-// when it has at most kSegWhole cells).  It first stages in LDS every
-// particle of the 9 neighbouring columns over the segment's z-range plus one
-// cell on each side (the whole column: no halo): the cell counts are read and
-// prefix-summed, then the positions are copied with all loads in flight
-// together (predicted velocities are read from global memory by the pair
-// evaluation, which keeps the block small enough for three per CU).  The segment's own particles form one contiguous
-// range of the staged set; each wavefront takes 64/Q of them at a time with Q
-// = 4 or 8 lanes per particle.
-// Scan: each lane walks the staged particles of its share of the particle's
-// 27 neighbour cells (LDS reads, kB at a time) and appends the pairs with
-// r < R_c = 1 to a wavefront queue in LDS.  Evaluation: the whole wavefront
-// takes the queued pairs 64 at a time (so the Philox draw and the pair force
-// run with full lanes however sparse the neighbours are) and adds each pair
-// force to i's int64 fixed-point accumulator in LDS.  Every pair is evaluated
-// from both of its particles (theta_ij = theta_ji keeps the pair forces
-// antisymmetric), so no thread writes another particle's force; the
-// fixed-point sums (2^-36) are exact, so the result does not depend on the
-// order in which pairs are visited.  With species, the cell slot's predicted
-// velocity carries the species in w and the amplitude a_ij is read from the
-// symmetric table in the parameters.  A segment whose neighbourhood holds
-// more than kPairStage particles (dense cells) runs the same algorithm with
-// the candidates read from global memory instead.  Blocks are mapped so that
-// each of the 8 XCDs (which take the blocks of a launch round-robin) works on
-// one contiguous slab of columns.  Particles beyond a full cell's capacity
-// (reported as ENUF_EOVERFLOW by the binning) get no force.
+// Pair forces by column segment.  A block takes a segment of about
+// kSegTarget consecutive cells of one z-column of the DPD cell grid (small
+// blocks leave room on every CU for the mesh passes that run beside this
+// kernel, and spread the work evenly).  It stages in LDS every particle of
+// the 9 neighbouring columns over the segment's z-range plus one cell on each
+// side (periodic images in a whole column), ordered by z-slice first and
+// column second: then the 27 neighbour cells of any cell of the segment are
+// three consecutive z-slices, so the candidates of all particles of that cell
+// form ONE contiguous range of the staged set.  Each staged particle keeps its
+// position (with its index), its predicted velocity (with its species) and an
+// FP32 position relative to the segment, shifted to the periodic image next
+// to it.
+// Scan: a wavefront takes the segment's cells one at a time (a shared
+// counter deals them out); its 64 lanes take (particle, candidate) pairs of
+// the cell, g particles x 64/g candidates per step, and append the pairs that
+// pass the FP32 test r^2 < 1 + kPairMargin to a wavefront queue.
+// Evaluation: the wavefront takes the queue 64 pairs at a time (full lanes
+// however sparse the neighbours are), re-tests r < R_c = 1 exactly in FP64
+// with the minimum image, and adds each pair force to i's int64 fixed-point
+// accumulator in LDS.  Every pair is evaluated from both of its particles
+// (theta_ij = theta_ji keeps the pair forces antisymmetric), so no thread
+// writes another particle's force; the fixed-point sums (2^-36) are exact, so
+// the result does not depend on the order in which pairs are visited.  The
+// bonds of each particle are added last, and its force written once.
+// A segment whose staged set exceeds the LDS stage (dense cells) is taken in
+// chunks of whole z-cells that fit; a single z-cell that does not fit is
+// taken with every candidate read from global memory instead.  Blocks are
+// mapped so that each of the 8 XCDs (which take the blocks of a launch
+// round-robin) works on one contiguous slab of columns.  Particles beyond a
+// full cell's capacity (reported as ENUF_EOVERFLOW by the binning) get no
+// force.  Grids of fewer than 3 cells per side (where a cell is its own
+// neighbour more than once) test every staged particle of the column set.
 constexpr int kPairThreads = 256;
-constexpr int kPairQueue = 128;   // queued pairs per wavefront (flushed at > 64)
+constexpr int kSegTarget = 10;    // cells per column segment, about
+constexpr int kPairWaves = kPairThreads / kWave;
+constexpr int kPairQueue = 128;   // queued pairs per wavefront (64 evaluated at a time)
 constexpr int kXcds = 8;          // MI355X: blocks of a launch are dealt round-robin to 8 XCDs
-constexpr int kPairCells = 256;   // staged cells: 9 columns x at most 28 z-cells
-constexpr int kSegWhole = 24;     // columns of at most this many cells are one segment
-constexpr int kSegCells = 16;     // segment length of longer columns
+constexpr int kPairZ = kSegTarget + 2;   // staged z-slices at most
+constexpr int kPairCells = 9 * kPairZ;   // staged cells at most
+static_assert(kPairCells <= kPairThreads, "the prefix sum takes one staged cell per thread");
+static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
+constexpr int kPairU = 4;         // candidate steps in flight per lane
+constexpr int kPairPer = (kPairStage + kPairThreads - 1) / kPairThreads;  // staged particles copied per thread
+constexpr float kPairMargin = 1.0e-3f;
 
-// Per-wavefront LDS of the pair evaluation: the pair queue and the rows of
-// the particles of the current round.
-template <int Q>
-struct PairScratch {
-  static constexpr int PPW = kWave / Q;
-  static constexpr int NW = kPairThreads / kWave;
-  int qs[NW][kPairQueue];
-  int ql[NW][kPairQueue];
-  double rv[NW][PPW][6];
-  int id[NW][PPW];
-  int sp[NW][PPW];
-  unsigned long long f[NW][PPW][3];
+struct PairShared {
+  int cnt[kPairCells];    // counts of the staged cells (cell zslice * 9 + column)
+  int off[kPairCells + 1];
+  int gcell[kPairCells];  // grid cell of each staged cell
+  int ownoff[kPairZ + 1]; // prefix over z-slices of the own column's counts
+  unsigned char cellof[kPairStageMax];  // staged cell (from the chunk's first) of each staged particle
+  int wsum[kPairWaves];
+  int next;               // next own z-cell of the chunk (wavefront work counter)
+  int qj[kPairWaves][kPairQueue];  // queued pairs: j, i (staged index or grid slot), i's accumulator
+  int qi[kPairWaves][kPairQueue];
+  unsigned char qa[kPairWaves][kPairQueue];
+  unsigned long long acc[kPairOwn][3];
 };
 
-template <int Q, bool STAGED>
+// Scan and evaluation over the own z-cells [zs, ze) of a chunk.  STAGED:
+// candidates are staged indices (virtual index - base); otherwise grid slots.
+template <bool STAGED>
 __device__ __forceinline__ void
-dpd_pair_segment(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
-                 gptr<const double4> __restrict__ cpos, gptr<const double4> __restrict__ cvel,
-                 gptr<const int> __restrict__ bond_start, gptr<const int> __restrict__ bond_to,
-                 gptr<double> __restrict__ fdpd, PairScratch<Q> &sh, const int *s_cnt, const int *s_off,
-                 const int *s_gcell, const double4 *s_pos, const int *s_gs, const int *s_pc, int Sz, int zlo,
-                 int zhi) {
-  constexpr int PPW = kWave / Q;
-  constexpr int NW = kPairThreads / kWave;
-  auto &s_qs = sh.qs;
-  auto &s_ql = sh.ql;
-  auto &s_rv = sh.rv;
-  auto &s_id = sh.id;
-  auto &s_sp = sh.sp;
-  auto &s_f = sh.f;
+dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict__ cpos,
+               gptr<const double4> __restrict__ cvel, PairShared &sh, const double4 *s_pos,
+               const double4 *s_vel, const float4 *s_rel, int base, int zs, int ze, int nz, bool tiny) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int n = P.ncell, cap = P.cap;
-  const int lp = lane / Q, quad = lane % Q;
+  const int cap = P.cap;
   const double L = P.L, invL = 1.0 / L, isdt = 1.0 / sqrt(P.dt);
-  int *qs = s_qs[w], *ql = s_ql[w];
-  const bool whole = P.seg_whole != 0;
-  // staged index of particle s of staged cell k (STAGED) or its global slot
-  auto where = [&](int k, int sl) { return STAGED ? s_off[k] + sl : s_gcell[k] * cap + sl; };
-  auto cand = [&](int q) -> double4 { return STAGED ? s_pos[q] : gload(cpos + q); };
-  auto cvel_of = [&](int q) -> double4 { return gload(cvel + (STAGED ? s_gs[q] : q)); };
+  int *qj = sh.qj[w], *qi = sh.qi[w];
+  unsigned char *qa = sh.qa[w];
+  const int own0 = sh.ownoff[zs];
 
   auto wave_sync = []() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  auto flush = [&](int qn) {
+  // grid slot of virtual staged index q, s_off[k0] <= q < s_off[k1]
+  auto slot_of = [&](int q, int k0, int k1) -> int {
+    int lo = k0, hi = k1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (sh.off[mid] <= q) lo = mid; else hi = mid;
+    }
+    return sh.gcell[lo] * cap + (q - sh.off[lo]);
+  };
+  // evaluate queue entries [0, n) (n <= 64: one per lane)
+  auto evaluate = [&](int n) {
     wave_sync();
-    for (int e = lane; e < qn; e += kWave) {
-      const int l = ql[e];
-      const int q = qs[e];
-      const int ii = s_id[w][l];
-      const double4 ej = cand(q);
-      const double4 vj = cvel_of(q);
-      const int j = (int)ej.w;
-      double dx = s_rv[w][l][0] - ej.x, dy = s_rv[w][l][1] - ej.y, dz = s_rv[w][l][2] - ej.z;
+    if (lane < n) {
+      const int jq = qj[lane], iq = qi[lane], ia = qa[lane];
+      const double4 pi = STAGED ? s_pos[iq] : gload(cpos + iq);
+      const double4 vi = STAGED ? s_vel[iq] : gload(cvel + iq);
+      const double4 pj = STAGED ? s_pos[jq] : gload(cpos + jq);
+      const double4 vj = STAGED ? s_vel[jq] : gload(cvel + jq);
+      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
       dx -= L * rint(dx * invL);
       dy -= L * rint(dy * invL);
       dz -= L * rint(dz * invL);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double r = sqrt(r2), ir = 1.0 / r;
-      const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
-      const double wr = 1.0 - r;
-      const double vdot = (s_rv[w][l][3] - vj.x) * ex + (s_rv[w][l][4] - vj.y) * ey + (s_rv[w][l][5] - vj.z) * ez;
-      const double th = dpd_theta(P.seed, step, ii, j);
-      const double aij = P.nspec > 1 ? P.atab[4 * s_sp[w][l] + (int)vj.w] : P.a;
-      const double mag = aij * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
-      atomicAdd(&s_f[w][l][0], (unsigned long long)to_fixed(mag * ex, kRealFxScale));
-      atomicAdd(&s_f[w][l][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
-      atomicAdd(&s_f[w][l][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
+      if (r2 < 1.0 && r2 != 0.0) {
+        const double r = sqrt(r2), ir = 1.0 / r;
+        const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
+        const double wr = 1.0 - r;
+        const double vdot = (vi.x - vj.x) * ex + (vi.y - vj.y) * ey + (vi.z - vj.z) * ez;
+        const double th = dpd_theta(P.seed, step, (int)pi.w, (int)pj.w);
+        const double aij = P.nspec > 1 ? P.atab[4 * (int)vi.w + (int)vj.w] : P.a;
+        const double mag = aij * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
+        atomicAdd(&sh.acc[ia][0], (unsigned long long)to_fixed(mag * ex, kRealFxScale));
+        atomicAdd(&sh.acc[ia][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
+        atomicAdd(&sh.acc[ia][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
+      }
     }
     wave_sync();
   };
+  // evaluate 64 queued pairs and move the rest (fewer than 64) to the front
+  auto flush64 = [&](int qn) {
+    evaluate(kWave);
+    int j = 0, i = 0, a = 0;
+    const bool mv = lane + kWave < qn;
+    if (mv) {
+      j = qj[lane + kWave];
+      i = qi[lane + kWave];
+      a = qa[lane + kWave];
+    }
+    wave_sync();
+    if (mv) {
+      qj[lane] = j;
+      qi[lane] = i;
+      qa[lane] = (unsigned char)a;
+    }
+  };
 
-  // own particles: staged cells 4 Sz + zlo .. 4 Sz + zhi - 1 (column (0, 0)), contiguous
-  const int own0 = 4 * Sz;
-  const int plo = s_off[own0 + zlo], phi = s_off[own0 + zhi];
-  for (int r0 = plo + w * PPW; r0 < phi; r0 += NW * PPW) {
-    const int pidx = r0 + lp;
-    const bool has = pidx < phi;
-    int zi = 0, i = -1;
-    double rx = 0.0, ry = 0.0, rz = 0.0;
-    if (has) {
-      int k;
-      if (STAGED) {
-        k = s_pc[pidx];
-      } else {
-        k = own0 + zlo;
-        while (k < own0 + zhi - 1 && pidx >= s_off[k + 1]) ++k;
-      }
-      zi = k - own0;
-      const int q = where(k, pidx - s_off[k]);
-      const double4 e = cand(q);
-      rx = e.x;
-      ry = e.y;
-      rz = e.z;
-      i = (int)e.w;
-      if (quad < 3) s_f[w][lp][quad] = 0ull;
-      if (quad == 0) {
-        const double4 v = cvel_of(q);
-        s_rv[w][lp][0] = rx;
-        s_rv[w][lp][1] = ry;
-        s_rv[w][lp][2] = rz;
-        s_rv[w][lp][3] = v.x;
-        s_rv[w][lp][4] = v.y;
-        s_rv[w][lp][5] = v.z;
-        s_id[w][lp] = i;
-        s_sp[w][lp] = (int)v.w;
-      }
-    }
-    // The lane's share of the 27 neighbour cells (o = quad, quad + Q, ...),
-    // as staged cells; its candidates t = 0 .. T-1 (cell by cell, slot by
-    // slot) are read kB at a time.
-    constexpr int KC = (27 + Q - 1) / Q;
-    constexpr int kB = 4;
-    int cb[KC], cnk[KC], pre[KC];
-    int T = 0;
+  int qn = 0;  // wavefront-uniform queue length, < 64 between steps
+  for (;;) {
+    int zi = 0;
+    if (lane == 0) zi = atomicAdd(&sh.next, 1);
+    zi = zs + __shfl(zi, 0, kWave);
+    if (zi >= ze) break;
+    const int ko = zi * 9 + 4;                  // the own column's cell of slice zi
+    const int a_lo = sh.off[ko], n_a = sh.off[ko + 1] - a_lo;
+    const int k0 = tiny ? 0 : (zi - 1) * 9, k1 = tiny ? nz * 9 : (zi + 2) * 9;
+    const int lo = sh.off[k0], T = sh.off[k1] - lo;
+    const int abase = sh.ownoff[zi] - own0;
+    for (int a0 = 0; a0 < n_a; a0 += kWave) {
+      const int g = (n_a - a0) < kWave ? (n_a - a0) : kWave;
+      const int m = kWave / g;
+      const bool act = lane < g * m;
+      const int a = a0 + lane % g;
+      int t = lane / g;
+      const int ia = abase + a;
+      const int iref = STAGED ? a_lo + a - base : sh.gcell[ko] * cap + a;
+      float4 ri = make_float4(0.f, 0.f, 0.f, 0.f);
+      double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (STAGED) ri = s_rel[iref];
+      else pi = gload(cpos + iref);
+      for (;; t += kPairU * m) {
+        if (__ballot(act && t < T) == 0ull) break;
+        int jref[kPairU];
+        float4 rj[kPairU];
+        double4 pj[kPairU];
+        // every lane loads (an in-range index when its step is past the
+        // end), so that the loads of all steps are in flight together
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int o = quad + k * Q;
-      const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
-      const bool ok = has && o < 27 && dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n) &&
-                      dpd_offset_valid(oz, n);
-      int z = zi + oz;
-      if (whole) z = z < 0 ? z + Sz : (z >= Sz ? z - Sz : z);
-      const int kc = ((ox + 1) * 3 + (oy + 1)) * Sz + z;
-      cnk[k] = ok ? s_cnt[kc] : 0;
-      cb[k] = ok ? where(kc, 0) : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      pre[k] = T;
-      T += cnk[k];
-    }
-    int qn = 0;  // wavefront-uniform queue length
-    for (int t0 = 0;; t0 += kB) {
-      if (__ballot(t0 < T) == 0ull) break;
-      int slot[kB];
-      double4 e[kB];
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const int t = t0 + u;
-        int sl = -1;
-#pragma unroll
-        for (int k = 0; k < KC; ++k)
-          if (t >= pre[k] && t < pre[k] + cnk[k]) sl = cb[k] + (t - pre[k]);
-        slot[u] = sl;
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u)
-        if (slot[u] >= 0) e[u] = cand(slot[u]);
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        bool take = false;
-        if (slot[u] >= 0) {
-          const int j = (int)e[u].w;
-          double dx = rx - e[u].x, dy = ry - e[u].y, dz = rz - e[u].z;
-          dx -= L * rint(dx * invL);
-          dy -= L * rint(dy * invL);
-          dz -= L * rint(dz * invL);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          take = (j != i) && (r2 < 1.0) && (r2 != 0.0);
+        for (int u = 0; u < kPairU; ++u) {
+          const int tu = t + u * m;
+          const bool ok = act && tu < T;
+          if (STAGED) {
+            jref[u] = ok ? lo + tu - base : -1;
+            rj[u] = s_rel[ok ? lo + tu - base : iref];
+          } else {
+            jref[u] = ok ? slot_of(lo + tu, k0, k1) : -1;
+            pj[u] = gload(cpos + (ok ? jref[u] : iref));
+          }
         }
-        const unsigned long long m = __ballot(take);
-        if (take) {
-          const int at = qn + (int)__popcll(m & __lanemask_lt());
-          qs[at] = slot[u];
-          ql[at] = lp;
-        }
-        qn += (int)__popcll(m);
-        if (qn > kPairQueue - kWave) {
-          flush(qn);
-          qn = 0;
+#pragma unroll
+        for (int u = 0; u < kPairU; ++u) {
+          bool take;
+          if (STAGED) {
+            const float dx = ri.x - rj[u].x, dy = ri.y - rj[u].y, dz = ri.z - rj[u].z;
+            take = jref[u] >= 0 && jref[u] != iref && (tiny || dx * dx + dy * dy + dz * dz < 1.0f + kPairMargin);
+          } else {
+            double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
+            dx -= L * rint(dx * invL);
+            dy -= L * rint(dy * invL);
+            dz -= L * rint(dz * invL);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            take = jref[u] >= 0 && jref[u] != iref && r2 < 1.0 && r2 != 0.0;
+          }
+          const unsigned long long bm = __ballot(take);
+          if (take) {
+            const int at = qn + (int)__popcll(bm & __lanemask_lt());
+            qj[at] = jref[u];
+            qi[at] = iref;
+            qa[at] = (unsigned char)ia;
+          }
+          qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(bm));
+          if (qn >= kWave) {
+            flush64(qn);
+            qn -= kWave;
+          }
         }
       }
     }
-    flush(qn);
+  }
+  if (qn > 0) evaluate(qn);
+}
 
-    // harmonic bonds of i, F_i = -K (r - r0) rhat_ij
-    if (has && quad == 0) {
-      long long fx = (long long)s_f[w][lp][0], fy = (long long)s_f[w][lp][1], fz = (long long)s_f[w][lp][2];
-      for (int b = bond_start[i]; b < bond_start[i + 1]; ++b) {
+__device__ __forceinline__ void
+dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
+              gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
+              gptr<const double4> __restrict__ cvel, gptr<const int> __restrict__ bond_start,
+              gptr<const int> __restrict__ bond_to, gptr<double> __restrict__ fdpd, int pb, int nb) {
+  extern __shared__ __align__(16) unsigned char pair_smem[];
+  __shared__ PairShared sh;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
+  const int n = P.ncell, cap = P.cap;
+  const int col = lb / P.nseg, seg = lb % P.nseg;
+  if (col >= n * n) return;  // whole block leaves together
+  const int cx = col / n, cy = col % n;
+  const bool tiny = n < 3;
+  const int z0 = seg * P.seg_cells;
+  const int zn = (n - z0) < P.seg_cells ? (n - z0) : P.seg_cells;  // own cells of the segment
+  const int nz = tiny ? n : zn + 2;                                  // staged z-slices
+  const int ncells = 9 * nz;
+  const double L = P.L, edge = L / n, invL = 1.0 / L;
+  // counts of the staged cells (invalid aliasing columns of tiny grids count 0)
+  for (int k = threadIdx.x; k < ncells; k += kPairThreads) {
+    const int zsl = k / 9, c9 = k % 9;
+    const int ox = c9 / 3 - 1, oy = c9 % 3 - 1;
+    int c = 0, cnt = 0;
+    if (dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n)) {
+      const int z = tiny ? zsl : mod_pos(z0 - 1 + zsl, n);
+      c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + z;
+      cnt = dcnt[c];
+      cnt = cnt < cap ? cnt : cap;
+    }
+    sh.cnt[k] = cnt;
+    sh.gcell[k] = c;
+  }
+  __syncthreads();
+  // exclusive prefix sum over at most 256 cells: one per thread, wavefront scans
+  {
+    const int k = threadIdx.x;
+    const int v = k < ncells ? sh.cnt[k] : 0;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) sh.wsum[w] = x;
+    __syncthreads();
+    int b = 0;
+    for (int q = 0; q < w; ++q) b += sh.wsum[q];
+    if (k < ncells) sh.off[k] = b + x - v;
+    if (k == ncells - 1) sh.off[ncells] = b + x;
+    if (k <= nz) {
+      int s = 0;
+      for (int z = 0; z < k; ++z) s += sh.cnt[z * 9 + 4];
+      sh.ownoff[k] = s;
+    }
+    __syncthreads();
+  }
+  const int stage_cap = P.pair_stage;
+  double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
+  double4 *s_vel = s_pos + stage_cap;
+  float4 *s_rel = reinterpret_cast<float4 *>(s_vel + stage_cap);
+  // periodic image shifts and origin of the segment
+  const double ox0 = cx * edge, oy0 = cy * edge, oz0 = (z0 - 1) * edge;
+  const int zlo = tiny ? 0 : 1, zhi = zlo + (tiny ? n : zn);
+  for (int zs = zlo; zs < zhi;) {
+    // the chunk [zs, ze): the most own z-cells whose staged set and own
+    // particles fit (every thread finds the same from LDS)
+    const int kz0 = tiny ? 0 : zs - 1;
+    int ze = zs;
+    while (ze < zhi) {
+      const int kz1 = tiny ? nz : ze + 2;
+      if (sh.off[kz1 * 9] - sh.off[kz0 * 9] > stage_cap || sh.ownoff[ze + 1] - sh.ownoff[zs] > kPairOwn) break;
+      ++ze;
+    }
+    bool staged = true;
+    if (ze == zs) {  // one z-cell (at most cap <= kPairOwn own particles), read from global memory
+      ze = zs + 1;
+      staged = false;
+    }
+    const int kz1 = tiny ? nz : ze + 1;
+    const int base = sh.off[kz0 * 9], S = sh.off[kz1 * 9] - base;
+    const int nown = sh.ownoff[ze] - sh.ownoff[zs];
+    if (staged) {
+      // staged cell of each staged particle, then the copy: kPairPer
+      // particles per thread with all their loads in flight together (an
+      // index past the end repeats the last particle, which is written twice)
+      for (int k = kz0 * 9 + threadIdx.x; k < kz1 * 9; k += kPairThreads) {
+        const int o = sh.off[k] - base, c = sh.cnt[k];
+        for (int q = 0; q < c; ++q) sh.cellof[o + q] = (unsigned char)(k - kz0 * 9);
+      }
+      __syncthreads();
+      if (S > 0) {
+        for (int p0 = 0; p0 < S; p0 += kPairPer * kPairThreads) {
+          int pp[kPairPer], kk[kPairPer];
+          double4 e[kPairPer], v[kPairPer];
+#pragma unroll
+          for (int r = 0; r < kPairPer; ++r) {
+            const int p = p0 + threadIdx.x + r * kPairThreads;
+            pp[r] = p < S ? p : S - 1;
+            kk[r] = kz0 * 9 + sh.cellof[pp[r]];
+          }
+#pragma unroll
+          for (int r = 0; r < kPairPer; ++r) {
+            const size_t g = (size_t)sh.gcell[kk[r]] * cap + (pp[r] + base - sh.off[kk[r]]);
+            e[r] = gload(cpos + g);
+            v[r] = gload(cvel + g);
+          }
+#pragma unroll
+          for (int r = 0; r < kPairPer; ++r) {
+            const int zsl = kk[r] / 9, c9 = kk[r] % 9;
+            const int X = cx + c9 / 3 - 1, Y = cy + c9 % 3 - 1, Z = z0 - 1 + zsl;
+            const double sx = (X < 0 ? -L : (X >= n ? L : 0.0)) - ox0;
+            const double sy = (Y < 0 ? -L : (Y >= n ? L : 0.0)) - oy0;
+            const double sz = (Z < 0 ? -L : (Z >= n ? L : 0.0)) - oz0;
+            s_pos[pp[r]] = e[r];
+            s_vel[pp[r]] = v[r];
+            s_rel[pp[r]] = make_float4((float)(e[r].x + sx), (float)(e[r].y + sy), (float)(e[r].z + sz), 0.f);
+          }
+        }
+      }
+    }
+    for (int k = threadIdx.x; k < nown; k += kPairThreads) {
+      sh.acc[k][0] = 0ull;
+      sh.acc[k][1] = 0ull;
+      sh.acc[k][2] = 0ull;
+    }
+    if (threadIdx.x == 0) sh.next = 0;
+    __syncthreads();
+    if (staged)
+      dpd_pair_cells<true>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+    else
+      dpd_pair_cells<false>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+    __syncthreads();
+    // bonds, F_i = -K (r - r0) rhat_ij, and the force of each own particle
+    for (int t = threadIdx.x; t < nown; t += kPairThreads) {
+      int zi = zs;
+      while (sh.ownoff[zi + 1] - sh.ownoff[zs] <= t) ++zi;
+      const int a = t - (sh.ownoff[zi] - sh.ownoff[zs]);
+      const int ko = zi * 9 + 4;
+      const double4 e = staged ? s_pos[sh.off[ko] + a - base] : gload(cpos + (sh.gcell[ko] * cap + a));
+      const int i = (int)e.w;
+      long long fx = (long long)sh.acc[t][0], fy = (long long)sh.acc[t][1], fz = (long long)sh.acc[t][2];
+      const int b1 = bond_start[i + 1];
+      for (int b = bond_start[i]; b < b1; ++b) {
         const int j = bond_to[b];
-        double dx = rx - pos[3 * j], dy = ry - pos[3 * j + 1], dz = rz - pos[3 * j + 2];
+        double dx = e.x - pos[3 * j], dy = e.y - pos[3 * j + 1], dz = e.z - pos[3 * j + 2];
         dx -= L * rint(dx * invL);
         dy -= L * rint(dy * invL);
         dz -= L * rint(dz * invL);
@@ -393,122 +530,32 @@ dpd_pair_segment(const DpdParams &P, uint64_t step, gptr<const double> __restric
       fdpd[3 * i + 1] = (double)fy * kRealFxInv;
       fdpd[3 * i + 2] = (double)fz * kRealFxInv;
     }
-    wave_sync();  // the next round reuses the LDS rows of this one
+    __syncthreads();  // the next chunk restages
+    zs = ze;
   }
 }
 
-template <int Q>
-__device__ __forceinline__ void
-dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
-              gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
-              gptr<const double4> __restrict__ cvel, gptr<const int> __restrict__ bond_start,
-              gptr<const int> __restrict__ bond_to, gptr<double> __restrict__ fdpd, int pb, int nb) {
-  extern __shared__ __align__(16) unsigned char pair_smem[];
-  __shared__ PairScratch<Q> sh;
-  __shared__ int s_cnt[kPairCells], s_off[kPairCells + 1], s_gcell[kPairCells];
-  __shared__ int s_wsum[kPairThreads / kWave];
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int lb = (pb % kXcds) * (nb / kXcds) + pb / kXcds;  // XCD-contiguous logical block
-  const int n = P.ncell, cap = P.cap;
-  const int col = lb / P.nseg, seg = lb % P.nseg;
-  if (col >= n * n) return;  // whole block leaves together
-  const int cx = col / n, cy = col % n;
-  const bool whole = P.seg_whole != 0;
-  const int z0 = seg * P.seg_cells;
-  const int zn = (n - z0) < P.seg_cells ? (n - z0) : P.seg_cells;  // own cells of the segment
-  const int Sz = whole ? n : P.seg_cells + 2;                         // staged z-cells per column
-  const int zlo = whole ? 0 : 1, zhi = zlo + zn;
-  const int ncells = 9 * Sz;
-  // counts of the staged cells (invalid aliasing columns of tiny grids count 0)
-  for (int k = threadIdx.x; k < ncells; k += kPairThreads) {
-    const int c9 = k / Sz, zs = k % Sz;
-    const int ox = c9 / 3 - 1, oy = c9 % 3 - 1;
-    int c = 0, cnt = 0;
-    if (dpd_offset_valid(ox, n) && dpd_offset_valid(oy, n)) {
-      const int z = whole ? zs : mod_pos(z0 - 1 + zs, n);
-      c = (mod_pos(cx + ox, n) * n + mod_pos(cy + oy, n)) * n + z;
-      cnt = dcnt[c];
-      cnt = cnt < cap ? cnt : cap;
-    }
-    s_cnt[k] = cnt;
-    s_gcell[k] = c;
-  }
-  __syncthreads();
-  // exclusive prefix sum over at most 256 cells: one per thread, wavefront scans
-  {
-    const int k = threadIdx.x;
-    const int v = k < ncells ? s_cnt[k] : 0;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int y = __shfl_up(x, o, kWave);
-      if (lane >= o) x += y;
-    }
-    if (lane == kWave - 1) s_wsum[w] = x;
-    __syncthreads();
-    int base = 0;
-    for (int q = 0; q < w; ++q) base += s_wsum[q];
-    if (k < ncells) s_off[k] = base + x - v;
-    if (k == ncells - 1) s_off[ncells] = base + x;
-    __syncthreads();
-  }
-  const int S = s_off[ncells];
-  const int stage_cap = P.pair_stage;
-  double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
-  int *s_gs = reinterpret_cast<int *>(s_pos + stage_cap);  // global slot of each staged particle
-  int *s_pc = s_gs + stage_cap;                             // its staged cell
-  if (S <= stage_cap) {
-    // copy the staged particles: particle p of staged cell k (binary search over the offsets)
-    for (int p = threadIdx.x; p < S; p += kPairThreads) {
-      int lo = 0, hi = ncells;  // s_off[lo] <= p < s_off[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[mid] <= p) lo = mid; else hi = mid;
-      }
-      const int g = s_gcell[lo] * cap + (p - s_off[lo]);
-      s_pos[p] = gload(cpos + g);
-      s_gs[p] = g;
-      s_pc[p] = lo;
-    }
-    __syncthreads();
-    dpd_pair_segment<Q, true>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
-                              s_pos, s_gs, s_pc, Sz, zlo, zhi);
-  } else {
-    dpd_pair_segment<Q, false>(P, step, pos, cpos, cvel, bond_start, bond_to, fdpd, sh, s_cnt, s_off, s_gcell,
-                               s_pos, s_gs, s_pc, Sz, zlo, zhi);
-  }
-}
-
-template <int Q>
 __global__ void __launch_bounds__(kPairThreads)
 k_dpd_pair(DpdParams P, uint64_t step, const double *__restrict__ pos, const int *__restrict__ dcnt,
            const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to, double *__restrict__ fdpd) {
-  dpd_pair_body<Q>(P, step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start), to_g(bond_to),
-                   to_g(fdpd), blockIdx.x, gridDim.x);
+  dpd_pair_body(P, step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start), to_g(bond_to),
+                to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
-void pair_segments(int n, int *seg_cells, int *nseg, int *whole) {
-  if (n <= kSegWhole) {
-    *seg_cells = n;
-    *nseg = 1;
-    *whole = 1;
-  } else {
-    *seg_cells = kSegCells;
-    *nseg = (n + kSegCells - 1) / kSegCells;
-    *whole = 0;
-  }
+void pair_segments(int n, int *seg_cells, int *nseg) {
+  *nseg = (n + kSegTarget - 1) / kSegTarget;
+  *seg_cells = (n + *nseg - 1) / *nseg;
 }
 
-int pair_blocks(const DpdParams &P, int lanes) {
-  (void)lanes;
+int pair_blocks(const DpdParams &P) {
   int64_t blocks = (int64_t)P.ncell * P.ncell * P.nseg;
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   return (int)blocks;
 }
 
 size_t pair_lds_bytes(const DpdParams &P) {
-  return (size_t)P.pair_stage * (sizeof(double4) + 2 * sizeof(int));
+  return (size_t)P.pair_stage * (2 * sizeof(double4) + sizeof(float4));
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -540,13 +587,12 @@ kb_dpd_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, in
   dpd_pre_body(m.N, mode, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt, m.cpos, m.cvel, m.status, m.ch, w.y);
 }
 
-template <int Q>
 __global__ void __launch_bounds__(kPairThreads)
 kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pair_body<Q>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel), to_g(m.bond_start),
-                   to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
+  dpd_pair_body(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel), to_g(m.bond_start),
+                to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
@@ -554,12 +600,11 @@ __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
 }
 
 // every member stages kPairStage particles
-constexpr size_t kPairLdsBytes = (size_t)kPairStage * (sizeof(double4) + 2 * sizeof(int));
+constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + sizeof(float4));
 
 hipError_t configure_pair_kernels(size_t lds_bytes) {
   const int v = (int)(lds_bytes > kPairLdsBytes ? lds_bytes : kPairLdsBytes);
-  const void *k[] = {(const void *)k_dpd_pair<4>, (const void *)k_dpd_pair<8>, (const void *)kb_dpd_pair<4>,
-                     (const void *)kb_dpd_pair<8>};
+  const void *k[] = {(const void *)k_dpd_pair, (const void *)kb_dpd_pair};
   for (const void *f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
     if (e != hipSuccess) return e;
@@ -572,13 +617,8 @@ hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, i
   return hipGetLastError();
 }
 
-hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int lanes, hipStream_t st) {
-  if (nmap > 0) {
-    if (lanes == 8)
-      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
-    else
-      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
-  }
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st) {
+  if (nmap > 0) hipLaunchKernelGGL(kb_dpd_pair, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
   return hipGetLastError();
 }
 
@@ -600,18 +640,14 @@ hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, 
 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd, int lanes,
-                           hipStream_t st, KernelTimer *tm) {
+                           const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
+                           KernelTimer *tm) {
   (void)N;
   (void)v0;
-  const int nb = pair_blocks(P, lanes);
+  const int nb = pair_blocks(P);
   if (tm) tm->before(1, st);
-  if (lanes == 8)
-    hipLaunchKernelGGL(k_dpd_pair<8>, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos, cvel,
-                       bond_start, bond_to, fdpd);
-  else
-    hipLaunchKernelGGL(k_dpd_pair<4>, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos, cvel,
-                       bond_start, bond_to, fdpd);
+  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos,
+                     cvel, bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }

@@ -4,7 +4,6 @@
 
 #include <algorithm>
 #include <array>
-#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -741,11 +740,10 @@ struct enuf_dpd {
   int *dslot = nullptr;       // [N] static compact slot of each particle (-1: neutral)
   int64_t nq = 0;
   DpdCharges charges{};
-  hipStream_t side[2] = {nullptr, nullptr};  // forked streams (pair forces, real space)
+  hipStream_t side = nullptr;  // forked stream (pair forces, then real space)
   int concurrent = 1;
-  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   unsigned long long *step_ctr = nullptr;  // [1] next step index when stepped in a batch
-  int pair_lanes = 8;                      // lanes per particle of the pair kernel (4 or 8)
   int *species = nullptr;                  // [N] species of each particle (read when P.nspec > 1)
   int batches = 0;                         // batches this integrator is a member of
   size_t bytes = 0;
@@ -772,10 +770,8 @@ struct enuf_dpd {
   }
   ~enuf_dpd() {
     drop_events();
-    for (int k = 0; k < 2; ++k) {
-      if (side[k]) (void)hipStreamDestroy(side[k]);
-      if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
-    }
+    if (side) (void)hipStreamDestroy(side);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (void *ptr : allocations) (void)hipFree(ptr);
   }
@@ -796,6 +792,11 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   if (!q) { set_error("NULL charges"); return nullptr; }
   if (nbonds < 0 || (nbonds > 0 && !bonds)) { set_error("invalid bond list"); return nullptr; }
   if (plan && (plan->N != N || plan->L != box)) { set_error("plan N / box differ from the integrator's"); return nullptr; }
+  {
+    int nc0, cap0;
+    dpd_geometry(N, box, &nc0, &cap0);
+    if (cap0 > kPairOwn) { set_error("density too high: DPD cells would need more than 128 slots"); return nullptr; }
+  }
   std::vector<int> deg(N + 1, 0);
   for (int64_t b = 0; b < nbonds; ++b) {
     const int64_t i = bonds[2 * b], j = bonds[2 * b + 1];
@@ -824,7 +825,7 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   P.ncell = nc;
   P.cap = cap;
   P.inv_cell = (double)nc / box;
-  pair_segments(nc, &P.seg_cells, &P.nseg, &P.seg_whole);
+  pair_segments(nc, &P.seg_cells, &P.nseg);
   P.pair_stage = kPairStage;
   if (configure_pair_kernels(pair_lds_bytes(P)) != hipSuccess) {
     set_error("configuring the pair kernels failed");
@@ -910,16 +911,10 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
     ch.sc = plan->buf.sc;
     ch.stat = st;
   }
-  for (int k = 0; k < 2; ++k) {
-    if (hipStreamCreateWithFlags(&d->side[k], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&d->join_ev[k], hipEventDisableTiming) != hipSuccess) {
-      set_error("creating the side streams failed");
-      delete d;
-      return nullptr;
-    }
-  }
-  if (hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming) != hipSuccess) {
-    set_error("creating the fork event failed");
+  if (hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&d->join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    set_error("creating the side stream failed");
     delete d;
     return nullptr;
   }
@@ -933,9 +928,11 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
   return ENUF_OK;
 }
 
-// One force evaluation (mode 1) or step (mode 0).  With a plan the pair
-// forces and the real-space term run on two forked streams while the mesh
-// passes run on the integrator's stream; the combine kernel joins them.
+// One force evaluation (mode 1) or step (mode 0).  With a plan the mesh
+// passes (the longest chain) are enqueued first on the integrator's stream;
+// the pair forces and then the real-space term run on one forked stream
+// beside them (a second forked stream costs more in cross-stream waits than
+// it gains); the combine kernel joins the two.
 // energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
 // reports the last one; steps inside a run other than its last skip it).
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step,
@@ -948,26 +945,24 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
   if (!d->plan) {
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, d->pair_lanes, st, tm);
+                          d->fdpd, st, tm);
     if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
   } else {
     enuf_plan *pl = d->plan;
     pl->stream = st;
     const bool fork = d->concurrent != 0;
-    hipStream_t s0 = fork ? d->side[0] : st, s1 = fork ? d->side[1] : st;
+    hipStream_t s1 = fork ? d->side : st;
     if (fork) {
       if (e == hipSuccess) e = hipEventRecord(d->fork_ev, st);
-      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(d->side[k], d->fork_ev, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s1, d->fork_ev, 0);
     }
+    if (e == hipSuccess) e = launch_recip(pl->cfg, pl->buf, d->nq, st, tm);
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, d->pair_lanes, s0, tm);
-    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[0], s0);
+                          d->fdpd, s1, tm);
     if (e == hipSuccess) e = launch_real(pl->cfg, pl->buf, d->nq, s1, tm);
-    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev[1], s1);
-    if (e == hipSuccess) e = launch_recip(pl->cfg, pl->buf, d->nq, st, tm);
-    if (fork)
-      for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, d->join_ev[k], 0);
+    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev, s1);
+    if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, d->join_ev, 0);
     if (e == hipSuccess) {
       FinishArgs fa;
       fa.mode = mode;
@@ -1134,7 +1129,6 @@ struct enuf_batch {
   hipEvent_t in_ev = nullptr, out_ev = nullptr;
   int concurrent = 1;
   int use_graph = 1;
-  int pair_lanes = 4;
   int ik = -1;       // force mode of the members (all alike; -1 while empty)
   std::vector<Member> members;
   int next_id = 0;
@@ -1177,7 +1171,7 @@ struct enuf_batch {
 
 namespace {
 
-BatchMember member_view(const enuf_batch::Member &mb, int pair_lanes) {
+BatchMember member_view(const enuf_batch::Member &mb) {
   const enuf_dpd *d = mb.d;
   const enuf_plan *pl = d->plan;
   BatchMember m{};
@@ -1185,7 +1179,7 @@ BatchMember member_view(const enuf_batch::Member &mb, int pair_lanes) {
   m.buf = pl->buf;
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
-  m.pair_blocks = pair_blocks(d->P, pair_lanes);
+  m.pair_blocks = pair_blocks(d->P);
   const int64_t g = (d->nq + 3) / 4;
   m.real_blocks = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   m.fscale = pl->cfg.mesh.ik ? 2.0 / (pl->cfg.L * pl->cfg.L) : (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
@@ -1220,7 +1214,7 @@ int batch_rebuild(enuf_batch *b) {
   std::vector<int2> map[7];
   size_t lf = 0, lx = 0, lb = 0;
   for (int k : order) {
-    const BatchMember m = member_view(b->members[k], b->pair_lanes);
+    const BatchMember m = member_view(b->members[k]);
     const int id = (int)mem.size();
     mem.push_back(m);
     const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;  // work-groups of the spread and gather passes
@@ -1293,7 +1287,7 @@ hipError_t batch_step(enuf_batch *b, bool fork) {
     if (e == hipSuccess) e = hipEventRecord(b->fork_ev, st);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
   }
-  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], b->pair_lanes, s0);
+  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], s0);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[0], s0);
   if (e == hipSuccess) e = launch_batch_real(b->dmem, mp + o[2], o[3] - o[2], s1);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
@@ -1457,113 +1451,6 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
   }
   HIP_OR_RETURN(hipEventRecord(b->out_ev, b->own), ENUF_EDEVICE);
   HIP_OR_RETURN(hipStreamWaitEvent(b->stream, b->out_ev, 0), ENUF_EDEVICE);
-  return ENUF_OK;
-}
-
-int enuf_batch_set_tuning(enuf_batch *b, int pair_lanes) {
-  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
-  if (pair_lanes != 4 && pair_lanes != 8) { set_error("pair_lanes must be 4 or 8"); return ENUF_EINVAL; }
-  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
-  b->pair_lanes = pair_lanes;
-  b->dirty = true;
-  return ENUF_OK;
-}
-
-int enuf_batch_autotune(enuf_batch *b, int trial_steps, int *pair_lanes, int *concurrent) {
-  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
-  if (trial_steps < 1 || trial_steps > 10000) { set_error("trial_steps must be in [1, 10000]"); return ENUF_EINVAL; }
-  if (b->members.empty()) { set_error("empty batch"); return ENUF_EINVAL; }
-  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
-  HIP_OR_RETURN(hipStreamSynchronize(b->stream), ENUF_EDEVICE);
-  // snapshot of every member's state, restored before each trial and at the end
-  struct Snap {
-    double *buf = nullptr;
-    unsigned long long step = 0;
-  };
-  std::vector<Snap> snap(b->members.size());
-  auto release = [&]() {
-    for (auto &sn : snap)
-      if (sn.buf) (void)hipFree(sn.buf);
-  };
-  for (size_t k = 0; k < snap.size(); ++k) {
-    const auto &mb = b->members[k];
-    const size_t n3 = 3 * (size_t)mb.d->N;
-    if (hipMalloc(&snap[k].buf, 3 * n3 * sizeof(double)) != hipSuccess ||
-        hipMemcpy(snap[k].buf, mb.pos, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-        hipMemcpy(snap[k].buf + n3, mb.vel, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-        hipMemcpy(snap[k].buf + 2 * n3, mb.force, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-        hipMemcpy(&snap[k].step, mb.d->step_ctr, sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess) {
-      release();
-      set_error("autotune: snapshot of the member state failed");
-      return ENUF_ENOMEM;
-    }
-  }
-  auto restore = [&]() -> bool {
-    for (size_t k = 0; k < snap.size(); ++k) {
-      const auto &mb = b->members[k];
-      const size_t n3 = 3 * (size_t)mb.d->N;
-      if (hipMemcpy(mb.pos, snap[k].buf, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-          hipMemcpy(mb.vel, snap[k].buf + n3, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-          hipMemcpy(mb.force, snap[k].buf + 2 * n3, n3 * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
-          hipMemcpy(mb.d->step_ctr, &snap[k].step, sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
-        return false;
-    }
-    return hipDeviceSynchronize() == hipSuccess;
-  };
-  // Trials launch eagerly (no graph is captured or destroyed while tuning);
-  // with graphs on, the forked schedule is not a candidate (a graph holds
-  // the single-stream step).
-  const int old_lanes = b->pair_lanes, old_conc = b->concurrent, old_graph = b->use_graph;
-  b->use_graph = 0;
-  b->drop_graph();
-  double best = 1e300;
-  int best_lanes = old_lanes, best_conc = old_conc;
-  for (int lanes : {4, 8}) {
-    for (int conc : {1, 0}) {
-      if (old_graph && conc) continue;
-      b->pair_lanes = lanes;
-      b->concurrent = conc;
-      b->dirty = true;
-      if (!restore()) {
-        release();
-        set_error("autotune: restoring the member state failed");
-        return ENUF_EDEVICE;
-      }
-      int rc = enuf_batch_run(b, 1);  // builds the tables, warms up
-      if (rc == ENUF_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = ENUF_EDEVICE;
-      const auto t0 = std::chrono::steady_clock::now();
-      if (rc == ENUF_OK) rc = enuf_batch_run(b, trial_steps);
-      if (rc == ENUF_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = ENUF_EDEVICE;
-      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      if (rc != ENUF_OK) {
-        release();
-        b->use_graph = old_graph;
-        return rc;
-      }
-      if (dt < best) {
-        best = dt;
-        best_lanes = lanes;
-        best_conc = conc;
-      }
-    }
-  }
-  const bool ok = restore();
-  release();
-  b->pair_lanes = best_lanes;
-  b->concurrent = best_conc;
-  b->use_graph = old_graph;
-  b->dirty = true;
-  if (!ok) { set_error("autotune: restoring the member state failed"); return ENUF_EDEVICE; }
-  if (pair_lanes) *pair_lanes = best_lanes;
-  if (concurrent) *concurrent = best_conc;
-  return ENUF_OK;
-}
-
-int enuf_dpd_set_tuning(enuf_dpd *d, int pair_lanes) {
-  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
-  if (pair_lanes != 4 && pair_lanes != 8) { set_error("pair_lanes must be 4 or 8"); return ENUF_EINVAL; }
-  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
-  d->pair_lanes = pair_lanes;
   return ENUF_OK;
 }
 

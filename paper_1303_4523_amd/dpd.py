@@ -67,10 +67,6 @@ class DPD:
         """Overlap pair forces and real space with the mesh passes (default) or not."""
         check(lib.enuf_dpd_set_concurrency(self._h, int(bool(enable))), "enuf_dpd_set_concurrency")
 
-    def set_tuning(self, pair_lanes):
-        """Lanes per particle of the pair-force kernel (4 or 8, the default)."""
-        check(lib.enuf_dpd_set_tuning(self._h, int(pair_lanes)), "enuf_dpd_set_tuning")
-
     def set_species(self, species, a_table):
         """Species-dependent conservative amplitudes a_ij (eq. 3): species is
         an int per particle in [0, nspecies), a_table the symmetric

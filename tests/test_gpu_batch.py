@@ -163,42 +163,6 @@ def test_mixed_member_against_oracle():
     assert np.abs(ddp).max() < 1e-5
 
 
-def test_autotune_restores_state_and_keeps_results():
-    """The autotuner times the launch configurations on the members and leaves
-    their states as they were; the tuned run equals the untuned one."""
-    from paper_1303_4523_amd.batch import Batch
-    reps = _replicas([2, 5, 11])
-    b = Batch("mixed", device=0)
-    mem = [_member(s) for s in reps]
-    for m in mem:
-        b.add(*m, first_step=1)
-    before = [[t.cpu().numpy() for t in m[1:]] for m in mem]
-    lanes, conc = b.autotune(2)
-    print(f"case: autotune -> pair lanes {lanes}, concurrent {conc}", flush=True)
-    assert lanes in (4, 8)
-    after = [[t.cpu().numpy() for t in m[1:]] for m in mem]
-    assert all(np.array_equal(x, y) for a, c in zip(before, after) for x, y in zip(a, c))
-    b.run(3)
-    torch.cuda.synchronize()
-    for s, m in zip(reps, mem):
-        assert _same(tuple(t.cpu().numpy() for t in m[1:]), _alone(s, 3)[:3])
-    b.close()
-    for m in mem:
-        m[0].close()
-
-
-@pytest.mark.parametrize("lanes", [4, 8])
-def test_pair_lanes_do_not_change_results(lanes):
-    """Four or eight lanes per particle in the pair kernel: same bits."""
-    s = wl.replica(3, n_max=9000)
-    d, pos, vel, F = _member(s, "fp64")
-    d.set_tuning(lanes)
-    d.run(pos, vel, F, 1, 3)
-    got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy())
-    d.close()
-    assert _same(got, _alone(s, 3, precision="fp64")[:3])
-
-
 def _requests(ids, n_max=12000, steps=10, rate=None):
     from paper_1303_4523_amd.serving import Request
     t = wl.poisson_arrivals(len(ids), rate) if rate else np.zeros(len(ids))

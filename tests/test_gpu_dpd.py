@@ -80,6 +80,30 @@ def test_initial_forces(elec):
         assert np.abs(Fg.sum(0)).max() < 1e-8   # momentum, up to fixed-point rounding
 
 
+@pytest.mark.parametrize("L,density", [(2.5, 3.0), (10.0, 6.0), (6.0, 12.0), (4.0, 40.0), (27.0, 3.0)])
+def test_pair_forces_grid_regimes(L, density):
+    """Pair and bond forces against the oracle where the pair kernel takes its
+    other routes: a grid of 2 cells per side (cells are their own neighbours
+    twice), dense cells whose column segment does not fit the LDS stage
+    (chunks of several z-cells, and of one), cells so dense that one z-cell's
+    neighbourhood does not fit (candidates from global memory), and a column
+    split into three segments."""
+    pos, vel, q, bonds = _system(L, density=density, nq=0, chain=min(12, int(density * L ** 3) // 2), seed=9)
+    d = _gpu(L, q, bonds, elec=False)
+    tp, tv = _t(pos), _t(vel)
+    F = torch.empty_like(tp)
+    d.forces(tp, tv, F, step=0)
+    Fg = F.cpu().numpy()
+    st = d.status()
+    d.close()
+    Fo, _ = oracle.dpd_forces(pos, vel, q, bonds, _oracle_params(L, False), seed=PRM["seed"], step=0)
+    err = np.linalg.norm(Fg - Fo) / np.linalg.norm(Fo)
+    print(f"L={L} density={density} N={len(pos)}: force rel rms {err:.3e}")
+    assert st == 0
+    assert err < 1e-11
+    assert np.abs(Fg.sum(0)).max() < 1e-8
+
+
 def test_trajectory_segment_matches_oracle():
     """Ten steps on both sides with the same random numbers."""
     L = 8.0
@@ -157,3 +181,26 @@ def test_dpd_polyelectrolyte_24k_first_steps():
     print(f"3 steps: max |dr| {np.abs(ddp).max():.3e}")
     assert np.abs(ddp).max() < 1e-6
     assert np.linalg.norm(gF - Fo) / np.linalg.norm(Fo) < 1e-6
+
+
+def test_forked_and_single_stream_steps_are_identical():
+    """The pair and real-space kernels beside the mesh passes (default) and the
+    whole step on one stream give bitwise the same trajectory: every force
+    sum is taken in fixed point or in a fixed order."""
+    s = wl.dpd_polyelectrolyte_24k()
+    from paper_1303_4523_amd.dpd import DPD
+    out = []
+    for conc in (True, False):
+        d = DPD(s.L, s.q, dict(s.meta["dpd"], seed=3), bonds=s.bonds, enuf=s.meta["enuf"], device=0)
+        d.set_concurrency(conc)
+        tp, tv = _t(s.pos), _t(s.vel)
+        F = torch.empty_like(tp)
+        d.forces(tp, tv, F, step=0)
+        d.run(tp, tv, F, 1, 20)
+        st = d.status()
+        e = d.energy().cpu().numpy()
+        out.append((tp.cpu().numpy(), tv.cpu().numpy(), F.cpu().numpy(), e))
+        d.close()
+        assert st == 0
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
