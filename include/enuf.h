@@ -227,6 +227,15 @@ int enuf_dpd_set_species(enuf_dpd *dpd, int nspecies, const int *species, const 
  * stream (0).  Results are the same either way. */
 int enuf_dpd_set_concurrency(enuf_dpd *dpd, int enable);
 
+/* Launch the steps of enuf_dpd_run (all but its last) as HIP graphs of 8
+ * steps (enable = 1, the default), captured on the first run with given
+ * pos / vel / force buffers and captured again when they or the parameters
+ * change; the fork and join of the concurrent schedule are graph edges.  With
+ * 0, or while a kernel is being timed, every step is launched eagerly.
+ * Results are the same either way (the step index of a replayed step is read
+ * from device memory).  Synchronises the integrator's stream. */
+int enuf_dpd_set_graphs(enuf_dpd *dpd, int enable);
+
 /* Copy (on the stream) the ENUF energy components of the last force
  * evaluation, unscaled by kappa, into the device array energy5 (as in
  * enuf_compute_components).  Without a plan all five are 0. */

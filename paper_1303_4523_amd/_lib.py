@@ -59,6 +59,8 @@ lib.enuf_dpd_run.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64, _int]
 lib.enuf_dpd_run.restype = _int
 lib.enuf_dpd_set_concurrency.argtypes = [_vp, _int]
 lib.enuf_dpd_set_concurrency.restype = _int
+lib.enuf_dpd_set_graphs.argtypes = [_vp, _int]
+lib.enuf_dpd_set_graphs.restype = _int
 lib.enuf_dpd_energy.argtypes = [_vp, _vp]
 lib.enuf_dpd_energy.restype = _int
 lib.enuf_dpd_status.argtypes = [_vp, ctypes.POINTER(_int)]
@@ -112,7 +114,8 @@ EXPORTED = [
     "enuf_plan_create", "enuf_destroy", "enuf_last_error", "enuf_plan_set_stream",
     "enuf_plan_set_options", "enuf_compute", "enuf_compute_components", "enuf_plan_status",
     "enuf_plan_footprint_bytes",
-    "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_set_concurrency", "enuf_dpd_forces", "enuf_dpd_run",
+    "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_set_concurrency", "enuf_dpd_set_graphs",
+    "enuf_dpd_forces", "enuf_dpd_run",
     "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
     "enuf_dpd_time_kernel", "enuf_dpd_kernel_time", "enuf_dpd_footprint_bytes",
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",

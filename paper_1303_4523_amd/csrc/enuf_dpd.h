@@ -89,6 +89,7 @@ hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, con
 hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *map, int nmap, int mode,
                                 hipStream_t st);
 hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hipStream_t st);
+hipError_t launch_add_u64(unsigned long long *dst, hipStream_t st);  // *dst += 1
 
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
                           const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
@@ -96,7 +97,7 @@ hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
                            const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
-                           KernelTimer *tm = nullptr);
+                           KernelTimer *tm = nullptr, const unsigned long long *step_dev = nullptr);
 hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,
                            KernelTimer *tm = nullptr);

@@ -535,12 +535,14 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
   }
 }
 
+// step_dev: the step index is read from device memory (steps replayed from a
+// graph), else it is `step`.
 __global__ void __launch_bounds__(kPairThreads)
-k_dpd_pair(DpdParams P, uint64_t step, const double *__restrict__ pos, const int *__restrict__ dcnt,
-           const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
+k_dpd_pair(DpdParams P, uint64_t step, const unsigned long long *step_dev, const double *__restrict__ pos,
+           const int *__restrict__ dcnt, const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to, double *__restrict__ fdpd) {
-  dpd_pair_body(P, step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel), to_g(bond_start), to_g(bond_to),
-                to_g(fdpd), blockIdx.x, gridDim.x);
+  dpd_pair_body(P, step_dev ? (uint64_t)*step_dev : step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel),
+                to_g(bond_start), to_g(bond_to), to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
 void pair_segments(int n, int *seg_cells, int *nseg) {
@@ -599,6 +601,10 @@ __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
   if (threadIdx.x == 0) dst[0] = value;
 }
 
+__global__ void k_add_u64(unsigned long long *dst) {
+  if (threadIdx.x == 0) dst[0] += 1ull;
+}
+
 // every member stages kPairStage particles
 constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + sizeof(float4));
 
@@ -622,6 +628,11 @@ hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, 
   return hipGetLastError();
 }
 
+hipError_t launch_add_u64(unsigned long long *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, st, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hipStream_t st) {
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, dst, value);
   return hipGetLastError();
@@ -641,13 +652,13 @@ hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, 
 hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
                            const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
-                           KernelTimer *tm) {
+                           KernelTimer *tm, const unsigned long long *step_dev) {
   (void)N;
   (void)v0;
   const int nb = pair_blocks(P);
   if (tm) tm->before(1, st);
-  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, pos, dcnt, cpos,
-                     cvel, bond_start, bond_to, fdpd);
+  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, step_dev, pos,
+                     dcnt, cpos, cvel, bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();
 }

@@ -178,6 +178,7 @@ struct FinishArgs {
   int *dcnt = nullptr;               // DPD cell counts, cleared for the next step
   int ndcell3 = 0;
   int energies = 1;                  // 0: skip the energy reduction (a step whose energies no one reads)
+  unsigned long long *step_inc = nullptr;  // device step index, advanced by one (steps replayed from a graph)
 };
 
 // The ENUF evaluation in four phases (launch_compute runs them in order on

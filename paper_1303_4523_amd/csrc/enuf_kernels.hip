@@ -480,6 +480,28 @@ __device__ inline int stage_plane_charges(int e0, int cnt, int P2, const int *pr
   return *s_n;
 }
 
+// The same staging split in two, for a plane whose charges all fit one stage
+// and one per thread: plane_charge_slot issues the load of thread t's compact
+// index (charge t of the plane) early; stage_plane_commit appends the charge
+// (its record loaded by the caller in between) when it belongs to this
+// work-group's share.  *s_n must have been cleared before a barrier.
+__device__ inline int plane_charge_slot(int total, int P2, const int *pre, const int *cell,
+                                        gptr<const int> __restrict__ xslot, int xcap, int *b_out) {
+  if ((int)threadIdx.x >= total) return -1;
+  return plane_charge(threadIdx.x, P2, pre, cell, xslot, xcap, b_out);
+}
+__device__ inline int stage_plane_commit(bool take, int j, int b, const double4 &c, double4 *s_c, int *s_jb,
+                                         int *s_n) {
+  if (take) {
+    const int k = atomicAdd(s_n, 1);
+    s_c[k] = c;
+    s_jb[2 * k] = j;
+    s_jb[2 * k + 1] = b;
+  }
+  __syncthreads();
+  return *s_n;
+}
+
 // Mesh cell and fractional offset of one coordinate.
 __device__ inline int cell_frac(double x, double m_over_l, int M, double *frac) {
   double t;
@@ -823,7 +845,16 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
     twi[m] = t.y;
   }
   for (int k = tid; k < 2 * P2 * (D + 1); k += nt) cv[(k / (D + 1)) * Ds + k % (D + 1)] = wcoef[k];
+  if (tid == 0) *s_n = 0;
   const int total = plane_bins(x0, M, p, xcnt, mp.xcap, pre, bcell);  // synchronises
+  // When the plane's charges fit one stage (one per thread), their loads are
+  // issued now and complete under the transforms below.
+  const bool early = total <= mp.stage && total <= nt;
+  int ej = -1, eb = 0;
+  double4 ec = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (early) ej = plane_charge_slot(total, P2, pre, bcell, xslot, mp.xcap, &eb);
+  bool staged = false;
+  int nstaged = 0;
   const int gbase = lane & ~(P2pad - 1);
   // Gradient forces: one field h, gathered with the window and its gradient.
   // ik forces (eq. 24-25): the three fields i k_t h, gathered with the window.
@@ -847,6 +878,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
       Zre[kz * Mz + m] = v.x;
       Zim[kz * Mz + m] = v.y;
     }
+    if (early && comp == 0 && ej >= 0 && ej % mp.parts == wpart) ec = gload(xq + ej);
     __syncthreads();
     lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
 
@@ -882,8 +914,13 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
 
       const int chunk = r0 / R;
       for (int e0 = 0; e0 < total; e0 += mp.stage) {
-      const int cnt = stage_plane_charges(e0, (total - e0) < mp.stage ? (total - e0) : mp.stage, P2, pre, bcell,
-                                          xslot, mp.xcap, xq, wpart, mp.parts, s_c, s_jb, s_n);
+      if (early && !staged) {
+        nstaged = stage_plane_commit(ej >= 0 && ej % mp.parts == wpart, ej, eb, ec, s_c, s_jb, s_n);
+        staged = true;
+      }
+      const int cnt = early ? nstaged
+                            : stage_plane_charges(e0, (total - e0) < mp.stage ? (total - e0) : mp.stage, P2, pre,
+                                                  bcell, xslot, mp.xcap, xq, wpart, mp.parts, s_c, s_jb, s_n);
       const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
       for (int it = tid; it < items; it += nt) {
         const int e = it / P2pad, sy = it % P2pad;
@@ -999,7 +1036,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
           }
         }
       }
-      __syncthreads();  // the next batch restages the charges
+      if (!early) __syncthreads();  // the next batch restages the charges
       }
       __syncthreads();  // the next chunk overwrites the plane
     }
@@ -1031,6 +1068,8 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
   const int tid = threadIdx.x;
   const int64_t i = (int64_t)bid * blockDim.x + tid;
   {
+    // the pair kernel of this step has read the step index; the next reads the advanced one
+    if (fa.step_inc && bid == 0 && tid == 0) *fa.step_inc += 1ull;
     // cell counts are left cleared for the next evaluation (their consumers ran before)
     const int64_t stride = (int64_t)nblk * blockDim.x;
     for (int64_t c = i; c < ncell3; c += stride) ccnt[c] = 0;

@@ -747,6 +747,21 @@ struct enuf_dpd {
   int *species = nullptr;                  // [N] species of each particle (read when P.nspec > 1)
   int batches = 0;                         // batches this integrator is a member of
   size_t bytes = 0;
+  // kGraphSteps steps of enuf_dpd_run captured in a graph (no cross-stream
+  // events: the fork and join are dependency edges), valid for the state
+  // buffers and the configuration it was captured with
+  int use_graph = 1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void *gkey[3] = {nullptr, nullptr, nullptr};
+  std::vector<unsigned char> gcfg;  // parameters the kernels were captured with
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
   // object), each at a 256-byte aligned offset.  False on failure.
@@ -769,6 +784,7 @@ struct enuf_dpd {
     timer = KernelTimer();
   }
   ~enuf_dpd() {
+    drop_graph();
     drop_events();
     if (side) (void)hipStreamDestroy(side);
     if (join_ev) (void)hipEventDestroy(join_ev);
@@ -935,34 +951,63 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
 // it gains); the combine kernel joins the two.
 // energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
 // reports the last one; steps inside a run other than its last skip it).
+// Steps of enuf_dpd_run per graph launch.
+constexpr int kGraphSteps = 8;
+
+// The last node captured on a capturing stream (its single dependency).
+static hipError_t capture_tail(hipStream_t st, hipGraphNode_t *node) {
+  hipStreamCaptureStatus cs;
+  const hipGraphNode_t *deps = nullptr;
+  size_t nd = 0;
+  hipError_t e = hipStreamGetCaptureInfo_v2(st, &cs, nullptr, nullptr, &deps, &nd);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusActive || nd != 1 || !deps) return hipErrorIllegalState;
+  *node = deps[0];
+  return hipSuccess;
+}
+
+// graph_st: capture of a step for a graph on that stream (the step index is
+// read from and advanced in device memory; the fork and join become
+// dependency edges of the capture instead of events).
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step,
-                    bool energies = true) {
+                    bool energies = true, hipStream_t graph_st = nullptr) {
   const int64_t N = d->N;
-  KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
-  hipStream_t st = d->stream;
+  const bool graph = graph_st != nullptr;
+  KernelTimer *tm = d->timer.kernel >= 0 && !graph ? &d->timer : nullptr;
+  hipStream_t st = graph ? graph_st : d->stream;
+  const unsigned long long *step_dev = graph ? d->step_ctr : nullptr;
   hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
                                 d->charges, st, tm);
   if (!d->plan) {
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, st, tm);
+                          d->fdpd, st, tm, step_dev);
     if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
+    if (graph && e == hipSuccess) e = launch_add_u64(d->step_ctr, st);
   } else {
     enuf_plan *pl = d->plan;
-    pl->stream = st;
+    if (!graph) pl->stream = st;
     const bool fork = d->concurrent != 0;
-    hipStream_t s1 = fork ? d->side : st;
-    if (fork) {
+    const bool events = fork && !graph;
+    hipStream_t s1 = events ? d->side : st;
+    hipGraphNode_t n_pre = nullptr, n_bwd = nullptr;
+    if (events) {
       if (e == hipSuccess) e = hipEventRecord(d->fork_ev, st);
       if (e == hipSuccess) e = hipStreamWaitEvent(s1, d->fork_ev, 0);
     }
+    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_pre);
     if (e == hipSuccess) e = launch_recip(pl->cfg, pl->buf, d->nq, st, tm);
+    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_bwd);
+    // the pair forces and the real-space term depend on the pre kernel only
+    if (graph && fork && e == hipSuccess) e = hipStreamUpdateCaptureDependencies(st, &n_pre, 1, hipStreamSetCaptureDependencies);
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
-                          d->fdpd, s1, tm);
+                          d->fdpd, s1, tm, step_dev);
     if (e == hipSuccess) e = launch_real(pl->cfg, pl->buf, d->nq, s1, tm);
-    if (fork && e == hipSuccess) e = hipEventRecord(d->join_ev, s1);
-    if (fork && e == hipSuccess) e = hipStreamWaitEvent(st, d->join_ev, 0);
+    if (events && e == hipSuccess) e = hipEventRecord(d->join_ev, s1);
+    if (events && e == hipSuccess) e = hipStreamWaitEvent(st, d->join_ev, 0);
+    // the combine kernel depends on the mesh passes and the real-space term
+    if (graph && fork && e == hipSuccess) e = hipStreamUpdateCaptureDependencies(st, &n_bwd, 1, hipStreamAddCaptureDependencies);
     if (e == hipSuccess) {
       FinishArgs fa;
       fa.mode = mode;
@@ -973,6 +1018,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
       fa.dcnt = d->dcnt;
       fa.ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
       fa.energies = energies ? 1 : 0;
+      fa.step_inc = graph ? d->step_ctr : nullptr;
       e = launch_combine(pl->cfg, pl->buf, force, nullptr, d->e5, fa, st, tm);
     }
   }
@@ -1002,14 +1048,86 @@ int enuf_dpd_forces(enuf_dpd *d, double *pos, const double *vel, double *force, 
   return dpd_eval(d, 1, pos, const_cast<double *>(vel), force, step);
 }
 
+// Bytes of everything the captured kernels take by value: when they change
+// (integrator parameters, species, concurrency, the plan's configuration),
+// the graph is captured again.
+static std::vector<unsigned char> dpd_graph_config(const enuf_dpd *d) {
+  std::vector<unsigned char> v;
+  auto put = [&v](const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    v.insert(v.end(), c, c + n);
+  };
+  put(&d->P, sizeof(DpdParams));
+  put(&d->concurrent, sizeof(int));
+  put(&d->charges, sizeof(DpdCharges));
+  if (d->plan) {
+    put(&d->plan->cfg, sizeof(ComputeConfig));
+    put(&d->plan->buf, sizeof(ComputeBuffers));
+  }
+  return v;
+}
+
+// Capture kGraphSteps steps (no energy reduction) on the integrator's side
+// stream.  False (and no graph) if capture is not available; the caller then
+// launches the steps eagerly.
+static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force) {
+  d->drop_graph();
+  hipStream_t cs = d->side;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  int rc = ENUF_OK;
+  for (int k = 0; k < kGraphSteps && rc == ENUF_OK; ++k) rc = dpd_eval(d, 0, pos, vel, force, 0, false, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc != ENUF_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    g_last_error.clear();
+    return false;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  d->graph = g;
+  d->gexec = x;
+  d->gkey[0] = pos;
+  d->gkey[1] = vel;
+  d->gkey[2] = force;
+  d->gcfg = dpd_graph_config(d);
+  return true;
+}
+
 int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t first_step, int nsteps) {
   int rc = dpd_check(d, pos, vel, force);
   if (rc != ENUF_OK) return rc;
   if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
-  for (int s = 0; s < nsteps; ++s) {
+  int s = 0;
+  // all but the last step in graphs of kGraphSteps steps (one launch each);
+  // the rest, and the last step with its energy reduction, eagerly
+  const int body = nsteps - 1;
+  if (d->use_graph && d->timer.kernel < 0 && body >= kGraphSteps) {
+    const bool same = d->gexec && d->gkey[0] == pos && d->gkey[1] == vel && d->gkey[2] == force &&
+                      d->gcfg == dpd_graph_config(d);
+    if (same || dpd_capture(d, pos, vel, force)) {
+      HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, d->stream), ENUF_EDEVICE);
+      for (; s + kGraphSteps <= body; s += kGraphSteps)
+        HIP_OR_RETURN(hipGraphLaunch(d->gexec, d->stream), ENUF_EDEVICE);
+    }
+  }
+  for (; s < nsteps; ++s) {
     rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s, s == nsteps - 1);
     if (rc != ENUF_OK) return rc;
   }
+  return ENUF_OK;
+}
+
+int enuf_dpd_set_graphs(enuf_dpd *d, int enable) {
+  if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
+  d->use_graph = enable ? 1 : 0;
+  d->drop_graph();
   return ENUF_OK;
 }
 

@@ -67,6 +67,10 @@ class DPD:
         """Overlap pair forces and real space with the mesh passes (default) or not."""
         check(lib.enuf_dpd_set_concurrency(self._h, int(bool(enable))), "enuf_dpd_set_concurrency")
 
+    def set_graphs(self, enable):
+        """Launch the steps of run() as HIP graphs of 8 steps (default) or eagerly."""
+        check(lib.enuf_dpd_set_graphs(self._h, int(bool(enable))), "enuf_dpd_set_graphs")
+
     def set_species(self, species, a_table):
         """Species-dependent conservative amplitudes a_ij (eq. 3): species is
         an int per particle in [0, nspecies), a_table the symmetric

@@ -204,3 +204,40 @@ def test_forked_and_single_stream_steps_are_identical():
         assert st == 0
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("conc", [True, False])
+def test_graph_replayed_steps_match_eager(conc):
+    """Steps replayed from a graph (8 per launch, step index in device memory)
+    against eager launches: bitwise the same state after each of three runs
+    (with eager work and synchronisation between the runs), and after the
+    buffers change (a new capture)."""
+    s = wl.dpd_polyelectrolyte_24k()
+    from paper_1303_4523_amd.dpd import DPD
+    runs = [(1, 19), (20, 17), (37, 9)]
+    out = []
+    for graphs in (True, False):
+        d = DPD(s.L, s.q, dict(s.meta["dpd"], seed=4), bonds=s.bonds, enuf=s.meta["enuf"], device=0)
+        d.set_concurrency(conc)
+        d.set_graphs(graphs)
+        tp, tv = _t(s.pos), _t(s.vel)
+        F = torch.empty_like(tp)
+        d.forces(tp, tv, F, step=0)
+        states = []
+        for first, n in runs:
+            d.run(tp, tv, F, first, n)
+            torch.cuda.synchronize()
+            states.append((tp.cpu().numpy(), tv.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy()))
+            tp.add_(0.0)  # eager work between the runs
+        # other buffers: the graph is captured again
+        tp2, tv2, F2 = tp.clone(), tv.clone(), F.clone()
+        d.run(tp2, tv2, F2, 46, 10)
+        torch.cuda.synchronize()
+        states.append((tp2.cpu().numpy(), tv2.cpu().numpy(), F2.cpu().numpy(), d.energy().cpu().numpy()))
+        st = d.status()
+        d.close()
+        assert st == 0
+        out.append(states)
+    for k, (a, b) in enumerate(zip(out[0], out[1])):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), f"run {k}"
