@@ -8,6 +8,7 @@
 //   k_dpd_post   (5) F = F_dpd + kappa F_elec, (6) v += dt F / 2; clear the grid
 #include "enuf_device.h"
 #include "enuf_dpd.h"
+#include "enuf_combine.h"
 
 namespace enuf {
 
@@ -577,6 +578,41 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
     force[3 * i + a] = f;
     if (mode == 0) vel[3 * i + a] += 0.5 * P.dt * f;
   }
+}
+
+// The combine kernel of step k (forces, closing half kick, energy partials)
+// and the pre kernel of step k + 1 (predictor, half kick, drift, binning) in
+// one launch: thread i finishes particle i's step and starts its next one.
+// The real-space and mesh bin counts come in two sets: the combine part
+// clears step k's set (b) while the pre part bins into step k + 1's (ch); the
+// DPD cell counts were cleared by the real-space kernel.
+__global__ void __launch_bounds__(kPrepThreads)
+k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
+              const unsigned long long *__restrict__ freal, const double4 *__restrict__ part, int P2S,
+              double fscale, int nblk, double *blk_eg, const unsigned long long *__restrict__ ereal,
+              long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
+              DpdParams P, double *pos, double *v0, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+              DpdCharges ch) {
+  combine_body(N, to_g(slot), to_g(xq), to_g(freal), to_g(part), P2S, fscale, nblk, blk_eg, to_g(ereal), blk_er,
+               ccnt, ncell3, xcnt, M, fa, forces, blockIdx.x);
+  __syncthreads();  // the step's loads and stores come before the next step's
+  dpd_pre_body(N, 0, P, pos, fa.vel, forces, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
+}
+
+hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
+                              const FinishArgs &fa, const DpdParams &P, double *pos, double *v0, int *dcnt,
+                              double4 *cpos, double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,
+                              KernelTimer *tm) {
+  const double fscale = combine_fscale(cfg);
+  if (tm) tm->before(9, st);
+  hipLaunchKernelGGL(k_combine_pre, dim3(cfg.nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
+                     (const double4 *)b.xq, (const unsigned long long *)b.freal, (const double4 *)b.part,
+                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, cfg.nblk, b.blk_eg,
+                     (const unsigned long long *)b.ereal, b.blk_er, b.ccnt,
+                     cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell, b.xcnt, cfg.mesh.M, fa, forces, P, pos,
+                     v0, dcnt, cpos, cvel, status, ch);
+  if (tm) tm->after(9, st);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

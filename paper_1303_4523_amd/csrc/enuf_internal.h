@@ -113,7 +113,7 @@ struct ComputeBuffers {
   int *idx;              // [N] particle index of compact slot j
   int *slot;             // [N] compact slot of particle i, or -1
   // real-space cell grid
-  int *ccnt;             // [ncell^3]
+  int *ccnt;             // [2 ncell^3] two sets: a DPD step bins into one while the other is cleared
   double4 *cgrid;        // [ncell^3 * cap] (x, y, z, q) per cell slot
   int *cidx;             // [ncell^3 * cap] compact index per cell slot
   unsigned long long *freal;  // [N * 3] fixed-point real-space force per compact slot
@@ -126,7 +126,7 @@ struct ComputeBuffers {
   void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
   double *epart;         // [nky * xsplit] k-space energy per (ky row, kz range)
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
-  int *xcnt;             // [M] charges per mesh x-cell (zero between calls)
+  int *xcnt;             // [2 M] charges per mesh x-cell (zero between calls; two sets like ccnt)
   int *xslot;            // [M * xcap] compact indices of the charges of each x-cell
   double *wcoef64;       // [2p (D+1) + 2p D] window series coefficients (value, then derivative)
   float *wcoef32;
@@ -181,12 +181,19 @@ struct FinishArgs {
   unsigned long long *step_inc = nullptr;  // device step index, advanced by one (steps replayed from a graph)
 };
 
+// Scale of the gathered mesh field in the combine kernel: 2 / L^2 for ik
+// forces, M / (pi L^2) for the window-gradient forces.
+inline double combine_fscale(const ComputeConfig &cfg) {
+  const double L = cfg.L;
+  return cfg.mesh.ik ? 2.0 / (L * L) : (double)cfg.mesh.M / (3.14159265358979323846 * L * L);
+}
+
 // The ENUF evaluation in four phases (launch_compute runs them in order on
 // one stream; the DPD step forks the real-space phase onto another stream).
 hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
                        const double *q, hipStream_t st, KernelTimer *tm);
 hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                       KernelTimer *tm);
+                       KernelTimer *tm, int *pre_zero = nullptr, int npre = 0);
 hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
                         KernelTimer *tm);
 hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,

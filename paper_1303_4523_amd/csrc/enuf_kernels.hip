@@ -18,51 +18,13 @@
 // int64 fixed-point sums, so results are bitwise reproducible.
 #include "enuf_device.h"
 #include "enuf_dpd.h"
+#include "enuf_combine.h"
 
 namespace enuf {
 
 template <typename T> struct CplxOf;
 template <> struct CplxOf<double> { using type = double2; };
 template <> struct CplxOf<float> { using type = float2; };
-
-// ---------------------------------------------------------------------------
-// Block reductions with a fixed order of additions.
-// scratch needs blockDim.x / 64 entries.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ T block_sum(T v, T *scratch) {
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane == 0) scratch[w] = v;
-  __syncthreads();
-  T s = 0;
-  for (int i = 0; i < nw; ++i) s += scratch[i];
-  return s;
-}
-
-__device__ int block_sum_int(int v, int *scratch) {
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  __syncthreads();
-  if (lane == 0) scratch[w] = v;
-  __syncthreads();
-  int s = 0;
-  for (int i = 0; i < nw; ++i) s += scratch[i];
-  return s;
-}
-
-__device__ long long block_sum_ll(long long v, long long *scratch) {
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  v = wave_sum_ll(v);
-  __syncthreads();
-  if (lane == 0) scratch[w] = v;
-  __syncthreads();
-  long long s = 0;
-  for (int i = 0; i < nw; ++i) s += scratch[i];
-  return s;
-}
 
 __device__ inline double wrap_coord(double x, double L) {
   double y = x - L * floor(x / L);
@@ -397,10 +359,14 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
   }
 }
 
+// pre_zero: counts of an earlier kernel's cells, cleared first (their reader
+// finished before this kernel).
 __global__ void __launch_bounds__(kRealThreads)
 k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
        const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
-       DevScalars *sc, unsigned long long *freal, unsigned long long *ereal) {
+       DevScalars *sc, unsigned long long *freal, unsigned long long *ereal, int *pre_zero, int npre) {
+  if (pre_zero)
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < npre; c += gridDim.x * blockDim.x) pre_zero[c] = 0;
   real_body(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
             to_g(ereal), blockIdx.x, gridDim.x);
 }
@@ -1057,82 +1023,6 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
 // ---------------------------------------------------------------------------
 // Combine: forces per particle and per-block energy partials.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void
-combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> __restrict__ xq,
-             gptr<const unsigned long long> freal, gptr<const double4> __restrict__ part, int P2S,
-             double fscale, int nblk, double *blk_eg, gptr<const unsigned long long> __restrict__ ereal,
-             long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, const FinishArgs &fa, double *forces,
-             int bid) {
-  __shared__ double s_dbl[kPrepThreads / kWave];
-  __shared__ long long s_ll[kPrepThreads / kWave];
-  const int tid = threadIdx.x;
-  const int64_t i = (int64_t)bid * blockDim.x + tid;
-  {
-    // the pair kernel of this step has read the step index; the next reads the advanced one
-    if (fa.step_inc && bid == 0 && tid == 0) *fa.step_inc += 1ull;
-    // cell counts are left cleared for the next evaluation (their consumers ran before)
-    const int64_t stride = (int64_t)nblk * blockDim.x;
-    for (int64_t c = i; c < ncell3; c += stride) ccnt[c] = 0;
-    for (int64_t c = i; c < M; c += stride) xcnt[c] = 0;
-    if (fa.mode >= 0)
-      for (int64_t c = i; c < fa.ndcell3; c += stride) fa.dcnt[c] = 0;
-  }
-  double eg = 0.0;
-  long long er = 0, esl = 0;
-  if (i < N) {
-    // the pair forces and velocities do not depend on the slot: loaded with it
-    double fp[3] = {0.0, 0.0, 0.0}, vv[3] = {0.0, 0.0, 0.0};
-    if (fa.mode >= 0) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        fp[a] = fa.fdpd[3 * i + a];
-        if (fa.mode == 0) vv[a] = fa.vel[3 * i + a];
-      }
-    }
-    const int j = slot[i];
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (j >= 0) {
-      er = (long long)ereal[2 * (size_t)j];
-      esl = (long long)ereal[2 * (size_t)j + 1];
-      double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
-#pragma unroll 8
-      for (int s = 0; s < P2S; ++s) {
-        const double4 v = gload(part + (size_t)j * P2S + s);
-        bx += v.x;
-        by += v.y;
-        bz += v.z;
-        a += v.w;
-      }
-      const double qj = gload(xq + j).w;
-      fx = (double)(long long)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
-      fy = (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
-      fz = (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
-      eg = qj * a;
-    }
-    if (fa.mode < 0) {
-      forces[3 * i] = fx;
-      forces[3 * i + 1] = fy;
-      forces[3 * i + 2] = fz;
-    } else {
-      const double fe[3] = {fx, fy, fz};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double f = fp[a] + fa.kappa * fe[a];
-        forces[3 * i + a] = f;
-        if (fa.mode == 0) fa.vel[3 * i + a] = vv[a] + 0.5 * fa.dt * f;
-      }
-    }
-  }
-  eg = block_sum(eg, s_dbl);
-  er = block_sum_ll(er, s_ll);
-  esl = block_sum_ll(esl, s_ll);
-  if (tid == 0) {
-    blk_eg[bid] = eg;
-    blk_er[2 * bid] = er;
-    blk_er[2 * bid + 1] = esl;
-  }
-}
-
 // Final energies of one evaluation from the per-block partials of the combine
 // kernel and the k-space sums per (ky row, kz range) (one block; a separate launch, so the
 // partials of every combine block are visible without a device-wide fence).
@@ -1432,13 +1322,13 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
 }
 
 hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                       KernelTimer *tm) {
+                       KernelTimer *tm, int *pre_zero, int npre) {
   int64_t g = (nq_max + 3) / 4;
   const int grid_real = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(kRealThreads), 0, st, (const double4 *)b.xq,
                      (const int *)b.ccnt, (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L,
-                     cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal);
+                     cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal, pre_zero, npre);
   if (tm) tm->after(4, st);
   return hipGetLastError();
 }
@@ -1459,7 +1349,7 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
   const int nblk = cfg.nblk;
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   const double L = cfg.L;
-  const double fscale = cfg.mesh.ik ? 2.0 / (L * L) : (double)cfg.mesh.M / (M_PI * L * L);
+  const double fscale = combine_fscale(cfg);
   const double inv2piL = 1.0 / (2.0 * M_PI * L);
   const int kid = fa.mode < 0 ? 8 : 9;
   if (tm) tm->before(kid, st);

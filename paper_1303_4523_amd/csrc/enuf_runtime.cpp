@@ -377,7 +377,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           n * sizeof(double4),                                // xq
           n * sizeof(int),                                    // idx
           n * sizeof(int),                                    // slot
-          ncell3 * sizeof(int),                               // ccnt
+          2 * ncell3 * sizeof(int),                           // ccnt (two sets)
           ncell3 * cap * sizeof(double4),                     // cgrid
           ncell3 * cap * sizeof(int),                         // cidx
           n * 3 * sizeof(unsigned long long),                 // freal
@@ -388,7 +388,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           nky * (size_t)Kc * sizeof(double),                  // epart (x-pass splits <= Kc)
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
-          (size_t)M * sizeof(int),                            // xcnt
+          2 * (size_t)M * sizeof(int),                        // xcnt (two sets)
           (size_t)M * (size_t)g.xcap * sizeof(int),           // xslot
           P2 * (2 * kMaxChebDeg + 2) * sizeof(double),        // wcoef64
           P2 * (2 * kMaxChebDeg + 2) * sizeof(float),         // wcoef32
@@ -397,12 +397,15 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           (size_t)M * sizeof(float2)};                        // tw32
 }
 
-// LDS bytes per block the plans of this device may use: the device's limit,
-// or the lower value of ENUF_MAX_LDS_BYTES.  0 if the device cannot be queried.
+// LDS bytes per block the plans of this device may use: the device's limit
+// less a reserve for the kernels' static LDS, or the lower value of
+// ENUF_MAX_LDS_BYTES.  0 if the device cannot be queried.
 size_t lds_budget(int device) {
+  constexpr size_t kStaticLdsReserve = 256;
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return 0;
-  size_t v = (size_t)lds;
+  if ((size_t)lds <= kStaticLdsReserve) return 0;
+  size_t v = (size_t)lds - kStaticLdsReserve;
   if (const char *cap = std::getenv("ENUF_MAX_LDS_BYTES")) {
     const long long c = std::atoll(cap);
     if (c > 0 && (size_t)c < v) v = (size_t)c;
@@ -517,8 +520,8 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.tw32 = (float2 *)ptr[23];
   if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
       hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(b.ccnt, 0, ncell3 * sizeof(int)) != hipSuccess ||
-      hipMemset(b.xcnt, 0, (size_t)M * sizeof(int)) != hipSuccess) {
+      hipMemset(b.ccnt, 0, 2 * ncell3 * sizeof(int)) != hipSuccess ||
+      hipMemset(b.xcnt, 0, 2 * (size_t)M * sizeof(int)) != hipSuccess) {
     set_error("hipMemset failed");
     delete pl;
     return nullptr;
@@ -750,17 +753,23 @@ struct enuf_dpd {
   // kGraphSteps steps of enuf_dpd_run captured in a graph (no cross-stream
   // events: the fork and join are dependency edges), valid for the state
   // buffers and the configuration it was captured with
+  // One graph per parity of the first replayed step (the bin-count set a
+  // step uses is its index mod 2; a graph of an even number of steps keeps it).
   int use_graph = 1;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  const void *gkey[3] = {nullptr, nullptr, nullptr};
-  std::vector<unsigned char> gcfg;  // parameters the kernels were captured with
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  const void *gkey[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  std::vector<unsigned char> gcfg[2];  // parameters the kernels were captured with
 
+  void drop_graph(int par) {
+    if (gexec[par]) (void)hipGraphExecDestroy(gexec[par]);
+    if (graph[par]) (void)hipGraphDestroy(graph[par]);
+    gexec[par] = nullptr;
+    graph[par] = nullptr;
+  }
   void drop_graph() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
+    drop_graph(0);
+    drop_graph(1);
   }
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
@@ -951,63 +960,110 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
 // it gains); the combine kernel joins the two.
 // energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
 // reports the last one; steps inside a run other than its last skip it).
+// The plan's buffers with the real-space and mesh bin counts of set `par`
+// (a DPD step bins into one set while the combine clears the other).
+static ComputeBuffers plan_buffers_set(const enuf_plan *pl, int par) {
+  ComputeBuffers b = pl->buf;
+  const int nc = pl->cfg.cells.ncell;
+  b.ccnt += (size_t)par * nc * nc * nc;
+  b.xcnt += (size_t)par * pl->cfg.mesh.M;
+  return b;
+}
+
+static DpdCharges dpd_charges_set(const enuf_dpd *d, int par) {
+  DpdCharges ch = d->charges;
+  if (ch.enabled && d->plan) {
+    const ComputeBuffers b = plan_buffers_set(d->plan, par);
+    ch.ccnt = b.ccnt;
+    ch.xcnt = b.xcnt;
+  }
+  return ch;
+}
+
 // Steps of enuf_dpd_run per graph launch.
 constexpr int kGraphSteps = 8;
+static_assert(kGraphSteps % 2 == 0, "a replayed graph keeps the parity of the bin-count set");
 
-// The last node captured on a capturing stream (its single dependency).
-static hipError_t capture_tail(hipStream_t st, hipGraphNode_t *node) {
+// The last node captured on a capturing stream (its single dependency)
+// (*count = 0 before the first node of the capture.)
+static hipError_t capture_tail(hipStream_t st, hipGraphNode_t *node, size_t *count) {
   hipStreamCaptureStatus cs;
   const hipGraphNode_t *deps = nullptr;
   size_t nd = 0;
   hipError_t e = hipStreamGetCaptureInfo_v2(st, &cs, nullptr, nullptr, &deps, &nd);
   if (e != hipSuccess) return e;
-  if (cs != hipStreamCaptureStatusActive || nd != 1 || !deps) return hipErrorIllegalState;
-  *node = deps[0];
+  if (cs != hipStreamCaptureStatusActive || nd > 1 || (nd == 1 && !deps)) return hipErrorIllegalState;
+  *node = nd == 1 ? deps[0] : nullptr;
+  *count = nd;
   return hipSuccess;
 }
 
-// graph_st: capture of a step for a graph on that stream (the step index is
-// read from and advanced in device memory; the fork and join become
-// dependency edges of the capture instead of events).
+// One force evaluation (mode 1) or step (mode 0).
+//   pre:  launch the pre kernel first (else the previous step's combine ran it)
+//   next: fuse the pre kernel of the next step (mode 0) into the combine
+//   graph_st: capture for a graph on that stream (the step index is read from
+//         and advanced in device memory; the fork and join are dependency
+//         edges of the capture instead of events).
+// With a plan, the mesh passes (the longest chain) are enqueued first on the
+// integrator's stream; the pair forces and then the real-space term run on
+// one forked stream beside them (a second forked stream costs more in
+// cross-stream waits than it gains); the combine kernel joins the two.  The
+// real-space kernel clears the DPD cell counts (the pair kernel has read
+// them), its last block the real-space cell counts, and the last block of the
+// backward pass the mesh x-bin counts, so that the fused combine can bin the
+// next step at once.
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step,
-                    bool energies = true, hipStream_t graph_st = nullptr) {
+                    bool energies, bool pre, bool next, hipStream_t graph_st = nullptr) {
   const int64_t N = d->N;
   const bool graph = graph_st != nullptr;
   KernelTimer *tm = d->timer.kernel >= 0 && !graph ? &d->timer : nullptr;
   hipStream_t st = graph ? graph_st : d->stream;
   const unsigned long long *step_dev = graph ? d->step_ctr : nullptr;
-  hipError_t e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
-                                d->charges, st, tm);
+  // the real-space and mesh bin counts of step k are set k mod 2
+  const int par = (int)(step & 1);
+  const DpdCharges ch = dpd_charges_set(d, par), ch_next = dpd_charges_set(d, par ^ 1);
+  hipError_t e = hipSuccess;
+  if (pre)
+    e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch, st, tm);
   if (!d->plan) {
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, st, tm, step_dev);
     if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
     if (graph && e == hipSuccess) e = launch_add_u64(d->step_ctr, st);
+    if (next && e == hipSuccess)
+      e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch_next, st,
+                         tm);
   } else {
     enuf_plan *pl = d->plan;
+    const ComputeBuffers bk = plan_buffers_set(pl, par);
     if (!graph) pl->stream = st;
     const bool fork = d->concurrent != 0;
     const bool events = fork && !graph;
     hipStream_t s1 = events ? d->side : st;
     hipGraphNode_t n_pre = nullptr, n_bwd = nullptr;
+    size_t c_pre = 0;
     if (events) {
       if (e == hipSuccess) e = hipEventRecord(d->fork_ev, st);
       if (e == hipSuccess) e = hipStreamWaitEvent(s1, d->fork_ev, 0);
     }
-    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_pre);
-    if (e == hipSuccess) e = launch_recip(pl->cfg, pl->buf, d->nq, st, tm);
-    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_bwd);
+    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_pre, &c_pre);
+    if (e == hipSuccess) e = launch_recip(pl->cfg, bk, d->nq, st, tm);
+    size_t c_bwd = 0;
+    if (graph && fork && e == hipSuccess) e = capture_tail(st, &n_bwd, &c_bwd);
     // the pair forces and the real-space term depend on the pre kernel only
-    if (graph && fork && e == hipSuccess) e = hipStreamUpdateCaptureDependencies(st, &n_pre, 1, hipStreamSetCaptureDependencies);
+    if (graph && fork && e == hipSuccess)
+      e = hipStreamUpdateCaptureDependencies(st, &n_pre, c_pre, hipStreamSetCaptureDependencies);
     if (e == hipSuccess)
       e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, s1, tm, step_dev);
-    if (e == hipSuccess) e = launch_real(pl->cfg, pl->buf, d->nq, s1, tm);
+    const int ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
+    if (e == hipSuccess) e = launch_real(pl->cfg, bk, d->nq, s1, tm, d->dcnt, ndcell3);
     if (events && e == hipSuccess) e = hipEventRecord(d->join_ev, s1);
     if (events && e == hipSuccess) e = hipStreamWaitEvent(st, d->join_ev, 0);
     // the combine kernel depends on the mesh passes and the real-space term
-    if (graph && fork && e == hipSuccess) e = hipStreamUpdateCaptureDependencies(st, &n_bwd, 1, hipStreamAddCaptureDependencies);
+    if (graph && fork && e == hipSuccess)
+      e = hipStreamUpdateCaptureDependencies(st, &n_bwd, c_bwd, hipStreamAddCaptureDependencies);
     if (e == hipSuccess) {
       FinishArgs fa;
       fa.mode = mode;
@@ -1015,11 +1071,19 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
       fa.dt = d->P.dt;
       fa.fdpd = d->fdpd;
       fa.vel = vel;
-      fa.dcnt = d->dcnt;
-      fa.ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
+      fa.dcnt = nullptr;  // cleared by the real-space kernel
+      fa.ndcell3 = ndcell3;
       fa.energies = energies ? 1 : 0;
       fa.step_inc = graph ? d->step_ctr : nullptr;
-      e = launch_combine(pl->cfg, pl->buf, force, nullptr, d->e5, fa, st, tm);
+      if (next && !energies)
+        e = launch_combine_pre(pl->cfg, bk, force, fa, d->P, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
+                               ch_next, st, tm);
+      else {
+        e = launch_combine(pl->cfg, bk, force, nullptr, d->e5, fa, st, tm);
+        if (next && e == hipSuccess)
+          e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch_next,
+                             st, tm);
+      }
     }
   }
   if (e != hipSuccess) {
@@ -1045,7 +1109,7 @@ static int dpd_check(enuf_dpd *d, const void *a, const void *b, const void *c) {
 int enuf_dpd_forces(enuf_dpd *d, double *pos, const double *vel, double *force, uint64_t step) {
   int rc = dpd_check(d, pos, vel, force);
   if (rc != ENUF_OK) return rc;
-  return dpd_eval(d, 1, pos, const_cast<double *>(vel), force, step);
+  return dpd_eval(d, 1, pos, const_cast<double *>(vel), force, step, true, true, false);
 }
 
 // Bytes of everything the captured kernels take by value: when they change
@@ -1070,12 +1134,15 @@ static std::vector<unsigned char> dpd_graph_config(const enuf_dpd *d) {
 // Capture kGraphSteps steps (no energy reduction) on the integrator's side
 // stream.  False (and no graph) if capture is not available; the caller then
 // launches the steps eagerly.
-static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force) {
-  d->drop_graph();
+static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force, int par) {
+  d->drop_graph(par);
   hipStream_t cs = d->side;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
   int rc = ENUF_OK;
-  for (int k = 0; k < kGraphSteps && rc == ENUF_OK; ++k) rc = dpd_eval(d, 0, pos, vel, force, 0, false, cs);
+  // the step index passed here only selects the bin-count set; the replayed
+  // steps read their index from the device counter
+  for (int k = 0; k < kGraphSteps && rc == ENUF_OK; ++k)
+    rc = dpd_eval(d, 0, pos, vel, force, (uint64_t)(par + k), false, false, true, cs);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(cs, &g);
   if (rc != ENUF_OK || e != hipSuccess || !g) {
@@ -1090,12 +1157,12 @@ static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force) {
     (void)hipGetLastError();
     return false;
   }
-  d->graph = g;
-  d->gexec = x;
-  d->gkey[0] = pos;
-  d->gkey[1] = vel;
-  d->gkey[2] = force;
-  d->gcfg = dpd_graph_config(d);
+  d->graph[par] = g;
+  d->gexec[par] = x;
+  d->gkey[par][0] = pos;
+  d->gkey[par][1] = vel;
+  d->gkey[par][2] = force;
+  d->gcfg[par] = dpd_graph_config(d);
   return true;
 }
 
@@ -1103,21 +1170,29 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
   int rc = dpd_check(d, pos, vel, force);
   if (rc != ENUF_OK) return rc;
   if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
+  if (nsteps == 0) return ENUF_OK;
+  // the first step's pre kernel; each later one runs fused into the combine
+  // kernel of the step before
+  KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
+  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
+                               dpd_charges_set(d, (int)(first_step & 1)), d->stream, tm),
+                ENUF_EDEVICE);
   int s = 0;
   // all but the last step in graphs of kGraphSteps steps (one launch each);
   // the rest, and the last step with its energy reduction, eagerly
   const int body = nsteps - 1;
   if (d->use_graph && d->timer.kernel < 0 && body >= kGraphSteps) {
-    const bool same = d->gexec && d->gkey[0] == pos && d->gkey[1] == vel && d->gkey[2] == force &&
-                      d->gcfg == dpd_graph_config(d);
-    if (same || dpd_capture(d, pos, vel, force)) {
+    const int par = (int)(first_step & 1);
+    const bool same = d->gexec[par] && d->gkey[par][0] == pos && d->gkey[par][1] == vel &&
+                      d->gkey[par][2] == force && d->gcfg[par] == dpd_graph_config(d);
+    if (same || dpd_capture(d, pos, vel, force, par)) {
       HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, d->stream), ENUF_EDEVICE);
       for (; s + kGraphSteps <= body; s += kGraphSteps)
-        HIP_OR_RETURN(hipGraphLaunch(d->gexec, d->stream), ENUF_EDEVICE);
+        HIP_OR_RETURN(hipGraphLaunch(d->gexec[par], d->stream), ENUF_EDEVICE);
     }
   }
   for (; s < nsteps; ++s) {
-    rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s, s == nsteps - 1);
+    rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s, s == nsteps - 1, false, s < nsteps - 1);
     if (rc != ENUF_OK) return rc;
   }
   return ENUF_OK;
