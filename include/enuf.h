@@ -90,9 +90,12 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
  * differ between part counts only in the last bits).  The default spreads
  * one system's mesh passes over about half the device, leaving the rest to
  * the pair and real-space kernels that run beside them: parts = min(8, 128 / M)
- * (ENUF_MESH_PARTS, read at plan creation, overrides it).  The x pass takes
- * min(Kc, 64 / (2 Kc - 1)) work-groups per ky row (ENUF_X_SPLIT overrides it).  Systems stepped together in a batch already
- * fill the device: 1 part per plane avoids the repeated transforms there.
+ * (ENUF_MESH_PARTS, read at plan creation, overrides it).  The gather pass
+ * takes as many work-groups per plane (ENUF_BWD_PARTS overrides it at plan
+ * creation; this call sets both).  The x pass takes min(Kc, 64 / (2 Kc - 1))
+ * work-groups per ky row (ENUF_X_SPLIT overrides it).  Systems stepped
+ * together in a batch already fill the device: 1 part per plane avoids the
+ * repeated transforms there.
  * A batch reads the value when its membership changes.  Synchronises the
  * plan's stream.  ENUF_EINVAL outside the allowed range.
  */

@@ -65,6 +65,8 @@ struct MeshParams {
   int stage;       // charges of a plane staged in LDS at a time (<= kStage)
   int parts;       // work-groups per plane in the spread and gather passes, each
                    // taking a contiguous share of the plane's charges (<= kMaxParts)
+  int bparts;      // work-groups per plane in the backward (gather) pass, each taking
+                   // the charges j with j mod bparts equal to its index (<= kMaxParts)
   int xsplit;      // work-groups per ky row in the x pass, each a contiguous range of kz
   double gscale_f; // fixed-point scale of the partial spectra, relative to the
                    // spread's scale: 2^-(3 ceil(log2 2p) + 3)

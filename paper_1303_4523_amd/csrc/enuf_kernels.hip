@@ -844,7 +844,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
       Zre[kz * Mz + m] = v.x;
       Zim[kz * Mz + m] = v.y;
     }
-    if (early && comp == 0 && ej >= 0 && ej % mp.parts == wpart) ec = gload(xq + ej);
+    if (early && comp == 0 && ej >= 0 && ej % mp.bparts == wpart) ec = gload(xq + ej);
     __syncthreads();
     lds_fft<T>(Zre, Zim, Mz, Kc, mp.fft, twr, twi, true);
 
@@ -881,12 +881,12 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
       const int chunk = r0 / R;
       for (int e0 = 0; e0 < total; e0 += mp.stage) {
       if (early && !staged) {
-        nstaged = stage_plane_commit(ej >= 0 && ej % mp.parts == wpart, ej, eb, ec, s_c, s_jb, s_n);
+        nstaged = stage_plane_commit(ej >= 0 && ej % mp.bparts == wpart, ej, eb, ec, s_c, s_jb, s_n);
         staged = true;
       }
       const int cnt = early ? nstaged
                             : stage_plane_charges(e0, (total - e0) < mp.stage ? (total - e0) : mp.stage, P2, pre,
-                                                  bcell, xslot, mp.xcap, xq, wpart, mp.parts, s_c, s_jb, s_n);
+                                                  bcell, xslot, mp.xcap, xq, wpart, mp.bparts, s_c, s_jb, s_n);
       const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
       for (int it = tid; it < items; it += nt) {
         const int e = it / P2pad, sy = it % P2pad;
@@ -1293,11 +1293,11 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
   if (mp.ik)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, true>), dim3(nplane), dim3(kPassThreads), cfg.lds_bwd, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, true>), dim3(mp.M * mp.bparts), dim3(kPassThreads), cfg.lds_bwd, st,
                        (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
                        (const DevScalars *)b.sc, mp, tw, (const C *)gh, (const C *)b.gzx, b.part);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, false>), dim3(nplane), dim3(kPassThreads), cfg.lds_bwd, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_recip_bwd<T, false>), dim3(mp.M * mp.bparts), dim3(kPassThreads), cfg.lds_bwd, st,
                        (const double4 *)b.xq, (const int *)b.xcnt, (const int *)b.xslot, wc,
                        (const DevScalars *)b.sc, mp, tw, (const C *)gh, (const C *)b.gzx, b.part);
   if (tm) tm->after(7, st);

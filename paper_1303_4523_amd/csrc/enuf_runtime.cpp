@@ -315,6 +315,16 @@ int mesh_parts(int M) {
   return std::max(1, std::min(kMaxParts, 128 / M));
 }
 
+// Work-groups per plane of the backward pass: as many as the spread's, or
+// ENUF_BWD_PARTS (1..8) (tuning and testing).
+int mesh_bparts(int parts) {
+  if (const char *v = std::getenv("ENUF_BWD_PARTS")) {
+    const int n = std::atoi(v);
+    if (n >= 1) return std::min(kMaxParts, n);
+  }
+  return parts;
+}
+
 // Work-groups per ky row of the x pass: about 64 in all, each a range of kz
 // lines.  ENUF_X_SPLIT (1..Kc) overrides the choice (tuning and testing).
 int mesh_xsplit(int Kc, int nky) {
@@ -462,6 +472,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.win = make_window(ENUF_WINDOW_KB, p, sigma);
   m.fft = fp;
   m.parts = mesh_parts(M);
+  m.bparts = mesh_bparts(m.parts);
   pl->max_parts = m.parts;  // the spectrum buffer holds this many partial spectra
   m.xsplit = mesh_xsplit(Kc, m.nky);
   m.gscale_f = mesh_gscale_factor(p);
@@ -616,6 +627,7 @@ int enuf_plan_set_parts(enuf_plan *plan, int parts) {
   }
   HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
   plan->cfg.mesh.parts = parts;
+  plan->cfg.mesh.bparts = parts;
   return ENUF_OK;
 }
 
@@ -1410,9 +1422,10 @@ int batch_rebuild(enuf_batch *b) {
     const BatchMember m = member_view(b->members[k]);
     const int id = (int)mem.size();
     mem.push_back(m);
-    const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;  // work-groups of the spread and gather passes
+    const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;     // work-groups of the spread pass
+    const int bplanes = m.cfg.mesh.M * m.cfg.mesh.bparts;   // and of the gather pass
     const int counts[7] = {m.nblk,  m.pair_blocks, m.real_blocks, planes, m.cfg.mesh.nky * m.cfg.mesh.xsplit,
-                           planes, m.nblk};
+                           bplanes, m.nblk};
     for (int s = 0; s < 7; ++s)
       for (int i = 0; i < counts[s]; ++i) map[s].push_back(make_int2(id, i));
     lf = std::max(lf, m.cfg.lds_fwd);
