@@ -113,13 +113,15 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
       }
     }
   }
-  eg = block_sum(eg, s_dbl);
-  er = block_sum_ll(er, s_ll);
-  esl = block_sum_ll(esl, s_ll);
-  if (tid == 0) {
-    blk_eg[bid] = eg;
-    blk_er[2 * bid] = er;
-    blk_er[2 * bid + 1] = esl;
+  if (fa.energies) {  // block-uniform: the per-block energy partials only when they are reduced
+    eg = block_sum(eg, s_dbl);
+    er = block_sum_ll(er, s_ll);
+    esl = block_sum_ll(esl, s_ll);
+    if (tid == 0) {
+      blk_eg[bid] = eg;
+      blk_er[2 * bid] = er;
+      blk_er[2 * bid + 1] = esl;
+    }
   }
 }
 

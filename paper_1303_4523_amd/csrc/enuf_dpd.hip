@@ -116,7 +116,7 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     cz = cz < cp.ncell ? cz : cp.ncell - 1;
     c = (cx * cp.ncell + cy) * cp.ncell + cz;
     double t;
-    xc = mesh_cell(r[0], ch.m_over_l, ch.M, &t);
+    xc = mesh_cell(r[0], ch.m_over_l, ch.M, &t) * kXSub + (j & (kXSub - 1));  // x-cell sub-bin
   }
   // the slot claims are independent: all are in flight together
   const int s = atomicAdd(&dcnt[cell], 1);
@@ -594,7 +594,7 @@ k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict
               DpdParams P, double *pos, double *v0, int *dcnt, double4 *cpos, double4 *cvel, int *status,
               DpdCharges ch) {
   combine_body(N, to_g(slot), to_g(xq), to_g(freal), to_g(part), P2S, fscale, nblk, blk_eg, to_g(ereal), blk_er,
-               ccnt, ncell3, xcnt, M, fa, forces, blockIdx.x);
+               ccnt, ncell3, xcnt, M * kXSub, fa, forces, blockIdx.x);
   __syncthreads();  // the step's loads and stores come before the next step's
   dpd_pre_body(N, 0, P, pos, fa.vel, forces, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
 }

@@ -10,6 +10,8 @@ namespace enuf {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kPrepThreads = 256;  // threads per block of the particle-parallel kernels
 constexpr int kPassThreads = 512;  // threads per block of the mesh-plane kernels
+constexpr int kXSub = 8;           // sub-bins of a mesh x-cell (by compact index mod 8): the binning's
+                                   // slot counters are shared by 8 times fewer charges
 constexpr int kMaxRadixPasses = 16;
 constexpr int kMaxChebDeg = 24;    // highest degree of the window series
 constexpr int kStage = 512;        // most charges of a plane staged in LDS at a time by the mesh passes
@@ -51,7 +53,7 @@ struct WindowParams {
 // (last coefficient 0), so that both kinds evaluate in one recurrence.
 struct MeshParams {
   int cheb_deg;    // degree of the value series (derivative: cheb_deg - 1)
-  int xcap;        // slots per x-bin of the charge binning
+  int xcap;        // slots per x-cell sub-bin of the charge binning
   int M;           // mesh points per side
   int Mp;          // padded row stride of LDS planes (elements)
   int Mz;          // padded line stride of LDS spectrum buffers (elements)
@@ -128,8 +130,8 @@ struct ComputeBuffers {
   void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
   double *epart;         // [nky * xsplit] k-space energy per (ky row, kz range)
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
-  int *xcnt;             // [2 M] charges per mesh x-cell (zero between calls; two sets like ccnt)
-  int *xslot;            // [M * xcap] compact indices of the charges of each x-cell
+  int *xcnt;             // [2 M kXSub] charges per mesh x-cell sub-bin (zero between calls; two sets like ccnt)
+  int *xslot;            // [M kXSub xcap] compact indices of the charges of each x-cell sub-bin
   double *wcoef64;       // [2p (D+1) + 2p D] window series coefficients (value, then derivative)
   float *wcoef32;
   double *blk_eg;        // [nblk] per-block sums of q * A

@@ -112,9 +112,10 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
       }
       double t;
       const int xc = mesh_cell(x, m_over_l, M, &t);
-      const int xs = atomicAdd(&xcnt[xc], 1);
+      const int xb = xc * kXSub + (j & (kXSub - 1));
+      const int xs = atomicAdd(&xcnt[xb], 1);
       if (xs < xcap)
-        xslot[(size_t)xc * xcap + xs] = j;
+        xslot[(size_t)xb * xcap + xs] = j;
       else
         set_status(sc, kEOverflow);
     } else {
@@ -390,32 +391,47 @@ struct PlaneCharges {
   int *cell; // [2p] x-cell of bin b (LDS)
 };
 
-// Fill the LDS prefix sums of the plane's 2p x-bins; returns the charge count.
+// Fill the LDS prefix sums of the plane's 2p x-cells, kXSub sub-bins each
+// (2p kXSub <= blockDim.x entries, one per thread); returns the charge count.
 __device__ inline int plane_bins(int x0, int M, int p, gptr<const int> __restrict__ xcnt, int xcap, int *pre,
                                  int *cell) {
-  const int P2 = 2 * p;
-  if (threadIdx.x < P2) {
-    const int c = mod_pos(x0 - p + (int)threadIdx.x, M);
-    const int n = xcnt[c];
-    cell[threadIdx.x] = c;
-    pre[threadIdx.x + 1] = n < xcap ? n : xcap;
+  __shared__ int s_ws[kPassThreads / kWave];
+  const int NB = 2 * p * kXSub;
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+  int n = 0;
+  if (t < NB) {
+    const int c = mod_pos(x0 - p + t / kXSub, M) * kXSub + t % kXSub;
+    n = xcnt[c];
+    n = n < xcap ? n : xcap;
+    cell[t] = c;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    pre[0] = 0;
-    for (int b = 0; b < P2; ++b) pre[b + 1] += pre[b];
+  int x = n;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
   }
+  if (lane == kWave - 1) s_ws[w] = x;
   __syncthreads();
-  return pre[P2];
+  int base = 0;
+  for (int q = 0; q < w; ++q) base += s_ws[q];
+  if (t < NB) pre[t + 1] = base + x;
+  if (t == 0) pre[0] = 0;
+  __syncthreads();
+  return pre[NB];
 }
 
-// Offsets of charge e of the plane: x-bin b, and the compact index.
+// Offsets of charge e of the plane: its x-cell offset b (0 .. 2p-1) in the
+// stencil, and its compact index.
 __device__ inline int plane_charge(int e, int P2, const int *pre, const int *cell, gptr<const int> __restrict__ xslot,
                                    int xcap, int *b_out) {
-  int b = 0;
-  while (b < P2 - 1 && e >= pre[b + 1]) ++b;
-  *b_out = b;
-  return xslot[(size_t)cell[b] * xcap + (e - pre[b])];
+  int lo = 0, hi = P2 * kXSub;  // pre[lo] <= e < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= e) lo = mid; else hi = mid;
+  }
+  *b_out = lo / kXSub;
+  return xslot[(size_t)cell[lo] * xcap + (e - pre[lo])];
 }
 
 // Stage in LDS those of the plane's charges e0 .. e0 + cnt - 1 that belong to
@@ -513,8 +529,8 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   T *cv = reinterpret_cast<T *>(smem + off);  // [P2][Ds] value series
   off += (size_t)P2 * Ds * sizeof(T);
   int *pre = reinterpret_cast<int *>(smem + off);
-  int *bcell = pre + P2 + 1;
-  off = (off + (size_t)(2 * P2 + 1) * sizeof(int) + 31) & ~(size_t)31;
+  int *bcell = pre + P2 * kXSub + 1;
+  off = (off + (size_t)(2 * P2 * kXSub + 1) * sizeof(int) + 31) & ~(size_t)31;
   double4 *s_c = reinterpret_cast<double4 *>(smem + off);  // [stage] staged charges
   int *s_jb = reinterpret_cast<int *>(s_c + mp.stage);      // [stage][2] compact index, x-bin
   int *s_n = s_jb + 2 * mp.stage;                            // staged count
@@ -799,8 +815,8 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   T *cd = cv + (size_t)P2 * Ds;               // [P2][Ds] derivative series
   off += (size_t)P2 * 2 * Ds * sizeof(T);
   int *pre = reinterpret_cast<int *>(smem + off);
-  int *bcell = pre + P2 + 1;
-  off = (off + (size_t)(2 * P2 + 1) * sizeof(int) + 31) & ~(size_t)31;
+  int *bcell = pre + P2 * kXSub + 1;
+  off = (off + (size_t)(2 * P2 * kXSub + 1) * sizeof(int) + 31) & ~(size_t)31;
   double4 *s_c = reinterpret_cast<double4 *>(smem + off);  // [stage] staged charges
   int *s_jb = reinterpret_cast<int *>(s_c + mp.stage);      // [stage][2] compact index, x-bin
   int *s_n = s_jb + 2 * mp.stage;                            // staged count
@@ -1152,7 +1168,7 @@ kb_combine(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, in
   const int nc = m.cfg.cells.ncell;
   combine_body(m.N, to_g(m.buf.slot), to_g(m.buf.xq), to_g(m.buf.freal), to_g(m.buf.part),
                2 * m.cfg.mesh.win.p * m.cfg.mesh.nslot, m.fscale, m.nblk, m.buf.blk_eg, to_g(m.buf.ereal),
-               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M, fa, m.force, w.y);
+               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M * kXSub, fa, m.force, w.y);
 }
 
 __global__ void __launch_bounds__(kPrepThreads)
@@ -1207,7 +1223,7 @@ hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *ma
 void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, size_t *bwd) {
   const size_t ts = precision == 0 ? sizeof(double) : sizeof(float);
   const int P2 = 2 * m.win.p;
-  const size_t misc = (size_t)P2 * 2 * ((m.cheb_deg + 1) | 1) * ts + (3 * (size_t)P2 + 2) * sizeof(int) + 32 +
+  const size_t misc = (size_t)P2 * 2 * ((m.cheb_deg + 1) | 1) * ts + (2 * (size_t)P2 * kXSub + P2 + 2) * sizeof(int) + 32 +
                       (size_t)m.stage * (sizeof(double4) + 2 * sizeof(int)) + 48;
   const size_t a16 = 15;
   const size_t acc = ((size_t)m.rows * m.Mp * sizeof(long long) + a16) & ~a16;
@@ -1309,7 +1325,7 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   if (tm) tm->before(2, st);
   hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
-                     ncell3, b.xcnt, cfg.mesh.M);
+                     ncell3, b.xcnt, cfg.mesh.M * kXSub);
   if (tm) tm->after(2, st);
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
@@ -1356,7 +1372,8 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
   hipLaunchKernelGGL(k_combine, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
                      (const double4 *)b.xq, (const unsigned long long *)b.freal, (const double4 *)b.part,
                      2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, nblk, b.blk_eg,
-                     (const unsigned long long *)b.ereal, b.blk_er, b.ccnt, ncell3, b.xcnt, cfg.mesh.M, fa, forces);
+                     (const unsigned long long *)b.ereal, b.blk_er, b.ccnt, ncell3, b.xcnt, cfg.mesh.M * kXSub, fa,
+                     forces);
   if (fa.energies)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
                        (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky * cfg.mesh.xsplit,

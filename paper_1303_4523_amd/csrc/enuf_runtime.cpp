@@ -359,8 +359,8 @@ bool plan_geometry(int64_t N, double box, int p, int M, int Kc, double r_cut, si
   const double mean = (double)N / ((double)ncell * ncell * ncell);
   g->ncell = ncell;
   g->cap = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
-  const double xmean = (double)N / (double)M;
-  g->xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 16.0);
+  const double xmean = (double)N / ((double)M * kXSub);  // charges per x-cell sub-bin, at most
+  g->xcap = (int)std::ceil(xmean + 6.0 * std::sqrt(xmean) + 8.0);
   g->nblk = (int)((N + kPrepThreads - 1) / kPrepThreads);
   // the gather partials are sized for the largest series degree in either precision
   MeshParams m{};
@@ -398,8 +398,8 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           nky * (size_t)Kc * sizeof(double),                  // epart (x-pass splits <= Kc)
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
-          2 * (size_t)M * sizeof(int),                        // xcnt (two sets)
-          (size_t)M * (size_t)g.xcap * sizeof(int),           // xslot
+          2 * (size_t)M * kXSub * sizeof(int),                // xcnt (two sets)
+          (size_t)M * kXSub * (size_t)g.xcap * sizeof(int),   // xslot
           P2 * (2 * kMaxChebDeg + 2) * sizeof(double),        // wcoef64
           P2 * (2 * kMaxChebDeg + 2) * sizeof(float),         // wcoef32
           nky * sizeof(double),                               // atab
@@ -532,7 +532,7 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
       hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(b.ccnt, 0, 2 * ncell3 * sizeof(int)) != hipSuccess ||
-      hipMemset(b.xcnt, 0, 2 * (size_t)M * sizeof(int)) != hipSuccess) {
+      hipMemset(b.xcnt, 0, 2 * (size_t)M * kXSub * sizeof(int)) != hipSuccess) {
     set_error("hipMemset failed");
     delete pl;
     return nullptr;
@@ -978,7 +978,7 @@ static ComputeBuffers plan_buffers_set(const enuf_plan *pl, int par) {
   ComputeBuffers b = pl->buf;
   const int nc = pl->cfg.cells.ncell;
   b.ccnt += (size_t)par * nc * nc * nc;
-  b.xcnt += (size_t)par * pl->cfg.mesh.M;
+  b.xcnt += (size_t)par * pl->cfg.mesh.M * kXSub;
   return b;
 }
 
