@@ -380,6 +380,9 @@ k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const doubl
 // never straddles a wavefront); lane sy evaluates the window of offset sy on
 // each axis and the group shares them with shuffles.
 // ---------------------------------------------------------------------------
+// v mod M for -M <= v < 2M (a stencil index next to the mesh): no division.
+__device__ __forceinline__ int wrap_once(int v, int M) { return v < 0 ? v + M : (v >= M ? v - M : v); }
+
 __device__ inline int pow2_at_least(int v) {
   int r = 1;
   while (r < v) r <<= 1;
@@ -511,7 +514,7 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, p = mp.win.p, P2 = 2 * p, D = mp.cheb_deg;
   const int R = mp.rows;
-  const int P2pad = pow2_at_least(P2);
+  const int P2pad = pow2_at_least(P2), lg_pad = __builtin_ctz(P2pad);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const float inv_kc = 1.0f / (float)Kc;
 
@@ -555,7 +558,7 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
     // whole wavefronts iterate together so that the group shuffles see every lane
     const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
     for (int it = tid; it < items; it += nt) {
-      const int e = it / P2pad, sy = it % P2pad;
+      const int e = it >> lg_pad, sy = it & (P2pad - 1);
       const bool has = e < cnt;
       bool act = has && sy < P2, in = false;
       T wz = (T)0, wrow = (T)0;
@@ -574,7 +577,7 @@ recip_fwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
           T w3[3];
           clenshaw_n<T, 3>(ser, arg, D, w3);
           wz = w3[0];
-          row = mod_pos(cy - p + 1 + sy, M) - r0;
+          row = wrap_once(cy - p + 1 + sy, M) - r0;
           in = (unsigned)row < (unsigned)nr;
           if (in)
             wrow = (T)c.w * w3[1] * w3[2];
@@ -797,7 +800,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
   extern __shared__ __align__(16) unsigned char smem[];
   const int M = mp.M, Mp = mp.Mp, Mz = mp.Mz, Kc = mp.Kc, nky = mp.nky, p = mp.win.p, P2 = 2 * p;
   const int D = mp.cheb_deg, R = mp.rows, nslot = mp.nslot;
-  const int P2pad = pow2_at_least(P2);
+  const int P2pad = pow2_at_least(P2), lg_pad = __builtin_ctz(P2pad);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & (kWave - 1);
   const float inv_kc = 1.0f / (float)Kc, inv_m = 1.0f / (float)M;
 
@@ -905,7 +908,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
                                                   bcell, xslot, mp.xcap, xq, wpart, mp.bparts, s_c, s_jb, s_n);
       const int items = ((cnt * P2pad + kWave - 1) / kWave) * kWave;
       for (int it = tid; it < items; it += nt) {
-        const int e = it / P2pad, sy = it % P2pad;
+        const int e = it >> lg_pad, sy = it & (P2pad - 1);
         const bool has = e < cnt, act = has && sy < P2;
         bool in = false;
         int j = 0, sx = 0, row = 0, bz = 0, cy = 0;
@@ -941,7 +944,7 @@ recip_bwd_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__
               wy = o[4];
               dwy = o[5];
             }
-            row = mod_pos(cy - p + 1 + sy, M) - r0;
+            row = wrap_once(cy - p + 1 + sy, M) - r0;
             in = (unsigned)row < (unsigned)nr;
             if (!in) {
               row = 0;
