@@ -208,7 +208,10 @@ int enuf_dpd_forces(enuf_dpd *dpd, double *pos, const double *vel, double *force
 
 /* Advance nsteps steps in place.  On entry force holds the force of the last
  * step (from enuf_dpd_forces or a previous run); step s uses the random
- * numbers of step s, s = first_step .. first_step + nsteps - 1. */
+ * numbers of step s, s = first_step .. first_step + nsteps - 1.  Within a
+ * run, each step's closing kernel also starts the next step (one launch), and
+ * all but the last step are replayed from graphs (enuf_dpd_set_graphs); the
+ * ENUF energies are reduced on the last step only.  Enqueue-only. */
 int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_t first_step,
                  int nsteps);
 
