@@ -197,7 +197,7 @@ inline double combine_fscale(const ComputeConfig &cfg) {
 hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const double *pos,
                        const double *q, hipStream_t st, KernelTimer *tm);
 hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                       KernelTimer *tm, int *pre_zero = nullptr, int npre = 0);
+                       KernelTimer *tm);
 hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
                         KernelTimer *tm);
 hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,

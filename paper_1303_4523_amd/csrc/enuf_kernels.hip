@@ -360,14 +360,10 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
   }
 }
 
-// pre_zero: counts of an earlier kernel's cells, cleared first (their reader
-// finished before this kernel).
 __global__ void __launch_bounds__(kRealThreads)
 k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
        const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
-       DevScalars *sc, unsigned long long *freal, unsigned long long *ereal, int *pre_zero, int npre) {
-  if (pre_zero)
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < npre; c += gridDim.x * blockDim.x) pre_zero[c] = 0;
+       DevScalars *sc, unsigned long long *freal, unsigned long long *ereal) {
   real_body(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
             to_g(ereal), blockIdx.x, gridDim.x);
 }
@@ -1341,13 +1337,13 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
 }
 
 hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                       KernelTimer *tm, int *pre_zero, int npre) {
+                       KernelTimer *tm) {
   int64_t g = (nq_max + 3) / 4;
   const int grid_real = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(kRealThreads), 0, st, (const double4 *)b.xq,
                      (const int *)b.ccnt, (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L,
-                     cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal, pre_zero, npre);
+                     cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal);
   if (tm) tm->after(4, st);
   return hipGetLastError();
 }

@@ -720,7 +720,7 @@ std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t 
           3 * n * sizeof(double),                                    // v0
           3 * n * sizeof(double),                                    // fdpd
           5 * sizeof(double),                                        // e5
-          nc3 * sizeof(int),                                         // dcnt
+          2 * nc3 * sizeof(int),                                     // dcnt (two sets)
           nc3 * (size_t)cap * sizeof(double4),                       // cpos
           nc3 * (size_t)cap * sizeof(double4),                       // cvel
           (n + 1) * sizeof(int),                                     // bond_start
@@ -743,7 +743,7 @@ struct enuf_dpd {
   double *v0 = nullptr;       // [N * 3] predicted velocities
   double *fdpd = nullptr;     // [N * 3] pair + bond forces
   double *e5 = nullptr;       // [5]
-  int *dcnt = nullptr;        // [ncell^3]
+  int *dcnt = nullptr;        // [2 ncell^3] two sets, like the plan's bin counts
   double4 *cpos = nullptr;    // [ncell^3 * cap] (x, y, z, index) per cell slot
   double4 *cvel = nullptr;    // [ncell^3 * cap] predicted velocity per cell slot
   int *bond_start = nullptr;  // [N + 1]
@@ -891,7 +891,7 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
       hipMemcpy(d->bond_start, deg.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d->bond_to, to.data(), to.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(d->dcnt, 0, nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
+      hipMemset(d->dcnt, 0, 2 * nc3 * sizeof(int)) != hipSuccess || hipMemset(d->e5, 0, 5 * sizeof(double)) != hipSuccess ||
 
       hipMemset(d->status, 0, sizeof(int)) != hipSuccess || hipMemset(d->species, 0, n * sizeof(int)) != hipSuccess ||
       hipStreamSynchronize(nullptr) != hipSuccess) {
@@ -965,13 +965,6 @@ int enuf_dpd_set_stream(enuf_dpd *d, void *hip_stream) {
   return ENUF_OK;
 }
 
-// One force evaluation (mode 1) or step (mode 0).  With a plan the mesh
-// passes (the longest chain) are enqueued first on the integrator's stream;
-// the pair forces and then the real-space term run on one forked stream
-// beside them (a second forked stream costs more in cross-stream waits than
-// it gains); the combine kernel joins the two.
-// energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
-// reports the last one; steps inside a run other than its last skip it).
 // The plan's buffers with the real-space and mesh bin counts of set `par`
 // (a DPD step bins into one set while the combine clears the other).
 static ComputeBuffers plan_buffers_set(const enuf_plan *pl, int par) {
@@ -980,6 +973,12 @@ static ComputeBuffers plan_buffers_set(const enuf_plan *pl, int par) {
   b.ccnt += (size_t)par * nc * nc * nc;
   b.xcnt += (size_t)par * pl->cfg.mesh.M * kXSub;
   return b;
+}
+
+// The DPD cell counts of set `par` (with a plan; without one the post kernel
+// clears the only set before the next step bins).
+static int *dpd_counts_set(const enuf_dpd *d, int par) {
+  return d->plan ? d->dcnt + (size_t)par * d->P.ncell * d->P.ncell * d->P.ncell : d->dcnt;
 }
 
 static DpdCharges dpd_charges_set(const enuf_dpd *d, int par) {
@@ -1019,11 +1018,12 @@ static hipError_t capture_tail(hipStream_t st, hipGraphNode_t *node, size_t *cou
 // With a plan, the mesh passes (the longest chain) are enqueued first on the
 // integrator's stream; the pair forces and then the real-space term run on
 // one forked stream beside them (a second forked stream costs more in
-// cross-stream waits than it gains); the combine kernel joins the two.  The
-// real-space kernel clears the DPD cell counts (the pair kernel has read
-// them), its last block the real-space cell counts, and the last block of the
-// backward pass the mesh x-bin counts, so that the fused combine can bin the
-// next step at once.
+// cross-stream waits than it gains); the combine kernel joins the two.  All
+// cell and bin counts come in two sets, step k using set k mod 2, so that the
+// fused combine can clear step k's set while it bins step k + 1 into the
+// other.
+// energies: reduce the ENUF energies of this evaluation (enuf_dpd_energy
+// reports the last one; steps inside a run other than its last skip it).
 static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *force, uint64_t step,
                     bool energies, bool pre, bool next, hipStream_t graph_st = nullptr) {
   const int64_t N = d->N;
@@ -1034,18 +1034,19 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
   // the real-space and mesh bin counts of step k are set k mod 2
   const int par = (int)(step & 1);
   const DpdCharges ch = dpd_charges_set(d, par), ch_next = dpd_charges_set(d, par ^ 1);
+  int *dcnt = dpd_counts_set(d, par), *dcnt_next = dpd_counts_set(d, par ^ 1);
   hipError_t e = hipSuccess;
   if (pre)
-    e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch, st, tm);
+    e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, dcnt, d->cpos, d->cvel, d->status, ch, st, tm);
   if (!d->plan) {
     if (e == hipSuccess)
-      e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+      e = launch_dpd_pair(N, d->P, step, pos, d->v0, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, st, tm, step_dev);
-    if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, d->dcnt, st, tm);
+    if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, dcnt, st, tm);
     if (graph && e == hipSuccess) e = launch_add_u64(d->step_ctr, st);
     if (next && e == hipSuccess)
-      e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch_next, st,
-                         tm);
+      e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
+                         st, tm);
   } else {
     enuf_plan *pl = d->plan;
     const ComputeBuffers bk = plan_buffers_set(pl, par);
@@ -1067,10 +1068,10 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
     if (graph && fork && e == hipSuccess)
       e = hipStreamUpdateCaptureDependencies(st, &n_pre, c_pre, hipStreamSetCaptureDependencies);
     if (e == hipSuccess)
-      e = launch_dpd_pair(N, d->P, step, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+      e = launch_dpd_pair(N, d->P, step, pos, d->v0, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, s1, tm, step_dev);
     const int ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
-    if (e == hipSuccess) e = launch_real(pl->cfg, bk, d->nq, s1, tm, d->dcnt, ndcell3);
+    if (e == hipSuccess) e = launch_real(pl->cfg, bk, d->nq, s1, tm);
     if (events && e == hipSuccess) e = hipEventRecord(d->join_ev, s1);
     if (events && e == hipSuccess) e = hipStreamWaitEvent(st, d->join_ev, 0);
     // the combine kernel depends on the mesh passes and the real-space term
@@ -1083,17 +1084,17 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
       fa.dt = d->P.dt;
       fa.fdpd = d->fdpd;
       fa.vel = vel;
-      fa.dcnt = nullptr;  // cleared by the real-space kernel
+      fa.dcnt = dcnt;  // this step's set, cleared while the next is filled
       fa.ndcell3 = ndcell3;
       fa.energies = energies ? 1 : 0;
       fa.step_inc = graph ? d->step_ctr : nullptr;
       if (next && !energies)
-        e = launch_combine_pre(pl->cfg, bk, force, fa, d->P, pos, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
+        e = launch_combine_pre(pl->cfg, bk, force, fa, d->P, pos, d->v0, dcnt_next, d->cpos, d->cvel, d->status,
                                ch_next, st, tm);
       else {
         e = launch_combine(pl->cfg, bk, force, nullptr, d->e5, fa, st, tm);
         if (next && e == hipSuccess)
-          e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status, ch_next,
+          e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
                              st, tm);
       }
     }
@@ -1186,7 +1187,8 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
   // the first step's pre kernel; each later one runs fused into the combine
   // kernel of the step before
   KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
-  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, d->dcnt, d->cpos, d->cvel, d->status,
+  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, dpd_counts_set(d, (int)(first_step & 1)),
+                               d->cpos, d->cvel, d->status,
                                dpd_charges_set(d, (int)(first_step & 1)), d->stream, tm),
                 ENUF_EDEVICE);
   int s = 0;
