@@ -583,9 +583,9 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
 // The combine kernel of step k (forces, closing half kick, energy partials)
 // and the pre kernel of step k + 1 (predictor, half kick, drift, binning) in
 // one launch: thread i finishes particle i's step and starts its next one.
-// The real-space and mesh bin counts come in two sets: the combine part
-// clears step k's set (b) while the pre part bins into step k + 1's (ch); the
-// DPD cell counts were cleared by the real-space kernel.
+// The real-space and mesh bin counts and the DPD cell counts come in two sets:
+// the combine part clears step k's sets (b, fa.dcnt) while the pre part bins
+// into step k + 1's (ch, dcnt).
 __global__ void __launch_bounds__(kPrepThreads)
 k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
               const unsigned long long *__restrict__ freal, const double4 *__restrict__ part, int P2S,
