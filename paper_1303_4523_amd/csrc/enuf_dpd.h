@@ -98,7 +98,8 @@ hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const d
                            const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
                            const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
                            KernelTimer *tm = nullptr, const unsigned long long *step_dev = nullptr);
-// The combine kernel of a DPD step fused with the next step's pre kernel.
+// The combine kernel of a DPD step fused with the next step's pre kernel
+// (no energy reduction: fa.energies must be 0, else hipErrorInvalidValue).
 hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
                               const FinishArgs &fa, const DpdParams &P, double *pos, double *v0, int *dcnt,
                               double4 *cpos, double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,

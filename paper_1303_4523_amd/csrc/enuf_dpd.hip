@@ -580,13 +580,19 @@ k_dpd_post(int64_t N, int mode, DpdParams P, const double *__restrict__ fdpd,
   }
 }
 
-// The combine kernel of step k (forces, closing half kick, energy partials)
-// and the pre kernel of step k + 1 (predictor, half kick, drift, binning) in
-// one launch: thread i finishes particle i's step and starts its next one.
-// The real-space and mesh bin counts and the DPD cell counts come in two sets:
-// the combine part clears step k's sets (b, fa.dcnt) while the pre part bins
-// into step k + 1's (ch, dcnt).
-__global__ void __launch_bounds__(kPrepThreads)
+// The combine kernel of step k (forces, closing half kick) and the pre kernel
+// of step k + 1 (predictor, half kick, drift, binning) in one launch: thread i
+// finishes particle i's step and starts its next one.  No energy partials
+// (steps inside a run skip them).  The real-space and mesh bin counts and the
+// DPD cell counts come in two sets: the combine part clears step k's sets (b,
+// fa.dcnt) while the pre part bins into step k + 1's (ch, dcnt).
+// One wavefront per block: the kernel is a chain of dependent loads, stores
+// and slot atomics per particle, and 4x more blocks spread it over 4x more
+// CUs' memory pipelines (about 1 us less per step at N = 24000 than blocks of
+// 256 threads).
+constexpr int kCombinePreThreads = 64;
+
+__global__ void __launch_bounds__(kCombinePreThreads)
 k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ xq,
               const unsigned long long *__restrict__ freal, const double4 *__restrict__ part, int P2S,
               double fscale, int nblk, double *blk_eg, const unsigned long long *__restrict__ ereal,
@@ -603,11 +609,14 @@ hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b,
                               const FinishArgs &fa, const DpdParams &P, double *pos, double *v0, int *dcnt,
                               double4 *cpos, double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,
                               KernelTimer *tm) {
+  // the per-block energy partials are sized for blocks of kPrepThreads
+  if (fa.energies) return hipErrorInvalidValue;
   const double fscale = combine_fscale(cfg);
+  const int nb = (int)((cfg.N + kCombinePreThreads - 1) / kCombinePreThreads);
   if (tm) tm->before(9, st);
-  hipLaunchKernelGGL(k_combine_pre, dim3(cfg.nblk), dim3(kPrepThreads), 0, st, cfg.N, (const int *)b.slot,
+  hipLaunchKernelGGL(k_combine_pre, dim3(nb), dim3(kCombinePreThreads), 0, st, cfg.N, (const int *)b.slot,
                      (const double4 *)b.xq, (const unsigned long long *)b.freal, (const double4 *)b.part,
-                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, cfg.nblk, b.blk_eg,
+                     2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, nb, b.blk_eg,
                      (const unsigned long long *)b.ereal, b.blk_er, b.ccnt,
                      cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell, b.xcnt, cfg.mesh.M, fa, forces, P, pos,
                      v0, dcnt, cpos, cvel, status, ch);
