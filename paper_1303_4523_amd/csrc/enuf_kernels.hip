@@ -183,17 +183,22 @@ __device__ inline bool real_pair(double r, double a, double lam, double *u, doub
   if (lam > 0.0 && r < 0.5 * lam) {
     const double x = r / lam, y = 2.0 * x, z = a * r, z2 = z * z;
     double b2 = 4.0 / 3.0, term = 4.0 / 3.0, b1 = 1.0 + 2.0 * x + b2 * x * x;
+    // the series stay rolled: this branch is rare (r < lambda / 2), and
+    // unrolled it set the register count of the whole real-space kernel
+#pragma unroll 1
     for (int n = 4; n < 30; ++n) {
       term *= y / n;
       b2 += term;
       b1 += term * x * x;
     }
     double t0 = 1.0, g0 = 1.0;
+#pragma unroll 1
     for (int n = 1; n < 20; ++n) {
       t0 *= 2.0 * z2 / (2.0 * n + 1.0);
       g0 += t0;
     }
     double t1 = 2.0 / 3.0, g1 = 0.0;
+#pragma unroll 1
     for (int n = 1; n < 20; ++n) {
       g1 += t1;
       t1 *= 2.0 * z2 / (2.0 * n + 3.0);
@@ -234,7 +239,7 @@ __device__ inline bool cell_offset_valid(int o, int n) {
 // force) and the energy of the pairs with k > j, as exact int64 fixed point;
 // the energies go to j's own slot (no shared accumulator).
 constexpr int kRealThreads = 256;
-constexpr int kRealQueue = 128;  // queued pairs per wavefront (flushed at > 64)
+constexpr int kRealQueue = 192;  // queued pairs per wavefront (flushed at > 64; 2 x 64 appends per pass)
 
 __device__ __forceinline__ void real_flush(int qn, const double *qx, const double *qy, const double *qz,
                                            const double *qc, const int *qk, int j, double qj, double alpha,
@@ -301,19 +306,14 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
     }
     const size_t cbase = (size_t)(c < 0 ? 0 : c) * cp.cap;
     int qn = 0;  // wavefront-uniform queue length
-    while (true) {
-      const bool live = s < cnt;
-      if (__ballot(live) == 0ull) break;
+    // test one candidate per lane and append the pairs within r_cut to the queue
+    auto test = [&](bool live, int k, const double4 &cj) {
       bool take = false;
-      int k = 0;
-      double dx = 0.0, dy = 0.0, dz = 0.0, qo = 0.0;
+      double dx = 0.0, dy = 0.0, dz = 0.0;
       if (live) {
-        k = cidx[cbase + s];
-        const double4 cj = gload(cgrid + cbase + s);
         dx = ci.x - cj.x;
         dy = ci.y - cj.y;
         dz = ci.z - cj.z;
-        qo = cj.w;
         dx -= L * rint(dx * invL);
         dy -= L * rint(dy * invL);
         dz -= L * rint(dz * invL);
@@ -325,12 +325,31 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
         qx[at] = dx;
         qy[at] = dy;
         qz[at] = dz;
-        qc[at] = qo;
+        qc[at] = cj.w;
         qk[at] = k;
       }
-      s += 2;
       qn += (int)__popcll(m);
-      if (qn > kRealQueue - kWave) {
+    };
+    // two candidates per lane and pass (slots s and s + 2 of the lane's cell),
+    // both loads issued before either is tested; the sums are fixed point, so
+    // the queue order does not change the result
+    while (true) {
+      const bool live0 = s < cnt, live1 = s + 2 < cnt;
+      if (__ballot(live0) == 0ull) break;
+      int k0 = 0, k1 = 0;
+      double4 c0 = make_double4(0.0, 0.0, 0.0, 0.0), c1 = c0;
+      if (live0) {
+        k0 = cidx[cbase + s];
+        c0 = gload(cgrid + cbase + s);
+      }
+      if (live1) {
+        k1 = cidx[cbase + s + 2];
+        c1 = gload(cgrid + cbase + s + 2);
+      }
+      test(live0, k0, c0);
+      test(live1, k1, c1);
+      s += 4;
+      if (qn > kRealQueue - 2 * kWave) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
