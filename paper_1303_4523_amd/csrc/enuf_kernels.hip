@@ -239,7 +239,6 @@ __device__ inline bool cell_offset_valid(int o, int n) {
 // force) and the energy of the pairs with k > j, as exact int64 fixed point;
 // the energies go to j's own slot (no shared accumulator).
 constexpr int kRealThreads = 256;
-constexpr int kRealQueue = 192;  // queued pairs per wavefront (flushed at > 64; 2 x 64 appends per pass)
 
 __device__ __forceinline__ void real_flush(int qn, const double *qx, const double *qy, const double *qz,
                                            const double *qc, const int *qk, int j, double qj, double alpha,
@@ -269,15 +268,20 @@ __device__ __forceinline__ void real_flush(int qn, const double *qx, const doubl
   }
 }
 
+// U: candidates per lane and pass (slots s, s + 2, ..., s + 2 (U - 1) of the
+// lane's cell), all U loads issued before any is tested.  The queue takes
+// U x 64 appends per pass and is flushed at > 64 entries.
+template <int U>
 __device__ __forceinline__ void
 real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt,
           gptr<const double4> __restrict__ cgrid, gptr<const int> __restrict__ cidx, const CellParams &cp,
           double L, double alpha, double rc2, double lam, gptr<DevScalars> sc, gptr<unsigned long long> freal,
           gptr<unsigned long long> ereal, int bid, int nbid) {
-  __shared__ double s_qx[kRealThreads / kWave][kRealQueue], s_qy[kRealThreads / kWave][kRealQueue],
-      s_qz[kRealThreads / kWave][kRealQueue];
-  __shared__ double s_qc[kRealThreads / kWave][kRealQueue];
-  __shared__ int s_qk[kRealThreads / kWave][kRealQueue];
+  constexpr int kQueue = (U + 1) * kWave;  // queued pairs per wavefront
+  __shared__ double s_qx[kRealThreads / kWave][kQueue], s_qy[kRealThreads / kWave][kQueue],
+      s_qz[kRealThreads / kWave][kQueue];
+  __shared__ double s_qc[kRealThreads / kWave][kQueue];
+  __shared__ int s_qk[kRealThreads / kWave][kQueue];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
   double *qx = s_qx[w], *qy = s_qy[w], *qz = s_qz[w];
@@ -330,26 +334,29 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
       }
       qn += (int)__popcll(m);
     };
-    // two candidates per lane and pass (slots s and s + 2 of the lane's cell),
-    // both loads issued before either is tested; the sums are fixed point, so
-    // the queue order does not change the result
+    // the sums are fixed point, so the queue order does not change the result
     while (true) {
-      const bool live0 = s < cnt, live1 = s + 2 < cnt;
-      if (__ballot(live0) == 0ull) break;
-      int k0 = 0, k1 = 0;
-      double4 c0 = make_double4(0.0, 0.0, 0.0, 0.0), c1 = c0;
-      if (live0) {
-        k0 = cidx[cbase + s];
-        c0 = gload(cgrid + cbase + s);
+      bool live[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) live[u] = s + 2 * u < cnt;
+      if (__ballot(live[0]) == 0ull) break;
+      int kk[U];
+      double4 cc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        kk[u] = 0;
+        cc[u] = make_double4(0.0, 0.0, 0.0, 0.0);
       }
-      if (live1) {
-        k1 = cidx[cbase + s + 2];
-        c1 = gload(cgrid + cbase + s + 2);
-      }
-      test(live0, k0, c0);
-      test(live1, k1, c1);
-      s += 4;
-      if (qn > kRealQueue - 2 * kWave) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (live[u]) {
+          kk[u] = cidx[cbase + s + 2 * u];
+          cc[u] = gload(cgrid + cbase + s + 2 * u);
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u) test(live[u], kk[u], cc[u]);
+      s += 2 * U;
+      if (qn > kQueue - U * kWave) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -379,12 +386,14 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
   }
 }
 
+// one system: two candidates per lane and pass at the kernel's natural
+// 168 VGPRs (3 waves per SIMD)
 __global__ void __launch_bounds__(kRealThreads)
 k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
        const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
        DevScalars *sc, unsigned long long *freal, unsigned long long *ereal) {
-  real_body(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
-            to_g(ereal), blockIdx.x, gridDim.x);
+  real_body<2>(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
+               to_g(ereal), blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,13 +1126,16 @@ k_combine(int64_t N, const int *__restrict__ slot, const double4 *__restrict__ x
 // Batched kernels: one launch covers every member of a batch; block b works
 // on block map[b].y of member map[b].x with that member's geometry and buffers.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kRealThreads)
+// batches (dense members, many passes per charge): four candidates per lane
+// and pass, held to 3 waves per SIMD (4.2 % less batch step time than two
+// candidates; one system alone ran 0.6 us slower with four)
+__global__ void __launch_bounds__(kRealThreads, 3)
 kb_real(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  real_body(to_g(m.buf.xq), to_g(m.buf.ccnt), to_g(m.buf.cgrid), to_g(m.buf.cidx), m.cfg.cells, m.cfg.L,
-            m.cfg.alpha, m.cfg.r_cut * m.cfg.r_cut, m.cfg.lambda, to_g(m.buf.sc), to_g(m.buf.freal),
-            to_g(m.buf.ereal), w.y, m.real_blocks);
+  real_body<4>(to_g(m.buf.xq), to_g(m.buf.ccnt), to_g(m.buf.cgrid), to_g(m.buf.cidx), m.cfg.cells, m.cfg.L,
+               m.cfg.alpha, m.cfg.r_cut * m.cfg.r_cut, m.cfg.lambda, to_g(m.buf.sc), to_g(m.buf.freal),
+               to_g(m.buf.ereal), w.y, m.real_blocks);
 }
 
 template <typename T> struct MemberTables;
