@@ -77,6 +77,46 @@ def test_batch_equals_each_system_alone(use_graph, concurrent):
         d.close()
 
 
+def _dense_member_system():
+    """A densely charged DPD system: one fully charged chain, its counterions
+    and 1:1 salt at 1.2 cations per unit volume (about 2.5 charges per unit
+    volume, some 280 real-space pairs per charge within r_cut = 3)."""
+    import math
+    L = 10.5
+    seed = wl.BASE_SEED + 77
+    s = wl.polyelectrolyte(L, 3.0, 50, 1.0, 1.2, 1, seed)
+    M = wl.mesh_size(3.2 * L)
+    s.meta["enuf"] = wl.enuf_params(L, M=M, Kc=min(int(math.floor(0.8 * L)), M // 4))
+    s.meta["dpd"] = dict(wl.DPD_DEFAULTS, L=L, seed=seed)
+    s.meta["name"] = f"dense salt L={L} N={s.N}"
+    return s
+
+
+def test_dense_member_equals_alone():
+    """With a densely charged member the real-space kernels flush their pair
+    queues within a charge's scan (the batched kernel tests four candidates
+    per lane and pass, the single-system one two): every member of the batch
+    is still bitwise the state it gets alone."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = [_dense_member_system()] + _replicas([3])
+    print("case: dense batch", [r.meta["name"] for r in reps], flush=True)
+    b = Batch("mixed", device=0)
+    members = []
+    for s in reps:
+        d, pos, vel, F = _member(s)
+        b.add(d, pos, vel, F, first_step=1)
+        members.append((d, pos, vel, F))
+    b.run(3)
+    torch.cuda.synchronize()
+    for s, (d, pos, vel, F) in zip(reps, members):
+        got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy())
+        assert d.status() == 0
+        assert _same(got, _alone(s, 3)), s.meta["name"]
+    b.close()
+    for d, *_ in members:
+        d.close()
+
+
 def test_graph_replays_match_eager_steps():
     """Each replay of the captured step, with host reads and synchronisation
     between replays, equals the eager launch sequence."""
