@@ -203,7 +203,12 @@ constexpr int kPairZ = kSegTarget + 2;   // staged z-slices at most
 constexpr int kPairCells = 9 * kPairZ;   // staged cells at most
 static_assert(kPairCells <= kPairThreads, "the prefix sum takes one staged cell per thread");
 static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
-constexpr int kPairU = 4;         // candidate steps in flight per lane
+// candidate steps in flight per lane: 8 for one system (150 VGPRs, 3 waves
+// per SIMD; 4.5 % less step time than 4 at N = 24000, where the kernel runs
+// beside the mesh passes), 4 in batches (128 VGPRs, 4 waves per SIMD; 8 %
+// less batch step time than 8, the batch filling the chip)
+constexpr int kPairU = 8;
+constexpr int kPairUBatch = 4;
 constexpr int kPairPer = (kPairStage + kPairThreads - 1) / kPairThreads;  // staged particles copied per thread
 constexpr float kPairMargin = 1.0e-3f;
 
@@ -223,7 +228,7 @@ struct PairShared {
 
 // Scan and evaluation over the own z-cells [zs, ze) of a chunk.  STAGED:
 // candidates are staged indices (virtual index - base); otherwise grid slots.
-template <bool STAGED>
+template <int U, bool STAGED>
 __device__ __forceinline__ void
 dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict__ cpos,
                gptr<const double4> __restrict__ cvel, PairShared &sh, const double4 *s_pos,
@@ -319,15 +324,15 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
       double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
       if (STAGED) ri = s_rel[iref];
       else pi = gload(cpos + iref);
-      for (;; t += kPairU * m) {
+      for (;; t += U * m) {
         if (__ballot(act && t < T) == 0ull) break;
-        int jref[kPairU];
-        float4 rj[kPairU];
-        double4 pj[kPairU];
+        int jref[U];
+        float4 rj[U];
+        double4 pj[U];
         // every lane loads (an in-range index when its step is past the
         // end), so that the loads of all steps are in flight together
 #pragma unroll
-        for (int u = 0; u < kPairU; ++u) {
+        for (int u = 0; u < U; ++u) {
           const int tu = t + u * m;
           const bool ok = act && tu < T;
           if (STAGED) {
@@ -339,7 +344,7 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
           }
         }
 #pragma unroll
-        for (int u = 0; u < kPairU; ++u) {
+        for (int u = 0; u < U; ++u) {
           bool take;
           if (STAGED) {
             const float dx = ri.x - rj[u].x, dy = ri.y - rj[u].y, dz = ri.z - rj[u].z;
@@ -371,6 +376,7 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
   if (qn > 0) evaluate(qn);
 }
 
+template <int U>
 __device__ __forceinline__ void
 dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
               gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
@@ -500,9 +506,9 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
     if (threadIdx.x == 0) sh.next = 0;
     __syncthreads();
     if (staged)
-      dpd_pair_cells<true>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+      dpd_pair_cells<U, true>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
     else
-      dpd_pair_cells<false>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+      dpd_pair_cells<U, false>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
     __syncthreads();
     // bonds, F_i = -K (r - r0) rhat_ij, and the force of each own particle
     for (int t = threadIdx.x; t < nown; t += kPairThreads) {
@@ -542,8 +548,8 @@ __global__ void __launch_bounds__(kPairThreads)
 k_dpd_pair(DpdParams P, uint64_t step, const unsigned long long *step_dev, const double *__restrict__ pos,
            const int *__restrict__ dcnt, const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to, double *__restrict__ fdpd) {
-  dpd_pair_body(P, step_dev ? (uint64_t)*step_dev : step, to_g(pos), to_g(dcnt), to_g(cpos), to_g(cvel),
-                to_g(bond_start), to_g(bond_to), to_g(fdpd), blockIdx.x, gridDim.x);
+  dpd_pair_body<kPairU>(P, step_dev ? (uint64_t)*step_dev : step, to_g(pos), to_g(dcnt), to_g(cpos),
+                        to_g(cvel), to_g(bond_start), to_g(bond_to), to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
 void pair_segments(int n, int *seg_cells, int *nseg) {
@@ -638,8 +644,8 @@ __global__ void __launch_bounds__(kPairThreads)
 kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pair_body(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel), to_g(m.bond_start),
-                to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
+  dpd_pair_body<kPairUBatch>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
+                             to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
