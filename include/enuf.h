@@ -210,10 +210,20 @@ int enuf_dpd_forces(enuf_dpd *dpd, double *pos, const double *vel, double *force
  * step (from enuf_dpd_forces or a previous run); step s uses the random
  * numbers of step s, s = first_step .. first_step + nsteps - 1.  Within a
  * run, each step's closing kernel also starts the next step (one launch), and
- * all but the last step are replayed from graphs (enuf_dpd_set_graphs); the
- * ENUF energies are reduced on the last step only.  Enqueue-only. */
+ * all but the last step are replayed from graphs of 8 and of 2 steps
+ * (enuf_dpd_set_graphs; at most one of them is launched eagerly); the ENUF
+ * energies are reduced on the last step only.  Enqueue-only, except that a
+ * graph missing for these buffers is first captured, which synchronises the
+ * integrator's stream (enuf_dpd_prepare_graphs captures them ahead). */
 int enuf_dpd_run(enuf_dpd *dpd, double *pos, double *vel, double *force, uint64_t first_step,
                  int nsteps);
+
+/* Capture, for these state buffers, every graph enuf_dpd_run replays (8- and
+ * 2-step graphs, for runs starting on even and on odd steps), so that later
+ * runs on these buffers launch without capturing.  Launches no step.
+ * Synchronises the integrator's stream.  ENUF_OK without doing anything when
+ * graphs are disabled; ENUF_EDEVICE if capture fails. */
+int enuf_dpd_prepare_graphs(enuf_dpd *dpd, double *pos, double *vel, double *force);
 
 /* Species-dependent conservative amplitudes (eq. 3; Sec. 2 sets
  * a_ij = a_ii + 2.05 chi_ij between species).
@@ -234,7 +244,7 @@ int enuf_dpd_set_species(enuf_dpd *dpd, int nspecies, const int *species, const 
 int enuf_dpd_set_concurrency(enuf_dpd *dpd, int enable);
 
 /* Launch the steps of enuf_dpd_run (all but its last) as HIP graphs of 8
- * steps (enable = 1, the default), captured on the first run with given
+ * and 2 steps (enable = 1, the default), captured on the first run with given
  * pos / vel / force buffers and captured again when they or the parameters
  * change; the fork and join of the concurrent schedule are graph edges.  With
  * 0, or while a kernel is being timed, every step is launched eagerly.
@@ -339,6 +349,18 @@ size_t enuf_batch_footprint_bytes(const enuf_batch *batch);
 /* kernel = ENUF_K_* to start timing it (resets the totals), -1 to stop. */
 int enuf_dpd_time_kernel(enuf_dpd *dpd, int kernel, int max_launches);
 int enuf_dpd_kernel_time(enuf_dpd *dpd, double *total_ms, int *launches);
+
+/* The same for the kernels of enuf_compute / enuf_compute_components on a
+ * plan (ENUF_K_PREP_COUNT ... ENUF_K_COMBINE). */
+int enuf_plan_time_kernel(enuf_plan *plan, int kernel, int max_launches);
+int enuf_plan_kernel_time(enuf_plan *plan, double *total_ms, int *launches);
+
+/* The same for one stage of a batch's step (ENUF_K_DPD_PRE, _DPD_PAIR, _REAL,
+ * _MESH_FWD, _MESH_X, _MESH_BWD, _COMBINE; each is one launch for all members).
+ * While timing is on, enuf_batch_run launches every step eagerly on one
+ * stream, without its graph. */
+int enuf_batch_time_kernel(enuf_batch *batch, int kernel, int max_launches);
+int enuf_batch_kernel_time(enuf_batch *batch, double *total_ms, int *launches);
 
 /* ------------------------------------------------------------------------
  * Structure observables, sampled on the device between steps (enqueued on

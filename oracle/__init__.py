@@ -68,6 +68,8 @@ def _load():
     lib.oracle_chain_rg2.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_self.argtypes = [i64, ip, d]
     lib.oracle_self.restype = d
     lib.oracle_philox4x64_10.argtypes = [ip, ip, ip]
@@ -147,6 +149,12 @@ def recip_direct(pos, q, L, alpha, Kc, sel=None):
 def num_threads():
     """OpenMP threads used by the oracle's parallel loops."""
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's parallel loops started from the calling
+    thread from now on."""
+    _load().oracle_set_threads(int(n))
 
 
 def self_energy(q, alpha):

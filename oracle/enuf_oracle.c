@@ -383,6 +383,10 @@ int oracle_recip(int64_t n, const double *pos, const double *q, double L,
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
 
+/* Threads of the parallel loops that the calling host thread starts from now
+ * on (n >= 1; timing of the oracle on one core or on all of them). */
+void oracle_set_threads(int n) { if (n >= 1) omp_set_num_threads(n); }
+
 /* Self term of eq. 16: -(alpha/sqrt(pi)) sum_j q_j^2. */
 double oracle_self(int64_t n, const double *q, double alpha)
 {

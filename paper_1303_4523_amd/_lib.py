@@ -57,6 +57,8 @@ lib.enuf_dpd_forces.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
 lib.enuf_dpd_forces.restype = _int
 lib.enuf_dpd_run.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64, _int]
 lib.enuf_dpd_run.restype = _int
+lib.enuf_dpd_prepare_graphs.argtypes = [_vp, _vp, _vp, _vp]
+lib.enuf_dpd_prepare_graphs.restype = _int
 lib.enuf_dpd_set_concurrency.argtypes = [_vp, _int]
 lib.enuf_dpd_set_concurrency.restype = _int
 lib.enuf_dpd_set_graphs.argtypes = [_vp, _int]
@@ -71,6 +73,14 @@ lib.enuf_dpd_time_kernel.argtypes = [_vp, _int, _int]
 lib.enuf_dpd_time_kernel.restype = _int
 lib.enuf_dpd_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_int)]
 lib.enuf_dpd_kernel_time.restype = _int
+lib.enuf_plan_time_kernel.argtypes = [_vp, _int, _int]
+lib.enuf_plan_time_kernel.restype = _int
+lib.enuf_plan_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_int)]
+lib.enuf_plan_kernel_time.restype = _int
+lib.enuf_batch_time_kernel.argtypes = [_vp, _int, _int]
+lib.enuf_batch_time_kernel.restype = _int
+lib.enuf_batch_kernel_time.argtypes = [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_int)]
+lib.enuf_batch_kernel_time.restype = _int
 lib.enuf_dpd_footprint_bytes.argtypes = [_vp]
 lib.enuf_dpd_footprint_bytes.restype = _sz
 lib.enuf_plan_footprint_estimate.argtypes = [_i64, _dbl, _int, _int, _int, _dbl]
@@ -115,13 +125,14 @@ EXPORTED = [
     "enuf_plan_set_options", "enuf_compute", "enuf_compute_components", "enuf_plan_status",
     "enuf_plan_footprint_bytes",
     "enuf_dpd_create", "enuf_dpd_set_stream", "enuf_dpd_set_concurrency", "enuf_dpd_set_graphs",
-    "enuf_dpd_forces", "enuf_dpd_run",
+    "enuf_dpd_forces", "enuf_dpd_run", "enuf_dpd_prepare_graphs",
     "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
     "enuf_dpd_time_kernel", "enuf_dpd_kernel_time", "enuf_dpd_footprint_bytes",
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
     "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",
+    "enuf_plan_time_kernel", "enuf_plan_kernel_time", "enuf_batch_time_kernel", "enuf_batch_kernel_time",
 ]
 
 # Status codes (include/enuf.h).

@@ -58,6 +58,19 @@ class Batch:
         self._bind_stream()
         check(lib.enuf_batch_run(self._h, int(nsteps)), "enuf_batch_run")
 
+    def time_kernel(self, name, max_launches):
+        """Start event timing of one stage of the batched step (name as in
+        _lib.KERNELS); runs are then launched eagerly on one stream.  None
+        stops."""
+        k = -1 if name is None else _lib.KERNELS[name]
+        check(lib.enuf_batch_time_kernel(self._h, k, int(max_launches)), "enuf_batch_time_kernel")
+
+    def kernel_time(self):
+        """(total milliseconds, launches) of the timed stage."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+        check(lib.enuf_batch_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)), "enuf_batch_kernel_time")
+        return ms.value, n.value
+
     @property
     def footprint_bytes(self):
         return int(lib.enuf_batch_footprint_bytes(self._h))

@@ -1217,9 +1217,14 @@ hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, 
 template <typename T>
 static void launch_batch_mesh(const BatchMember *mem, int ik, const int2 *fwd, int nfwd, const int2 *x, int nx,
                               const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
-                              hipStream_t st) {
+                              hipStream_t st, KernelTimer *tm) {
+  if (tm) tm->before(5, st);
   if (nfwd > 0) hipLaunchKernelGGL(kb_recip_fwd<T>, dim3(nfwd), dim3(kPassThreads), lds_fwd, st, mem, fwd);
+  if (tm) tm->after(5, st);
+  if (tm) tm->before(6, st);
   if (nx > 0) hipLaunchKernelGGL(kb_recip_x<T>, dim3(nx), dim3(kPassThreads), lds_x, st, mem, x);
+  if (tm) tm->after(6, st);
+  if (tm) tm->before(7, st);
   if (nbwd > 0) {
     if (ik)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, true>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
@@ -1228,15 +1233,16 @@ static void launch_batch_mesh(const BatchMember *mem, int ik, const int2 *fwd, i
       hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, false>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
                          bwd);
   }
+  if (tm) tm->after(7, st);
 }
 
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
                               const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
-                              size_t lds_bwd, hipStream_t st) {
+                              size_t lds_bwd, hipStream_t st, KernelTimer *tm) {
   if (precision == 0)
-    launch_batch_mesh<double>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+    launch_batch_mesh<double>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st, tm);
   else
-    launch_batch_mesh<float>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st);
+    launch_batch_mesh<float>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st, tm);
   return hipGetLastError();
 }
 

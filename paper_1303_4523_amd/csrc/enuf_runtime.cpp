@@ -76,6 +76,56 @@ size_t arena_bytes(const size_t *sizes, int n) {
   return t;
 }
 
+// Event timing of one kernel class (ENUF_K_* ids) over at most `cap`
+// launches: a pair of events per launch, summed by total().
+struct EventTimer {
+  KernelTimer t;
+  std::vector<hipEvent_t> ev;
+  KernelTimer *active() { return t.kernel >= 0 ? &t : nullptr; }
+  void drop() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    t = KernelTimer();
+  }
+  // kernel < 0 stops timing.  False if the events cannot be created.
+  bool start(int kernel, int cap) {
+    drop();
+    if (kernel < 0) return true;
+    ev.resize(2 * (size_t)cap);
+    for (size_t k = 0; k < ev.size(); ++k) {
+      if (hipEventCreate(&ev[k]) != hipSuccess) {
+        ev.resize(k);
+        drop();
+        return false;
+      }
+    }
+    t.kernel = kernel;
+    t.cap = cap;
+    t.count = 0;
+    t.ev = ev.data();
+    return true;
+  }
+  // Milliseconds summed over the recorded launches (the stream that holds
+  // them must have been synchronised).
+  hipError_t total(double *ms, int *launches) const {
+    double sum = 0.0;
+    for (int k = 0; k < t.count; ++k) {
+      float m = 0.0f;
+      const hipError_t e = hipEventElapsedTime(&m, ev[2 * k], ev[2 * k + 1]);
+      if (e != hipSuccess) return e;
+      sum += m;
+    }
+    *ms = sum;
+    *launches = t.count;
+    return hipSuccess;
+  }
+  ~EventTimer() { drop(); }
+};
+
+bool valid_timer_args(int kernel, int max_launches) {
+  return kernel < 0 || (kernel <= ENUF_K_DPD_POST && max_launches >= 1 && max_launches <= (1 << 20));
+}
+
 }  // namespace
 
 struct enuf_plan {
@@ -92,6 +142,7 @@ struct enuf_plan {
   ComputeBuffers buf{};
   std::vector<void *> allocations;
   size_t bytes = 0;
+  EventTimer timer;  // enuf_plan_time_kernel
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
   // object), each at a 256-byte aligned offset.  False on failure.
@@ -662,7 +713,7 @@ static int compute_impl(enuf_plan *plan, const double *pos, const double *q, dou
   int dev = -1;
   HIP_OR_RETURN(hipGetDevice(&dev), ENUF_EDEVICE);
   if (dev != plan->device) HIP_OR_RETURN(hipSetDevice(plan->device), ENUF_EDEVICE);
-  hipError_t e = launch_compute(c, plan->buf, pos, q, forces, energy, energy5, plan->stream);
+  hipError_t e = launch_compute(c, plan->buf, pos, q, forces, energy, energy5, plan->stream, plan->timer.active());
   if (dev != plan->device) (void)hipSetDevice(dev);
   if (e != hipSuccess) {
     set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -692,6 +743,21 @@ int enuf_plan_status(enuf_plan *plan, int *status) {
 }
 
 size_t enuf_plan_footprint_bytes(const enuf_plan *plan) { return plan ? plan->bytes : 0; }
+
+int enuf_plan_time_kernel(enuf_plan *plan, int kernel, int max_launches) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  if (!valid_timer_args(kernel, max_launches)) { set_error("invalid kernel id or launch count"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  if (!plan->timer.start(kernel, max_launches)) { set_error("hipEventCreate failed"); return ENUF_EDEVICE; }
+  return ENUF_OK;
+}
+
+int enuf_plan_kernel_time(enuf_plan *plan, double *total_ms, int *launches) {
+  if (!plan || !total_ms || !launches) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  HIP_OR_RETURN(plan->timer.total(total_ms, launches), ENUF_EDEVICE);
+  return ENUF_OK;
+}
 
 }  // extern "C"
 
@@ -750,8 +816,7 @@ struct enuf_dpd {
   int *bond_to = nullptr;     // [2 nbonds]
   int *status = nullptr;      // [1]
   std::vector<void *> allocations;
-  KernelTimer timer;
-  std::vector<hipEvent_t> events;
+  EventTimer timer;  // enuf_dpd_time_kernel
   int *dslot = nullptr;       // [N] static compact slot of each particle (-1: neutral)
   int64_t nq = 0;
   DpdCharges charges{};
@@ -762,26 +827,31 @@ struct enuf_dpd {
   int *species = nullptr;                  // [N] species of each particle (read when P.nspec > 1)
   int batches = 0;                         // batches this integrator is a member of
   size_t bytes = 0;
-  // kGraphSteps steps of enuf_dpd_run captured in a graph (no cross-stream
-  // events: the fork and join are dependency edges), valid for the state
-  // buffers and the configuration it was captured with
-  // One graph per parity of the first replayed step (the bin-count set a
-  // step uses is its index mod 2; a graph of an even number of steps keeps it).
+  // Steps of enuf_dpd_run captured in graphs (no cross-stream events: the
+  // fork and join are dependency edges), one per graph length (kGraphLen) and
+  // per parity of the first replayed step (the bin-count set a step uses is
+  // its index mod 2; a graph of an even number of steps keeps it).  Each is
+  // valid for the state buffers and the configuration it was captured with.
+  struct GraphSlot {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *key[3] = {nullptr, nullptr, nullptr};
+    std::vector<unsigned char> cfg;  // parameters the kernels were captured with
+  };
   int use_graph = 1;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  const void *gkey[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-  std::vector<unsigned char> gcfg[2];  // parameters the kernels were captured with
+  GraphSlot gslot[2][2];  // [length index][parity]
 
-  void drop_graph(int par) {
-    if (gexec[par]) (void)hipGraphExecDestroy(gexec[par]);
-    if (graph[par]) (void)hipGraphDestroy(graph[par]);
-    gexec[par] = nullptr;
-    graph[par] = nullptr;
+  // Callers synchronise the stream first: an exec may still be queued on it.
+  void drop_graph(int len, int par) {
+    GraphSlot &g = gslot[len][par];
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
   }
   void drop_graph() {
-    drop_graph(0);
-    drop_graph(1);
+    for (int l = 0; l < 2; ++l)
+      for (int par = 0; par < 2; ++par) drop_graph(l, par);
   }
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
@@ -799,14 +869,9 @@ struct enuf_dpd {
     }
     return true;
   }
-  void drop_events() {
-    for (hipEvent_t e : events) (void)hipEventDestroy(e);
-    events.clear();
-    timer = KernelTimer();
-  }
   ~enuf_dpd() {
     drop_graph();
-    drop_events();
+    timer.drop();
     if (side) (void)hipStreamDestroy(side);
     if (join_ev) (void)hipEventDestroy(join_ev);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
@@ -991,9 +1056,12 @@ static DpdCharges dpd_charges_set(const enuf_dpd *d, int par) {
   return ch;
 }
 
-// Steps of enuf_dpd_run per graph launch.
-constexpr int kGraphSteps = 8;
-static_assert(kGraphSteps % 2 == 0, "a replayed graph keeps the parity of the bin-count set");
+// Steps per graph launch of enuf_dpd_run: long graphs for the body of a run,
+// short ones for its remainder (at most one step of the body is then
+// launched eagerly, plus the last step with its energy reduction).
+constexpr int kGraphLen[2] = {8, 2};
+static_assert(kGraphLen[0] % 2 == 0 && kGraphLen[1] % 2 == 0,
+              "a replayed graph keeps the parity of the bin-count set");
 
 // The last node captured on a capturing stream (its single dependency)
 // (*count = 0 before the first node of the capture.)
@@ -1028,7 +1096,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
                     bool energies, bool pre, bool next, hipStream_t graph_st = nullptr) {
   const int64_t N = d->N;
   const bool graph = graph_st != nullptr;
-  KernelTimer *tm = d->timer.kernel >= 0 && !graph ? &d->timer : nullptr;
+  KernelTimer *tm = graph ? nullptr : d->timer.active();
   hipStream_t st = graph ? graph_st : d->stream;
   const unsigned long long *step_dev = graph ? d->step_ctr : nullptr;
   // the real-space and mesh bin counts of step k are set k mod 2
@@ -1144,17 +1212,22 @@ static std::vector<unsigned char> dpd_graph_config(const enuf_dpd *d) {
   return v;
 }
 
-// Capture kGraphSteps steps (no energy reduction) on the integrator's side
+// Capture kGraphLen[len] steps (no energy reduction) on the integrator's side
 // stream.  False (and no graph) if capture is not available; the caller then
-// launches the steps eagerly.
-static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force, int par) {
-  d->drop_graph(par);
+// launches the steps eagerly.  Synchronises the integrator's stream first,
+// since the graph it replaces may still be queued there.
+static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force, int len, int par) {
+  if (hipStreamSynchronize(d->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  d->drop_graph(len, par);
   hipStream_t cs = d->side;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
   int rc = ENUF_OK;
   // the step index passed here only selects the bin-count set; the replayed
   // steps read their index from the device counter
-  for (int k = 0; k < kGraphSteps && rc == ENUF_OK; ++k)
+  for (int k = 0; k < kGraphLen[len] && rc == ENUF_OK; ++k)
     rc = dpd_eval(d, 0, pos, vel, force, (uint64_t)(par + k), false, false, true, cs);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(cs, &g);
@@ -1170,13 +1243,24 @@ static bool dpd_capture(enuf_dpd *d, double *pos, double *vel, double *force, in
     (void)hipGetLastError();
     return false;
   }
-  d->graph[par] = g;
-  d->gexec[par] = x;
-  d->gkey[par][0] = pos;
-  d->gkey[par][1] = vel;
-  d->gkey[par][2] = force;
-  d->gcfg[par] = dpd_graph_config(d);
+  enuf_dpd::GraphSlot &gs = d->gslot[len][par];
+  gs.graph = g;
+  gs.exec = x;
+  gs.key[0] = pos;
+  gs.key[1] = vel;
+  gs.key[2] = force;
+  gs.cfg = dpd_graph_config(d);
   return true;
+}
+
+// The graph of kGraphLen[len] steps from parity par for these buffers, captured
+// now if it is missing or stale; nullptr if capture is not available.
+static hipGraphExec_t dpd_graph(enuf_dpd *d, double *pos, double *vel, double *force, int len, int par) {
+  const enuf_dpd::GraphSlot &gs = d->gslot[len][par];
+  const bool same = gs.exec && gs.key[0] == pos && gs.key[1] == vel && gs.key[2] == force &&
+                    gs.cfg == dpd_graph_config(d);
+  if (same || dpd_capture(d, pos, vel, force, len, par)) return d->gslot[len][par].exec;
+  return nullptr;
 }
 
 int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t first_step, int nsteps) {
@@ -1184,31 +1268,52 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
   if (rc != ENUF_OK) return rc;
   if (nsteps < 0) { set_error("nsteps must be >= 0"); return ENUF_EINVAL; }
   if (nsteps == 0) return ENUF_OK;
+  const int par = (int)(first_step & 1);
+  const int body = nsteps - 1;
+  // graphs first: capturing one synchronises the stream, which must not
+  // happen between the launches of this run
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  if (d->use_graph && !d->timer.active()) {
+    if (body >= kGraphLen[0]) gx[0] = dpd_graph(d, pos, vel, force, 0, par);
+    const int rest = body - (gx[0] ? (body / kGraphLen[0]) * kGraphLen[0] : 0);
+    if (rest >= kGraphLen[1]) gx[1] = dpd_graph(d, pos, vel, force, 1, par);
+  }
   // the first step's pre kernel; each later one runs fused into the combine
   // kernel of the step before
-  KernelTimer *tm = d->timer.kernel >= 0 ? &d->timer : nullptr;
-  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, dpd_counts_set(d, (int)(first_step & 1)),
-                               d->cpos, d->cvel, d->status,
-                               dpd_charges_set(d, (int)(first_step & 1)), d->stream, tm),
+  KernelTimer *tm = d->timer.active();
+  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, dpd_counts_set(d, par),
+                               d->cpos, d->cvel, d->status, dpd_charges_set(d, par), d->stream, tm),
                 ENUF_EDEVICE);
   int s = 0;
-  // all but the last step in graphs of kGraphSteps steps (one launch each);
-  // the rest, and the last step with its energy reduction, eagerly
-  const int body = nsteps - 1;
-  if (d->use_graph && d->timer.kernel < 0 && body >= kGraphSteps) {
-    const int par = (int)(first_step & 1);
-    const bool same = d->gexec[par] && d->gkey[par][0] == pos && d->gkey[par][1] == vel &&
-                      d->gkey[par][2] == force && d->gcfg[par] == dpd_graph_config(d);
-    if (same || dpd_capture(d, pos, vel, force, par)) {
-      HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, d->stream), ENUF_EDEVICE);
-      for (; s + kGraphSteps <= body; s += kGraphSteps)
-        HIP_OR_RETURN(hipGraphLaunch(d->gexec[par], d->stream), ENUF_EDEVICE);
+  // all but the last step from graphs (long ones, then short ones; every
+  // graph holds an even number of steps, so each starts on parity par); the
+  // rest, and the last step with its energy reduction, eagerly
+  if (gx[0] || gx[1]) {
+    HIP_OR_RETURN(launch_set_u64(d->step_ctr, (unsigned long long)first_step, d->stream), ENUF_EDEVICE);
+    for (int len = 0; len < 2; ++len) {
+      if (!gx[len]) continue;
+      for (; s + kGraphLen[len] <= body; s += kGraphLen[len])
+        HIP_OR_RETURN(hipGraphLaunch(gx[len], d->stream), ENUF_EDEVICE);
     }
   }
   for (; s < nsteps; ++s) {
     rc = dpd_eval(d, 0, pos, vel, force, first_step + (uint64_t)s, s == nsteps - 1, false, s < nsteps - 1);
     if (rc != ENUF_OK) return rc;
   }
+  return ENUF_OK;
+}
+
+int enuf_dpd_prepare_graphs(enuf_dpd *d, double *pos, double *vel, double *force) {
+  int rc = dpd_check(d, pos, vel, force);
+  if (rc != ENUF_OK) return rc;
+  if (!d->use_graph) return ENUF_OK;
+  for (int len = 0; len < 2; ++len)
+    for (int par = 0; par < 2; ++par)
+      if (!dpd_graph(d, pos, vel, force, len, par)) {
+        set_error("HIP graph capture of the DPD step failed");
+        return ENUF_EDEVICE;
+      }
+  HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
   return ENUF_OK;
 }
 
@@ -1251,40 +1356,16 @@ int enuf_dpd_status(enuf_dpd *d, int *status) {
 
 int enuf_dpd_time_kernel(enuf_dpd *d, int kernel, int max_launches) {
   if (!d) { set_error("NULL integrator"); return ENUF_EINVAL; }
+  if (!valid_timer_args(kernel, max_launches)) { set_error("invalid kernel id or launch count"); return ENUF_EINVAL; }
   HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
-  d->drop_events();
-  if (kernel < 0) return ENUF_OK;
-  if (kernel > ENUF_K_DPD_POST || max_launches < 1 || max_launches > (1 << 20)) {
-    set_error("invalid kernel id or launch count");
-    return ENUF_EINVAL;
-  }
-  d->events.resize(2 * (size_t)max_launches);
-  for (size_t k = 0; k < d->events.size(); ++k) {
-    if (hipEventCreate(&d->events[k]) != hipSuccess) {
-      d->events.resize(k);
-      d->drop_events();
-      set_error("hipEventCreate failed");
-      return ENUF_EDEVICE;
-    }
-  }
-  d->timer.kernel = kernel;
-  d->timer.cap = max_launches;
-  d->timer.count = 0;
-  d->timer.ev = d->events.data();
+  if (!d->timer.start(kernel, max_launches)) { set_error("hipEventCreate failed"); return ENUF_EDEVICE; }
   return ENUF_OK;
 }
 
 int enuf_dpd_kernel_time(enuf_dpd *d, double *total_ms, int *launches) {
   if (!d || !total_ms || !launches) { set_error("NULL argument"); return ENUF_EINVAL; }
   HIP_OR_RETURN(hipStreamSynchronize(d->stream), ENUF_EDEVICE);
-  double t = 0.0;
-  for (int k = 0; k < d->timer.count; ++k) {
-    float ms = 0.0f;
-    HIP_OR_RETURN(hipEventElapsedTime(&ms, d->events[2 * k], d->events[2 * k + 1]), ENUF_EDEVICE);
-    t += ms;
-  }
-  *total_ms = t;
-  *launches = d->timer.count;
+  HIP_OR_RETURN(d->timer.total(total_ms, launches), ENUF_EDEVICE);
   return ENUF_OK;
 }
 
@@ -1352,6 +1433,7 @@ struct enuf_batch {
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  EventTimer timer;  // enuf_batch_time_kernel: eager single-stream steps while active
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1485,26 +1567,35 @@ int batch_rebuild(enuf_batch *b) {
 // One step of every member: pre on the batch stream; pair forces and real
 // space forked onto two side streams (fork = true) or kept on the batch
 // stream; the mesh passes on the batch stream; the combine joins them.
-hipError_t batch_step(enuf_batch *b, bool fork) {
+// tm (eager single-stream steps only) brackets one stage with events.
+hipError_t batch_step(enuf_batch *b, bool fork, KernelTimer *tm = nullptr) {
   const int *o = b->off;
   const int2 *mp = b->dmap;
   hipStream_t st = b->own;
   hipStream_t s0 = fork ? b->side[0] : st, s1 = fork ? b->side[1] : st;
+  if (tm) tm->before(ENUF_K_DPD_PRE, st);
   hipError_t e = launch_batch_pre(b->dmem, mp + o[0], o[1] - o[0], 0, st);
+  if (tm) tm->after(ENUF_K_DPD_PRE, st);
   if (fork) {
     if (e == hipSuccess) e = hipEventRecord(b->fork_ev, st);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
   }
+  if (tm) tm->before(ENUF_K_DPD_PAIR, s0);
   if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], s0);
+  if (tm) tm->after(ENUF_K_DPD_PAIR, s0);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[0], s0);
+  if (tm) tm->before(ENUF_K_REAL, s1);
   if (e == hipSuccess) e = launch_batch_real(b->dmem, mp + o[2], o[3] - o[2], s1);
+  if (tm) tm->after(ENUF_K_REAL, s1);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
   if (e == hipSuccess)
     e = launch_batch_recip(b->dmem, b->precision, b->ik, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4],
-                           mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st);
+                           mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st, tm);
   if (fork)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->join_ev[k], 0);
+  if (tm) tm->before(ENUF_K_COMBINE, st);
   if (e == hipSuccess) e = launch_batch_combine(b->dmem, b->nmem, mp + o[6], o[7] - o[6], 0, st);
+  if (tm) tm->after(ENUF_K_COMBINE, st);
   return e;
 }
 
@@ -1629,7 +1720,8 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
   }
   // The captured step is the single-stream schedule: no cross-stream event
   // record / wait inside a capture.
-  if (b->use_graph && !b->exec) {
+  KernelTimer *tm = b->timer.active();
+  if (b->use_graph && !b->exec && !tm) {
     HIP_OR_RETURN(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), ENUF_EDEVICE);
     const hipError_t e = batch_step(b, false);
     hipGraph_t g = nullptr;
@@ -1651,7 +1743,8 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
   HIP_OR_RETURN(hipEventRecord(b->in_ev, b->stream), ENUF_EDEVICE);
   HIP_OR_RETURN(hipStreamWaitEvent(b->own, b->in_ev, 0), ENUF_EDEVICE);
   for (int s = 0; s < nsteps; ++s) {
-    const hipError_t e = b->use_graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0);
+    const hipError_t e = tm ? batch_step(b, false, tm)
+                            : (b->use_graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0));
     if (e != hipSuccess) {
       set_error(std::string("batched step launch failed: ") + hipGetErrorString(e));
       return ENUF_EDEVICE;
@@ -1689,6 +1782,21 @@ int enuf_dpd_set_species(enuf_dpd *d, int nspecies, const int *species, const do
   for (int s = 0; s < nspecies; ++s)
     for (int t = 0; t < nspecies; ++t) P.atab[4 * s + t] = a_table[s * nspecies + t];
   P.nspec = nspecies;
+  return ENUF_OK;
+}
+
+int enuf_batch_time_kernel(enuf_batch *b, int kernel, int max_launches) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if (!valid_timer_args(kernel, max_launches)) { set_error("invalid kernel id or launch count"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  if (!b->timer.start(kernel, max_launches)) { set_error("hipEventCreate failed"); return ENUF_EDEVICE; }
+  return ENUF_OK;
+}
+
+int enuf_batch_kernel_time(enuf_batch *b, double *total_ms, int *launches) {
+  if (!b || !total_ms || !launches) { set_error("NULL argument"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  HIP_OR_RETURN(b->timer.total(total_ms, launches), ENUF_EDEVICE);
   return ENUF_OK;
 }
 

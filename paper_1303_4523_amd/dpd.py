@@ -63,12 +63,18 @@ class DPD:
         check(lib.enuf_dpd_run(self._h, *self._state(pos, vel, force), int(first_step), int(nsteps)),
               "enuf_dpd_run")
 
+    def prepare_graphs(self, pos, vel, force):
+        """Capture the step graphs run() replays for these state tensors (no
+        step is taken); later runs on them launch without capturing."""
+        self._bind_stream()
+        check(lib.enuf_dpd_prepare_graphs(self._h, *self._state(pos, vel, force)), "enuf_dpd_prepare_graphs")
+
     def set_concurrency(self, enable):
         """Overlap pair forces and real space with the mesh passes (default) or not."""
         check(lib.enuf_dpd_set_concurrency(self._h, int(bool(enable))), "enuf_dpd_set_concurrency")
 
     def set_graphs(self, enable):
-        """Launch the steps of run() as HIP graphs of 8 steps (default) or eagerly."""
+        """Launch the steps of run() as HIP graphs of 8 and 2 steps (default) or eagerly."""
         check(lib.enuf_dpd_set_graphs(self._h, int(bool(enable))), "enuf_dpd_set_graphs")
 
     def set_species(self, species, a_table):

@@ -100,6 +100,18 @@ class Plan:
         check(lib.enuf_plan_status(self._h, ctypes.byref(st)), "enuf_plan_status")
         return st.value
 
+    def time_kernel(self, name, max_launches):
+        """Start event timing of one kernel of compute() (name as in
+        _lib.KERNELS); None stops."""
+        k = -1 if name is None else _lib.KERNELS[name]
+        check(lib.enuf_plan_time_kernel(self._h, k, int(max_launches)), "enuf_plan_time_kernel")
+
+    def kernel_time(self):
+        """(total milliseconds, launches) of the timed kernel."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_int(0)
+        check(lib.enuf_plan_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)), "enuf_plan_kernel_time")
+        return ms.value, n.value
+
     @property
     def footprint_bytes(self):
         return int(lib.enuf_plan_footprint_bytes(self._h))

@@ -15,8 +15,13 @@ random stream).
 
 Reported per request: arrival, admission and completion times (latency =
 completion - arrival), the final ENUF energy components and the device
-status.  Host-side scheduling only: every step of every system runs in the
-library's HIP kernels.
+status.  With ``sample_every = k`` every k-th request (by id) also carries an
+accuracy sample: after its completion time is taken, its plan evaluates the
+electrostatic forces and energies of the final state (same precision and
+settings as in the batch) and the host keeps them with the final positions
+and charges, for a caller to compare with an independent reference.
+Host-side scheduling only: every step of every system runs in the library's
+HIP kernels.
 """
 import collections
 import dataclasses
@@ -51,6 +56,7 @@ class Result:
     energy5: np.ndarray
     footprint: int
     state: tuple = None   # (pos, vel, force) as NumPy arrays when kept
+    sample: dict = None   # accuracy sample: pos, q, F (electrostatic), energy5, enuf parameters
 
     @property
     def latency(self):
@@ -81,12 +87,14 @@ class Server:
     keep_state: copy each finished system's final (pos, vel, force) to the host.
     """
 
-    def __init__(self, hbm_budget, max_members=256, precision="mixed", device=0, keep_state=False):
+    def __init__(self, hbm_budget, max_members=256, precision="mixed", device=0, keep_state=False,
+                 sample_every=0):
         self.device = torch.device("cuda", device) if isinstance(device, int) else device
         self.budget = int(hbm_budget)
         self.max_members = int(max_members)
         self.precision = precision
         self.keep_state = keep_state
+        self.sample_every = int(sample_every)
         self.stream = torch.cuda.Stream(self.device)   # non-blocking, default priority
         self.batch = Batch(precision, device=self.device)
         self.used = 0
@@ -120,9 +128,22 @@ class Server:
         if self.keep_state:
             state = (m.pos.cpu().numpy(), m.vel.cpu().numpy(), m.force.cpu().numpy())
         self.batch.remove(m.mid)
+        sample = None
+        if self.sample_every > 0 and m.req.rid % self.sample_every == 0:
+            sample = self._accuracy_sample(m)
         m.dpd.close()
         return Result(rid=m.req.rid, N=m.req.system.N, arrival=m.req.arrival, admitted=m.admitted, finished=now,
-                      steps=m.req.steps, status=st, energy5=e5, footprint=m.footprint, state=state)
+                      steps=m.req.steps, status=st, energy5=e5, footprint=m.footprint, state=state,
+                      sample=sample)
+
+    def _accuracy_sample(self, m):
+        """Electrostatic forces and energies of the member's final state from
+        its own plan (the completion time is already taken)."""
+        F, E5 = m.dpd.plan.compute_components(m.pos, m.dpd._q)
+        s = m.req.system
+        return dict(pos=m.pos.cpu().numpy(), q=np.asarray(s.q, dtype=np.float64), F=F.cpu().numpy(),
+                    energy5=E5.cpu().numpy(), enuf=dict(s.meta["enuf"]), status=m.dpd.plan.status(),
+                    precision=self.precision)
 
     def serve(self, requests, clock=time.perf_counter):
         """Serve the requests (arrival times relative to the call); returns the

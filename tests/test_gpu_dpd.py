@@ -241,3 +241,39 @@ def test_graph_replayed_steps_match_eager(conc):
     for k, (a, b) in enumerate(zip(out[0], out[1])):
         for x, y in zip(a, b):
             assert np.array_equal(x, y), f"run {k}"
+
+
+def test_back_to_back_runs_on_new_buffers():
+    """Runs that switch state buffers with no host synchronisation between
+    them (each switch captures the step graphs again while the previous run's
+    graphs may still be queued), and graphs captured ahead with
+    prepare_graphs: bitwise the states of eager launches."""
+    s = wl.dpd_polyelectrolyte_24k()
+    from paper_1303_4523_amd.dpd import DPD
+    out = []
+    for mode in ("graphs", "prepared", "eager"):
+        print(f"case: back-to-back runs, {mode}", flush=True)
+        d = DPD(s.L, s.q, dict(s.meta["dpd"], seed=5), bonds=s.bonds, enuf=s.meta["enuf"], device=0)
+        d.set_graphs(mode != "eager")
+        tp, tv = _t(s.pos), _t(s.vel)
+        F = torch.empty_like(tp)
+        d.forces(tp, tv, F, step=0)
+        bufs = [(tp, tv, F)] + [tuple(torch.empty_like(x) for x in (tp, tv, F)) for _ in range(2)]
+        if mode == "prepared":
+            for b in bufs:
+                d.prepare_graphs(*b)
+        first = 1
+        for k in range(len(bufs)):
+            if k > 0:  # hand the state over to the next buffers on the stream
+                for dst, src in zip(bufs[k], bufs[k - 1]):
+                    dst.copy_(src)
+            d.run(*bufs[k], first, 11 + 2 * k)
+            first += 11 + 2 * k
+        torch.cuda.synchronize()
+        st = d.status()
+        out.append(tuple(x.cpu().numpy() for x in bufs[-1]) + (d.energy().cpu().numpy(),))
+        d.close()
+        assert st == 0
+    for other in out[1:]:
+        for x, y in zip(out[0], other):
+            assert np.array_equal(x, y)

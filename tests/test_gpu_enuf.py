@@ -36,11 +36,23 @@ def _run(plan, pos, q, components=True):
     return F.cpu().numpy(), E.cpu().numpy(), plan.status()
 
 
+# Per-particle bar beside the RMS one: no single force may be off by more than
+# this fraction of the RMS force (one wrong particle among many would pass an
+# RMS bar).
+PER_PARTICLE = {"fp64": 1e-3, "mixed": 5e-2}
+
+
 def _errors(F, E5, ref):
     ef = np.linalg.norm(F - ref["F"]) / np.linalg.norm(ref["F"])
     Et = E5[0] + E5[2] + E5[3]
     ee = abs(Et - ref["E"]) / abs(ref["E"])
     return ef, ee, Et
+
+
+def _worst_particle(F, Fref):
+    """max_i |F_i - Fref_i| / RMS_i |Fref_i| (over the rows given)."""
+    rms = np.sqrt(np.mean(np.sum(Fref ** 2, axis=1)))
+    return float(np.max(np.linalg.norm(F - Fref, axis=1)) / rms)
 
 
 def _case(sys_, precision="fp64", window="kb", **over):
@@ -60,9 +72,11 @@ def test_single_eval_small_parity(precision):
     F, E5, st, ref = _case(s, precision)
     assert st == 0
     ef, ee, Et = _errors(F, E5, ref)
-    print(f"force rel rms {ef:.3e}  energy rel {ee:.3e}  E={Et:.10f} ref={ref['E']:.10f}")
+    wp = _worst_particle(F, ref["F"])
+    print(f"force rel rms {ef:.3e}  energy rel {ee:.3e}  worst particle {wp:.3e}  E={Et:.10f} ref={ref['E']:.10f}")
     tf, te = TOL[precision]
     assert ef <= tf and ee <= te
+    assert wp <= PER_PARTICLE[precision]
     # components: the real-space and self terms are exact sums
     assert abs(E5[0] - ref["E_real"]) < 1e-9 * abs(ref["E_real"]) + 1e-9
     assert abs(E5[1] - ref["E_slater"]) < 1e-9 * abs(ref["E_slater"]) + 1e-9
@@ -254,12 +268,87 @@ def test_n_sweep_parity(L, precision):
     F, E5, st = _run(plan, s.pos, s.q)
     plan.close()
     ef, ee, Et = _errors(F, E5, ref)
+    wp = _worst_particle(F, ref["F"])
     scale = abs(ref["E_real"]) + abs(ref["E_recip"]) + abs(ref["E_self"])
     print(f"L={L} {precision}: force rel rms {ef:.3e}  energy rel {ee:.3e} "
-          f"(vs sum of |components| {abs(Et - ref['E']) / scale:.3e})")
+          f"(vs sum of |components| {abs(Et - ref['E']) / scale:.3e})  worst particle {wp:.3e}")
     assert st == 0
     tf, te = TOL[precision]
     assert ef <= tf and ee <= te
+    assert wp <= PER_PARTICLE[precision]
+    assert np.all(F[s.q == 0.0] == 0.0)
+
+
+# The largest systems the batched and serving workloads run, against the
+# oracle: every force and the energy where the direct sums are affordable,
+# otherwise S(k) over all charges with the forces of a seeded sample of 1000
+# charged beads (the reciprocal energy and the self term are still exact
+# sums over every charge).
+_BIG_REF = {}
+
+
+def _big_system(which):
+    if which == "replica_largest":
+        # the largest member (by mesh) of the 64-replica batched workload: M = 80
+        reps = [wl.replica(s) for s in range(64)]
+        return max(reps, key=lambda r: (r.meta["enuf"]["M"], r.N))
+    if which == "replica_m90":
+        # the recipe of the batched workload at its largest N (48000) with the
+        # densest charges (f = 1, z = 3): M = 90 = 2 3^2 5, Kc = 20
+        L = (48000 / 3.0) ** (1.0 / 3.0)
+        s = wl.polyelectrolyte(L, 3.0, 50, 1.0, 0.1, 3, wl.BASE_SEED + 900)
+        M = wl.mesh_size(3.2 * L)
+        s.meta["enuf"] = wl.enuf_params(L, M=M, Kc=min(int(np.floor(0.8 * L + 1e-9)), M // 4))
+        s.meta["name"] = f"replica recipe N={s.N} f=1 z=3 M={M}"
+        return s
+    if which == "request_m144":
+        # the most densely charged M = 144 request of the 2000-request serving
+        # stream (N = 199627, 185421 charged, Kc = 32)
+        return wl.serving_request(986)
+    raise ValueError(which)
+
+
+def _big_ref(which):
+    if which not in _BIG_REF:
+        s = _big_system(which)
+        e = s.meta["enuf"]
+        sel = None
+        if s.Nq > 20000:
+            qi = np.nonzero(s.q)[0]
+            sel = np.sort(np.random.default_rng(20240613).choice(qi, 1000, replace=False))
+        ref = oracle.ewald(s.pos, s.q, e["L"], e["alpha"], e["Kc"], e["r_cut"], e["lam"], sel=sel)
+        _BIG_REF[which] = (s, sel, ref)
+    return _BIG_REF[which]
+
+
+@pytest.mark.parametrize("which,precision", [("replica_largest", "mixed"), ("replica_m90", "mixed"),
+                                             ("replica_m90", "fp64"), ("request_m144", "mixed"),
+                                             ("request_m144", "fp64")])
+def test_largest_workload_meshes(which, precision):
+    """Meshes of the batched (M = 80, 90) and serving (M = 144, row-chunked in
+    FP64) workloads, with the member settings (one work-group per plane)."""
+    s, sel, ref = _big_ref(which)
+    e = s.meta["enuf"]
+    print(f"case: {s.meta['name']} N={s.N} Nq={s.Nq} M={e['M']} Kc={e['Kc']} {precision} "
+          f"sample={'all' if sel is None else len(sel)}", flush=True)
+    plan = _plan(s.N, e, precision)
+    plan.set_parts(1)
+    F, E5, st = _run(plan, s.pos, s.q)
+    plan.close()
+    assert st == 0
+    tf, te = TOL[precision]
+    if sel is None:
+        ef, ee, _ = _errors(F, E5, ref)
+        Fs, Fr = F, ref["F"]
+    else:
+        Fs, Fr = F[sel], ref["F"]
+        ef = np.linalg.norm(Fs - Fr) / np.linalg.norm(Fr)
+        # E_recip and E_self are complete sums in the sampled reference too
+        ee = abs(E5[2] + E5[3] - ref["E_recip"] - ref["E_self"]) / abs(ref["E_recip"] + ref["E_self"])
+    wp = _worst_particle(Fs, Fr)
+    print(f"{which} {precision}: force rel rms {ef:.3e} energy rel {ee:.3e} worst particle {wp:.3e}")
+    assert ef <= tf and ee <= te
+    assert wp <= PER_PARTICLE[precision]
     assert np.all(F[s.q == 0.0] == 0.0)
 
 
