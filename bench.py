@@ -61,7 +61,9 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector
 # rounds are integer work and are not counted.
 PAIR_FLOPS = 44.0
 
-STEP_KERNELS = ["dpd_pair", "real", "mesh_fwd", "mesh_x", "mesh_bwd", "combine"]
+# kernel classes of a DPD step ("dpd_post": the closing kernel, which in a run
+# is step k's combine fused with step k+1's predictor and binning)
+STEP_KERNELS = ["dpd_pair", "real", "mesh_fwd", "mesh_x", "mesh_bwd", "dpd_post"]
 
 
 def parse():

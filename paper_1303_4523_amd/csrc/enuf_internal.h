@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace enuf {
 
 constexpr int kWave = 64;          // CDNA wavefront width
@@ -208,6 +210,19 @@ hipError_t launch_compute(const ComputeConfig &cfg, const ComputeBuffers &b,
                           const double *pos, const double *q, double *forces,
                           double *energy_total, double *energy5, hipStream_t stream,
                           KernelTimer *timer = nullptr);
+
+// Host-computed tables of a plan: influence factors per wave number
+// (exp(-pi^2 k^2/(alpha L)^2) / Phi(k/M)^2), FFT twiddles, and the window
+// series of the given precision (cheb_deg its degree).
+struct PlanTables {
+  std::vector<double> atab;
+  std::vector<double2> tw64;
+  std::vector<float2> tw32;
+  std::vector<double> wcoef64;  // filled for ENUF_FP64
+  std::vector<float> wcoef32;   // filled for ENUF_MIXED
+  int cheb_deg = 0;
+};
+int plan_tables(const ComputeConfig &c, int precision, PlanTables *t);
 
 // LDS bytes the three mesh passes need for the given geometry, precision and
 // m.rows.

@@ -302,54 +302,77 @@ int cached_window_series(const WindowParams &w, int fp32, std::vector<long doubl
   return it->second.D;
 }
 
-int upload_window_series(enuf_plan *pl) {
-  std::vector<long double> coef;
-  const int fp32 = pl->precision == ENUF_MIXED;
+// Device layout of the window series for one precision: value series and
+// derivative series, both at stride D + 1 (the derivative's last coefficient
+// 0).  Returns the degree D.
+int window_table(const WindowParams &w, int fp32, std::vector<long double> *coef) {
   std::vector<long double> fit;
-  const int D = cached_window_series(pl->cfg.mesh.win, fp32, &fit);
-  pl->cfg.mesh.cheb_deg = D;
-  // device layout: value series and derivative series both at stride D + 1
-  const int P2 = 2 * pl->cfg.mesh.win.p;
-  coef.assign((size_t)P2 * 2 * (D + 1), 0.0L);
+  const int D = cached_window_series(w, fp32, &fit);
+  const int P2 = 2 * w.p;
+  coef->assign((size_t)P2 * 2 * (D + 1), 0.0L);
   for (int s = 0; s < P2; ++s) {
-    for (int k = 0; k <= D; ++k) coef[(size_t)s * (D + 1) + k] = fit[(size_t)s * (D + 1) + k];
+    for (int k = 0; k <= D; ++k) (*coef)[(size_t)s * (D + 1) + k] = fit[(size_t)s * (D + 1) + k];
     for (int k = 0; k < D; ++k)
-      coef[(size_t)(P2 + s) * (D + 1) + k] = fit[(size_t)P2 * (D + 1) + (size_t)s * D + k];
+      (*coef)[(size_t)(P2 + s) * (D + 1) + k] = fit[(size_t)P2 * (D + 1) + (size_t)s * D + k];
   }
-  const size_t n = coef.size();
+  return D;
+}
+
+}  // namespace
+
+namespace enuf {
+
+int plan_tables(const ComputeConfig &c, int precision, PlanTables *t) {
+  const int Kc = c.mesh.Kc, M = c.mesh.M, nky = 2 * Kc - 1;
+  const WindowParams &w = c.mesh.win;
+  t->atab.resize(nky);
+  const long double aL = (long double)c.alpha * c.L;
+  for (int i = 0; i < nky; ++i) {
+    const long double k = (long double)(i - (Kc - 1));
+    const long double ph = window_hat(w, k / (long double)M);
+    t->atab[i] = (double)(std::exp(-(long double)M_PI * (long double)M_PI * k * k / (aL * aL)) / (ph * ph));
+  }
+  t->tw64.resize(M);
+  t->tw32.resize(M);
+  for (int m = 0; m < M; ++m) {
+    const long double ang = -2.0L * (long double)M_PI * (long double)m / (long double)M;
+    t->tw64[m] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+    t->tw32[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  std::vector<long double> coef;
+  const int fp32 = precision == ENUF_MIXED;
+  t->cheb_deg = window_table(w, fp32, &coef);
+  t->wcoef64.clear();
+  t->wcoef32.clear();
   if (fp32) {
-    std::vector<float> h(n);
-    for (size_t k = 0; k < n; ++k) h[k] = (float)coef[k];
-    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef32, h.data(), n * sizeof(float), hipMemcpyHostToDevice), ENUF_EDEVICE);
+    t->wcoef32.resize(coef.size());
+    for (size_t k = 0; k < coef.size(); ++k) t->wcoef32[k] = (float)coef[k];
   } else {
-    std::vector<double> h(n);
-    for (size_t k = 0; k < n; ++k) h[k] = (double)coef[k];
-    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef64, h.data(), n * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
+    t->wcoef64.resize(coef.size());
+    for (size_t k = 0; k < coef.size(); ++k) t->wcoef64[k] = (double)coef[k];
   }
   return ENUF_OK;
 }
 
+}  // namespace enuf
+
+namespace {
+
 int upload_tables(enuf_plan *pl) {
-  const int Kc = pl->Kc, M = pl->M, nky = 2 * Kc - 1;
-  const WindowParams &w = pl->cfg.mesh.win;
-  std::vector<double> atab(nky);
-  const long double aL = (long double)pl->alpha * pl->L;
-  for (int i = 0; i < nky; ++i) {
-    const long double k = (long double)(i - (Kc - 1));
-    const long double ph = window_hat(w, k / (long double)M);
-    atab[i] = (double)(std::exp(-(long double)M_PI * (long double)M_PI * k * k / (aL * aL)) / (ph * ph));
-  }
-  std::vector<double2> tw64(M);
-  std::vector<float2> tw32(M);
-  for (int m = 0; m < M; ++m) {
-    const long double ang = -2.0L * (long double)M_PI * (long double)m / (long double)M;
-    tw64[m] = make_double2((double)std::cos(ang), (double)std::sin(ang));
-    tw32[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
-  HIP_OR_RETURN(hipMemcpy(pl->buf.atab, atab.data(), nky * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
-  HIP_OR_RETURN(hipMemcpy(pl->buf.tw64, tw64.data(), M * sizeof(double2), hipMemcpyHostToDevice), ENUF_EDEVICE);
-  HIP_OR_RETURN(hipMemcpy(pl->buf.tw32, tw32.data(), M * sizeof(float2), hipMemcpyHostToDevice), ENUF_EDEVICE);
-  return upload_window_series(pl);
+  PlanTables t;
+  plan_tables(pl->cfg, pl->precision, &t);
+  pl->cfg.mesh.cheb_deg = t.cheb_deg;
+  const int M = pl->M, nky = 2 * pl->Kc - 1;
+  HIP_OR_RETURN(hipMemcpy(pl->buf.atab, t.atab.data(), nky * sizeof(double), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipMemcpy(pl->buf.tw64, t.tw64.data(), M * sizeof(double2), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  HIP_OR_RETURN(hipMemcpy(pl->buf.tw32, t.tw32.data(), M * sizeof(float2), hipMemcpyHostToDevice), ENUF_EDEVICE);
+  if (!t.wcoef32.empty())
+    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef32, t.wcoef32.data(), t.wcoef32.size() * sizeof(float),
+                            hipMemcpyHostToDevice), ENUF_EDEVICE);
+  if (!t.wcoef64.empty())
+    HIP_OR_RETURN(hipMemcpy(pl->buf.wcoef64, t.wcoef64.data(), t.wcoef64.size() * sizeof(double),
+                            hipMemcpyHostToDevice), ENUF_EDEVICE);
+  return ENUF_OK;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -480,39 +503,37 @@ extern "C" {
 
 const char *enuf_last_error(void) { return g_last_error.c_str(); }
 
-enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc,
-                            double r_cut, double lambda) {
-  g_last_error.clear();
-  // ---- validation (host only; no device call before it passes) ----
-  if (N < 1 || N > (int64_t)1 << 28) { set_error("N must be in [1, 2^28]"); return nullptr; }
-  if (!finite_pos(box)) { set_error("box must be finite and > 0"); return nullptr; }
-  if (!finite_pos(alpha)) { set_error("alpha must be finite and > 0"); return nullptr; }
-  if (!(std::isfinite(sigma) && sigma >= 1.0)) { set_error("sigma must be finite and >= 1"); return nullptr; }
-  if (p < 1 || p > 15) { set_error("p must be in [1, 15]"); return nullptr; }
-  if (M < 4 || M % 2 != 0 || M > 4096) { set_error("M must be even and in [4, 4096]"); return nullptr; }
-  FftPlan fp{};
-  if (!factor_235(M, &fp)) { set_error("M must be of the form 2^a 3^b 5^c"); return nullptr; }
-  if (2 * p > M / 2) { set_error("need 2p <= M/2"); return nullptr; }
-  if (Kc < 1 || (double)Kc > (double)M / (2.0 * sigma)) { set_error("need 1 <= Kc <= M/(2 sigma)"); return nullptr; }
-  if (!finite_pos(r_cut) || r_cut > 0.5 * box) { set_error("need 0 < r_cut <= box/2"); return nullptr; }
-  if (!(std::isfinite(lambda) && lambda >= 0.0)) { set_error("lambda must be finite and >= 0"); return nullptr; }
+}  // extern "C"
 
-  enuf_plan *pl = new enuf_plan();
-  pl->N = N; pl->L = box; pl->alpha = alpha; pl->sigma = sigma; pl->r_cut = r_cut; pl->lambda = lambda;
-  pl->p = p; pl->M = M; pl->Kc = Kc;
-  if (hipGetDevice(&pl->device) != hipSuccess) {
-    set_error("hipGetDevice failed");
-    delete pl;
-    return nullptr;
-  }
-  pl->max_lds = lds_budget(pl->device);
-  if (pl->max_lds == 0) {
-    set_error("hipDeviceGetAttribute failed");
-    delete pl;
-    return nullptr;
-  }
+namespace {
 
-  ComputeConfig &c = pl->cfg;
+// Host-side argument checks of a plan (no device call); the FFT factorisation
+// of M in *fp.  ENUF_OK or ENUF_EINVAL with the message set.
+int check_plan_args(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc, double r_cut,
+                    double lambda, FftPlan *fp) {
+  if (N < 1 || N > (int64_t)1 << 28) { set_error("N must be in [1, 2^28]"); return ENUF_EINVAL; }
+  if (!finite_pos(box)) { set_error("box must be finite and > 0"); return ENUF_EINVAL; }
+  if (!finite_pos(alpha)) { set_error("alpha must be finite and > 0"); return ENUF_EINVAL; }
+  if (!(std::isfinite(sigma) && sigma >= 1.0)) { set_error("sigma must be finite and >= 1"); return ENUF_EINVAL; }
+  if (p < 1 || p > 15) { set_error("p must be in [1, 15]"); return ENUF_EINVAL; }
+  if (M < 4 || M % 2 != 0 || M > 4096) { set_error("M must be even and in [4, 4096]"); return ENUF_EINVAL; }
+  *fp = FftPlan{};
+  if (!factor_235(M, fp)) { set_error("M must be of the form 2^a 3^b 5^c"); return ENUF_EINVAL; }
+  if (2 * p > M / 2) { set_error("need 2p <= M/2"); return ENUF_EINVAL; }
+  if (Kc < 1 || (double)Kc > (double)M / (2.0 * sigma)) { set_error("need 1 <= Kc <= M/(2 sigma)"); return ENUF_EINVAL; }
+  if (!finite_pos(r_cut) || r_cut > 0.5 * box) { set_error("need 0 < r_cut <= box/2"); return ENUF_EINVAL; }
+  if (!(std::isfinite(lambda) && lambda >= 0.0)) { set_error("lambda must be finite and >= 0"); return ENUF_EINVAL; }
+  return ENUF_OK;
+}
+
+// Configuration and buffer geometry of a plan with checked arguments (FP64,
+// Kaiser-Bessel window, gradient forces, default parts); the mesh passes'
+// row chunking is chosen later for the precision (plan_rows).  False (message
+// set) when no row chunking fits the LDS budget.
+bool plan_config(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc, double r_cut,
+                 double lambda, const FftPlan &fp, size_t max_lds, ComputeConfig *cfg, PlanGeom *g) {
+  ComputeConfig &c = *cfg;
+  c = ComputeConfig{};
   c.N = N;
   c.nblk = (int)((N + kPrepThreads - 1) / kPrepThreads);
   c.L = box; c.alpha = alpha; c.r_cut = r_cut; c.lambda = lambda;
@@ -524,38 +545,37 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   m.fft = fp;
   m.parts = mesh_parts(M);
   m.bparts = mesh_bparts(m.parts);
-  pl->max_parts = m.parts;  // the spectrum buffer holds this many partial spectra
   m.xsplit = mesh_xsplit(Kc, m.nky);
   m.gscale_f = mesh_gscale_factor(p);
-  PlanGeom g;
-  if (!plan_geometry(N, box, p, M, Kc, r_cut, pl->max_lds, &g)) {
-    set_error("mesh too large: no row chunking of the plane passes fits in " + std::to_string(pl->max_lds) +
+  if (!plan_geometry(N, box, p, M, Kc, r_cut, max_lds, g)) {
+    set_error("mesh too large: no row chunking of the plane passes fits in " + std::to_string(max_lds) +
               " bytes of LDS");
-    delete pl;
-    return nullptr;
+    return false;
   }
-  const int ncell = g.ncell;
-  c.cells.ncell = ncell;
-  c.cells.cap = g.cap;
-  c.cells.inv_cell = (double)ncell / box;
-  m.xcap = g.xcap;
-  pl->part_slots = g.part_slots;
+  c.cells.ncell = g->ncell;
+  c.cells.cap = g->cap;
+  c.cells.inv_cell = (double)g->ncell / box;
+  m.xcap = g->xcap;
   m.cheb_deg = kMaxChebDeg;
   m.rows = M;
   m.nchunk = 1;
   m.nslot = 1;
   m.stage = kStage;
   mesh_lds_bytes(m, 0, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
+  return true;
+}
 
-  ComputeBuffers &b = pl->buf;
-  const size_t n = (size_t)N, ncell3 = (size_t)ncell * ncell * ncell;
-  const std::array<size_t, kPlanBuffers> sz = plan_buffer_bytes(N, p, M, Kc, g);
-  void *ptr[kPlanBuffers];
-  if (!pl->alloc_arena(sz.data(), kPlanBuffers, ptr)) {
-    set_error("device allocation failed");
-    delete pl;
-    return nullptr;
-  }
+// Row chunking of the mesh passes for a precision (false: it does not fit).
+bool plan_rows(ComputeConfig *c, int precision, size_t max_lds, int part_slots) {
+  MeshParams &m = c->mesh;
+  if (!mesh_choose_rows(m, precision, max_lds) || m.nslot > part_slots) return false;
+  mesh_lds_bytes(m, precision, &c->lds_fwd, &c->lds_x, &c->lds_bwd);
+  return true;
+}
+
+// The plan's buffers at the offsets of one arena (ptr[k]: buffer k of plan_buffer_bytes).
+ComputeBuffers carve_buffers(void *const *ptr) {
+  ComputeBuffers b{};
   b.blk_cnt = (int *)ptr[0];
   b.blk_sums = (double *)ptr[1];
   b.sc = (DevScalars *)ptr[2];
@@ -580,34 +600,99 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
   b.atab = (double *)ptr[21];
   b.tw64 = (double2 *)ptr[22];
   b.tw32 = (float2 *)ptr[23];
-  if (hipMemset(b.sc, 0, sizeof(DevScalars)) != hipSuccess ||
-      hipMemset(b.freal, 0, n * 3 * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(b.ccnt, 0, 2 * ncell3 * sizeof(int)) != hipSuccess ||
-      hipMemset(b.xcnt, 0, 2 * (size_t)M * kXSub * sizeof(int)) != hipSuccess) {
-    set_error("hipMemset failed");
+  return b;
+}
+
+// Buffers that must hold zeros before the first evaluation (the kernels keep
+// them so between evaluations): (pointer, bytes) pairs, returns their count.
+int zeroed_buffers(const ComputeConfig &c, const ComputeBuffers &b, void **ptr, size_t *bytes) {
+  const size_t n = (size_t)c.N, nc = (size_t)c.cells.ncell;
+  ptr[0] = b.sc;    bytes[0] = sizeof(DevScalars);
+  ptr[1] = b.freal; bytes[1] = n * 3 * sizeof(unsigned long long);
+  ptr[2] = b.ccnt;  bytes[2] = 2 * nc * nc * nc * sizeof(int);
+  ptr[3] = b.xcnt;  bytes[3] = 2 * (size_t)c.mesh.M * kXSub * sizeof(int);
+  return 4;
+}
+
+// Dynamic-LDS limits of the mesh kernels, raised once per process.
+hipError_t configure_once(size_t max_lds) {
+  static std::mutex mu;
+  static bool done = false;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done) return hipSuccess;
+  const hipError_t e = configure_kernels(max_lds);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc,
+                            double r_cut, double lambda) {
+  g_last_error.clear();
+  // ---- validation (host only; no device call before it passes) ----
+  FftPlan fp{};
+  if (check_plan_args(N, box, alpha, p, sigma, M, Kc, r_cut, lambda, &fp) != ENUF_OK) return nullptr;
+
+  enuf_plan *pl = new enuf_plan();
+  pl->N = N; pl->L = box; pl->alpha = alpha; pl->sigma = sigma; pl->r_cut = r_cut; pl->lambda = lambda;
+  pl->p = p; pl->M = M; pl->Kc = Kc;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    set_error("hipGetDevice failed");
     delete pl;
     return nullptr;
+  }
+  pl->max_lds = lds_budget(pl->device);
+  if (pl->max_lds == 0) {
+    set_error("hipDeviceGetAttribute failed");
+    delete pl;
+    return nullptr;
+  }
+  PlanGeom g;
+  if (!plan_config(N, box, alpha, p, sigma, M, Kc, r_cut, lambda, fp, pl->max_lds, &pl->cfg, &g)) {
+    delete pl;
+    return nullptr;
+  }
+  pl->max_parts = pl->cfg.mesh.parts;  // the spectrum buffer holds this many partial spectra
+  pl->part_slots = g.part_slots;
+
+  const std::array<size_t, kPlanBuffers> sz = plan_buffer_bytes(N, p, M, Kc, g);
+  void *ptr[kPlanBuffers];
+  if (!pl->alloc_arena(sz.data(), kPlanBuffers, ptr)) {
+    set_error("device allocation failed");
+    delete pl;
+    return nullptr;
+  }
+  pl->buf = carve_buffers(ptr);
+  void *zp[8];
+  size_t zb[8];
+  const int nz = zeroed_buffers(pl->cfg, pl->buf, zp, zb);
+  for (int k = 0; k < nz; ++k) {
+    if (hipMemset(zp[k], 0, zb[k]) != hipSuccess) {
+      set_error("hipMemset failed");
+      delete pl;
+      return nullptr;
+    }
   }
   if (upload_tables(pl) != ENUF_OK) {
     delete pl;
     return nullptr;
   }
-  if (!mesh_choose_rows(m, ENUF_FP64, pl->max_lds) || m.nslot > pl->part_slots) {
+  if (!plan_rows(&pl->cfg, ENUF_FP64, pl->max_lds, pl->part_slots)) {
     // FP64 does not fit; the plan stays usable after switching to the mixed mode
+    MeshParams &m = pl->cfg.mesh;
     m.rows = M;
     m.nchunk = 1;
     m.nslot = 1;
     m.stage = kStage;
+    mesh_lds_bytes(m, ENUF_FP64, &pl->cfg.lds_fwd, &pl->cfg.lds_x, &pl->cfg.lds_bwd);
   }
-  mesh_lds_bytes(m, ENUF_FP64, &c.lds_fwd, &c.lds_x, &c.lds_bwd);
-  static bool configured = false;
-  if (!configured) {
-    if (configure_kernels(pl->max_lds) != hipSuccess) {
-      set_error("hipFuncSetAttribute failed");
-      delete pl;
-      return nullptr;
-    }
-    configured = true;
+  if (configure_once(pl->max_lds) != hipSuccess) {
+    set_error("hipFuncSetAttribute failed");
+    delete pl;
+    return nullptr;
   }
   if (hipStreamSynchronize(nullptr) != hipSuccess) {
     set_error("device synchronisation after plan setup failed");

@@ -126,3 +126,4 @@ class Plan:
             self.close()
         except Exception:
             pass
+

@@ -130,22 +130,29 @@ def test_thermostat_reaches_kT():
     assert abs(np.mean(ke) - 1.0) < 0.04
 
 
-def test_step_follows_table2_order():
-    """Table 2: predictor (0), half kick (1), drift (2), forces at the new
-    positions with the predicted velocities (3-5), half kick (6)."""
-    L = 5.0
-    pos, vel, q, bonds = _dpd_box(200, L, 4, nq=20, chain=6)
-    P = dict(BASE, L=L, kappa=1.1, alpha=0.8, r_cut=2.5, lambda_e=0.25, Kc=8, use_elec=1)
-    F0, _ = oracle.dpd_forces(pos, vel, q, bonds, P, seed=2, step=0)
-    p1, v1, F1, _ = oracle.dpd_step(pos, vel, F0, q, bonds, P, seed=2, step=1)
-    dt, lam = P["dt"], P["lam"]
-    v0 = vel + lam * dt * F0
-    vh = vel + 0.5 * dt * F0
-    pr = (pos + dt * vh) % L
-    Fr, _ = oracle.dpd_forces(pr, v0, q, bonds, P, seed=2, step=1)
-    assert np.abs(p1 - pr).max() < 1e-13
-    assert np.abs(F1 - Fr).max() < 1e-9 * np.abs(Fr).max()
-    assert np.abs(v1 - (vh + 0.5 * dt * Fr)).max() < 1e-12
+def test_one_step_worked_by_hand():
+    """Table 2 on two beads with dissipation only, worked by hand.  Beads at
+    x = 1.0 and 1.5 (y = z = 2, L = 10), velocities +1 and -1 along x, the
+    force of the last step F = +2 and -2, dt = 0.1, gamma = 4.5,
+    lambda = 0.65, a = sigma = 0:
+      (0) predicted v0 = v + lambda dt F = +1.13 / -1.13
+      (1) half kick   v  = v + dt F / 2   = +1.1 / -1.1
+      (2) drift       x  = x + dt v       = 1.11 / 1.39, so r = 0.28
+      (3-5) F^D on bead 0 = -gamma (1 - r)^2 (rhat . v0_01) rhat with
+            rhat = -x, v0_01 = 2.26 x: magnitude 4.5 * 0.5184 * 2.26 =
+            5.272128 along -x (bead 1: +x)
+      (6) half kick   v  = 1.1 - 0.05 * 5.272128 = 0.8363936 / -0.8363936.
+    Reading the half-kicked velocity (1.1) or the old one (1.0) in the
+    dissipative force, or lambda = 1/2, would give 5.13216 or 4.6656."""
+    L = 10.0
+    pos = np.array([[1.0, 2.0, 2.0], [1.5, 2.0, 2.0]])
+    vel = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    F0 = np.array([[2.0, 0.0, 0.0], [-2.0, 0.0, 0.0]])
+    P = dict(BASE, L=L, a=0.0, gamma=4.5, sigma=0.0, dt=0.1, lam=0.65, k_bond=0.0, use_elec=0)
+    p1, v1, F1, _ = oracle.dpd_step(pos, vel, F0, np.zeros(2), np.zeros((0, 2)), P, seed=3, step=1)
+    assert np.allclose(p1, [[1.11, 2.0, 2.0], [1.39, 2.0, 2.0]], rtol=0, atol=1e-14)
+    assert np.allclose(F1, [[-5.272128, 0.0, 0.0], [5.272128, 0.0, 0.0]], rtol=0, atol=1e-12)
+    assert np.allclose(v1, [[0.8363936, 0.0, 0.0], [-0.8363936, 0.0, 0.0]], rtol=0, atol=1e-13)
 
 
 def test_species_amplitudes_hand_computed():
