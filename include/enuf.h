@@ -150,6 +150,34 @@ int enuf_compute(enuf_plan *plan, const double *pos, const double *q,
 int enuf_compute_components(enuf_plan *plan, const double *pos, const double *q,
                             double *forces, double *energy5);
 
+/*
+ * enuf_compute_components without a plan and without allocating device memory,
+ * for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The arguments are those of
+ * enuf_plan_create (Kaiser-Bessel window, window-gradient forces, the default
+ * work-groups per plane) plus:
+ *   precision : ENUF_FP64 or ENUF_MIXED.
+ *   pos, q, forces, energy5 : as for enuf_compute_components (DEVICE pointers on
+ *            the current device).
+ *   status   : DEVICE pointer to one int, or NULL; receives the evaluation's
+ *            data-dependent status (ENUF_OK, ENUF_ENONNEUTRAL, ...).
+ *   hip_stream : stream the work is enqueued on (NULL = null stream).
+ * The buffers of the evaluation live in one fixed device array of
+ * ENUF_NOALLOC_SCRATCH_BYTES per device, held from the library's first use of
+ * a device until the process ends; tables reach the device as kernel
+ * arguments.  Sizes whose buffers exceed that array, or M > 256, return
+ * ENUF_EINVAL (the message gives the bytes needed).  The call issues no
+ * hipMalloc, hipFree or hipMemset: every launch is a kernel.  All calls on one
+ * device share the array, and each call starts by clearing what it needs, so
+ * calls that overlap on one device (two streams, or two threads) race: order
+ * them on one stream.  Enqueue-only; the results equal enuf_compute_components
+ * on a plan of the same parameters and precision.
+ */
+#define ENUF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int enuf_compute_noalloc(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc,
+                         double r_cut, double lambda, int precision, const double *pos, const double *q,
+                         double *forces, double *energy5, int *status, void *hip_stream);
+
 /* Synchronise the plan's stream and return the sticky status word in *status
  * (ENUF_OK or the first data-dependent error since the last call); clears it. */
 int enuf_plan_status(enuf_plan *plan, int *status);

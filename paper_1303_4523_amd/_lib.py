@@ -40,6 +40,9 @@ lib.enuf_plan_footprint_bytes.argtypes = [_vp]
 lib.enuf_plan_footprint_bytes.restype = _sz
 lib.enuf_plan_set_force_mode.argtypes = [_vp, _int]
 lib.enuf_plan_set_force_mode.restype = _int
+lib.enuf_compute_noalloc.argtypes = [_i64, _dbl, _dbl, _int, _dbl, _int, _int, _dbl, _dbl, _int,
+                                     _vp, _vp, _vp, _vp, _vp, _vp]
+lib.enuf_compute_noalloc.restype = _int
 
 
 
@@ -133,6 +136,7 @@ EXPORTED = [
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
     "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",
     "enuf_plan_time_kernel", "enuf_plan_kernel_time", "enuf_batch_time_kernel", "enuf_batch_kernel_time",
+    "enuf_compute_noalloc",
 ]
 
 # Status codes (include/enuf.h).

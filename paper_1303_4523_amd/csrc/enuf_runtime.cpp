@@ -847,6 +847,161 @@ int enuf_plan_kernel_time(enuf_plan *plan, double *total_ms, int *launches) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// One evaluation that allocates nothing: the plan's buffers are carved out of
+// a fixed device array instead of a hipMalloc'd arena.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;  // ENUF_NOALLOC_SCRATCH_BYTES in enuf.h
+constexpr int kNoAllocMaxM = 256;
+constexpr int kMaxDevices = 64;
+
+// Every device the library runs on holds its own copy until the process ends.
+// Host code never names it in a device context: the address each device
+// gives for it (scratch_address) is what kernels and copies receive.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of scratch, looked up once per
+// device with that device current.
+int scratch_address(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device index out of range for the static scratch table");
+    return ENUF_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return ENUF_EDEVICE;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return ENUF_OK;
+}
+
+// Small host tables reach the device as kernel arguments (no copy from host
+// memory, no staging allocation): 500 words per launch.
+constexpr int kFillWords = 500;
+struct FillChunk {
+  uint32_t n;
+  uint32_t w[kFillWords];
+};
+
+__global__ void k_fill_words(uint32_t *dst, FillChunk c) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c.n) dst[i] = c.w[i];
+}
+
+__global__ void k_zero_words(uint32_t *dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = 0u;
+}
+
+__global__ void k_copy_status(const DevScalars *sc, int *status) { *status = sc->status; }
+
+hipError_t fill_words(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  const uint32_t *w = static_cast<const uint32_t *>(src);
+  uint32_t *d = static_cast<uint32_t *>(dst);
+  const size_t n = bytes / 4;
+  for (size_t k0 = 0; k0 < n; k0 += kFillWords) {
+    FillChunk c;
+    c.n = (uint32_t)std::min<size_t>(kFillWords, n - k0);
+    std::memcpy(c.w, w + k0, c.n * 4);
+    hipLaunchKernelGGL(k_fill_words, dim3((c.n + 255) / 256), dim3(256), 0, st, d + k0, c);
+  }
+  return hipGetLastError();
+}
+
+hipError_t zero_words(void *dst, size_t bytes, hipStream_t st) {
+  const size_t n = (bytes + 3) / 4;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(256), 0, st,
+                     static_cast<uint32_t *>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" int enuf_compute_noalloc(int64_t N, double box, double alpha, int p, double sigma, int M, int Kc,
+                                    double r_cut, double lambda, int precision, const double *pos,
+                                    const double *q, double *forces, double *energy5, int *status,
+                                    void *hip_stream) {
+  g_last_error.clear();
+  FftPlan fp{};
+  int rc = check_plan_args(N, box, alpha, p, sigma, M, Kc, r_cut, lambda, &fp);
+  if (rc != ENUF_OK) return rc;
+  if (precision != ENUF_FP64 && precision != ENUF_MIXED) { set_error("unknown precision"); return ENUF_EINVAL; }
+  if (M > kNoAllocMaxM) {
+    set_error("M must be <= " + std::to_string(kNoAllocMaxM) + " without allocation");
+    return ENUF_EINVAL;
+  }
+  if (!pos || !q || !forces || !energy5) { set_error("NULL buffer"); return ENUF_EINVAL; }
+  int dev = 0;
+  HIP_OR_RETURN(hipGetDevice(&dev), ENUF_EDEVICE);
+  const size_t max_lds = lds_budget(dev);
+  if (max_lds == 0) { set_error("hipDeviceGetAttribute failed"); return ENUF_EDEVICE; }
+  ComputeConfig cfg;
+  PlanGeom g;
+  if (!plan_config(N, box, alpha, p, sigma, M, Kc, r_cut, lambda, fp, max_lds, &cfg, &g)) return ENUF_EINVAL;
+  cfg.precision = precision;
+  PlanTables t;
+  plan_tables(cfg, precision, &t);
+  cfg.mesh.cheb_deg = t.cheb_deg;
+  if (!plan_rows(&cfg, precision, max_lds, g.part_slots)) {
+    set_error("mesh too large for the LDS in this precision");
+    return ENUF_EINVAL;
+  }
+  const std::array<size_t, kPlanBuffers> sz = plan_buffer_bytes(N, p, M, Kc, g);
+  const size_t need = arena_bytes(sz.data(), kPlanBuffers);
+  if (need > kScratchBytes) {
+    set_error("these sizes need " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+              std::to_string(kScratchBytes));
+    return ENUF_EINVAL;
+  }
+  void *base = nullptr;
+  rc = scratch_address(dev, &base);
+  if (rc != ENUF_OK) return rc;
+  void *ptr[kPlanBuffers];
+  size_t off = 0;
+  for (int k = 0; k < kPlanBuffers; ++k) {
+    ptr[k] = (char *)base + off;
+    off += arena_slot(sz[k]);
+  }
+  const ComputeBuffers buf = carve_buffers(ptr);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the previous call's contents: clear what the kernels expect to start at zero
+  void *zp[8];
+  size_t zb[8];
+  const int nz = zeroed_buffers(cfg, buf, zp, zb);
+  for (int k = 0; k < nz; ++k) HIP_OR_RETURN(zero_words(zp[k], zb[k], st), ENUF_EDEVICE);
+  const int nky = 2 * Kc - 1;
+  HIP_OR_RETURN(fill_words(buf.atab, t.atab.data(), nky * sizeof(double), st), ENUF_EDEVICE);
+  HIP_OR_RETURN(fill_words(buf.tw64, t.tw64.data(), M * sizeof(double2), st), ENUF_EDEVICE);
+  HIP_OR_RETURN(fill_words(buf.tw32, t.tw32.data(), M * sizeof(float2), st), ENUF_EDEVICE);
+  if (precision == ENUF_MIXED)
+    HIP_OR_RETURN(fill_words(buf.wcoef32, t.wcoef32.data(), t.wcoef32.size() * sizeof(float), st), ENUF_EDEVICE);
+  else
+    HIP_OR_RETURN(fill_words(buf.wcoef64, t.wcoef64.data(), t.wcoef64.size() * sizeof(double), st), ENUF_EDEVICE);
+  HIP_OR_RETURN(configure_once(max_lds), ENUF_EDEVICE);
+  hipError_t e = launch_compute(cfg, buf, pos, q, forces, nullptr, energy5, st);
+  if (e == hipSuccess && status) {
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, st, (const DevScalars *)buf.sc, status);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return ENUF_EDEVICE;
+  }
+  return ENUF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // DPD integrator
 // ---------------------------------------------------------------------------
 namespace {

@@ -127,3 +127,27 @@ class Plan:
         except Exception:
             pass
 
+
+def compute_noalloc(pos, q, box, alpha, p, sigma, M, Kc, r_cut, lam, precision="fp64", forces=None,
+                    energy5=None, status=None):
+    """One evaluation through enuf_compute_noalloc (no plan, no device
+    allocation inside the library) on the current stream; forces, energy5 and
+    status (1 int32) may be passed preallocated.  Returns (forces, energy5,
+    status)."""
+    N = int(q.shape[0])
+    dev = pos.device
+    if forces is None:
+        forces = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    if energy5 is None:
+        energy5 = torch.empty((5,), dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty((1,), dtype=torch.int32, device=dev)
+    pr = {"fp64": _lib.FP64, "mixed": _lib.MIXED}[precision]
+    args = (_dev_ptr(pos, "pos", (N, 3)), _dev_ptr(q, "q", (N,)), _dev_ptr(forces, "forces", (N, 3)),
+            _dev_ptr(energy5, "energy5", (5,)), _dev_ptr(status, "status", (1,), torch.int32))
+    s = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        check(lib.enuf_compute_noalloc(N, float(box), float(alpha), int(p), float(sigma), int(M), int(Kc),
+                                       float(r_cut), float(lam), pr, *args, ctypes.c_void_p(s)),
+              "enuf_compute_noalloc")
+    return forces, energy5, status
