@@ -82,9 +82,12 @@ hipError_t configure_pair_kernels(size_t lds_bytes);
 // rounds over the XCDs).
 int pair_blocks(const DpdParams &P);
 hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
+// pass_threads, x_threads: work-group sizes of the spread/gather passes and of
+// the x pass (at least fft_max_butterflies of every member).
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
                               const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
-                              size_t lds_bwd, hipStream_t st, KernelTimer *tm = nullptr);
+                              size_t lds_bwd, int pass_threads, int x_threads, hipStream_t st,
+                              KernelTimer *tm = nullptr);
 // Combine for every member, then the final energies (one block per member).
 hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *map, int nmap, int mode,
                                 hipStream_t st);

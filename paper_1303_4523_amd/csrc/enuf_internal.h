@@ -17,6 +17,15 @@ constexpr int kXSub = 8;           // sub-bins of a mesh x-cell (by compact inde
 constexpr int kMaxRadixPasses = 16;
 constexpr int kMaxChebDeg = 24;    // highest degree of the window series
 constexpr int kStage = 512;        // most charges of a plane staged in LDS at a time by the mesh passes
+// Batched mesh passes: work-groups of kBatchPassThreads threads staging at most
+// kBatchStage charges, so that two work-groups share a CU (the passes need
+// about 200-256 VGPRs per lane, two waves per SIMD): one work-group's waits on
+// memory and barriers overlap the other's work.
+constexpr int kBatchPassThreads = 256;
+constexpr int kBatchStage = 256;
+// The batched x pass (no charges, little LDS) in work-groups of 128 threads:
+// four share a CU.
+constexpr int kBatchXThreads = 128;
 constexpr int kMaxParts = 8;       // most work-groups per plane in the spread and gather passes
 
 // Device-resident scalars produced by the preparation kernels of one compute.
@@ -36,6 +45,15 @@ struct FftPlan {
   int npass;
   int radix[kMaxRadixPasses];
 };
+
+// Most butterflies per line of any radix pass of a plan: the LDS transforms
+// give each butterfly of a line its own thread, so a work-group needs at least
+// this many threads.
+inline int fft_max_butterflies(const FftPlan &f) {
+  int b = 0;
+  for (int k = 0; k < f.npass; ++k) b = f.n / f.radix[k] > b ? f.n / f.radix[k] : b;
+  return b;
+}
 
 // NFFT window, normalised to phi(0) = 1.  u is the offset t - l in mesh cells.
 struct WindowParams {

@@ -721,8 +721,8 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   T *twr = Xim + (size_t)nset * Kc * Mz;
   T *twi = twr + M;
   const size_t red_off = ((2 * (size_t)nset * Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
-  double *red = reinterpret_cast<double *>(smem + red_off);
-  double *at = red + kPassThreads / kWave;  // [nky] influence table
+  double *at = reinterpret_cast<double *>(smem + red_off);  // [nky] influence table
+  double *chunk = at + nky;  // [ceil(lines * M / 64)] energy of each run of 64 modes
 
   int nkz = 0;  // lines kz < nkz hold modes of the sphere
   while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
@@ -759,30 +759,42 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   lds_fft<T>(Xre + (size_t)kz_lo * Mz, Xim + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, false);
 
   const double ay = at[kyi];
-  double e = 0.0;
-  for (int id = tid; id < nl * M; id += nt) {
-    int m;
-    const int kz = kz_lo + fdivmod(id, M, inv_m, &m);
-    const int kx = m < M / 2 ? m : m - M;
-    const int k2 = kx * kx + ky * ky + kz * kz;
-    T hr = (T)0, hi = (T)0;
-    if (kx > -Kc && kx < Kc && k2 < Kc * Kc && k2 > 0) {
-      const double c = at[kx + Kc - 1] * ay * at[kz + Kc - 1] / (double)k2;
-      const double gr = (double)Xre[kz * Mz + m], gi = (double)Xim[kz * Mz + m];
-      e += (kz > 0 ? 2.0 : 1.0) * c * (gr * gr + gi * gi);
-      hr = (T)(c * gr);
-      hi = (T)(c * gi);
+  // Modes in runs of 64 (one wavefront each): the energy of a run is a
+  // wavefront sum and the runs add in order, so the result does not depend on
+  // the work-group size.
+  const int nmodes = nl * M, lane = tid & (kWave - 1);
+  for (int base = tid - lane; base < nmodes; base += nt) {
+    const int id = base + lane;
+    double e = 0.0;
+    if (id < nmodes) {
+      int m;
+      const int kz = kz_lo + fdivmod(id, M, inv_m, &m);
+      const int kx = m < M / 2 ? m : m - M;
+      const int k2 = kx * kx + ky * ky + kz * kz;
+      T hr = (T)0, hi = (T)0;
+      if (kx > -Kc && kx < Kc && k2 < Kc * Kc && k2 > 0) {
+        const double c = at[kx + Kc - 1] * ay * at[kz + Kc - 1] / (double)k2;
+        const double gr = (double)Xre[kz * Mz + m], gi = (double)Xim[kz * Mz + m];
+        e = (kz > 0 ? 2.0 : 1.0) * c * (gr * gr + gi * gi);
+        hr = (T)(c * gr);
+        hi = (T)(c * gi);
+      }
+      Xre[kz * Mz + m] = hr;
+      Xim[kz * Mz + m] = hi;
+      if (nset == 2) {  // i kx (hr + i hi)
+        Xre[(Kc + kz) * Mz + m] = -(T)kx * hi;
+        Xim[(Kc + kz) * Mz + m] = (T)kx * hr;
+      }
     }
-    Xre[kz * Mz + m] = hr;
-    Xim[kz * Mz + m] = hi;
-    if (nset == 2) {  // i kx (hr + i hi)
-      Xre[(Kc + kz) * Mz + m] = -(T)kx * hi;
-      Xim[(Kc + kz) * Mz + m] = (T)kx * hr;
-    }
+    e = wave_sum(e);
+    if (lane == 0) chunk[base / kWave] = e;
   }
-  e = block_sum(e, red);
-  if (tid == 0) epart[blk] = e;
   __syncthreads();
+  if (tid == 0) {
+    double e = 0.0;
+    for (int c = 0; c < (nmodes + kWave - 1) / kWave; ++c) e += chunk[c];
+    epart[blk] = e;
+  }
   for (int set = 0; set < nset; ++set) {
     T *re = Xre + (size_t)set * Kc * Mz, *im = Xim + (size_t)set * Kc * Mz;
     lds_fft<T>(re + (size_t)kz_lo * Mz, im + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, true);
@@ -1216,33 +1228,35 @@ hipError_t launch_batch_real(const BatchMember *mem, const int2 *map, int nmap, 
 
 template <typename T>
 static void launch_batch_mesh(const BatchMember *mem, int ik, const int2 *fwd, int nfwd, const int2 *x, int nx,
-                              const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd,
-                              hipStream_t st, KernelTimer *tm) {
+                              const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x, size_t lds_bwd, int tp,
+                              int tx, hipStream_t st, KernelTimer *tm) {
   if (tm) tm->before(5, st);
-  if (nfwd > 0) hipLaunchKernelGGL(kb_recip_fwd<T>, dim3(nfwd), dim3(kPassThreads), lds_fwd, st, mem, fwd);
+  if (nfwd > 0) hipLaunchKernelGGL(kb_recip_fwd<T>, dim3(nfwd), dim3(tp), lds_fwd, st, mem, fwd);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
-  if (nx > 0) hipLaunchKernelGGL(kb_recip_x<T>, dim3(nx), dim3(kPassThreads), lds_x, st, mem, x);
+  if (nx > 0) hipLaunchKernelGGL(kb_recip_x<T>, dim3(nx), dim3(tx), lds_x, st, mem, x);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
   if (nbwd > 0) {
     if (ik)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, true>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
-                         bwd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, true>), dim3(nbwd), dim3(tp), lds_bwd, st, mem, bwd);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, false>), dim3(nbwd), dim3(kPassThreads), lds_bwd, st, mem,
-                         bwd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(kb_recip_bwd<T, false>), dim3(nbwd), dim3(tp), lds_bwd, st, mem, bwd);
   }
   if (tm) tm->after(7, st);
 }
 
 hipError_t launch_batch_recip(const BatchMember *mem, int precision, int ik, const int2 *fwd, int nfwd,
                               const int2 *x, int nx, const int2 *bwd, int nbwd, size_t lds_fwd, size_t lds_x,
-                              size_t lds_bwd, hipStream_t st, KernelTimer *tm) {
+                              size_t lds_bwd, int pass_threads, int x_threads, hipStream_t st, KernelTimer *tm) {
+  if (pass_threads < 1 || pass_threads > kPassThreads || x_threads < 1 || x_threads > kPassThreads)
+    return hipErrorInvalidValue;
   if (precision == 0)
-    launch_batch_mesh<double>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st, tm);
+    launch_batch_mesh<double>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, pass_threads,
+                              x_threads, st, tm);
   else
-    launch_batch_mesh<float>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, st, tm);
+    launch_batch_mesh<float>(mem, ik, fwd, nfwd, x, nx, bwd, nbwd, lds_fwd, lds_x, lds_bwd, pass_threads,
+                             x_threads, st, tm);
   return hipGetLastError();
 }
 
@@ -1267,8 +1281,8 @@ void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, 
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
   *fwd = acc + zp + tw + misc;
-  *x = ((zp * (m.ik ? 2 : 1) + tw + 15) & ~(size_t)15) + (size_t)(kPassThreads / kWave) * sizeof(double) +
-       (size_t)m.nky * sizeof(double) + 16;
+  *x = ((zp * (m.ik ? 2 : 1) + tw + 15) & ~(size_t)15) + (size_t)m.nky * sizeof(double) +
+       (size_t)(((size_t)m.Kc * m.M + kWave - 1) / kWave) * sizeof(double) + 16;
   *bwd = rows_t + zp + tw + misc;
 }
 

@@ -519,6 +519,11 @@ int check_plan_args(int64_t N, double box, double alpha, int p, double sigma, in
   if (M < 4 || M % 2 != 0 || M > 4096) { set_error("M must be even and in [4, 4096]"); return ENUF_EINVAL; }
   *fp = FftPlan{};
   if (!factor_235(M, fp)) { set_error("M must be of the form 2^a 3^b 5^c"); return ENUF_EINVAL; }
+  if (fft_max_butterflies(*fp) > kPassThreads) {
+    set_error("M = " + std::to_string(M) + " needs more than " + std::to_string(kPassThreads) +
+              " butterflies per FFT pass (too few factors 4 and 8)");
+    return ENUF_EINVAL;
+  }
   if (2 * p > M / 2) { set_error("need 2p <= M/2"); return ENUF_EINVAL; }
   if (Kc < 1 || (double)Kc > (double)M / (2.0 * sigma)) { set_error("need 1 <= Kc <= M/(2 sigma)"); return ENUF_EINVAL; }
   if (!finite_pos(r_cut) || r_cut > 0.5 * box) { set_error("need 0 < r_cut <= box/2"); return ENUF_EINVAL; }
@@ -1670,6 +1675,7 @@ struct enuf_batch {
   int off[8] = {0};  // map offsets: pre, pair, real, fwd, x, bwd, comb, end
   int nmem = 0;      // members in the device table
   size_t lds_fwd = 0, lds_x = 0, lds_bwd = 0;
+  int pass_threads = kBatchPassThreads, x_threads = kBatchXThreads;  // work-group sizes of the mesh passes
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1705,6 +1711,10 @@ BatchMember member_view(const enuf_batch::Member &mb) {
   const enuf_plan *pl = d->plan;
   BatchMember m{};
   m.cfg = pl->cfg;
+  if (m.cfg.mesh.stage > kBatchStage) {  // the batch's smaller stage (less LDS per work-group)
+    m.cfg.mesh.stage = kBatchStage;
+    mesh_lds_bytes(m.cfg.mesh, pl->cfg.precision, &m.cfg.lds_fwd, &m.cfg.lds_x, &m.cfg.lds_bwd);
+  }
   m.buf = pl->buf;
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
@@ -1742,6 +1752,7 @@ int batch_rebuild(enuf_batch *b) {
   std::vector<BatchMember> mem;
   std::vector<int2> map[7];
   size_t lf = 0, lx = 0, lb = 0;
+  int tp = kBatchPassThreads, tx = kBatchXThreads;  // enough threads for every member's FFT passes
   for (int k : order) {
     const BatchMember m = member_view(b->members[k]);
     const int id = (int)mem.size();
@@ -1755,6 +1766,9 @@ int batch_rebuild(enuf_batch *b) {
     lf = std::max(lf, m.cfg.lds_fwd);
     lx = std::max(lx, m.cfg.lds_x);
     lb = std::max(lb, m.cfg.lds_bwd);
+    const int nbf = fft_max_butterflies(m.cfg.mesh.fft);
+    while (tp < nbf) tp *= 2;
+    while (tx < nbf) tx *= 2;
   }
   size_t nmap = 0;
   for (int s = 0; s < 7; ++s) {
@@ -1799,6 +1813,8 @@ int batch_rebuild(enuf_batch *b) {
   b->lds_fwd = lf;
   b->lds_x = lx;
   b->lds_bwd = lb;
+  b->pass_threads = tp;
+  b->x_threads = tx;
   b->drop_graph();
   b->dirty = false;
   return ENUF_OK;
@@ -1830,7 +1846,8 @@ hipError_t batch_step(enuf_batch *b, bool fork, KernelTimer *tm = nullptr) {
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
   if (e == hipSuccess)
     e = launch_batch_recip(b->dmem, b->precision, b->ik, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4],
-                           mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, st, tm);
+                           mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, b->pass_threads,
+                           b->x_threads, st, tm);
   if (fork)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->join_ev[k], 0);
   if (tm) tm->before(ENUF_K_COMBINE, st);

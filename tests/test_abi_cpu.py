@@ -48,6 +48,7 @@ BAD = [
     dict(N=0), dict(box=-1.0), dict(box=float("nan")), dict(alpha=0.0), dict(p=0), dict(p=16),
     dict(sigma=0.5), dict(M=31), dict(M=28), dict(M=14, p=4), dict(Kc=0), dict(Kc=9),
     dict(r_cut=5.1), dict(r_cut=0.0), dict(lam=-0.1), dict(M=2),
+    dict(M=1250),  # 2 x 5^4: a radix-2 pass of 625 butterflies per line, more than a work-group holds
 ]
 
 
