@@ -325,11 +325,17 @@ void enuf_batch_destroy(enuf_batch *batch);
  * work and drops its captured graph. */
 int enuf_batch_set_stream(enuf_batch *batch, void *hip_stream);
 
-/* use_graph: replay one captured step (1, default) or launch eagerly (0);
+/* use_graph: replay one captured step (1, default), launch eagerly (0), or
+ * ENUF_GRAPH_AUTO: capture only for a run of at least ENUF_GRAPH_AUTO_STEPS
+ * steps and replay the graph while the membership stays the same, launching
+ * shorter runs of a new membership eagerly (a capture costs milliseconds,
+ * more than the few steps between membership changes of a serving stream).
  * concurrent: in eager launches, fork the pair forces and real space onto
  * side streams (1, default) or keep the step on one stream (0).  The captured
  * step always uses the single-stream schedule.  Results do not depend on
- * either option. */
+ * either option.  Other values of use_graph return ENUF_EINVAL. */
+#define ENUF_GRAPH_AUTO        2
+#define ENUF_GRAPH_AUTO_STEPS 16
 int enuf_batch_set_options(enuf_batch *batch, int use_graph, int concurrent);
 
 /*

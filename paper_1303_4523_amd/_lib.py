@@ -147,6 +147,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
                 ECOINCIDENT: "ECOINCIDENT", EOVERFLOW: "EOVERFLOW"}
 FP64, MIXED = 0, 1
 WINDOW_KB, WINDOW_GAUSS = 0, 1
+GRAPH_AUTO, GRAPH_AUTO_STEPS = 2, 16
 FORCE_GRADIENT, FORCE_IK = 0, 1
 
 

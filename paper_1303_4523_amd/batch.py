@@ -27,8 +27,11 @@ class Batch:
         self.set_options(use_graph, concurrent)
 
     def set_options(self, use_graph=True, concurrent=True):
-        check(lib.enuf_batch_set_options(self._h, int(bool(use_graph)), int(bool(concurrent))),
-              "enuf_batch_set_options")
+        """use_graph: True (replay a captured step), False (eager launches) or
+        "auto" (capture only for runs of at least GRAPH_AUTO_STEPS steps and
+        reuse the graph while the membership is unchanged)."""
+        g = _lib.GRAPH_AUTO if use_graph == "auto" else int(bool(use_graph))
+        check(lib.enuf_batch_set_options(self._h, g, int(bool(concurrent))), "enuf_batch_set_options")
 
     def _bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream

@@ -128,6 +128,20 @@ __device__ inline long long to_fixed(double v, double scale) {
   return __double2ll_rn(v * scale);
 }
 
+// The same rounding (to nearest, ties to even) of v * scale in three
+// instructions for |v * scale| < 2^51 - 1: adding 1.5 * 2^52 moves the value
+// into the binade [2^52, 2^53), whose spacing is 1, so the addition itself
+// rounds to an integer and the bit pattern is that integer plus the constant's.
+// Larger magnitudes are clamped to +-(2^51 - 1) (the clamp also keeps the
+// product from being fused with the addition, which would round once instead
+// of twice).
+__device__ inline long long to_fixed_fast(double v, double scale) {
+  constexpr double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+  constexpr double kLim = 2251799813685247.0;     // 2^51 - 1
+  const double x = fmin(fmax(v * scale, -kLim), kLim);
+  return __double_as_longlong(x + kMagic) - __double_as_longlong(kMagic);
+}
+
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT over complex lines held in LDS (split re/im storage).
 // Line l, element e lives at re[l * ls + e], im[l * ls + e].  Each pass of

@@ -23,8 +23,10 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = M0 * c[0], hi0 = __umulhi(M0, c[0]);
-    const uint32_t lo1 = M1 * c[2], hi1 = __umulhi(M1, c[2]);
+    // one 32 x 32 -> 64-bit product gives both halves (a single multiply-add instruction)
+    const uint64_t p0 = (uint64_t)M0 * c[0], p1 = (uint64_t)M1 * c[2];
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;
@@ -276,9 +278,9 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
         const double th = dpd_theta(P.seed, step, (int)pi.w, (int)pj.w);
         const double aij = P.nspec > 1 ? P.atab[4 * (int)vi.w + (int)vj.w] : P.a;
         const double mag = aij * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
-        atomicAdd(&sh.acc[ia][0], (unsigned long long)to_fixed(mag * ex, kRealFxScale));
-        atomicAdd(&sh.acc[ia][1], (unsigned long long)to_fixed(mag * ey, kRealFxScale));
-        atomicAdd(&sh.acc[ia][2], (unsigned long long)to_fixed(mag * ez, kRealFxScale));
+        atomicAdd(&sh.acc[ia][0], (unsigned long long)to_fixed_fast(mag * ex, kRealFxScale));
+        atomicAdd(&sh.acc[ia][1], (unsigned long long)to_fixed_fast(mag * ey, kRealFxScale));
+        atomicAdd(&sh.acc[ia][2], (unsigned long long)to_fixed_fast(mag * ez, kRealFxScale));
       }
     }
     wave_sync();

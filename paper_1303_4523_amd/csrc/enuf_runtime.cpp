@@ -1909,8 +1909,9 @@ int enuf_batch_set_stream(enuf_batch *b, void *hip_stream) {
 
 int enuf_batch_set_options(enuf_batch *b, int use_graph, int concurrent) {
   if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  if (use_graph < 0 || use_graph > ENUF_GRAPH_AUTO) { set_error("use_graph must be 0, 1 or ENUF_GRAPH_AUTO"); return ENUF_EINVAL; }
   HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
-  b->use_graph = use_graph ? 1 : 0;
+  b->use_graph = use_graph;
   b->concurrent = concurrent ? 1 : 0;
   b->drop_graph();
   return ENUF_OK;
@@ -1978,7 +1979,9 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
   // The captured step is the single-stream schedule: no cross-stream event
   // record / wait inside a capture.
   KernelTimer *tm = b->timer.active();
-  if (b->use_graph && !b->exec && !tm) {
+  const bool graph = b->use_graph == 1 ||
+                     (b->use_graph == ENUF_GRAPH_AUTO && (b->exec || nsteps >= ENUF_GRAPH_AUTO_STEPS));
+  if (graph && !b->exec && !tm) {
     HIP_OR_RETURN(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), ENUF_EDEVICE);
     const hipError_t e = batch_step(b, false);
     hipGraph_t g = nullptr;
@@ -2001,7 +2004,7 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
   HIP_OR_RETURN(hipStreamWaitEvent(b->own, b->in_ev, 0), ENUF_EDEVICE);
   for (int s = 0; s < nsteps; ++s) {
     const hipError_t e = tm ? batch_step(b, false, tm)
-                            : (b->use_graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0));
+                            : (graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0));
     if (e != hipSuccess) {
       set_error(std::string("batched step launch failed: ") + hipGetErrorString(e));
       return ENUF_EDEVICE;

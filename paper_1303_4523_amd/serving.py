@@ -96,7 +96,9 @@ class Server:
         self.keep_state = keep_state
         self.sample_every = int(sample_every)
         self.stream = torch.cuda.Stream(self.device)   # non-blocking, default priority
-        self.batch = Batch(precision, device=self.device)
+        # membership changes every few steps: launch eagerly rather than
+        # capture a graph per membership
+        self.batch = Batch(precision, device=self.device, use_graph="auto")
         self.used = 0
         self.peak_used = 0
         self.peak_members = 0

@@ -41,6 +41,7 @@ def test_binding_lists_every_declared_symbol_and_code():
     assert d["ENUF_OK"] == _lib.OK and d["ENUF_EINVAL"] == _lib.EINVAL
     assert d["ENUF_ENONNEUTRAL"] == _lib.ENONNEUTRAL and d["ENUF_EOVERFLOW"] == _lib.EOVERFLOW
     assert d["ENUF_MIXED"] == _lib.MIXED and d["ENUF_WINDOW_GAUSS"] == _lib.WINDOW_GAUSS
+    assert d["ENUF_GRAPH_AUTO"] == _lib.GRAPH_AUTO and d["ENUF_GRAPH_AUTO_STEPS"] == _lib.GRAPH_AUTO_STEPS
 
 
 GOOD = dict(N=100, box=10.0, alpha=0.3, p=4, sigma=2.0, M=32, Kc=8, r_cut=3.0, lam=0.25)

@@ -49,7 +49,7 @@ def _same(a, b):
     return all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("use_graph,concurrent", [(True, True), (False, True), (True, False)])
+@pytest.mark.parametrize("use_graph,concurrent", [(True, True), (False, True), (True, False), ("auto", True)])
 def test_batch_equals_each_system_alone(use_graph, concurrent):
     """Six uneven replicas (valency 1-3, charge fraction 0.1-1, different M
     and Kc) stepped together: every member's state is bitwise the one it gets
@@ -169,6 +169,33 @@ def test_membership_changes_between_runs():
     for m in (m0, m1, m2):
         m[0].close()
     assert i1 != i0
+
+
+def test_auto_graph_policy_matches_eager():
+    """use_graph="auto": a long run captures and replays the step graph, a
+    shorter run of the same membership replays it again, and after a member
+    leaves a short run launches eagerly; the states equal those of an eager
+    batch taken through the same runs."""
+    from paper_1303_4523_amd import _lib
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([4, 7, 9])
+    print("case: auto graph policy", [r.meta["name"] for r in reps], flush=True)
+    out = {}
+    for mode in ("auto", False):
+        b = Batch("mixed", device=0, use_graph=mode)
+        mem = [_member(s) for s in reps]
+        ids = [b.add(*m, first_step=1) for m in mem]
+        b.run(_lib.GRAPH_AUTO_STEPS)
+        b.run(3)
+        b.remove(ids[0])
+        b.run(2)
+        torch.cuda.synchronize()
+        out[mode] = [tuple(t.cpu().numpy() for t in m[1:]) for m in mem]
+        b.close()
+        for m in mem:
+            m[0].close()
+    for a, c in zip(out["auto"], out[False]):
+        assert _same(a, c)
 
 
 def test_mixed_member_against_oracle():
