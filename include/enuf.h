@@ -338,6 +338,24 @@ int enuf_batch_set_stream(enuf_batch *batch, void *hip_stream);
 #define ENUF_GRAPH_AUTO_STEPS 16
 int enuf_batch_set_options(enuf_batch *batch, int use_graph, int concurrent);
 
+/* Launch parameters of the batched step; none of them changes any result bit
+ * (fixed-point sums, per-line k-space energies), only the time a step takes.
+ *   pass_threads: work-group size of the spread and gather passes, 256
+ *                 (default) or 512;
+ *   x_threads:    of the x pass, 128 (default), 256 or 512 (both are raised
+ *                 when a member's FFT has more butterflies per line);
+ *   stage:        most charges a mesh work-group stages in LDS at a time,
+ *                 32..512 (default 256; never more than the member's plan
+ *                 chose for its LDS budget);
+ *   pair_steps:   candidate steps in flight per lane of the pair kernel, 4
+ *                 (default) or 8;
+ *   x_split_mul:  x-pass work-groups per ky row, the plan's times this, 1..8
+ *                 (default 1; at most Kc).
+ * 0 keeps a value.  Takes effect at the next run (the graph is re-captured).
+ * ENUF_EINVAL (nothing changed) for values out of range. */
+int enuf_batch_set_tuning(enuf_batch *batch, int pass_threads, int x_threads, int stage, int pair_steps,
+                          int x_split_mul);
+
 /*
  * Add an integrator (with a plan of the batch's precision) and its state:
  * device arrays pos, vel, force of N x 3 FP64, owned by the caller and kept

@@ -99,6 +99,8 @@ lib.enuf_batch_set_stream.argtypes = [_vp, _vp]
 lib.enuf_batch_set_stream.restype = _int
 lib.enuf_batch_set_options.argtypes = [_vp, _int, _int]
 lib.enuf_batch_set_options.restype = _int
+lib.enuf_batch_set_tuning.argtypes = [_vp, _int, _int, _int, _int, _int]
+lib.enuf_batch_set_tuning.restype = _int
 lib.enuf_batch_add.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint64]
 lib.enuf_batch_add.restype = _int
 lib.enuf_batch_remove.argtypes = [_vp, _int]
@@ -132,6 +134,7 @@ EXPORTED = [
     "enuf_dpd_energy", "enuf_dpd_status", "enuf_dpd_destroy",
     "enuf_dpd_time_kernel", "enuf_dpd_kernel_time", "enuf_dpd_footprint_bytes",
     "enuf_batch_create", "enuf_batch_destroy", "enuf_batch_set_stream", "enuf_batch_set_options",
+    "enuf_batch_set_tuning",
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
     "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",

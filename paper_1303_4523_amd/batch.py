@@ -5,6 +5,10 @@ state tensors; one run advances all members with one kernel launch per stage
 of the step, replayed from a captured HIP graph.
 """
 import ctypes
+import hashlib
+import json
+import math
+import os
 
 import torch
 
@@ -55,6 +59,96 @@ class Batch:
 
     def __len__(self):
         return int(lib.enuf_batch_size(self._h))
+
+    # launch parameters of enuf_batch_set_tuning, with their defaults
+    TUNING_DEFAULTS = dict(pass_threads=256, x_threads=128, stage=256, pair_steps=4, x_split_mul=1)
+    # candidates per stage group: (stages timed, {parameter: values})
+    TUNING_SPACE = (
+        (("mesh_fwd", "mesh_bwd"), dict(pass_threads=(256, 512), stage=(128, 256, 512))),
+        (("mesh_x",), dict(x_threads=(128, 256), x_split_mul=(1, 2, 4))),
+        (("dpd_pair",), dict(pair_steps=(4, 8))),
+    )
+
+    def set_tuning(self, **params):
+        """Launch parameters of the batched step (names as TUNING_DEFAULTS);
+        results do not depend on them."""
+        bad = set(params) - set(self.TUNING_DEFAULTS)
+        if bad:
+            raise ValueError(f"unknown tuning parameters {sorted(bad)}")
+        p = [int(params.get(k, 0)) for k in self.TUNING_DEFAULTS]
+        check(lib.enuf_batch_set_tuning(self._h, *p), "enuf_batch_set_tuning")
+        self._tuning = dict(getattr(self, "_tuning", self.TUNING_DEFAULTS), **params)
+
+    def signature(self):
+        """Key of the batch's composition for the tuning cache: precision and
+        the sorted (M, Kc, p, log2 bucket of N_q, log2 bucket of N) of the
+        members."""
+        rows = []
+        for d, *_ in self._members.values():
+            e = d.enuf
+            rows.append((int(e["M"]), int(e["Kc"]), int(e["p"]), int(math.log2(max(d.nq, 1))),
+                         int(math.log2(max(d.N, 1)))))
+        text = json.dumps([self.precision, sorted(rows)])
+        return hashlib.sha1(text.encode()).hexdigest()[:16]
+
+    def _stage_us(self, names, steps):
+        t = 0.0
+        for k in names:
+            self.time_kernel(k, steps)
+            self.run(steps)
+            ms, n = self.kernel_time()
+            self.time_kernel(None, 1)
+            t += ms / max(n, 1) * 1e3
+        return t
+
+    def autotune(self, steps=3, cache=None):
+        """Choose the launch parameters by timing each candidate on this
+        batch's own steps (eager, one stage group at a time, keeping the
+        fastest; the members advance by the steps taken, so tune a batch of
+        the same systems built for the purpose, or accept the advance).  With
+        `cache` (a JSON file path) a stored choice for the same signature is
+        applied without timing, and a new choice is stored.  Returns
+        dict(params, default_us, tuned_us, signature, cached) with the timed
+        stage groups' microseconds per step under the defaults and the
+        choice."""
+        key = self.signature()
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+        if key in store:
+            self.set_tuning(**store[key]["params"])
+            return dict(store[key], signature=key, cached=True)
+        best = dict(self.TUNING_DEFAULTS)
+        self.set_tuning(**best)
+        self.run(1)   # rebuild and warm the kernels
+        default_us = {"+".join(n): self._stage_us(n, steps) for n, _ in self.TUNING_SPACE}
+        tuned_us = {}
+        for names, space in self.TUNING_SPACE:
+            tag = "+".join(names)
+            choice, t_best = None, None
+            keys = list(space)
+            combos = [()]
+            for k in keys:
+                combos = [c + (v,) for c in combos for v in space[k]]
+            for combo in combos:
+                trial = dict(best, **dict(zip(keys, combo)))
+                self.set_tuning(**trial)
+                self.run(1)
+                t = self._stage_us(names, steps)
+                if t_best is None or t < t_best:
+                    choice, t_best = dict(zip(keys, combo)), t
+            best.update(choice)
+            tuned_us[tag] = t_best
+        self.set_tuning(**best)
+        out = dict(params=best, default_us=default_us, tuned_us=tuned_us)
+        if cache:
+            store[key] = out
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(store, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(out, signature=key, cached=False)
 
     def run(self, nsteps):
         """Advance every member nsteps steps (ordered on the current stream)."""

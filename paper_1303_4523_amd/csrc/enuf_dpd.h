@@ -68,7 +68,8 @@ struct BatchMember {
 
 // Batched launches: map[b] = (member, block of that member) for block b.
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
-hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
+// steps: candidate steps in flight per lane (4 or 8, else hipErrorInvalidValue).
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int steps, hipStream_t st);
 // Column segments of the pair kernel for a grid of n cells per side.
 void pair_segments(int n, int *seg_cells, int *nseg);
 // Dynamic LDS bytes of the pair kernel (its staged particles).

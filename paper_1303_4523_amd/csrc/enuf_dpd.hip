@@ -207,10 +207,10 @@ static_assert(kPairCells <= kPairThreads, "the prefix sum takes one staged cell 
 static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
 // candidate steps in flight per lane: 8 for one system (150 VGPRs, 3 waves
 // per SIMD; 4.5 % less step time than 4 at N = 24000, where the kernel runs
-// beside the mesh passes), 4 in batches (128 VGPRs, 4 waves per SIMD; 8 %
-// less batch step time than 8, the batch filling the chip)
+// beside the mesh passes); batches take 4 (128 VGPRs, 4 waves per SIMD; 8 %
+// less batch step time than 8, the batch filling the chip) or 8
+// (enuf_batch_set_tuning)
 constexpr int kPairU = 8;
-constexpr int kPairUBatch = 4;
 constexpr int kPairPer = (kPairStage + kPairThreads - 1) / kPairThreads;  // staged particles copied per thread
 constexpr float kPairMargin = 1.0e-3f;
 
@@ -642,11 +642,12 @@ kb_dpd_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, in
   dpd_pre_body(m.N, mode, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt, m.cpos, m.cvel, m.status, m.ch, w.y);
 }
 
+template <int U>
 __global__ void __launch_bounds__(kPairThreads)
 kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pair_body<kPairUBatch>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
+  dpd_pair_body<U>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
                              to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
@@ -663,7 +664,7 @@ constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + siz
 
 hipError_t configure_pair_kernels(size_t lds_bytes) {
   const int v = (int)(lds_bytes > kPairLdsBytes ? lds_bytes : kPairLdsBytes);
-  const void *k[] = {(const void *)k_dpd_pair, (const void *)kb_dpd_pair};
+  const void *k[] = {(const void *)k_dpd_pair, (const void *)kb_dpd_pair<4>, (const void *)kb_dpd_pair<8>};
   for (const void *f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
     if (e != hipSuccess) return e;
@@ -676,8 +677,14 @@ hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, i
   return hipGetLastError();
 }
 
-hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st) {
-  if (nmap > 0) hipLaunchKernelGGL(kb_dpd_pair, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
+hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int steps, hipStream_t st) {
+  if (steps != 4 && steps != 8) return hipErrorInvalidValue;
+  if (nmap > 0) {
+    if (steps == 4)
+      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
+    else
+      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
+  }
   return hipGetLastError();
 }
 

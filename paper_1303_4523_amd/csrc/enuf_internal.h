@@ -148,7 +148,7 @@ struct ComputeBuffers {
                          // G[part][x][ky][kz] as fixed-point int64 pairs, then the field
                          // spectrum h[x][ky][kz] as complex T (double2 or float2)
   void *gzx;             // [M * nky * Kc] complex: i kx h for the ik forces
-  double *epart;         // [nky * xsplit] k-space energy per (ky row, kz range)
+  double *epart;         // [nky * Kc] k-space energy per (ky, kz) line
   double4 *part;         // [N * 2p * nslot] gather partials (dwx A, wx By, wx Bz, wx A)
   int *xcnt;             // [2 M kXSub] charges per mesh x-cell sub-bin (zero between calls; two sets like ccnt)
   int *xslot;            // [M kXSub xcap] compact indices of the charges of each x-cell sub-bin

@@ -722,14 +722,13 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   T *twi = twr + M;
   const size_t red_off = ((2 * (size_t)nset * Kc * Mz + 2 * (size_t)M) * sizeof(T) + 15) & ~(size_t)15;
   double *at = reinterpret_cast<double *>(smem + red_off);  // [nky] influence table
-  double *chunk = at + nky;  // [ceil(lines * M / 64)] energy of each run of 64 modes
 
   int nkz = 0;  // lines kz < nkz hold modes of the sphere
   while (nkz < Kc && nkz * nkz + ky * ky < Kc * Kc) ++nkz;
   const int l1 = nkz < kz_hi ? nkz : kz_hi;
   const int nl = l1 > kz_lo ? l1 - kz_lo : 0;  // transformed lines of this work-group
   const int nw = kz_hi - kz_lo;                 // stored lines (zero beyond nkz)
-  const float inv_nl = 1.0f / (float)(nl > 0 ? nl : 1), inv_m = 1.0f / (float)M,
+  const float inv_nl = 1.0f / (float)(nl > 0 ? nl : 1),
               inv_nw = 1.0f / (float)(nw > 0 ? nw : 1);
 
   for (int m = tid; m < M; m += nt) {
@@ -759,16 +758,18 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
   lds_fft<T>(Xre + (size_t)kz_lo * Mz, Xim + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, false);
 
   const double ay = at[kyi];
-  // Modes in runs of 64 (one wavefront each): the energy of a run is a
-  // wavefront sum and the runs add in order, so the result does not depend on
-  // the work-group size.
-  const int nmodes = nl * M, lane = tid & (kWave - 1);
-  for (int base = tid - lane; base < nmodes; base += nt) {
-    const int id = base + lane;
-    double e = 0.0;
-    if (id < nmodes) {
-      int m;
-      const int kz = kz_lo + fdivmod(id, M, inv_m, &m);
+  // A wavefront per kz line: the energy of the line is the sum of its runs of
+  // 64 modes (each a wavefront sum) in order, stored per line, so the total
+  // does not depend on the work-group size or on how lines are grouped into
+  // work-groups.  Stored lines past the sphere hold zero.
+  const int lane = tid & (kWave - 1), wv = tid / kWave, nwv = nt / kWave;
+  for (int l = wv; l < nw; l += nwv) {
+    const int kz = kz_lo + l;
+    double el = 0.0;
+    for (int m0 = 0; l < nl && m0 < M; m0 += kWave) {
+      const int m = m0 + lane;
+      double e = 0.0;
+      if (m < M) {
       const int kx = m < M / 2 ? m : m - M;
       const int k2 = kx * kx + ky * ky + kz * kz;
       T hr = (T)0, hi = (T)0;
@@ -785,16 +786,12 @@ recip_x_body(const MeshParams &mp, gptr<const double> __restrict__ atab,
         Xre[(Kc + kz) * Mz + m] = -(T)kx * hi;
         Xim[(Kc + kz) * Mz + m] = (T)kx * hr;
       }
+      }
+      el += wave_sum(e);
     }
-    e = wave_sum(e);
-    if (lane == 0) chunk[base / kWave] = e;
+    if (lane == 0) epart[(size_t)kyi * Kc + kz] = el;
   }
   __syncthreads();
-  if (tid == 0) {
-    double e = 0.0;
-    for (int c = 0; c < (nmodes + kWave - 1) / kWave; ++c) e += chunk[c];
-    epart[blk] = e;
-  }
   for (int set = 0; set < nset; ++set) {
     T *re = Xre + (size_t)set * Kc * Mz, *im = Xim + (size_t)set * Kc * Mz;
     lds_fft<T>(re + (size_t)kz_lo * Mz, im + (size_t)kz_lo * Mz, Mz, nl, mp.fft, twr, twi, true);
@@ -1079,11 +1076,11 @@ k_recip_bwd(const double4 *__restrict__ xq, const int *__restrict__ xcnt, const 
 // Combine: forces per particle and per-block energy partials.
 // ---------------------------------------------------------------------------
 // Final energies of one evaluation from the per-block partials of the combine
-// kernel and the k-space sums per (ky row, kz range) (one block; a separate launch, so the
+// kernel and the k-space sums per (ky, kz) line (one block; a separate launch, so the
 // partials of every combine block are visible without a device-wide fence).
 __device__ __forceinline__ void finish_body(int nblk, const double *__restrict__ blk_eg,
                                             const long long *__restrict__ blk_er,
-                                            const double *__restrict__ epart, int nky,
+                                            const double *__restrict__ epart, int nlines,
                                             const DevScalars *__restrict__ sc, double alpha, double inv2piL,
                                             double *energy, double *energy5, unsigned long long *step) {
   __shared__ double s_dbl[kPrepThreads / kWave];
@@ -1096,7 +1093,7 @@ __device__ __forceinline__ void finish_body(int nblk, const double *__restrict__
     tr += blk_er[2 * b];
     ts += blk_er[2 * b + 1];
   }
-  for (int b = tid; b < nky; b += blockDim.x) k += epart[b];
+  for (int b = tid; b < nlines; b += blockDim.x) k += epart[b];
   g = block_sum(g, s_dbl);
   k = block_sum(k, s_dbl);
   tr = block_sum_ll(tr, s_ll);
@@ -1120,9 +1117,9 @@ __device__ __forceinline__ void finish_body(int nblk, const double *__restrict__
 
 __global__ void __launch_bounds__(kPrepThreads)
 k_finish(int nblk, const double *__restrict__ blk_eg, const long long *__restrict__ blk_er,
-         const double *__restrict__ epart, int nky, const DevScalars *__restrict__ sc, double alpha,
+         const double *__restrict__ epart, int nlines, const DevScalars *__restrict__ sc, double alpha,
          double inv2piL, double *energy, double *energy5) {
-  finish_body(nblk, blk_eg, blk_er, epart, nky, sc, alpha, inv2piL, energy, energy5, nullptr);
+  finish_body(nblk, blk_eg, blk_er, epart, nlines, sc, alpha, inv2piL, energy, energy5, nullptr);
 }
 
 __global__ void __launch_bounds__(kPrepThreads)
@@ -1216,7 +1213,7 @@ kb_combine(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, in
 __global__ void __launch_bounds__(kPrepThreads)
 kb_finish(const BatchMember *__restrict__ mem, int mode) {
   const BatchMember &m = mem[blockIdx.x];
-  finish_body(m.nblk, m.buf.blk_eg, m.buf.blk_er, m.buf.epart, m.cfg.mesh.nky * m.cfg.mesh.xsplit, m.buf.sc,
+  finish_body(m.nblk, m.buf.blk_eg, m.buf.blk_er, m.buf.epart, m.cfg.mesh.nky * m.cfg.mesh.Kc, m.buf.sc,
               m.cfg.alpha, m.inv2piL,
               nullptr, m.e5, mode == 0 ? m.step : nullptr);
 }
@@ -1281,8 +1278,7 @@ void mesh_lds_bytes(const MeshParams &m, int precision, size_t *fwd, size_t *x, 
   const size_t zp = 2 * (size_t)m.Kc * m.Mz * ts;
   const size_t tw = 2 * (size_t)m.M * ts;
   *fwd = acc + zp + tw + misc;
-  *x = ((zp * (m.ik ? 2 : 1) + tw + 15) & ~(size_t)15) + (size_t)m.nky * sizeof(double) +
-       (size_t)(((size_t)m.Kc * m.M + kWave - 1) / kWave) * sizeof(double) + 16;
+  *x = ((zp * (m.ik ? 2 : 1) + tw + 15) & ~(size_t)15) + (size_t)m.nky * sizeof(double) + 16;
   *bwd = rows_t + zp + tw + misc;
 }
 
@@ -1426,7 +1422,7 @@ hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, dou
                      forces);
   if (fa.energies)
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const double *)b.blk_eg,
-                       (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky * cfg.mesh.xsplit,
+                       (const long long *)b.blk_er, (const double *)b.epart, cfg.mesh.nky * cfg.mesh.Kc,
                        (const DevScalars *)b.sc, cfg.alpha, inv2piL, energy_total, energy5);
   if (tm) tm->after(kid, st);
   return hipGetLastError();

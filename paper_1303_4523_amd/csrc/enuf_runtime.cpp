@@ -469,7 +469,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           nblk * 2 * sizeof(long long),                       // blk_er
           (size_t)(mesh_parts(M) + 1) * M * nky * (size_t)Kc * 16,  // gzy: partial spectra + field
           (size_t)M * nky * (size_t)Kc * sizeof(double2),     // gzx
-          nky * (size_t)Kc * sizeof(double),                  // epart (x-pass splits <= Kc)
+          nky * (size_t)Kc * sizeof(double),                  // epart: per (ky, kz) line
           n * P2 * (size_t)g.part_slots * sizeof(double4),    // part
           nblk * sizeof(double),                              // blk_eg
           2 * (size_t)M * kXSub * sizeof(int),                // xcnt (two sets)
@@ -1676,6 +1676,14 @@ struct enuf_batch {
   int nmem = 0;      // members in the device table
   size_t lds_fwd = 0, lds_x = 0, lds_bwd = 0;
   int pass_threads = kBatchPassThreads, x_threads = kBatchXThreads;  // work-group sizes of the mesh passes
+  // launch parameters (enuf_batch_set_tuning; none changes a result bit)
+  struct Tuning {
+    int pass_threads = kBatchPassThreads;  // spread / gather work-groups (raised to the members' FFT needs)
+    int x_threads = kBatchXThreads;        // x-pass work-groups (likewise)
+    int stage = kBatchStage;               // most charges staged per mesh work-group (at most the plan's)
+    int pair_steps = 4;                    // candidate steps in flight per lane of the pair kernel
+    int x_split_mul = 1;                   // x-pass work-groups per ky row: the plan's times this (<= Kc)
+  } tune;
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1706,15 +1714,18 @@ struct enuf_batch {
 
 namespace {
 
-BatchMember member_view(const enuf_batch::Member &mb) {
+BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &t) {
   const enuf_dpd *d = mb.d;
   const enuf_plan *pl = d->plan;
   BatchMember m{};
   m.cfg = pl->cfg;
-  if (m.cfg.mesh.stage > kBatchStage) {  // the batch's smaller stage (less LDS per work-group)
-    m.cfg.mesh.stage = kBatchStage;
+  if (m.cfg.mesh.stage > t.stage) {  // the batch's smaller stage (less LDS per work-group)
+    m.cfg.mesh.stage = t.stage;
     mesh_lds_bytes(m.cfg.mesh, pl->cfg.precision, &m.cfg.lds_fwd, &m.cfg.lds_x, &m.cfg.lds_bwd);
   }
+  // more x-pass work-groups per ky row (each a range of kz lines; the energy
+  // is kept per line, so the grouping does not change it)
+  m.cfg.mesh.xsplit = std::min(m.cfg.mesh.Kc, m.cfg.mesh.xsplit * t.x_split_mul);
   m.buf = pl->buf;
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
@@ -1752,9 +1763,9 @@ int batch_rebuild(enuf_batch *b) {
   std::vector<BatchMember> mem;
   std::vector<int2> map[7];
   size_t lf = 0, lx = 0, lb = 0;
-  int tp = kBatchPassThreads, tx = kBatchXThreads;  // enough threads for every member's FFT passes
+  int tp = b->tune.pass_threads, tx = b->tune.x_threads;  // enough threads for every member's FFT passes
   for (int k : order) {
-    const BatchMember m = member_view(b->members[k]);
+    const BatchMember m = member_view(b->members[k], b->tune);
     const int id = (int)mem.size();
     mem.push_back(m);
     const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;     // work-groups of the spread pass
@@ -1837,7 +1848,7 @@ hipError_t batch_step(enuf_batch *b, bool fork, KernelTimer *tm = nullptr) {
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
   }
   if (tm) tm->before(ENUF_K_DPD_PAIR, s0);
-  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], s0);
+  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], b->tune.pair_steps, s0);
   if (tm) tm->after(ENUF_K_DPD_PAIR, s0);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[0], s0);
   if (tm) tm->before(ENUF_K_REAL, s1);
@@ -1914,6 +1925,29 @@ int enuf_batch_set_options(enuf_batch *b, int use_graph, int concurrent) {
   b->use_graph = use_graph;
   b->concurrent = concurrent ? 1 : 0;
   b->drop_graph();
+  return ENUF_OK;
+}
+
+int enuf_batch_set_tuning(enuf_batch *b, int pass_threads, int x_threads, int stage, int pair_steps,
+                          int x_split_mul) {
+  if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
+  enuf_batch::Tuning t = b->tune;
+  if (pass_threads) t.pass_threads = pass_threads;
+  if (x_threads) t.x_threads = x_threads;
+  if (stage) t.stage = stage;
+  if (pair_steps) t.pair_steps = pair_steps;
+  if (x_split_mul) t.x_split_mul = x_split_mul;
+  if (t.pass_threads != 256 && t.pass_threads != 512) { set_error("pass_threads must be 256 or 512"); return ENUF_EINVAL; }
+  if (t.x_threads != 128 && t.x_threads != 256 && t.x_threads != 512) {
+    set_error("x_threads must be 128, 256 or 512");
+    return ENUF_EINVAL;
+  }
+  if (t.stage < 32 || t.stage > kStage) { set_error("stage must be in [32, " + std::to_string(kStage) + "]"); return ENUF_EINVAL; }
+  if (t.pair_steps != 4 && t.pair_steps != 8) { set_error("pair_steps must be 4 or 8"); return ENUF_EINVAL; }
+  if (t.x_split_mul < 1 || t.x_split_mul > 8) { set_error("x_split_mul must be in [1, 8]"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
+  b->tune = t;
+  b->dirty = true;  // rebuilt (and the graph dropped) at the next run
   return ENUF_OK;
 }
 

@@ -19,7 +19,10 @@ class DPD:
 
     def __init__(self, L, q, params, bonds=None, enuf=None, precision="fp64", device=None):
         self.device = _device(device)
-        q = torch.as_tensor(np.asarray(q, dtype=np.float64), device=self.device).contiguous()
+        qh = np.asarray(q, dtype=np.float64)
+        self.nq = int(np.count_nonzero(qh))            # charged particles
+        self.enuf = dict(enuf) if enuf is not None else None
+        q = torch.as_tensor(qh, device=self.device).contiguous()
         self.N = int(q.shape[0])
         self.L = float(L)
         self.plan = None

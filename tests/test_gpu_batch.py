@@ -198,6 +198,56 @@ def test_auto_graph_policy_matches_eager():
         assert _same(a, c)
 
 
+def test_tuning_does_not_change_results():
+    """Launch parameters other than the defaults (512-thread mesh passes,
+    256-thread x pass, stage 128, 8 pair steps, 4x x-split) give bitwise the
+    states and energies of the defaults."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([0, 3, 5, 10])
+    print("case: tuning", [r.meta["name"] for r in reps], flush=True)
+    out = {}
+    for tuned in (False, True):
+        b = Batch("mixed", device=0)
+        if tuned:
+            b.set_tuning(pass_threads=512, x_threads=256, stage=128, pair_steps=8, x_split_mul=4)
+        mem = [_member(s) for s in reps]
+        for m in mem:
+            b.add(*m, first_step=1)
+        b.run(3)
+        torch.cuda.synchronize()
+        out[tuned] = [tuple(t.cpu().numpy() for t in m[1:]) + (m[0].energy().cpu().numpy(),) for m in mem]
+        b.close()
+        for m in mem:
+            m[0].close()
+    for a, c in zip(out[False], out[True]):
+        assert _same(a, c)
+
+
+def test_autotune_caches_its_choice(tmp_path):
+    """autotune times the candidates once, stores the choice under the
+    batch's signature, and a batch of the same systems reuses it."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([4, 7])
+    cache = str(tmp_path / "tune.json")
+    got = []
+    for _ in range(2):
+        b = Batch("mixed", device=0)
+        mem = [_member(s) for s in reps]
+        for m in mem:
+            b.add(*m, first_step=1)
+        got.append(b.autotune(steps=1, cache=cache))
+        b.run(1)
+        torch.cuda.synchronize()
+        assert all(m[0].status() == 0 for m in mem)
+        b.close()
+        for m in mem:
+            m[0].close()
+    assert not got[0]["cached"] and got[1]["cached"]
+    assert got[0]["params"] == got[1]["params"] and got[0]["signature"] == got[1]["signature"]
+    with pytest.raises(Exception):
+        Batch("mixed", device=0).set_tuning(pass_threads=128)
+
+
 def test_mixed_member_against_oracle():
     """A replica with z = 3 salt in the mixed mode: forces at step 0 and the
     state after three steps against the FP64 oracle (mixed bar 5e-4)."""
