@@ -32,7 +32,7 @@ struct DpdCharges {
   int *slot = nullptr;          // plan: slot map read by the combine kernel
   int *ccnt = nullptr;          // plan: charge cell grid
   double4 *cgrid = nullptr;
-  int *cidx = nullptr;
+  float4 *cpre = nullptr;
   CellParams cells{};
   int *xcnt = nullptr;          // plan: charges binned by mesh x-cell
   int *xslot = nullptr;

@@ -141,7 +141,7 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
       const CellParams &cp = ch.cells;
       if (sl < cp.cap) {
         ch.cgrid[(size_t)c * cp.cap + sl] = make_double4(r[0], r[1], r[2], qi);
-        ch.cidx[(size_t)c * cp.cap + sl] = j;
+        ch.cpre[(size_t)c * cp.cap + sl] = make_float4((float)r[0], (float)r[1], (float)r[2], __int_as_float(j));
       } else {
         atomicCAS(&ch.sc->status, 0, kEOverflow);
       }

@@ -139,7 +139,8 @@ struct ComputeBuffers {
   // real-space cell grid
   int *ccnt;             // [2 ncell^3] two sets: a DPD step bins into one while the other is cleared
   double4 *cgrid;        // [ncell^3 * cap] (x, y, z, q) per cell slot
-  int *cidx;             // [ncell^3 * cap] compact index per cell slot
+  float4 *cpre;          // [ncell^3 * cap] FP32 (x, y, z) and the compact index (bits in w) per cell
+                         // slot: what the real-space scan's pre-test reads
   unsigned long long *freal;  // [N * 3] fixed-point real-space force per compact slot
   unsigned long long *ereal; // [2 N] fixed-point (E_real whole, E_slater) of the pairs (j, k > j), per compact slot j
   long long *blk_er;         // [2 nblk] per-block sums of ereal over the particles of the block

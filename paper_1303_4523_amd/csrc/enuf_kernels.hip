@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kPrepThreads)
 k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
                double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
                double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
-               int *cidx, int *xcnt, int *xslot, int M, double m_over_l, int xcap, DevScalars *sc) {
+               float4 *cpre, int *xcnt, int *xslot, int M, double m_over_l, int xcap, DevScalars *sc) {
   __shared__ int s_int[kPrepThreads / kWave];
   __shared__ int s_wcnt[kPrepThreads / kWave];
   __shared__ double s_dbl[kPrepThreads / kWave];
@@ -106,7 +106,7 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
       const int s = atomicAdd(&ccnt[cell], 1);
       if (s < cp.cap) {
         cgrid[(size_t)cell * cp.cap + s] = make_double4(x, y, z, qi);
-        cidx[(size_t)cell * cp.cap + s] = j;
+        cpre[(size_t)cell * cp.cap + s] = make_float4((float)x, (float)y, (float)z, __int_as_float(j));
       } else {
         set_status(sc, kEOverflow);
       }
@@ -230,32 +230,41 @@ __device__ inline bool cell_offset_valid(int o, int n) {
 }
 
 // One wavefront per charge j.  Scan: lanes 0..53 take one of the 27
-// neighbour cells and every other slot in it; the pairs within r_cut are
-// appended to a wavefront queue in LDS (with their minimum-image offsets).
-// Evaluation: the whole wavefront takes the queued pairs 64 at a time, so
-// the erfc / Slater terms run with full lanes however the pairs are spread
-// over the cells.  The wavefront sums the forces of all pairs of j (each pair
-// is evaluated from both of its charges, so no thread writes another charge's
-// force) and the energy of the pairs with k > j, as exact int64 fixed point;
-// the energies go to j's own slot (no shared accumulator).
+// neighbour cells and every other slot in it, test each candidate in FP32
+// (the slot's FP32 position copy, with a margin that covers its rounding) and
+// append those that pass to a wavefront queue in LDS (cell slot, compact
+// index).  Evaluation: the whole wavefront takes the queued candidates 64 at
+// a time, so the exact FP64 test (minimum image, r < r_cut) and the erfc /
+// Slater terms run with full lanes however the pairs are spread over the
+// cells; the pairs and displacements are exactly those of an all-FP64 scan.
+// The wavefront sums the forces of all pairs of j (each pair is evaluated
+// from both of its charges, so no thread writes another charge's force) and
+// the energy of the pairs with k > j, as exact int64 fixed point; the
+// energies go to j's own slot (no shared accumulator).
 constexpr int kRealThreads = 256;
 
-__device__ __forceinline__ void real_flush(int qn, const double *qx, const double *qy, const double *qz,
-                                           const double *qc, const int *qk, int j, double qj, double alpha,
-                                           double lam, long long &fx,
-                                           long long &fy, long long &fz, long long &ee, long long &es,
-                                           int &err) {
+// (charge j is read again here rather than kept in registers through the scan)
+__device__ __forceinline__ void real_flush(int qn, const int *qs, const int *qk, gptr<const double4> cgrid,
+                                           gptr<const double4> xq, int j, double L, double invL, double rc2,
+                                           double alpha, double lam, long long &fx, long long &fy,
+                                           long long &fz, long long &ee, long long &es, int &err) {
   const int lane = threadIdx.x & (kWave - 1);
+  const double4 ci = gload(xq + j);
   for (int e = lane; e < qn; e += kWave) {
-    const double dx = qx[e], dy = qy[e], dz = qz[e];
     const int k = qk[e];
+    const double4 cj = gload(cgrid + qs[e]);
+    double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
+    dx -= L * rint(dx * invL);
+    dy -= L * rint(dy * invL);
+    dz -= L * rint(dz * invL);
     const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < rc2)) continue;  // inside the FP32 margin only
     double u, us, f;
     if (!real_pair(sqrt(r2), alpha, lam, &u, &us, &f)) {
       err = kECoincident;
       continue;
     }
-    const double qq = qj * qc[e];
+    const double qq = ci.w * cj.w;
     const double g = qq * f;
     if (fabs(g) * sqrt(r2) * kRealFxScale > kFxLimit) err = kEOverflow;
     fx += to_fixed(g * dx, kRealFxScale);
@@ -268,30 +277,46 @@ __device__ __forceinline__ void real_flush(int qn, const double *qx, const doubl
   }
 }
 
+// Squared radius of the FP32 pre-test: r_cut plus 8 FP32 ulps of the box
+// length (the rounding of the positions, of L and of the differences stays
+// below 4 ulps of L per component), squared and rounded up.
+__device__ __forceinline__ float real_pretest_r2(double rc2, double L) {
+  int e;
+  frexp(L, &e);  // L < 2^e
+  const double rc = sqrt(rc2) + 8.0 * ldexp(1.0, e - 24);
+  return (float)(rc * rc * (1.0 + 1.0e-6));
+}
+
 // U: candidates per lane and pass (slots s, s + 2, ..., s + 2 (U - 1) of the
 // lane's cell), all U loads issued before any is tested.  The queue takes
 // U x 64 appends per pass and is flushed at > 64 entries.
 template <int U>
 __device__ __forceinline__ void
 real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt,
-          gptr<const double4> __restrict__ cgrid, gptr<const int> __restrict__ cidx, const CellParams &cp,
+          gptr<const double4> __restrict__ cgrid, gptr<const float4> __restrict__ cpre, const CellParams &cp,
           double L, double alpha, double rc2, double lam, gptr<DevScalars> sc, gptr<unsigned long long> freal,
           gptr<unsigned long long> ereal, int bid, int nbid) {
-  constexpr int kQueue = (U + 1) * kWave;  // queued pairs per wavefront
-  __shared__ double s_qx[kRealThreads / kWave][kQueue], s_qy[kRealThreads / kWave][kQueue],
-      s_qz[kRealThreads / kWave][kQueue];
-  __shared__ double s_qc[kRealThreads / kWave][kQueue];
-  __shared__ int s_qk[kRealThreads / kWave][kQueue];
+  constexpr int kQueue = (U + 1) * kWave;  // queued candidates per wavefront
+  __shared__ int s_qs[kRealThreads / kWave][kQueue];  // cell slot
+  __shared__ int s_qk[kRealThreads / kWave][kQueue];  // compact index
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int wpb = blockDim.x / kWave;
-  double *qx = s_qx[w], *qy = s_qy[w], *qz = s_qz[w];
-  double *qc = s_qc[w];
-  int *qk = s_qk[w];
+  int *qs = s_qs[w], *qk = s_qk[w];
   const int nq = sc->nq;
   const double invL = 1.0 / L;
+  const float Lf = (float)L, invLf = 1.0f / Lf, rc2f = real_pretest_r2(rc2, L);
   for (int j = bid * wpb + w; j < nq; j += nbid * wpb) {
-    const double4 ci = gload(xq + j);
-    int cx = (int)(ci.x * cp.inv_cell), cy = (int)(ci.y * cp.inv_cell), cz = (int)(ci.z * cp.inv_cell);
+    float cxf, cyf, czf;
+    int cx, cy, cz;
+    {
+      const double4 ci = gload(xq + j);
+      cxf = (float)ci.x;
+      cyf = (float)ci.y;
+      czf = (float)ci.z;
+      cx = (int)(ci.x * cp.inv_cell);
+      cy = (int)(ci.y * cp.inv_cell);
+      cz = (int)(ci.z * cp.inv_cell);
+    }
     cx = cx < cp.ncell ? cx : cp.ncell - 1;
     cy = cy < cp.ncell ? cy : cp.ncell - 1;
     cz = cz < cp.ncell ? cz : cp.ncell - 1;
@@ -308,31 +333,34 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
         cnt = cnt < cp.cap ? cnt : cp.cap;
       }
     }
-    const size_t cbase = (size_t)(c < 0 ? 0 : c) * cp.cap;
+    const int cbase = (c < 0 ? 0 : c) * cp.cap;
     int qn = 0;  // wavefront-uniform queue length
-    // test one candidate per lane and append the pairs within r_cut to the queue
-    auto test = [&](bool live, int k, const double4 &cj) {
+    // FP32 pre-test of one candidate per lane; those that pass are queued
+    auto test = [&](bool live, int sl, const float4 &cj) {
       bool take = false;
-      double dx = 0.0, dy = 0.0, dz = 0.0;
+      const int k = __float_as_int(cj.w);
       if (live) {
-        dx = ci.x - cj.x;
-        dy = ci.y - cj.y;
-        dz = ci.z - cj.z;
-        dx -= L * rint(dx * invL);
-        dy -= L * rint(dy * invL);
-        dz -= L * rint(dz * invL);
-        take = (k != j) && (dx * dx + dy * dy + dz * dz < rc2);
+        float dx = cxf - cj.x, dy = cyf - cj.y, dz = czf - cj.z;
+        dx -= Lf * rintf(dx * invLf);
+        dy -= Lf * rintf(dy * invLf);
+        dz -= Lf * rintf(dz * invLf);
+        take = (k != j) && (dx * dx + dy * dy + dz * dz < rc2f);
       }
       const unsigned long long m = __ballot(take);
       if (take) {
         const int at = qn + (int)__popcll(m & __lanemask_lt());
-        qx[at] = dx;
-        qy[at] = dy;
-        qz[at] = dz;
-        qc[at] = cj.w;
+        qs[at] = sl;
         qk[at] = k;
       }
       qn += (int)__popcll(m);
+    };
+    auto flush = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      real_flush(qn, qs, qk, cgrid, xq, j, L, invL, rc2, alpha, lam, fx, fy, fz, ee, es, err);
+      __builtin_amdgcn_wave_barrier();
+      qn = 0;
     };
     // the sums are fixed point, so the queue order does not change the result
     while (true) {
@@ -340,36 +368,18 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
 #pragma unroll
       for (int u = 0; u < U; ++u) live[u] = s + 2 * u < cnt;
       if (__ballot(live[0]) == 0ull) break;
-      int kk[U];
-      double4 cc[U];
+      float4 cc[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        kk[u] = 0;
-        cc[u] = make_double4(0.0, 0.0, 0.0, 0.0);
-      }
+      for (int u = 0; u < U; ++u) cc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (live[u]) {
-          kk[u] = cidx[cbase + s + 2 * u];
-          cc[u] = gload(cgrid + cbase + s + 2 * u);
-        }
+        if (live[u]) cc[u] = gload(cpre + cbase + s + 2 * u);
 #pragma unroll
-      for (int u = 0; u < U; ++u) test(live[u], kk[u], cc[u]);
+      for (int u = 0; u < U; ++u) test(live[u], cbase + s + 2 * u, cc[u]);
       s += 2 * U;
-      if (qn > kQueue - U * kWave) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        real_flush(qn, qx, qy, qz, qc, qk, j, ci.w, alpha, lam, fx, fy, fz, ee, es, err);
-        __builtin_amdgcn_wave_barrier();
-        qn = 0;
-      }
+      if (qn > kQueue - U * kWave) flush();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    real_flush(qn, qx, qy, qz, qc, qk, j, ci.w, alpha, lam, fx, fy, fz, ee, es, err);
-    __builtin_amdgcn_wave_barrier();
+    flush();
     if (err) set_status(sc, err);
     fx = wave_sum_ll(fx);
     fy = wave_sum_ll(fy);
@@ -388,11 +398,11 @@ real_body(gptr<const double4> __restrict__ xq, gptr<const int> __restrict__ ccnt
 
 // one system: two candidates per lane and pass at the kernel's natural
 // 168 VGPRs (3 waves per SIMD)
-__global__ void __launch_bounds__(kRealThreads)
+__global__ void __launch_bounds__(kRealThreads, 3)
 k_real(const double4 *__restrict__ xq, const int *__restrict__ ccnt, const double4 *__restrict__ cgrid,
-       const int *__restrict__ cidx, CellParams cp, double L, double alpha, double rc2, double lam,
+       const float4 *__restrict__ cpre, CellParams cp, double L, double alpha, double rc2, double lam,
        DevScalars *sc, unsigned long long *freal, unsigned long long *ereal) {
-  real_body<2>(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cidx), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
+  real_body<2>(to_g(xq), to_g(ccnt), to_g(cgrid), to_g(cpre), cp, L, alpha, rc2, lam, to_g(sc), to_g(freal),
                to_g(ereal), blockIdx.x, gridDim.x);
 }
 
@@ -1142,7 +1152,7 @@ __global__ void __launch_bounds__(kRealThreads, 3)
 kb_real(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  real_body<4>(to_g(m.buf.xq), to_g(m.buf.ccnt), to_g(m.buf.cgrid), to_g(m.buf.cidx), m.cfg.cells, m.cfg.L,
+  real_body<4>(to_g(m.buf.xq), to_g(m.buf.ccnt), to_g(m.buf.cgrid), to_g(m.buf.cpre), m.cfg.cells, m.cfg.L,
                m.cfg.alpha, m.cfg.r_cut * m.cfg.r_cut, m.cfg.lambda, to_g(m.buf.sc), to_g(m.buf.freal),
                to_g(m.buf.ereal), w.y, m.real_blocks);
 }
@@ -1376,7 +1386,7 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
                      (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
-                     b.cidx, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.sc);
+                     b.cpre, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.sc);
   hipLaunchKernelGGL(k_prep_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const int *)b.blk_cnt,
                      (const double *)b.blk_sums, b.sc);
   if (tm) tm->after(3, st);
@@ -1389,7 +1399,7 @@ hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_
   const int grid_real = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   if (tm) tm->before(4, st);
   hipLaunchKernelGGL(k_real, dim3(grid_real), dim3(kRealThreads), 0, st, (const double4 *)b.xq,
-                     (const int *)b.ccnt, (const double4 *)b.cgrid, (const int *)b.cidx, cfg.cells, cfg.L,
+                     (const int *)b.ccnt, (const double4 *)b.cgrid, (const float4 *)b.cpre, cfg.cells, cfg.L,
                      cfg.alpha, cfg.r_cut * cfg.r_cut, cfg.lambda, b.sc, b.freal, b.ereal);
   if (tm) tm->after(4, st);
   return hipGetLastError();

@@ -463,7 +463,7 @@ std::array<size_t, kPlanBuffers> plan_buffer_bytes(int64_t N, int p, int M, int 
           n * sizeof(int),                                    // slot
           2 * ncell3 * sizeof(int),                           // ccnt (two sets)
           ncell3 * cap * sizeof(double4),                     // cgrid
-          ncell3 * cap * sizeof(int),                         // cidx
+          ncell3 * cap * sizeof(float4),                      // cpre
           n * 3 * sizeof(unsigned long long),                 // freal
           n * 2 * sizeof(unsigned long long),                 // ereal
           nblk * 2 * sizeof(long long),                       // blk_er
@@ -557,6 +557,11 @@ bool plan_config(int64_t N, double box, double alpha, int p, double sigma, int M
               " bytes of LDS");
     return false;
   }
+  // the real-space scan numbers cell slots in 32 bits
+  if ((double)g->ncell * g->ncell * g->ncell * g->cap >= 2147483648.0) {
+    set_error("real-space cell grid too large: ncell^3 x capacity >= 2^31 slots (box / r_cut too large)");
+    return false;
+  }
   c.cells.ncell = g->ncell;
   c.cells.cap = g->cap;
   c.cells.inv_cell = (double)g->ncell / box;
@@ -589,7 +594,7 @@ ComputeBuffers carve_buffers(void *const *ptr) {
   b.slot = (int *)ptr[5];
   b.ccnt = (int *)ptr[6];
   b.cgrid = (double4 *)ptr[7];
-  b.cidx = (int *)ptr[8];
+  b.cpre = (float4 *)ptr[8];
   b.freal = (unsigned long long *)ptr[9];
   b.ereal = (unsigned long long *)ptr[10];
   b.blk_er = (long long *)ptr[11];
@@ -1248,7 +1253,7 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
     ch.slot = plan->buf.slot;
     ch.ccnt = plan->buf.ccnt;
     ch.cgrid = plan->buf.cgrid;
-    ch.cidx = plan->buf.cidx;
+    ch.cpre = plan->buf.cpre;
     ch.cells = plan->cfg.cells;
     ch.xcnt = plan->buf.xcnt;
     ch.xslot = plan->buf.xslot;
