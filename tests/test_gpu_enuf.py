@@ -103,6 +103,31 @@ def test_real_space_forces_exact():
     assert abs(E5[0] - Ee) < 1e-8
 
 
+def test_real_space_pairs_at_the_cutoff():
+    """Pairs 1e-9 inside and outside r_cut, at coordinates near 100 in a box
+    of 120 (where FP32 positions are off by up to 4e-6) and across the
+    periodic boundary: the FP32 pre-test of the scan keeps every pair the
+    exact FP64 test takes, so the forces and energy are the oracle's exact
+    real-space sums, the pair outside contributing nothing."""
+    from paper_1303_4523_amd import Plan
+    L, rc = 120.0, 3.0
+    pos = np.array([[100.123456789, 60.5, 60.5], [100.123456789 + rc * (1 - 1e-9), 60.5, 60.5],
+                    [10.5, 100.0987654321, 20.25], [10.5, 100.0987654321 + rc * (1 + 1e-9), 20.25],
+                    [50.25, 30.5, 0.0004], [50.25, 30.5, L - rc + 0.0004 + 3e-9]])
+    q = np.array([1.0, -1.0, 2.0, -2.0, 1.0, -1.0])
+    print("case: two pairs inside r_cut (one across the boundary), one just outside", flush=True)
+    p0 = Plan(len(q), L, 0.3, 4, 2.0, 32, 1, rc, 0.25)   # Kc = 1: real space only
+    F, E5, st = _run(p0, pos, q)
+    p0.close()
+    Fr, Ee, Es = oracle.real_space(pos, q, L, 0.3, rc, 0.25)
+    _, Eb, _ = oracle.real_space(pos[2:4], q[2:4], L, 0.3, rc, 0.25)
+    assert st == 0
+    assert Eb == 0.0 and Ee != 0.0
+    assert np.abs(F[2:4]).max() == 0.0
+    assert np.abs(F - Fr).max() < 1e-9
+    assert abs(E5[0] - Ee) < 1e-8
+
+
 @pytest.mark.parametrize("M,Kc,p,N,L", [(24, 6, 3, 257, 6.0), (30, 7, 3, 500, 7.5), (40, 10, 4, 1000, 8.0),
                                          (48, 12, 5, 1100, 12.0)])
 def test_mixed_radix_meshes(M, Kc, p, N, L):
