@@ -229,11 +229,15 @@ def headline(a, dev):
     if not bool(torch.isfinite(pos).all()):
         raise RuntimeError("non-finite positions after the timed steps")
 
-    # every kernel class of the step, event-timed on the stream it runs on
-    # (eager launches of the same schedule; separate steps from the timed ones)
+    # every kernel class of the step, event-timed on its stream in eager
+    # single-stream steps (separate from the timed ones), so that each pair of
+    # events brackets the kernel alone and not its wait for CUs held by the
+    # kernels of the other chain; the events add the dispatch of each launch
+    # (about 2-3 us) to the execution time a kernel trace reports
     first = 1 + a.warmup + K
     nk = max(10, min(K, 200))
     kern = {}
+    d.set_concurrency(False)
     for name in STEP_KERNELS:
         d.time_kernel(name, nk)
         d.run(pos, vel, F, first, nk)
