@@ -101,6 +101,15 @@ enuf_plan *enuf_plan_create(int64_t N, double box, double alpha, int p, double s
  */
 int enuf_plan_set_parts(enuf_plan *plan, int parts);
 
+/* Overlap the real-space term (Sec. 4, eq. 31-32, on an internal stream)
+ * with the mesh passes of the reciprocal sum (Sec. 3.3, eq. 14-25) in
+ * enuf_compute and enuf_compute_components (enable = 1, the default), or run
+ * the whole evaluation on the plan's stream (0).  The evaluation is serial
+ * anyway while the plan's stream is being captured into a graph or a kernel
+ * is being timed.  Results are the same either way.  Synchronises the plan's
+ * stream; ENUF_EINVAL for a NULL plan. */
+int enuf_plan_set_concurrency(enuf_plan *plan, int enable);
+
 /* Release the plan and its device memory.  Synchronises the plan's stream.  NULL is a no-op. */
 void enuf_destroy(enuf_plan *plan);
 

@@ -113,6 +113,8 @@ lib.enuf_batch_footprint_bytes.argtypes = [_vp]
 lib.enuf_batch_footprint_bytes.restype = _sz
 lib.enuf_plan_set_parts.argtypes = [_vp, _int]
 lib.enuf_plan_set_parts.restype = _int
+lib.enuf_plan_set_concurrency.argtypes = [_vp, _int]
+lib.enuf_plan_set_concurrency.restype = _int
 lib.enuf_dpd_set_species.argtypes = [_vp, _int, _vp, _vp]
 lib.enuf_dpd_set_species.restype = _int
 lib.enuf_pair_histogram.argtypes = [_vp, _i64, _i64, _vp, _vp, _int, _dbl, _dbl, _int, _vp, _vp]
@@ -138,6 +140,7 @@ EXPORTED = [
     "enuf_batch_add", "enuf_batch_remove", "enuf_batch_size", "enuf_batch_run", "enuf_batch_footprint_bytes",
     "enuf_plan_footprint_estimate", "enuf_dpd_footprint_estimate", "enuf_plan_set_force_mode",
     "enuf_dpd_set_species", "enuf_pair_histogram", "enuf_chain_rg2", "enuf_plan_set_parts",
+    "enuf_plan_set_concurrency",
     "enuf_plan_time_kernel", "enuf_plan_kernel_time", "enuf_batch_time_kernel", "enuf_batch_kernel_time",
     "enuf_compute_noalloc",
 ]

@@ -42,28 +42,83 @@ __device__ inline void set_status(gptr<DevScalars> sc, int code) {
 // ---------------------------------------------------------------------------
 // Preparation
 // ---------------------------------------------------------------------------
+// Per block: the number of charged particles and the sums of q, |q| and q^2,
+// a charge counting as 0 when its position or value is not finite (as the
+// compaction stores it; such input is reported as ENUF_ENONFINITE here, before
+// the neutrality of the sums is checked).
 __global__ void __launch_bounds__(kPrepThreads)
-k_prep_count(int64_t N, const double *__restrict__ q, int *blk_cnt, int *ccnt, int ncell3, int *xcnt,
-             int M) {
+k_prep_count(int64_t N, const double *__restrict__ pos, const double *__restrict__ q, int *blk_cnt,
+             double *blk_sums, int *ccnt, int ncell3, int *xcnt, int M, DevScalars *sc) {
+  __shared__ double s_dbl[kPrepThreads / kWave];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int flag = (i < N) && (q[i] != 0.0);
+  double qi = 0.0;
+  if (i < N) {
+    qi = q[i];
+    if (!(isfinite(pos[3 * i]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2]) && isfinite(qi))) {
+      qi = 0.0;
+      set_status(sc, kENonFinite);
+    }
+  }
   const int c = __syncthreads_count(flag);
-  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = c;
+  const double sq = block_sum(qi, s_dbl);
+  const double sa = block_sum(fabs(qi), s_dbl);
+  const double s2 = block_sum(qi * qi, s_dbl);
+  if (threadIdx.x == 0) {
+    blk_cnt[blockIdx.x] = c;
+    blk_sums[3 * blockIdx.x] = sq;
+    blk_sums[3 * blockIdx.x + 1] = sa;
+    blk_sums[3 * blockIdx.x + 2] = s2;
+  }
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = i; k < ncell3; k += stride) ccnt[k] = 0;
   for (int64_t k = i; k < M; k += stride) xcnt[k] = 0;
 }
 
+// Sums of the charges, their count and the fixed-point scale of the mesh
+// accumulator from the per-block partials of the count kernel (one block).
+__device__ inline void prep_scalars(int nblk, const int *__restrict__ blk_cnt, const double *__restrict__ blk_sums,
+                                    DevScalars *sc) {
+  __shared__ int s_int[kPrepThreads / kWave];
+  __shared__ double s_dbl[kPrepThreads / kWave];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0, c = 0.0;
+  int nq = 0;
+  for (int k = tid; k < nblk; k += blockDim.x) {
+    a += blk_sums[3 * k];
+    b += blk_sums[3 * k + 1];
+    c += blk_sums[3 * k + 2];
+    nq += blk_cnt[k];
+  }
+  a = block_sum(a, s_dbl);
+  b = block_sum(b, s_dbl);
+  c = block_sum(c, s_dbl);
+  nq = block_sum_int(nq, s_int);
+  if (tid == 0) {
+    sc->nq = nq;
+    sc->sum_q = a;
+    sc->sum_absq = b;
+    sc->sum_q2 = c;
+    // Mesh values are bounded by sum |q| (the window is <= 1): choose the
+    // largest power of two keeping sum|q| * scale below 2^61.
+    int e;
+    frexp(b + 1.0, &e);
+    sc->scale = ldexp(1.0, 61 - e);
+    sc->inv_scale = ldexp(1.0, e - 61);
+    if (fabs(a) > 1e-10 * b) set_status(sc, kENonNeutral);
+  }
+}
+
 __global__ void __launch_bounds__(kPrepThreads)
 k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restrict__ q,
                double L, CellParams cp, const int *__restrict__ blk_cnt, int nblk,
-               double *blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
+               const double *__restrict__ blk_sums, double4 *xq, int *idx, int *slot, int *ccnt, double4 *cgrid,
                float4 *cpre, int *xcnt, int *xslot, int M, double m_over_l, int xcap, DevScalars *sc) {
   __shared__ int s_int[kPrepThreads / kWave];
   __shared__ int s_wcnt[kPrepThreads / kWave];
-  __shared__ double s_dbl[kPrepThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (blockIdx.x == 0) prep_scalars(nblk, blk_cnt, blk_sums, sc);
 
   int part = 0;
   for (int b = tid; b < (int)blockIdx.x; b += blockDim.x) part += blk_cnt[b];
@@ -122,48 +177,6 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
       slot[i] = -1;
     }
     if (bad) set_status(sc, kENonFinite);
-  }
-  const double sq = block_sum(qi, s_dbl);
-  const double sa = block_sum(fabs(qi), s_dbl);
-  const double s2 = block_sum(qi * qi, s_dbl);
-  if (tid == 0) {
-    blk_sums[3 * blockIdx.x] = sq;
-    blk_sums[3 * blockIdx.x + 1] = sa;
-    blk_sums[3 * blockIdx.x + 2] = s2;
-  }
-}
-
-// Sums of the charges, their count and the fixed-point scale of the mesh
-// accumulator from the per-block partials of the compaction (one block).
-__global__ void __launch_bounds__(kPrepThreads)
-k_prep_finish(int nblk, const int *__restrict__ blk_cnt, const double *__restrict__ blk_sums, DevScalars *sc) {
-  __shared__ int s_int[kPrepThreads / kWave];
-  __shared__ double s_dbl[kPrepThreads / kWave];
-  const int tid = threadIdx.x;
-  double a = 0.0, b = 0.0, c = 0.0;
-  int nq = 0;
-  for (int k = tid; k < nblk; k += blockDim.x) {
-    a += blk_sums[3 * k];
-    b += blk_sums[3 * k + 1];
-    c += blk_sums[3 * k + 2];
-    nq += blk_cnt[k];
-  }
-  a = block_sum(a, s_dbl);
-  b = block_sum(b, s_dbl);
-  c = block_sum(c, s_dbl);
-  nq = block_sum_int(nq, s_int);
-  if (tid == 0) {
-    sc->nq = nq;
-    sc->sum_q = a;
-    sc->sum_absq = b;
-    sc->sum_q2 = c;
-    // Mesh values are bounded by sum |q| (the window is <= 1): choose the
-    // largest power of two keeping sum|q| * scale below 2^61.
-    int e;
-    frexp(b + 1.0, &e);
-    sc->scale = ldexp(1.0, 61 - e);
-    sc->inv_scale = ldexp(1.0, e - 61);
-    if (fabs(a) > 1e-10 * b) set_status(sc, kENonNeutral);
   }
 }
 
@@ -1380,15 +1393,13 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
   const int nblk = cfg.nblk;
   const int ncell3 = cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell;
   if (tm) tm->before(2, st);
-  hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, q, b.blk_cnt, b.ccnt,
-                     ncell3, b.xcnt, cfg.mesh.M * kXSub);
+  hipLaunchKernelGGL(k_prep_count, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, b.blk_cnt, b.blk_sums,
+                     b.ccnt, ncell3, b.xcnt, cfg.mesh.M * kXSub, b.sc);
   if (tm) tm->after(2, st);
   if (tm) tm->before(3, st);
   hipLaunchKernelGGL(k_prep_compact, dim3(nblk), dim3(kPrepThreads), 0, st, cfg.N, pos, q, cfg.L, cfg.cells,
-                     (const int *)b.blk_cnt, nblk, b.blk_sums, b.xq, b.idx, b.slot, b.ccnt, b.cgrid,
-                     b.cpre, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.sc);
-  hipLaunchKernelGGL(k_prep_finish, dim3(1), dim3(kPrepThreads), 0, st, nblk, (const int *)b.blk_cnt,
-                     (const double *)b.blk_sums, b.sc);
+                     (const int *)b.blk_cnt, nblk, (const double *)b.blk_sums, b.xq, b.idx, b.slot, b.ccnt,
+                     b.cgrid, b.cpre, b.xcnt, b.xslot, cfg.mesh.M, cfg.mesh.m_over_l, cfg.mesh.xcap, b.sc);
   if (tm) tm->after(3, st);
   return hipGetLastError();
 }

@@ -143,6 +143,9 @@ struct enuf_plan {
   std::vector<void *> allocations;
   size_t bytes = 0;
   EventTimer timer;  // enuf_plan_time_kernel
+  int concurrent = 1;                    // real-space term beside the mesh passes
+  hipStream_t side = nullptr;            // created at the first overlapped evaluation
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
   // All buffers in one device allocation (one hipMalloc / hipFree per
   // object), each at a 256-byte aligned offset.  False on failure.
@@ -160,6 +163,10 @@ struct enuf_plan {
     return true;
   }
   ~enuf_plan() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (side) (void)hipStreamDestroy(side);
     for (void *ptr : allocations) (void)hipFree(ptr);
   }
 };
@@ -777,6 +784,13 @@ int enuf_plan_set_parts(enuf_plan *plan, int parts) {
   return ENUF_OK;
 }
 
+int enuf_plan_set_concurrency(enuf_plan *plan, int enable) {
+  if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
+  HIP_OR_RETURN(hipStreamSynchronize(plan->stream), ENUF_EDEVICE);
+  plan->concurrent = enable ? 1 : 0;
+  return ENUF_OK;
+}
+
 int enuf_plan_set_force_mode(enuf_plan *plan, int mode) {
   if (!plan) { set_error("NULL plan"); return ENUF_EINVAL; }
   if (mode != ENUF_FORCE_GRADIENT && mode != ENUF_FORCE_IK) { set_error("unknown force mode"); return ENUF_EINVAL; }
@@ -808,7 +822,33 @@ static int compute_impl(enuf_plan *plan, const double *pos, const double *q, dou
   int dev = -1;
   HIP_OR_RETURN(hipGetDevice(&dev), ENUF_EDEVICE);
   if (dev != plan->device) HIP_OR_RETURN(hipSetDevice(plan->device), ENUF_EDEVICE);
-  hipError_t e = launch_compute(c, plan->buf, pos, q, forces, energy, energy5, plan->stream, plan->timer.active());
+  KernelTimer *tm = plan->timer.active();
+  hipStream_t st = plan->stream;
+  // the real-space term on the side stream, beside the mesh passes (no
+  // cross-stream events inside a capture, and one stream while timing)
+  bool fork = plan->concurrent && !tm;
+  if (fork) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    fork = hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+  }
+  hipError_t e = hipSuccess;
+  if (fork && !plan->side) {
+    e = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming);
+  }
+  if (e == hipSuccess && fork) {
+    e = launch_prep(c, plan->buf, pos, q, st, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(plan->fork_ev, st);
+    if (e == hipSuccess) e = launch_recip(c, plan->buf, c.N, st, nullptr);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->fork_ev, 0);
+    if (e == hipSuccess) e = launch_real(c, plan->buf, c.N, plan->side, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(plan->join_ev, plan->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, plan->join_ev, 0);
+    if (e == hipSuccess) e = launch_combine(c, plan->buf, forces, energy, energy5, FinishArgs(), st, nullptr);
+  } else if (e == hipSuccess) {
+    e = launch_compute(c, plan->buf, pos, q, forces, energy, energy5, st, tm);
+  }
   if (dev != plan->device) (void)hipSetDevice(dev);
   if (e != hipSuccess) {
     set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));

@@ -62,6 +62,11 @@ class Plan:
         batch, which already fills the device."""
         check(lib.enuf_plan_set_parts(self._h, int(parts)), "enuf_plan_set_parts")
 
+    def set_concurrency(self, enable):
+        """Real-space term beside the mesh passes (True, the default) or the
+        whole evaluation on one stream (False); results are the same."""
+        check(lib.enuf_plan_set_concurrency(self._h, int(bool(enable))), "enuf_plan_set_concurrency")
+
     def _bind_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib.enuf_plan_set_stream(self._h, ctypes.c_void_p(s)), "enuf_plan_set_stream")

@@ -1,7 +1,9 @@
 """Short fixed workloads for profiler runs (rocprofv3 counter and trace passes).
 
-    python -m paper_1303_4523_amd.profile_run [--single K] [--batch K]
+    python -m paper_1303_4523_amd.profile_run [--small K] [--single K] [--batch K]
 
+--small K:  K FP64 evaluations (Plan.compute) of the L = 10 system (N = 3000,
+            300 charges, M = 32, Kc = 8, p = 4);
 --single K: K FP64 evaluations (Plan.compute) of the DPD N = 24000 system
             (M = 64, Kc = 16, p = 4, 1650 charges);
 --batch K:  K eager single-stream steps of the 64-replica mixed batch
@@ -17,6 +19,21 @@ from . import Plan
 from . import workloads as wl
 from .batch import Batch
 from .dpd import DPD
+
+
+def small(k, dev):
+    s = wl.single_eval_small()
+    e = s.meta["enuf"]
+    p = Plan(s.N, e["L"], e["alpha"], e["p"], e["sigma"], e["M"], e["Kc"], e["r_cut"], e["lam"],
+             precision="fp64", device=dev)
+    pos = torch.tensor(s.pos, device=dev)
+    q = torch.tensor(s.q, device=dev)
+    F, E = p.compute(pos, q)
+    for _ in range(k):
+        p.compute(pos, q, F, E)
+    torch.cuda.synchronize()
+    p.close()
+    print(f"small: {k} evaluations of N={s.N}", flush=True)
 
 
 def single(k, dev):
@@ -58,10 +75,13 @@ def batch(k, dev):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--small", type=int, default=0)
     ap.add_argument("--single", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
     a = ap.parse_args()
     dev = torch.device("cuda", 0)
+    if a.small:
+        small(a.small, dev)
     if a.single:
         single(a.single, dev)
     if a.batch:

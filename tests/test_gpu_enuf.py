@@ -162,6 +162,73 @@ def test_deterministic_bitwise():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_overlapped_and_serial_evaluations_are_identical(precision):
+    """The real-space term beside the mesh passes (two streams) gives bitwise
+    the forces and energies of one stream, also for back-to-back evaluations
+    of different inputs enqueued without a synchronisation between them."""
+    dev = torch.device("cuda", 0)
+    systems = [wl.single_eval_small(), wl.n_sweep(15)]
+    print("case: overlapped vs serial", precision, [s.N for s in systems], flush=True)
+    out = {}
+    for conc in (True, False):
+        res = []
+        for s in systems:
+            plan = _plan(s.N, s.meta["enuf"], precision)
+            plan.set_concurrency(conc)
+            tp = torch.tensor(s.pos, device=dev)
+            tq = torch.tensor(s.q, device=dev)
+            shifted = tp + 0.37
+            runs = [plan.compute_components(x, tq) for x in (tp, shifted, tp)]
+            torch.cuda.synchronize()
+            res.append([(F.cpu().numpy(), E.cpu().numpy()) for F, E in runs] + [plan.status()])
+            plan.close()
+        out[conc] = res
+    for a, b in zip(out[True], out[False]):
+        assert a[-1] == 0 and b[-1] == 0
+        for (Fa, Ea), (Fb, Eb) in zip(a[:-1], b[:-1]):
+            assert np.array_equal(Fa, Fb) and np.array_equal(Ea, Eb)
+        assert np.array_equal(a[0][0], a[2][0])          # same input, same result
+        assert not np.array_equal(a[0][0], a[1][0])      # the shifted input was evaluated
+
+
+def test_evaluation_captured_in_a_graph_matches_eager():
+    """A graph captured around Plan.compute (the plan then keeps the whole
+    evaluation on the capturing stream) replays the eager result bitwise,
+    with eager evaluations of other inputs between the replays."""
+    dev = torch.device("cuda", 0)
+    s = wl.single_eval_small()
+    print("case: graph capture of Plan.compute", s.N, flush=True)
+    plan = _plan(s.N, s.meta["enuf"])
+    tp = torch.tensor(s.pos, device=dev)
+    tq = torch.tensor(s.q, device=dev)
+    F, E = plan.compute(tp, tq)
+    torch.cuda.synchronize()
+    Fe, Ee = F.clone(), E.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.compute(tp, tq, F, E)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.compute(tp, tq, F, E)
+    other = tp + 0.5
+    for _ in range(3):
+        F.zero_()
+        E.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(F, Fe) and torch.equal(E, Ee)
+        Fo, _ = plan.compute(other, tq)
+        torch.cuda.synchronize()
+        assert not torch.equal(Fo, Fe)
+    assert plan.status() == 0
+    del g
+    plan.close()
+
+
 def test_edge_cases():
     e = dict(L=10.0, alpha=0.3, p=4, sigma=2.0, M=32, Kc=8, r_cut=3.0, lam=0.25)
     rs = np.random.default_rng(0)
