@@ -219,8 +219,10 @@ hipError_t launch_prep(const ComputeConfig &cfg, const ComputeBuffers &b, const 
                        const double *q, hipStream_t st, KernelTimer *tm);
 hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
                        KernelTimer *tm);
+// x_threads: work-group size of the x pass (at least fft_max_butterflies of
+// the mesh, at most kPassThreads; others are raised or clamped to fit).
 hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                        KernelTimer *tm);
+                        KernelTimer *tm, int x_threads = kPassThreads);
 hipError_t launch_combine(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
                           double *energy_total, double *energy5, const FinishArgs &fa, hipStream_t st,
                           KernelTimer *tm);

@@ -1360,7 +1360,8 @@ hipError_t configure_kernels(size_t max_lds) {
 }
 
 template <typename T>
-static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st, KernelTimer *tm) {
+static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipStream_t st, KernelTimer *tm,
+                        int x_threads) {
   using C = typename CplxOf<T>::type;
   const C *tw = reinterpret_cast<const C *>(sizeof(T) == 8 ? (const void *)b.tw64 : (const void *)b.tw32);
   const T *wc = reinterpret_cast<const T *>(sizeof(T) == 8 ? (const void *)b.wcoef64 : (const void *)b.wcoef32);
@@ -1373,7 +1374,7 @@ static void launch_mesh(const ComputeConfig &cfg, const ComputeBuffers &b, hipSt
                      (const int *)b.xcnt, (const int *)b.xslot, wc, (const DevScalars *)b.sc, mp, tw, gfx);
   if (tm) tm->after(5, st);
   if (tm) tm->before(6, st);
-  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky * mp.xsplit), dim3(kPassThreads), cfg.lds_x, st, mp, b.atab, tw,
+  hipLaunchKernelGGL(k_recip_x<T>, dim3(mp.nky * mp.xsplit), dim3(x_threads), cfg.lds_x, st, mp, b.atab, tw,
                      (const DevScalars *)b.sc, (const longlong2 *)gfx, gh, reinterpret_cast<C *>(b.gzx), b.epart);
   if (tm) tm->after(6, st);
   if (tm) tm->before(7, st);
@@ -1417,12 +1418,17 @@ hipError_t launch_real(const ComputeConfig &cfg, const ComputeBuffers &b, int64_
 }
 
 hipError_t launch_recip(const ComputeConfig &cfg, const ComputeBuffers &b, int64_t nq_max, hipStream_t st,
-                        KernelTimer *tm) {
+                        KernelTimer *tm, int x_threads) {
   (void)nq_max;
+  // one thread per butterfly of an x line at least (the x pass sums its
+  // energy per (ky, kz) line, so the work-group size does not change it)
+  int tx = x_threads < kWave ? kWave : (x_threads > kPassThreads ? kPassThreads : x_threads);
+  while (tx < fft_max_butterflies(cfg.mesh.fft) && tx < kPassThreads) tx *= 2;
+  if (tx > kPassThreads) tx = kPassThreads;
   if (cfg.precision == 0)
-    launch_mesh<double>(cfg, b, st, tm);
+    launch_mesh<double>(cfg, b, st, tm, tx);
   else
-    launch_mesh<float>(cfg, b, st, tm);
+    launch_mesh<float>(cfg, b, st, tm, tx);
   return hipGetLastError();
 }
 
