@@ -13,6 +13,15 @@ boundaries and free their memory.  Members use one work-group per mesh plane
 it gets alone with that setting (each member keeps its own step counter and
 random stream).
 
+Creating an admitted system (its plan and integrator, the state upload and
+its initial forces) and destroying a finished one take milliseconds of host
+time each; two host threads do that work while the batched steps run (a
+system is created on a stream of its own and joins the batch, which waits
+for its initial forces, at the next step boundary), so the loop itself only
+joins prepared systems, launches the steps and reads the finished results.  Memory is counted from admission
+until the system is destroyed, so the resident footprint never exceeds the
+budget.
+
 Reported per request: arrival, admission and completion times (latency =
 completion - arrival), the final ENUF energy components and the device
 status.  With ``sample_every = k`` every k-th request (by id) also carries an
@@ -25,6 +34,8 @@ HIP kernels.
 """
 import collections
 import dataclasses
+import queue
+import threading
 import time
 
 import numpy as np
@@ -76,7 +87,7 @@ def footprint_estimate(system):
 
 
 class _Member:
-    __slots__ = ("req", "dpd", "pos", "vel", "force", "remaining", "admitted", "footprint", "mid")
+    __slots__ = ("req", "dpd", "pos", "vel", "force", "remaining", "admitted", "footprint", "reserved", "mid")
 
 
 class Server:
@@ -96,13 +107,20 @@ class Server:
         self.keep_state = keep_state
         self.sample_every = int(sample_every)
         self.stream = torch.cuda.Stream(self.device)   # non-blocking, default priority
+        # systems are created (uploads, initial forces) on a stream of their
+        # own: a copy on the server's stream would wait for the queued steps
+        self.create_stream = torch.cuda.Stream(self.device)
         # membership changes every few steps: launch eagerly rather than
         # capture a graph per membership
         self.batch = Batch(precision, device=self.device, use_graph="auto")
         self.used = 0
         self.peak_used = 0
         self.peak_members = 0
-        self.host_s = dict(admit=0.0, run=0.0, retire=0.0)   # wall time spent per phase
+        # wall time per phase: admit (creating systems, on the creator thread),
+        # run (launching and waiting for the batched steps), retire (reading
+        # results on the loop, destroying systems on the closer thread)
+        self.host_s = dict(admit=0.0, run=0.0, retire=0.0)
+        self._lock = threading.Lock()
 
     def _prepare(self, req, now):
         """Create the system on the device and queue its initial forces (runs
@@ -124,6 +142,8 @@ class Server:
         return m
 
     def _retire(self, m, now):
+        """Read a finished member's results and take it out of the batch (its
+        device memory is released later, by _destroy)."""
         e5 = m.dpd.energy().cpu().numpy()
         st = m.dpd.status()
         state = None
@@ -133,10 +153,20 @@ class Server:
         sample = None
         if self.sample_every > 0 and m.req.rid % self.sample_every == 0:
             sample = self._accuracy_sample(m)
-        m.dpd.close()
         return Result(rid=m.req.rid, N=m.req.system.N, arrival=m.req.arrival, admitted=m.admitted, finished=now,
                       steps=m.req.steps, status=st, energy5=e5, footprint=m.footprint, state=state,
                       sample=sample)
+
+    @staticmethod
+    def _destroy(m):
+        """Release a retired member's device memory (waits for the work queued
+        on the server's stream)."""
+        m.dpd.close()
+        m.dpd = m.pos = m.vel = m.force = None
+
+    def _add_time(self, phase, dt):
+        with self._lock:
+            self.host_s[phase] += dt
 
     def _accuracy_sample(self, m):
         """Electrostatic forces and energies of the member's final state from
@@ -152,20 +182,66 @@ class Server:
         results in completion order.  Requests larger than the whole budget
         are rejected (status EINVAL, no latency).
 
-        Loop: admit what has arrived and fits (creating the systems on the
-        device and queueing their initial forces), enqueue the batched steps up
-        to the next completion, admit again while the GPU works, then
-        synchronise, retire the finished members and let the prepared ones
-        join the batch."""
+        Loop: join the systems the creator thread has prepared, launch the
+        batched steps up to the next completion (one step while systems are
+        being created), admit what has arrived and
+        fits (the creator thread builds those systems and queues their initial
+        forces while the steps run), synchronise, read and retire the finished
+        members and hand them to the closer thread."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         active = {}
-        ready = []   # prepared, not yet members
         results = []
+        creating = 0   # admitted, not yet joined
+        to_create, to_close, made = queue.Queue(), queue.Queue(), queue.Queue()
+        freed = queue.Queue()
         t0 = clock()
 
+        def creator():
+            with torch.cuda.device(self.device), torch.cuda.stream(self.create_stream):
+                while True:
+                    job = to_create.get()
+                    if job is None:
+                        return
+                    try:
+                        ta = clock()
+                        m = self._prepare(job[0], job[1])
+                        m.reserved = job[2]
+                        self._add_time("admit", clock() - ta)
+                        made.put(m)
+                    except BaseException as ex:  # handed to the loop, which raises it
+                        made.put(ex)
+                        return
+
+        def closer():
+            with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+                while True:
+                    m = to_close.get()
+                    if m is None:
+                        return
+                    try:
+                        tc = clock()
+                        self._destroy(m)
+                        self._add_time("retire", clock() - tc)
+                        freed.put(m.reserved)
+                    except BaseException as ex:
+                        freed.put(ex)
+                        return
+
+        def settle_freed():
+            while True:
+                try:
+                    x = freed.get_nowait()
+                except queue.Empty:
+                    return
+                if isinstance(x, BaseException):
+                    raise x
+                self.used -= x
+
         def admit():
+            nonlocal creating
+            settle_freed()
             while pending and pending[0].arrival <= clock() - t0 and \
-                    len(active) + len(ready) < self.max_members:
+                    len(active) + creating < self.max_members:
                 req = pending[0]
                 need = footprint_estimate(req.system)
                 now = clock() - t0
@@ -178,45 +254,73 @@ class Server:
                 if self.used + need > self.budget:
                     break   # first come, first served: wait for memory
                 pending.popleft()
-                ta = clock()
-                m = self._prepare(req, now)
-                self.host_s["admit"] += clock() - ta
-                ready.append(m)
-                self.used += m.footprint
+                self.used += need   # the estimate is the footprint the system will hold
                 self.peak_used = max(self.peak_used, self.used)
+                creating += 1
+                to_create.put((req, now, need))
 
-        with torch.cuda.stream(self.stream):
-            while pending or active or ready:
-                admit()
-                if ready:
-                    for m in ready:
-                        m.mid = self.batch.add(m.dpd, m.pos, m.vel, m.force, first_step=1)
-                        active[m.mid] = m
-                    ready.clear()
-                self.peak_members = max(self.peak_members, len(active))
-                if not active:
-                    if pending:
-                        wait = pending[0].arrival - (clock() - t0)
-                        if wait > 0:
-                            time.sleep(min(wait, 0.01))
-                    continue
-                k = min(m.remaining for m in active.values())
-                tr = clock()
-                self.batch.run(k)
-                for m in active.values():
-                    m.remaining -= k
-                self.host_s["run"] += clock() - tr
-                admit()   # overlaps with the queued steps
-                tr = clock()
-                self.stream.synchronize()
-                self.host_s["run"] += clock() - tr
-                now = clock() - t0
-                tr = clock()
-                for mid in [mid for mid, m in active.items() if m.remaining == 0]:
-                    m = active.pop(mid)
-                    results.append(self._retire(m, now))
-                    self.used -= m.footprint
-                self.host_s["retire"] += clock() - tr
+        def join(block):
+            nonlocal creating
+            while creating:
+                try:
+                    m = made.get(block=block)
+                except queue.Empty:
+                    return
+                block = False
+                creating -= 1
+                if isinstance(m, BaseException):
+                    raise m
+                m.mid = self.batch.add(m.dpd, m.pos, m.vel, m.force, first_step=1)
+                active[m.mid] = m
+
+        threads = [threading.Thread(target=creator, daemon=True), threading.Thread(target=closer, daemon=True)]
+        for th in threads:
+            th.start()
+        try:
+            with torch.cuda.stream(self.stream):
+                while pending or active or creating:
+                    admit()
+                    # with nothing running, wait for a prepared system (or the next arrival)
+                    join(block=not active and creating > 0)
+                    self.peak_members = max(self.peak_members, len(active))
+                    if not active:
+                        if pending and not creating:
+                            wait = pending[0].arrival - (clock() - t0)
+                            if wait > 0:
+                                time.sleep(min(wait, 0.01))
+                        continue
+                    # up to the next completion, or one step while systems are
+                    # being created (they join at the next step boundary)
+                    k = min(m.remaining for m in active.values())
+                    if creating:
+                        k = 1
+                    tr = clock()
+                    self.batch.run(k)
+                    for m in active.values():
+                        m.remaining -= k
+                    self._add_time("run", clock() - tr)
+                    admit()   # overlaps with the queued steps
+                    tr = clock()
+                    self.stream.synchronize()
+                    self._add_time("run", clock() - tr)
+                    now = clock() - t0
+                    tr = clock()
+                    for mid in [mid for mid, m in active.items() if m.remaining == 0]:
+                        m = active.pop(mid)
+                        results.append(self._retire(m, now))
+                        to_close.put(m)
+                    self._add_time("retire", clock() - tr)
+        finally:
+            to_create.put(None)
+            to_close.put(None)
+            for th in threads:
+                th.join()
+            while not made.empty():   # prepared but never joined (after an error)
+                m = made.get()
+                if not isinstance(m, BaseException):
+                    self._destroy(m)
+                    self.used -= m.reserved
+            settle_freed()
         return results
 
     def close(self):
