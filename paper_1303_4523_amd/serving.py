@@ -96,16 +96,18 @@ class Server:
     hbm_budget: bytes of device memory the resident systems may hold.
     max_members: cap on concurrently resident systems.
     keep_state: copy each finished system's final (pos, vel, force) to the host.
+    creators: host threads that create admitted systems.
     """
 
     def __init__(self, hbm_budget, max_members=256, precision="mixed", device=0, keep_state=False,
-                 sample_every=0):
+                 sample_every=0, creators=2):
         self.device = torch.device("cuda", device) if isinstance(device, int) else device
         self.budget = int(hbm_budget)
         self.max_members = int(max_members)
         self.precision = precision
         self.keep_state = keep_state
         self.sample_every = int(sample_every)
+        self.creators = max(1, int(creators))
         self.stream = torch.cuda.Stream(self.device)   # non-blocking, default priority
         # systems are created (uploads, initial forces) on a stream of their
         # own: a copy on the server's stream would wait for the queued steps
@@ -116,7 +118,7 @@ class Server:
         self.used = 0
         self.peak_used = 0
         self.peak_members = 0
-        # wall time per phase: admit (creating systems, on the creator thread),
+        # wall time per phase: admit (creating systems, on the creator threads),
         # run (launching and waiting for the batched steps), retire (reading
         # results on the loop, destroying systems on the closer thread)
         self.host_s = dict(admit=0.0, run=0.0, retire=0.0)
@@ -182,10 +184,10 @@ class Server:
         results in completion order.  Requests larger than the whole budget
         are rejected (status EINVAL, no latency).
 
-        Loop: join the systems the creator thread has prepared, launch the
+        Loop: join the systems the creator threads have prepared, launch the
         batched steps up to the next completion (one step while systems are
         being created), admit what has arrived and
-        fits (the creator thread builds those systems and queues their initial
+        fits (the creator threads build those systems and queue their initial
         forces while the steps run), synchronise, read and retire the finished
         members and hand them to the closer thread."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -273,7 +275,8 @@ class Server:
                 m.mid = self.batch.add(m.dpd, m.pos, m.vel, m.force, first_step=1)
                 active[m.mid] = m
 
-        threads = [threading.Thread(target=creator, daemon=True), threading.Thread(target=closer, daemon=True)]
+        threads = [threading.Thread(target=creator, daemon=True) for _ in range(self.creators)]
+        threads.append(threading.Thread(target=closer, daemon=True))
         for th in threads:
             th.start()
         try:
@@ -311,7 +314,8 @@ class Server:
                         to_close.put(m)
                     self._add_time("retire", clock() - tr)
         finally:
-            to_create.put(None)
+            for _ in range(self.creators):
+                to_create.put(None)
             to_close.put(None)
             for th in threads:
                 th.join()
