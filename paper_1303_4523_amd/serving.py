@@ -15,12 +15,13 @@ random stream).
 
 Creating an admitted system (its plan and integrator, the state upload and
 its initial forces) and destroying a finished one take milliseconds of host
-time each; two host threads do that work while the batched steps run (a
-system is created on a stream of its own and joins the batch, which waits
-for its initial forces, at the next step boundary), so the loop itself only
-joins prepared systems, launches the steps and reads the finished results.  Memory is counted from admission
-until the system is destroyed, so the resident footprint never exceeds the
-budget.
+time each.  Host threads do that work while the batched steps run: creator
+threads build systems, each on a stream of its own, and a closer thread
+destroys finished ones.  A created system joins the batch, which waits for
+its initial forces, at the next step boundary, so the loop itself only joins
+prepared systems, launches the steps and reads the finished results.  Memory
+is counted from admission until the system is destroyed, so the resident
+footprint never exceeds the budget.
 
 Reported per request: arrival, admission and completion times (latency =
 completion - arrival), the final ENUF energy components and the device
