@@ -16,8 +16,8 @@ random stream).
 Creating an admitted system (its plan and integrator, the state upload and
 its initial forces) and destroying a finished one take milliseconds of host
 time each.  Host threads do that work while the batched steps run: creator
-threads build systems, each on a stream of its own, and a closer thread
-destroys finished ones.  A created system joins the batch, which waits for
+threads build systems on a creation stream (not the server's), and a
+closer thread destroys finished ones.  A created system joins the batch, which waits for
 its initial forces, at the next step boundary, so the loop itself only joins
 prepared systems, launches the steps and reads the finished results.  Memory
 is counted from admission until the system is destroyed, so the resident
