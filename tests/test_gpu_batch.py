@@ -329,3 +329,25 @@ def test_serving_admission_respects_the_budget():
     res2 = srv2.serve(reqs[:1])
     srv2.close()
     assert res2[0].status == -1 and res2[0].steps == 0
+
+
+def test_serving_reports_a_failed_creation():
+    """A request whose system cannot be created (its charges are not neutral,
+    which the footprint estimate does not check) makes serve raise the
+    library's error from the creator thread; the server's threads end and the
+    server can be closed."""
+    import threading
+
+    from paper_1303_4523_amd._lib import EnufError
+    from paper_1303_4523_amd.serving import Server
+    reqs = _requests(range(3), n_max=6000, steps=2)
+    bad = reqs[1].system
+    bad.q = np.array(bad.q, dtype=np.float64)
+    bad.q[np.flatnonzero(bad.q)[0]] += 1.0
+    print("case: serving with a non-neutral request", [r.system.meta["name"] for r in reqs], flush=True)
+    before = threading.active_count()
+    srv = Server(hbm_budget=8 << 30, precision="mixed", device=0)
+    with pytest.raises(EnufError):
+        srv.serve(reqs)
+    srv.close()
+    assert threading.active_count() == before
