@@ -359,11 +359,13 @@ int enuf_batch_set_options(enuf_batch *batch, int use_graph, int concurrent);
  *   pair_steps:   candidate steps in flight per lane of the pair kernel, 4
  *                 (default) or 8;
  *   x_split_mul:  x-pass work-groups per ky row, the plan's times this, 1..8
- *                 (default 1; at most Kc).
+ *                 (default 1; at most Kc);
+ *   pair_seg:     cells per column segment of the pair kernel, about, 1..26
+ *                 (default 26; a system stepped alone uses 10).
  * 0 keeps a value.  Takes effect at the next run (the graph is re-captured).
  * ENUF_EINVAL (nothing changed) for values out of range. */
 int enuf_batch_set_tuning(enuf_batch *batch, int pass_threads, int x_threads, int stage, int pair_steps,
-                          int x_split_mul);
+                          int x_split_mul, int pair_seg);
 
 /*
  * Add an integrator (with a plan of the batch's precision) and its state:

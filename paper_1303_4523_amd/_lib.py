@@ -99,7 +99,7 @@ lib.enuf_batch_set_stream.argtypes = [_vp, _vp]
 lib.enuf_batch_set_stream.restype = _int
 lib.enuf_batch_set_options.argtypes = [_vp, _int, _int]
 lib.enuf_batch_set_options.restype = _int
-lib.enuf_batch_set_tuning.argtypes = [_vp, _int, _int, _int, _int, _int]
+lib.enuf_batch_set_tuning.argtypes = [_vp, _int, _int, _int, _int, _int, _int]
 lib.enuf_batch_set_tuning.restype = _int
 lib.enuf_batch_add.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_uint64]
 lib.enuf_batch_add.restype = _int

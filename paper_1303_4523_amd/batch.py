@@ -61,12 +61,12 @@ class Batch:
         return int(lib.enuf_batch_size(self._h))
 
     # launch parameters of enuf_batch_set_tuning, with their defaults
-    TUNING_DEFAULTS = dict(pass_threads=256, x_threads=128, stage=256, pair_steps=4, x_split_mul=1)
+    TUNING_DEFAULTS = dict(pass_threads=256, x_threads=128, stage=256, pair_steps=4, x_split_mul=1, pair_seg=26)
     # candidates per stage group: (stages timed, {parameter: values})
     TUNING_SPACE = (
         (("mesh_fwd", "mesh_bwd"), dict(pass_threads=(256, 512), stage=(128, 256, 512))),
         (("mesh_x",), dict(x_threads=(128, 256), x_split_mul=(1, 2, 4))),
-        (("dpd_pair",), dict(pair_steps=(4, 8))),
+        (("dpd_pair",), dict(pair_steps=(4, 8), pair_seg=(10, 20, 26))),
     )
 
     def set_tuning(self, **params):

@@ -70,11 +70,17 @@ struct BatchMember {
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
 // steps: candidate steps in flight per lane (4 or 8, else hipErrorInvalidValue).
 hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int steps, hipStream_t st);
-// Column segments of the pair kernel for a grid of n cells per side.
-void pair_segments(int n, int *seg_cells, int *nseg);
-// Dynamic LDS bytes of the pair kernel (its staged particles).
-size_t pair_lds_bytes(const DpdParams &P);
-constexpr int kPairStage = 384;   // particles staged per segment (30 KB of LDS)
+// Column segments of the pair kernel for a grid of n cells per side, about
+// target cells each (1 .. kPairSegMax).
+void pair_segments(int n, int target, int *seg_cells, int *nseg);
+constexpr int kPairSeg = 10;      // cells per column segment, about: one system
+constexpr int kBatchPairSeg = 26; // batches (default of enuf_batch_set_tuning)
+constexpr int kPairSegMax = 26;   // longest segment the kernel's tables allow
+// Dynamic LDS bytes of the pair kernel (its staged particles; vlds: with their
+// velocities, as one system stages them).
+size_t pair_lds_bytes(const DpdParams &P, bool vlds);
+constexpr int kPairStage = 384;   // particles staged per segment, one system (30 KB of LDS with velocities)
+constexpr int kBatchPairStage = 600;  // batches (28 KB without velocities)
 constexpr int kPairStageMax = 1024;  // largest stage the kernel's tables allow
 constexpr int kPairOwn = 128;     // own particles of a chunk (LDS force accumulators); cell capacity limit
 // Allow the pair kernels the dynamic LDS of their staged particles.

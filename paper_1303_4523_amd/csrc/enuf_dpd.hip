@@ -160,22 +160,44 @@ k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__
   dpd_pre_body(N, mode, P, pos, vel, force, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
 }
 
+// Minimum-image separation d = a - b and |d|^2, with the rounding written
+// out (explicit fused multiply-adds, no contraction left to the compiler): the
+// scan's FP64 test and the evaluation agree, and every instantiation of the
+// pair kernels rounds alike, so a system's forces are bitwise the same alone
+// and in a batch.
+__device__ __forceinline__ double dpd_sep(const double4 &a, const double4 &b, double L, double invL, double &dx,
+                                          double &dy, double &dz) {
+#pragma clang fp contract(off)
+  dx = a.x - b.x;
+  dy = a.y - b.y;
+  dz = a.z - b.z;
+  dx = fma(-L, rint(dx * invL), dx);
+  dy = fma(-L, rint(dy * invL), dy);
+  dz = fma(-L, rint(dz * invL), dz);
+  return fma(dx, dx, fma(dy, dy, dz * dz));
+}
+
 __device__ inline bool dpd_offset_valid(int o, int n) {
   return n >= 3 || (n == 2 && o >= 0) || (n == 1 && o == 0);
 }
 
-// Pair forces by column segment.  A block takes a segment of about
-// kSegTarget consecutive cells of one z-column of the DPD cell grid (small
-// blocks leave room on every CU for the mesh passes that run beside this
-// kernel, and spread the work evenly).  It stages in LDS every particle of
+// Pair forces by column segment.  A block takes a segment of consecutive
+// cells of one z-column of the DPD cell grid: about kPairSeg for one system
+// (small blocks leave room on every CU for the mesh passes that run beside
+// this kernel, and spread the work evenly), longer in batches, which fill the
+// chip by themselves (the per-block counting and staging is then paid over
+// more cells).  It stages in LDS every particle of
 // the 9 neighbouring columns over the segment's z-range plus one cell on each
 // side (periodic images in a whole column), ordered by z-slice first and
 // column second: then the 27 neighbour cells of any cell of the segment are
 // three consecutive z-slices, so the candidates of all particles of that cell
 // form ONE contiguous range of the staged set.  Each staged particle keeps its
-// position (with its index), its predicted velocity (with its species) and an
-// FP32 position relative to the segment, shifted to the periodic image next
-// to it.
+// position (with its index), an FP32 position relative to the segment,
+// shifted to the periodic image next to it, with its cell slot, and (one
+// system) its predicted velocity (with its species).  Batches read the
+// velocity from the cell slot when a pair is evaluated: 48 instead of 80 bytes
+// of LDS per staged particle let a 600-particle stage (longer segments) fit
+// four blocks per CU.
 // Scan: a wavefront takes the segment's cells one at a time (a shared
 // counter deals them out); its 64 lanes take (particle, candidate) pairs of
 // the cell, g particles x 64/g candidates per step, and append the pairs that
@@ -197,11 +219,10 @@ __device__ inline bool dpd_offset_valid(int o, int n) {
 // force.  Grids of fewer than 3 cells per side (where a cell is its own
 // neighbour more than once) test every staged particle of the column set.
 constexpr int kPairThreads = 256;
-constexpr int kSegTarget = 10;    // cells per column segment, about
 constexpr int kPairWaves = kPairThreads / kWave;
 constexpr int kPairQueue = 128;   // queued pairs per wavefront (64 evaluated at a time)
 constexpr int kXcds = 8;          // MI355X: blocks of a launch are dealt round-robin to 8 XCDs
-constexpr int kPairZ = kSegTarget + 2;   // staged z-slices at most
+constexpr int kPairZ = kPairSegMax + 2;  // staged z-slices at most
 constexpr int kPairCells = 9 * kPairZ;   // staged cells at most
 static_assert(kPairCells <= kPairThreads, "the prefix sum takes one staged cell per thread");
 static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
@@ -211,7 +232,7 @@ static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
 // less batch step time than 8, the batch filling the chip) or 8
 // (enuf_batch_set_tuning)
 constexpr int kPairU = 8;
-constexpr int kPairPer = (kPairStage + kPairThreads - 1) / kPairThreads;  // staged particles copied per thread
+constexpr int kPairPer = (kPairStage + kPairThreads - 1) / kPairThreads;  // staged particles copied per thread and pass
 constexpr float kPairMargin = 1.0e-3f;
 
 struct PairShared {
@@ -230,7 +251,9 @@ struct PairShared {
 
 // Scan and evaluation over the own z-cells [zs, ze) of a chunk.  STAGED:
 // candidates are staged indices (virtual index - base); otherwise grid slots.
-template <int U, bool STAGED>
+// VLDS: the staged velocities are in LDS; otherwise they are read from their
+// cell slots when a pair is evaluated.
+template <int U, bool STAGED, bool VLDS>
 __device__ __forceinline__ void
 dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict__ cpos,
                gptr<const double4> __restrict__ cvel, PairShared &sh, const double4 *s_pos,
@@ -260,24 +283,25 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
   auto evaluate = [&](int n) {
     wave_sync();
     if (lane < n) {
+#pragma clang fp contract(off)
       const int jq = qj[lane], iq = qi[lane], ia = qa[lane];
       const double4 pi = STAGED ? s_pos[iq] : gload(cpos + iq);
-      const double4 vi = STAGED ? s_vel[iq] : gload(cvel + iq);
       const double4 pj = STAGED ? s_pos[jq] : gload(cpos + jq);
-      const double4 vj = STAGED ? s_vel[jq] : gload(cvel + jq);
-      double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-      dx -= L * rint(dx * invL);
-      dy -= L * rint(dy * invL);
-      dz -= L * rint(dz * invL);
-      const double r2 = dx * dx + dy * dy + dz * dz;
+      // staged: the velocities from LDS, or from the cell slots that the
+      // FP32 copies carry
+      const double4 vi = !STAGED ? gload(cvel + iq) : (VLDS ? s_vel[iq] : gload(cvel + __float_as_int(s_rel[iq].w)));
+      const double4 vj = !STAGED ? gload(cvel + jq) : (VLDS ? s_vel[jq] : gload(cvel + __float_as_int(s_rel[jq].w)));
+      double dx, dy, dz;
+      const double r2 = dpd_sep(pi, pj, L, invL, dx, dy, dz);
       if (r2 < 1.0 && r2 != 0.0) {
         const double r = sqrt(r2), ir = 1.0 / r;
         const double ex = dx * ir, ey = dy * ir, ez = dz * ir;
         const double wr = 1.0 - r;
-        const double vdot = (vi.x - vj.x) * ex + (vi.y - vj.y) * ey + (vi.z - vj.z) * ez;
+        const double vdot = fma(vi.x - vj.x, ex, fma(vi.y - vj.y, ey, (vi.z - vj.z) * ez));
         const double th = dpd_theta(P.seed, step, (int)pi.w, (int)pj.w);
         const double aij = P.nspec > 1 ? P.atab[4 * (int)vi.w + (int)vj.w] : P.a;
-        const double mag = aij * wr - P.gamma * wr * wr * vdot + P.sigma * wr * th * isdt;
+        // a_ij w - gamma w^2 (e.v) + sigma w theta / sqrt(dt)
+        const double mag = fma(aij, wr, fma(-(P.gamma * wr * wr), vdot, P.sigma * wr * th * isdt));
         atomicAdd(&sh.acc[ia][0], (unsigned long long)to_fixed_fast(mag * ex, kRealFxScale));
         atomicAdd(&sh.acc[ia][1], (unsigned long long)to_fixed_fast(mag * ey, kRealFxScale));
         atomicAdd(&sh.acc[ia][2], (unsigned long long)to_fixed_fast(mag * ez, kRealFxScale));
@@ -352,11 +376,8 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
             const float dx = ri.x - rj[u].x, dy = ri.y - rj[u].y, dz = ri.z - rj[u].z;
             take = jref[u] >= 0 && jref[u] != iref && (tiny || dx * dx + dy * dy + dz * dz < 1.0f + kPairMargin);
           } else {
-            double dx = pi.x - pj[u].x, dy = pi.y - pj[u].y, dz = pi.z - pj[u].z;
-            dx -= L * rint(dx * invL);
-            dy -= L * rint(dy * invL);
-            dz -= L * rint(dz * invL);
-            const double r2 = dx * dx + dy * dy + dz * dz;
+            double dx, dy, dz;
+            const double r2 = dpd_sep(pi, pj[u], L, invL, dx, dy, dz);
             take = jref[u] >= 0 && jref[u] != iref && r2 < 1.0 && r2 != 0.0;
           }
           const unsigned long long bm = __ballot(take);
@@ -378,7 +399,7 @@ dpd_pair_cells(const DpdParams &P, uint64_t step, gptr<const double4> __restrict
   if (qn > 0) evaluate(qn);
 }
 
-template <int U>
+template <int U, bool VLDS>
 __device__ __forceinline__ void
 dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__ pos,
               gptr<const int> __restrict__ dcnt, gptr<const double4> __restrict__ cpos,
@@ -436,10 +457,13 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
     }
     __syncthreads();
   }
+  // the stage: positions (with the particle index), with VLDS the predicted
+  // velocities (with the species), and the FP32 image-shifted positions with
+  // the particle's cell slot in the fourth word
   const int stage_cap = P.pair_stage;
   double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
   double4 *s_vel = s_pos + stage_cap;
-  float4 *s_rel = reinterpret_cast<float4 *>(s_vel + stage_cap);
+  float4 *s_rel = reinterpret_cast<float4 *>(s_pos + (VLDS ? 2 : 1) * stage_cap);
   // periodic image shifts and origin of the segment
   const double ox0 = cx * edge, oy0 = cy * edge, oz0 = (z0 - 1) * edge;
   const int zlo = tiny ? 0 : 1, zhi = zlo + (tiny ? n : zn);
@@ -472,7 +496,7 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       __syncthreads();
       if (S > 0) {
         for (int p0 = 0; p0 < S; p0 += kPairPer * kPairThreads) {
-          int pp[kPairPer], kk[kPairPer];
+          int pp[kPairPer], kk[kPairPer], gs[kPairPer];
           double4 e[kPairPer], v[kPairPer];
 #pragma unroll
           for (int r = 0; r < kPairPer; ++r) {
@@ -484,7 +508,8 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
           for (int r = 0; r < kPairPer; ++r) {
             const size_t g = (size_t)sh.gcell[kk[r]] * cap + (pp[r] + base - sh.off[kk[r]]);
             e[r] = gload(cpos + g);
-            v[r] = gload(cvel + g);
+            if (VLDS) v[r] = gload(cvel + g);
+            gs[r] = (int)g;
           }
 #pragma unroll
           for (int r = 0; r < kPairPer; ++r) {
@@ -494,8 +519,9 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
             const double sy = (Y < 0 ? -L : (Y >= n ? L : 0.0)) - oy0;
             const double sz = (Z < 0 ? -L : (Z >= n ? L : 0.0)) - oz0;
             s_pos[pp[r]] = e[r];
-            s_vel[pp[r]] = v[r];
-            s_rel[pp[r]] = make_float4((float)(e[r].x + sx), (float)(e[r].y + sy), (float)(e[r].z + sz), 0.f);
+            if (VLDS) s_vel[pp[r]] = v[r];
+            s_rel[pp[r]] = make_float4((float)(e[r].x + sx), (float)(e[r].y + sy), (float)(e[r].z + sz),
+                                       __int_as_float(gs[r]));
           }
         }
       }
@@ -508,9 +534,9 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
     if (threadIdx.x == 0) sh.next = 0;
     __syncthreads();
     if (staged)
-      dpd_pair_cells<U, true>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+      dpd_pair_cells<U, true, VLDS>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
     else
-      dpd_pair_cells<U, false>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
+      dpd_pair_cells<U, false, VLDS>(P, step, cpos, cvel, sh, s_pos, s_vel, s_rel, base, zs, ze, nz, tiny);
     __syncthreads();
     // bonds, F_i = -K (r - r0) rhat_ij, and the force of each own particle
     for (int t = threadIdx.x; t < nown; t += kPairThreads) {
@@ -524,11 +550,9 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
       const int b1 = bond_start[i + 1];
       for (int b = bond_start[i]; b < b1; ++b) {
         const int j = bond_to[b];
-        double dx = e.x - pos[3 * j], dy = e.y - pos[3 * j + 1], dz = e.z - pos[3 * j + 2];
-        dx -= L * rint(dx * invL);
-        dy -= L * rint(dy * invL);
-        dz -= L * rint(dz * invL);
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double4 pj = make_double4(pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], 0.0);
+        double dx, dy, dz;
+        const double r = sqrt(dpd_sep(e, pj, L, invL, dx, dy, dz));
         if (r == 0.0) continue;
         const double mag = -P.k_bond * (r - P.r0_bond) / r;
         fx += to_fixed(mag * dx, kRealFxScale);
@@ -550,12 +574,13 @@ __global__ void __launch_bounds__(kPairThreads)
 k_dpd_pair(DpdParams P, uint64_t step, const unsigned long long *step_dev, const double *__restrict__ pos,
            const int *__restrict__ dcnt, const double4 *__restrict__ cpos, const double4 *__restrict__ cvel,
            const int *__restrict__ bond_start, const int *__restrict__ bond_to, double *__restrict__ fdpd) {
-  dpd_pair_body<kPairU>(P, step_dev ? (uint64_t)*step_dev : step, to_g(pos), to_g(dcnt), to_g(cpos),
+  dpd_pair_body<kPairU, true>(P, step_dev ? (uint64_t)*step_dev : step, to_g(pos), to_g(dcnt), to_g(cpos),
                         to_g(cvel), to_g(bond_start), to_g(bond_to), to_g(fdpd), blockIdx.x, gridDim.x);
 }
 
-void pair_segments(int n, int *seg_cells, int *nseg) {
-  *nseg = (n + kSegTarget - 1) / kSegTarget;
+void pair_segments(int n, int target, int *seg_cells, int *nseg) {
+  target = target < 1 ? 1 : (target > kPairSegMax ? kPairSegMax : target);
+  *nseg = (n + target - 1) / target;
   *seg_cells = (n + *nseg - 1) / *nseg;
 }
 
@@ -565,8 +590,8 @@ int pair_blocks(const DpdParams &P) {
   return (int)blocks;
 }
 
-size_t pair_lds_bytes(const DpdParams &P) {
-  return (size_t)P.pair_stage * (2 * sizeof(double4) + sizeof(float4));
+size_t pair_lds_bytes(const DpdParams &P, bool vlds) {
+  return (size_t)P.pair_stage * ((vlds ? 2 : 1) * sizeof(double4) + sizeof(float4));
 }
 
 // mode 0: F = F_dpd + kappa F_elec and the closing half kick; mode 1: forces
@@ -647,7 +672,7 @@ __global__ void __launch_bounds__(kPairThreads)
 kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pair_body<U>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
+  dpd_pair_body<U, false>(m.P, *m.step, to_g(m.pos), to_g(m.dcnt), to_g(m.cpos), to_g(m.cvel),
                              to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
@@ -659,17 +684,19 @@ __global__ void k_add_u64(unsigned long long *dst) {
   if (threadIdx.x == 0) dst[0] += 1ull;
 }
 
-// every member stages kPairStage particles
+// one system stages kPairStage particles with their velocities; every
+// member of a batch stages kBatchPairStage without them
 constexpr size_t kPairLdsBytes = (size_t)kPairStage * (2 * sizeof(double4) + sizeof(float4));
+constexpr size_t kBatchPairLdsBytes = (size_t)kBatchPairStage * (sizeof(double4) + sizeof(float4));
 
 hipError_t configure_pair_kernels(size_t lds_bytes) {
   const int v = (int)(lds_bytes > kPairLdsBytes ? lds_bytes : kPairLdsBytes);
-  const void *k[] = {(const void *)k_dpd_pair, (const void *)kb_dpd_pair<4>, (const void *)kb_dpd_pair<8>};
-  for (const void *f : k) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void *)k_dpd_pair, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  const void *k[] = {(const void *)kb_dpd_pair<4>, (const void *)kb_dpd_pair<8>};
+  for (const void *f : k)
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchPairLdsBytes);
+  return e;
 }
 
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st) {
@@ -681,9 +708,9 @@ hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, 
   if (steps != 4 && steps != 8) return hipErrorInvalidValue;
   if (nmap > 0) {
     if (steps == 4)
-      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
+      hipLaunchKernelGGL(kb_dpd_pair<4>, dim3(nmap), dim3(kPairThreads), kBatchPairLdsBytes, st, mem, map);
     else
-      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), kPairLdsBytes, st, mem, map);
+      hipLaunchKernelGGL(kb_dpd_pair<8>, dim3(nmap), dim3(kPairThreads), kBatchPairLdsBytes, st, mem, map);
   }
   return hipGetLastError();
 }
@@ -717,7 +744,7 @@ hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const d
   (void)v0;
   const int nb = pair_blocks(P);
   if (tm) tm->before(1, st);
-  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P), st, P, step, step_dev, pos,
+  hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P, true), st, P, step, step_dev, pos,
                      dcnt, cpos, cvel, bond_start, bond_to, fdpd);
   if (tm) tm->after(1, st);
   return hipGetLastError();

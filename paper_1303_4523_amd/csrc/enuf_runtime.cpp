@@ -1188,6 +1188,11 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
     int nc0, cap0;
     dpd_geometry(N, box, &nc0, &cap0);
     if (cap0 > kPairOwn) { set_error("density too high: DPD cells would need more than 128 slots"); return nullptr; }
+    // the pair kernels hold cell slots in 32-bit integers
+    if ((int64_t)nc0 * nc0 * nc0 * cap0 >= (int64_t)1 << 31) {
+      set_error("DPD cell grid too large: ncell^3 x capacity >= 2^31 slots");
+      return nullptr;
+    }
   }
   std::vector<int> deg(N + 1, 0);
   for (int64_t b = 0; b < nbonds; ++b) {
@@ -1217,9 +1222,9 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   P.ncell = nc;
   P.cap = cap;
   P.inv_cell = (double)nc / box;
-  pair_segments(nc, &P.seg_cells, &P.nseg);
+  pair_segments(nc, kPairSeg, &P.seg_cells, &P.nseg);
   P.pair_stage = kPairStage;
-  if (configure_pair_kernels(pair_lds_bytes(P)) != hipSuccess) {
+  if (configure_pair_kernels(pair_lds_bytes(P, true)) != hipSuccess) {
     set_error("configuring the pair kernels failed");
     delete d;
     return nullptr;
@@ -1732,6 +1737,7 @@ struct enuf_batch {
     int stage = kBatchStage;               // most charges staged per mesh work-group (at most the plan's)
     int pair_steps = 4;                    // candidate steps in flight per lane of the pair kernel
     int x_split_mul = 1;                   // x-pass work-groups per ky row: the plan's times this (<= Kc)
+    int pair_seg = kBatchPairSeg;          // cells per column segment of the pair kernel, about
   } tune;
   bool dirty = true;
   hipGraph_t graph = nullptr;
@@ -1778,13 +1784,17 @@ BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &
   m.buf = pl->buf;
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
-  m.pair_blocks = pair_blocks(d->P);
   const int64_t g = (d->nq + 3) / 4;
   m.real_blocks = (int)(g < 1 ? 1 : (g < 2048 ? g : 2048));
   m.fscale = pl->cfg.mesh.ik ? 2.0 / (pl->cfg.L * pl->cfg.L) : (double)pl->cfg.mesh.M / (M_PI * pl->cfg.L * pl->cfg.L);
   m.inv2piL = 1.0 / (2.0 * M_PI * pl->cfg.L);
   m.N = d->N;
   m.P = d->P;
+  // the batch's segments and stage (the pair kernel reads velocities from
+  // their cell slots, so the stage holds more particles in less LDS)
+  pair_segments(m.P.ncell, t.pair_seg, &m.P.seg_cells, &m.P.nseg);
+  m.P.pair_stage = kBatchPairStage;
+  m.pair_blocks = pair_blocks(m.P);
   m.pos = mb.pos;
   m.vel = mb.vel;
   m.force = mb.force;
@@ -1978,7 +1988,7 @@ int enuf_batch_set_options(enuf_batch *b, int use_graph, int concurrent) {
 }
 
 int enuf_batch_set_tuning(enuf_batch *b, int pass_threads, int x_threads, int stage, int pair_steps,
-                          int x_split_mul) {
+                          int x_split_mul, int pair_seg) {
   if (!b) { set_error("NULL batch"); return ENUF_EINVAL; }
   enuf_batch::Tuning t = b->tune;
   if (pass_threads) t.pass_threads = pass_threads;
@@ -1986,6 +1996,7 @@ int enuf_batch_set_tuning(enuf_batch *b, int pass_threads, int x_threads, int st
   if (stage) t.stage = stage;
   if (pair_steps) t.pair_steps = pair_steps;
   if (x_split_mul) t.x_split_mul = x_split_mul;
+  if (pair_seg) t.pair_seg = pair_seg;
   if (t.pass_threads != 256 && t.pass_threads != 512) { set_error("pass_threads must be 256 or 512"); return ENUF_EINVAL; }
   if (t.x_threads != 128 && t.x_threads != 256 && t.x_threads != 512) {
     set_error("x_threads must be 128, 256 or 512");
@@ -1994,6 +2005,10 @@ int enuf_batch_set_tuning(enuf_batch *b, int pass_threads, int x_threads, int st
   if (t.stage < 32 || t.stage > kStage) { set_error("stage must be in [32, " + std::to_string(kStage) + "]"); return ENUF_EINVAL; }
   if (t.pair_steps != 4 && t.pair_steps != 8) { set_error("pair_steps must be 4 or 8"); return ENUF_EINVAL; }
   if (t.x_split_mul < 1 || t.x_split_mul > 8) { set_error("x_split_mul must be in [1, 8]"); return ENUF_EINVAL; }
+  if (t.pair_seg < 1 || t.pair_seg > kPairSegMax) {
+    set_error("pair_seg must be in [1, " + std::to_string(kPairSegMax) + "]");
+    return ENUF_EINVAL;
+  }
   HIP_OR_RETURN(hipStreamSynchronize(b->own), ENUF_EDEVICE);
   b->tune = t;
   b->dirty = true;  // rebuilt (and the graph dropped) at the next run

@@ -200,8 +200,8 @@ def test_auto_graph_policy_matches_eager():
 
 def test_tuning_does_not_change_results():
     """Launch parameters other than the defaults (512-thread mesh passes,
-    256-thread x pass, stage 128, 8 pair steps, 4x x-split) give bitwise the
-    states and energies of the defaults."""
+    256-thread x pass, stage 128, 8 pair steps, 4x x-split, 3-cell pair
+    segments) give bitwise the states and energies of the defaults."""
     from paper_1303_4523_amd.batch import Batch
     reps = _replicas([0, 3, 5, 10])
     print("case: tuning", [r.meta["name"] for r in reps], flush=True)
@@ -209,7 +209,7 @@ def test_tuning_does_not_change_results():
     for tuned in (False, True):
         b = Batch("mixed", device=0)
         if tuned:
-            b.set_tuning(pass_threads=512, x_threads=256, stage=128, pair_steps=8, x_split_mul=4)
+            b.set_tuning(pass_threads=512, x_threads=256, stage=128, pair_steps=8, x_split_mul=4, pair_seg=3)
         mem = [_member(s) for s in reps]
         for m in mem:
             b.add(*m, first_step=1)
@@ -246,6 +246,8 @@ def test_autotune_caches_its_choice(tmp_path):
     assert got[0]["params"] == got[1]["params"] and got[0]["signature"] == got[1]["signature"]
     with pytest.raises(Exception):
         Batch("mixed", device=0).set_tuning(pass_threads=128)
+    with pytest.raises(Exception):
+        Batch("mixed", device=0).set_tuning(pair_seg=27)
 
 
 def test_mixed_member_against_oracle():
