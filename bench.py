@@ -445,7 +445,8 @@ def batched(nsteps, dev):
     progress(f"batched tuning {tune['params']}")
     torch.cuda.synchronize()
     t = time.perf_counter()
-    b.run(1)   # rebuilds the member table and captures the step graph
+    b.run(1)   # rebuilds the member table and captures the last-step graph (the warm-up run below
+               # captures the step graphs with the fused combine + pre kernel)
     torch.cuda.synchronize()
     capture_ms = (time.perf_counter() - t) * 1e3
     b.run(10)

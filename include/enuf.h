@@ -384,7 +384,10 @@ int enuf_batch_remove(enuf_batch *batch, int member_id);
 /* Number of members. */
 int enuf_batch_size(const enuf_batch *batch);
 
-/* Advance every member nsteps steps (enqueue-only). */
+/* Advance every member nsteps steps (enqueue-only).  Replayed runs (graphs)
+ * fuse each step's combine with the next step's pre kernel and reduce the
+ * energies (enuf_dpd_energy) of the last step only; results are bitwise those
+ * of eager runs. */
 int enuf_batch_run(enuf_batch *batch, int nsteps);
 
 /* Device bytes of the batch's tables and of all members (with their plans). */

@@ -64,10 +64,18 @@ struct BatchMember {
   int *status;
   DpdCharges ch;
   unsigned long long *step;     // index of the member's next step
+  // the other set of bin counts: a fused combine + pre step clears this
+  // table's set (buf, dcnt) while it bins the next step into these
+  int *dcnt_next;
+  DpdCharges ch_next;
 };
 
 // Batched launches: map[b] = (member, block of that member) for block b.
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st);
+// Step k's combine (mode 0, no energy partials, the step index advanced) and
+// step k + 1's pre kernel in one launch, over the combine map (blocks of
+// 256 particles).
+hipError_t launch_batch_combine_pre(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st);
 // steps: candidate steps in flight per lane (4 or 8, else hipErrorInvalidValue).
 hipError_t launch_batch_pair(const BatchMember *mem, const int2 *map, int nmap, int steps, hipStream_t st);
 // Column segments of the pair kernel for a grid of n cells per side, about

@@ -676,6 +676,31 @@ kb_dpd_pair(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
                              to_g(m.bond_start), to_g(m.bond_to), to_g(m.fdpd), w.y, m.pair_blocks);
 }
 
+// Batched fused step boundary: the members' combine of step k (clearing
+// their set of bin counts) and pre of step k + 1 (binning into the other);
+// thread i finishes particle i's step and starts its next one.
+__global__ void __launch_bounds__(kPrepThreads)
+kb_combine_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map) {
+  const int2 w = map[blockIdx.x];
+  const BatchMember &m = mem[w.x];
+  FinishArgs fa;
+  fa.mode = 0;
+  fa.kappa = m.P.kappa;
+  fa.dt = m.P.dt;
+  fa.fdpd = m.fdpd;
+  fa.vel = m.vel;
+  fa.dcnt = m.dcnt;
+  fa.ndcell3 = m.P.ncell * m.P.ncell * m.P.ncell;
+  fa.energies = 0;
+  fa.step_inc = m.step;
+  const int nc = m.cfg.cells.ncell;
+  combine_body(m.N, to_g(m.buf.slot), to_g(m.buf.xq), to_g(m.buf.freal), to_g(m.buf.part),
+               2 * m.cfg.mesh.win.p * m.cfg.mesh.nslot, m.fscale, m.nblk, m.buf.blk_eg, to_g(m.buf.ereal),
+               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M * kXSub, fa, m.force, w.y);
+  __syncthreads();  // the step's loads and stores come before the next step's
+  dpd_pre_body(m.N, 0, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt_next, m.cpos, m.cvel, m.status, m.ch_next, w.y);
+}
+
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
   if (threadIdx.x == 0) dst[0] = value;
 }
@@ -701,6 +726,11 @@ hipError_t configure_pair_kernels(size_t lds_bytes) {
 
 hipError_t launch_batch_pre(const BatchMember *mem, const int2 *map, int nmap, int mode, hipStream_t st) {
   if (nmap > 0) hipLaunchKernelGGL(kb_dpd_pre, dim3(nmap), dim3(256), 0, st, mem, map, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_combine_pre(const BatchMember *mem, const int2 *map, int nmap, hipStream_t st) {
+  if (nmap > 0) hipLaunchKernelGGL(kb_combine_pre, dim3(nmap), dim3(kPrepThreads), 0, st, mem, map);
   return hipGetLastError();
 }
 

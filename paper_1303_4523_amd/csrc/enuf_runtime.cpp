@@ -1740,15 +1740,27 @@ struct enuf_batch {
     int pair_seg = kBatchPairSeg;          // cells per column segment of the pair kernel, about
   } tune;
   bool dirty = true;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // step graphs: [0][par] a step of table par that ends with the fused
+  // combine + pre kernel (binning the next step into the other set), [1][par]
+  // a run's last step (combine and energy reduction)
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   EventTimer timer;  // enuf_batch_time_kernel: eager single-stream steps while active
 
+  bool captured() const {
+    for (int k = 0; k < 2; ++k)
+      for (int p = 0; p < 2; ++p)
+        if (exec[k][p]) return true;
+    return false;
+  }
   void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
+    for (int k = 0; k < 2; ++k)
+      for (int p = 0; p < 2; ++p) {
+        if (exec[k][p]) (void)hipGraphExecDestroy(exec[k][p]);
+        if (graph[k][p]) (void)hipGraphDestroy(graph[k][p]);
+        exec[k][p] = nullptr;
+        graph[k][p] = nullptr;
+      }
   }
   ~enuf_batch() {
     drop_graph();
@@ -1769,7 +1781,9 @@ struct enuf_batch {
 
 namespace {
 
-BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &t) {
+// The member as table par sees it: bin-count set par (and the other set as
+// the next step's, for the fused combine + pre kernel).
+BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &t, int par) {
   const enuf_dpd *d = mb.d;
   const enuf_plan *pl = d->plan;
   BatchMember m{};
@@ -1781,7 +1795,7 @@ BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &
   // more x-pass work-groups per ky row (each a range of kz lines; the energy
   // is kept per line, so the grouping does not change it)
   m.cfg.mesh.xsplit = std::min(m.cfg.mesh.Kc, m.cfg.mesh.xsplit * t.x_split_mul);
-  m.buf = pl->buf;
+  m.buf = plan_buffers_set(pl, par);
   m.nq = (int)d->nq;
   m.nblk = pl->cfg.nblk;
   const int64_t g = (d->nq + 3) / 4;
@@ -1801,13 +1815,15 @@ BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &
   m.v0 = d->v0;
   m.fdpd = d->fdpd;
   m.e5 = d->e5;
-  m.dcnt = d->dcnt;
+  m.dcnt = dpd_counts_set(d, par);
+  m.dcnt_next = dpd_counts_set(d, par ^ 1);
   m.cpos = d->cpos;
   m.cvel = d->cvel;
   m.bond_start = d->bond_start;
   m.bond_to = d->bond_to;
   m.status = d->status;
-  m.ch = d->charges;
+  m.ch = dpd_charges_set(d, par);
+  m.ch_next = dpd_charges_set(d, par ^ 1);
   m.step = d->step_ctr;
   return m;
 }
@@ -1819,14 +1835,15 @@ int batch_rebuild(enuf_batch *b) {
   for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return b->members[x].d->N > b->members[y].d->N; });
-  std::vector<BatchMember> mem;
+  std::vector<BatchMember> mem, mem1;  // tables of bin-count sets 0 and 1
   std::vector<int2> map[7];
   size_t lf = 0, lx = 0, lb = 0;
   int tp = b->tune.pass_threads, tx = b->tune.x_threads;  // enough threads for every member's FFT passes
   for (int k : order) {
-    const BatchMember m = member_view(b->members[k], b->tune);
+    const BatchMember m = member_view(b->members[k], b->tune, 0);
     const int id = (int)mem.size();
     mem.push_back(m);
+    mem1.push_back(member_view(b->members[k], b->tune, 1));
     const int planes = m.cfg.mesh.M * m.cfg.mesh.parts;     // work-groups of the spread pass
     const int bplanes = m.cfg.mesh.M * m.cfg.mesh.bparts;   // and of the gather pass
     const int counts[7] = {m.nblk,  m.pair_blocks, m.real_blocks, planes, m.cfg.mesh.nky * m.cfg.mesh.xsplit,
@@ -1855,8 +1872,9 @@ int batch_rebuild(enuf_batch *b) {
     b->dmem = nullptr;
     b->hmem = nullptr;
     b->mem_cap = 0;
-    HIP_OR_RETURN(hipMalloc(&b->dmem, cap * sizeof(BatchMember)), ENUF_ENOMEM);
-    HIP_OR_RETURN(hipHostMalloc((void **)&b->hmem, cap * sizeof(BatchMember), hipHostMallocDefault), ENUF_ENOMEM);
+    HIP_OR_RETURN(hipMalloc(&b->dmem, 2 * cap * sizeof(BatchMember)), ENUF_ENOMEM);
+    HIP_OR_RETURN(hipHostMalloc((void **)&b->hmem, 2 * cap * sizeof(BatchMember), hipHostMallocDefault),
+                  ENUF_ENOMEM);
     b->mem_cap = cap;
   }
   if (nmap > b->map_cap) {
@@ -1872,9 +1890,10 @@ int batch_rebuild(enuf_batch *b) {
   }
   if (!mem.empty()) {
     std::memcpy(b->hmem, mem.data(), mem.size() * sizeof(BatchMember));
+    std::memcpy(b->hmem + mem.size(), mem1.data(), mem1.size() * sizeof(BatchMember));
     for (int s = 0; s < 7; ++s)
       if (!map[s].empty()) std::memcpy(b->hmap + b->off[s], map[s].data(), map[s].size() * sizeof(int2));
-    HIP_OR_RETURN(hipMemcpyAsync(b->dmem, b->hmem, mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice,
+    HIP_OR_RETURN(hipMemcpyAsync(b->dmem, b->hmem, 2 * mem.size() * sizeof(BatchMember), hipMemcpyHostToDevice,
                                  b->own), ENUF_EDEVICE);
     HIP_OR_RETURN(hipMemcpyAsync(b->dmap, b->hmap, nmap * sizeof(int2), hipMemcpyHostToDevice, b->own),
                   ENUF_EDEVICE);
@@ -1890,40 +1909,86 @@ int batch_rebuild(enuf_batch *b) {
   return ENUF_OK;
 }
 
-// One step of every member: pre on the batch stream; pair forces and real
-// space forked onto two side streams (fork = true) or kept on the batch
-// stream; the mesh passes on the batch stream; the combine joins them.
+// Member table par (bin-count set par) on the device.
+const BatchMember *batch_table(const enuf_batch *b, int par) { return b->dmem + (size_t)par * b->nmem; }
+
+// The forces of one step of every member, after its pre kernel: pair forces
+// and real space forked onto two side streams (fork = true) or kept on the
+// batch stream, the mesh passes on the batch stream, joined before return.
 // tm (eager single-stream steps only) brackets one stage with events.
-hipError_t batch_step(enuf_batch *b, bool fork, KernelTimer *tm = nullptr) {
+hipError_t batch_forces(enuf_batch *b, const BatchMember *mt, bool fork, KernelTimer *tm) {
   const int *o = b->off;
   const int2 *mp = b->dmap;
   hipStream_t st = b->own;
   hipStream_t s0 = fork ? b->side[0] : st, s1 = fork ? b->side[1] : st;
-  if (tm) tm->before(ENUF_K_DPD_PRE, st);
-  hipError_t e = launch_batch_pre(b->dmem, mp + o[0], o[1] - o[0], 0, st);
-  if (tm) tm->after(ENUF_K_DPD_PRE, st);
+  hipError_t e = hipSuccess;
   if (fork) {
-    if (e == hipSuccess) e = hipEventRecord(b->fork_ev, st);
+    e = hipEventRecord(b->fork_ev, st);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->side[k], b->fork_ev, 0);
   }
   if (tm) tm->before(ENUF_K_DPD_PAIR, s0);
-  if (e == hipSuccess) e = launch_batch_pair(b->dmem, mp + o[1], o[2] - o[1], b->tune.pair_steps, s0);
+  if (e == hipSuccess) e = launch_batch_pair(mt, mp + o[1], o[2] - o[1], b->tune.pair_steps, s0);
   if (tm) tm->after(ENUF_K_DPD_PAIR, s0);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[0], s0);
   if (tm) tm->before(ENUF_K_REAL, s1);
-  if (e == hipSuccess) e = launch_batch_real(b->dmem, mp + o[2], o[3] - o[2], s1);
+  if (e == hipSuccess) e = launch_batch_real(mt, mp + o[2], o[3] - o[2], s1);
   if (tm) tm->after(ENUF_K_REAL, s1);
   if (fork && e == hipSuccess) e = hipEventRecord(b->join_ev[1], s1);
   if (e == hipSuccess)
-    e = launch_batch_recip(b->dmem, b->precision, b->ik, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4],
+    e = launch_batch_recip(mt, b->precision, b->ik, mp + o[3], o[4] - o[3], mp + o[4], o[5] - o[4],
                            mp + o[5], o[6] - o[5], b->lds_fwd, b->lds_x, b->lds_bwd, b->pass_threads,
                            b->x_threads, st, tm);
   if (fork)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(st, b->join_ev[k], 0);
+  return e;
+}
+
+// One whole step of every member with table 0 (eager runs): pre, forces,
+// combine and the energy reduction.
+hipError_t batch_step(enuf_batch *b, bool fork, KernelTimer *tm = nullptr) {
+  const int *o = b->off;
+  const int2 *mp = b->dmap;
+  hipStream_t st = b->own;
+  const BatchMember *mt = batch_table(b, 0);
+  if (tm) tm->before(ENUF_K_DPD_PRE, st);
+  hipError_t e = launch_batch_pre(mt, mp + o[0], o[1] - o[0], 0, st);
+  if (tm) tm->after(ENUF_K_DPD_PRE, st);
+  if (e == hipSuccess) e = batch_forces(b, mt, fork, tm);
   if (tm) tm->before(ENUF_K_COMBINE, st);
-  if (e == hipSuccess) e = launch_batch_combine(b->dmem, b->nmem, mp + o[6], o[7] - o[6], 0, st);
+  if (e == hipSuccess) e = launch_batch_combine(mt, b->nmem, mp + o[6], o[7] - o[6], 0, st);
   if (tm) tm->after(ENUF_K_COMBINE, st);
   return e;
+}
+
+// The step graph [kind][par] (captured on first use): the forces of table
+// par, then (kind 0) the fused combine + pre kernel that bins the next step
+// into the other set, or (kind 1, a run's last step) the combine and the
+// energy reduction.  Single stream: no cross-stream event in a capture.
+int batch_capture(enuf_batch *b, int kind, int par) {
+  if (b->exec[kind][par]) return ENUF_OK;
+  const int *o = b->off;
+  const int2 *mp = b->dmap;
+  const BatchMember *mt = batch_table(b, par);
+  HIP_OR_RETURN(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), ENUF_EDEVICE);
+  hipError_t e = batch_forces(b, mt, false, nullptr);
+  if (e == hipSuccess)
+    e = kind == 0 ? launch_batch_combine_pre(mt, mp + o[6], o[7] - o[6], b->own)
+                  : launch_batch_combine(mt, b->nmem, mp + o[6], o[7] - o[6], 0, b->own);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->own, &g);
+  if (e != hipSuccess || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    set_error(std::string("capturing the batched step failed: ") + hipGetErrorString(e != hipSuccess ? e : ec));
+    return ENUF_EDEVICE;
+  }
+  b->graph[kind][par] = g;
+  if (hipGraphInstantiate(&b->exec[kind][par], g, nullptr, nullptr, 0) != hipSuccess) {
+    b->exec[kind][par] = nullptr;
+    b->drop_graph();
+    set_error("instantiating the batched step graph failed");
+    return ENUF_EDEVICE;
+  }
+  return ENUF_OK;
 }
 
 }  // namespace
@@ -2074,38 +2139,41 @@ int enuf_batch_run(enuf_batch *b, int nsteps) {
     const int rc = batch_rebuild(b);
     if (rc != ENUF_OK) return rc;
   }
-  // The captured step is the single-stream schedule: no cross-stream event
-  // record / wait inside a capture.
+  // Replayed runs: the first pre kernel, then steps whose combine is fused
+  // with the next step's pre kernel, alternating the two bin-count sets (step
+  // s of the run uses set s mod 2), and the last step with its energy
+  // reduction; every set is clear again at the end.  Eager and timed runs
+  // launch whole steps with set 0.
   KernelTimer *tm = b->timer.active();
-  const bool graph = b->use_graph == 1 ||
-                     (b->use_graph == ENUF_GRAPH_AUTO && (b->exec || nsteps >= ENUF_GRAPH_AUTO_STEPS));
-  if (graph && !b->exec && !tm) {
-    HIP_OR_RETURN(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), ENUF_EDEVICE);
-    const hipError_t e = batch_step(b, false);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(b->own, &g);
-    if (e != hipSuccess || ec != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      set_error(std::string("capturing the batched step failed: ") + hipGetErrorString(e != hipSuccess ? e : ec));
-      return ENUF_EDEVICE;
+  const bool graph = !tm && (b->use_graph == 1 ||
+                             (b->use_graph == ENUF_GRAPH_AUTO && (b->captured() || nsteps >= ENUF_GRAPH_AUTO_STEPS)));
+  if (graph) {
+    for (int s = 0; s < nsteps - 1 && s < 2; ++s) {
+      const int rc = batch_capture(b, 0, s & 1);
+      if (rc != ENUF_OK) return rc;
     }
-    b->graph = g;
-    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-      b->drop_graph();
-      set_error("instantiating the batched step graph failed");
-      return ENUF_EDEVICE;
-    }
+    const int rc = batch_capture(b, 1, (nsteps - 1) & 1);
+    if (rc != ENUF_OK) return rc;
   }
   // order after the caller's stream, run on the batch stream, order the
   // caller's later work after the run
   HIP_OR_RETURN(hipEventRecord(b->in_ev, b->stream), ENUF_EDEVICE);
   HIP_OR_RETURN(hipStreamWaitEvent(b->own, b->in_ev, 0), ENUF_EDEVICE);
-  for (int s = 0; s < nsteps; ++s) {
-    const hipError_t e = tm ? batch_step(b, false, tm)
-                            : (graph ? hipGraphLaunch(b->exec, b->own) : batch_step(b, b->concurrent != 0));
+  if (graph) {
+    hipError_t e = launch_batch_pre(batch_table(b, 0), b->dmap + b->off[0], b->off[1] - b->off[0], 0, b->own);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s)
+      e = hipGraphLaunch(b->exec[s == nsteps - 1 ? 1 : 0][s & 1], b->own);
     if (e != hipSuccess) {
       set_error(std::string("batched step launch failed: ") + hipGetErrorString(e));
       return ENUF_EDEVICE;
+    }
+  } else {
+    for (int s = 0; s < nsteps; ++s) {
+      const hipError_t e = batch_step(b, !tm && b->concurrent != 0, tm);
+      if (e != hipSuccess) {
+        set_error(std::string("batched step launch failed: ") + hipGetErrorString(e));
+        return ENUF_EDEVICE;
+      }
     }
   }
   HIP_OR_RETURN(hipEventRecord(b->out_ev, b->own), ENUF_EDEVICE);
@@ -2160,7 +2228,7 @@ int enuf_batch_kernel_time(enuf_batch *b, double *total_ms, int *launches) {
 
 size_t enuf_batch_footprint_bytes(const enuf_batch *b) {
   if (!b) return 0;
-  size_t t = b->mem_cap * sizeof(BatchMember) + b->map_cap * sizeof(int2);
+  size_t t = 2 * b->mem_cap * sizeof(BatchMember) + b->map_cap * sizeof(int2);
   for (const auto &mb : b->members) t += enuf_dpd_footprint_bytes(mb.d);
   return t;
 }
