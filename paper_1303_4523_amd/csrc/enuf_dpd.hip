@@ -226,9 +226,9 @@ constexpr int kPairZ = kPairSegMax + 2;  // staged z-slices at most
 constexpr int kPairCells = 9 * kPairZ;   // staged cells at most
 static_assert(kPairCells <= kPairThreads, "the prefix sum takes one staged cell per thread");
 static_assert(kPairCells <= 256, "staged cells are numbered in a byte");
-// candidate steps in flight per lane: 8 for one system (150 VGPRs, 3 waves
+// candidate steps in flight per lane: 8 for one system (153 VGPRs, 3 waves
 // per SIMD; 4.5 % less step time than 4 at N = 24000, where the kernel runs
-// beside the mesh passes); batches take 4 (128 VGPRs, 4 waves per SIMD; 8 %
+// beside the mesh passes); batches take 4 (122 VGPRs, 4 waves per SIMD; 8 %
 // less batch step time than 8, the batch filling the chip) or 8
 // (enuf_batch_set_tuning)
 constexpr int kPairU = 8;
@@ -462,7 +462,7 @@ dpd_pair_body(const DpdParams &P, uint64_t step, gptr<const double> __restrict__
   // the particle's cell slot in the fourth word
   const int stage_cap = P.pair_stage;
   double4 *s_pos = reinterpret_cast<double4 *>(pair_smem);
-  double4 *s_vel = s_pos + stage_cap;
+  double4 *s_vel = VLDS ? s_pos + stage_cap : nullptr;
   float4 *s_rel = reinterpret_cast<float4 *>(s_pos + (VLDS ? 2 : 1) * stage_cap);
   // periodic image shifts and origin of the segment
   const double ox0 = cx * edge, oy0 = cy * edge, oz0 = (z0 - 1) * edge;
