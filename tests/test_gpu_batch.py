@@ -77,6 +77,37 @@ def test_batch_equals_each_system_alone(use_graph, concurrent):
         d.close()
 
 
+def test_replayed_runs_of_any_length_equal_eager():
+    """Replayed runs fuse each step's combine with the next step's pre kernel
+    and alternate the two bin-count sets, the last step of a run using the
+    set of its parity.  Runs of 1, 2, 3, 1 and 5 steps (both parities of the
+    last step, runs starting after either) give bitwise the states and
+    energies of the same runs launched eagerly, after every run."""
+    from paper_1303_4523_amd.batch import Batch
+    reps = _replicas([1, 4, 7])
+    lengths = (1, 2, 3, 1, 5)
+    print("case: run lengths", lengths, [r.meta["name"] for r in reps], flush=True)
+    got = {}
+    for use_graph in (True, False):
+        b = Batch("mixed", device=0, use_graph=use_graph, concurrent=False)
+        mem = [_member(s) for s in reps]
+        for m in mem:
+            b.add(*m, first_step=1)
+        got[use_graph] = []
+        for n in lengths:
+            b.run(n)
+            torch.cuda.synchronize()
+            assert all(m[0].status() == 0 for m in mem)
+            got[use_graph].append([tuple(t.cpu().numpy() for t in m[1:]) + (m[0].energy().cpu().numpy(),)
+                                   for m in mem])
+        b.close()
+        for m in mem:
+            m[0].close()
+    for k, n in enumerate(lengths):
+        for a, c in zip(got[True][k], got[False][k]):
+            assert _same(a, c), f"after run {k} ({n} steps)"
+
+
 def _dense_member_system():
     """A densely charged DPD system: one fully charged chain, its counterions
     and 1:1 salt at 1.2 cations per unit volume (about 2.5 charges per unit
