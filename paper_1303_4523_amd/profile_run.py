@@ -1,13 +1,15 @@
 """Short fixed workloads for profiler runs (rocprofv3 counter and trace passes).
 
-    python -m paper_1303_4523_amd.profile_run [--small K] [--single K] [--batch K]
+    python -m paper_1303_4523_amd.profile_run [--small K] [--single K] [--batch K] [--batch-graph K]
 
 --small K:  K FP64 evaluations (Plan.compute) of the L = 10 system (N = 3000,
             300 charges, M = 32, Kc = 8, p = 4);
 --single K: K FP64 evaluations (Plan.compute) of the DPD N = 24000 system
             (M = 64, Kc = 16, p = 4, 1650 charges);
 --batch K:  K eager single-stream steps of the 64-replica mixed batch
-            (1.01M particles, M = 36-80), after one step that builds it.
+            (1.01M particles, M = 36-80), after one step that builds it;
+--batch-graph K: the same, the K steps replayed from the step graphs (each
+            step's combine fused with the next step's pre kernel).
 Each prints one line when it ends.  Under a counter pass every dispatch is
 serialised, so the runs are kept to a few launches of each kernel.
 """
@@ -50,7 +52,7 @@ def single(k, dev):
     print(f"single: {k} evaluations of N={s.N}", flush=True)
 
 
-def batch(k, dev):
+def batch(k, dev, graph=False):
     reps = wl.batched_replicas(64)
     mem = []
     for s in reps:
@@ -61,7 +63,9 @@ def batch(k, dev):
         F = torch.empty_like(pos)
         d.forces(pos, vel, F, step=0)
         mem.append((d, pos, vel, F))
-    b = Batch("mixed", device=dev, use_graph=False, concurrent=False)
+    # eager single-stream steps, or (graph) replayed steps whose combine is
+    # fused with the next step's pre kernel
+    b = Batch("mixed", device=dev, use_graph=graph, concurrent=False)
     for m in mem:
         b.add(*m, first_step=1)
     b.run(1)
@@ -70,7 +74,7 @@ def batch(k, dev):
     b.close()
     for m in mem:
         m[0].close()
-    print(f"batch: {k} steps of {len(reps)} replicas", flush=True)
+    print(f"batch: {k} {'replayed' if graph else 'eager'} steps of {len(reps)} replicas", flush=True)
 
 
 def main():
@@ -78,6 +82,7 @@ def main():
     ap.add_argument("--small", type=int, default=0)
     ap.add_argument("--single", type=int, default=0)
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--batch-graph", type=int, default=0)
     a = ap.parse_args()
     dev = torch.device("cuda", 0)
     if a.small:
@@ -86,6 +91,8 @@ def main():
         single(a.single, dev)
     if a.batch:
         batch(a.batch, dev)
+    if a.batch_graph:
+        batch(a.batch_graph, dev, graph=True)
 
 
 if __name__ == "__main__":
