@@ -57,7 +57,7 @@ struct BatchMember {
   int64_t N;
   DpdParams P;
   double *pos, *vel, *force;    // caller-owned state
-  double *v0, *fdpd, *e5;
+  double *fdpd, *e5;
   int *dcnt;
   double4 *cpos, *cvel;
   const int *bond_start, *bond_to;
@@ -109,18 +109,20 @@ hipError_t launch_batch_combine(const BatchMember *mem, int nmem, const int2 *ma
 hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hipStream_t st);
 hipError_t launch_add_u64(unsigned long long *dst, hipStream_t st);  // *dst += 1
 
+// The predicted velocity v0 = v + lam dt F is kept only in the cell slots
+// (the pair kernel reads it there).
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
-                          const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
-                          int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm = nullptr);
-hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
-                           const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
-                           KernelTimer *tm = nullptr, const unsigned long long *step_dev = nullptr);
+                          const double *force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+                          const DpdCharges &ch, hipStream_t st, KernelTimer *tm = nullptr);
+hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos, const int *dcnt,
+                           const double4 *cpos, const double4 *cvel, const int *bond_start, const int *bond_to,
+                           double *fdpd, hipStream_t st, KernelTimer *tm = nullptr,
+                           const unsigned long long *step_dev = nullptr);
 // The combine kernel of a DPD step fused with the next step's pre kernel
 // (no energy reduction: fa.energies must be 0, else hipErrorInvalidValue).
 hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
-                              const FinishArgs &fa, const DpdParams &P, double *pos, double *v0, int *dcnt,
-                              double4 *cpos, double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,
+                              const FinishArgs &fa, const DpdParams &P, double *pos, int *dcnt, double4 *cpos,
+                              double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,
                               KernelTimer *tm = nullptr);
 hipError_t launch_dpd_post(int64_t N, int mode, const DpdParams &P, const double *fdpd,
                            const double *felec, double *force, double *vel, int *dcnt, hipStream_t st,

@@ -63,8 +63,8 @@ __device__ inline int dpd_cell_of(double x, double inv_cell, int n) {
 // neighbour data contiguously.
 __device__ __forceinline__ void
 dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, double *__restrict__ vel,
-             const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
-             double4 *cvel, int *status, const DpdCharges &ch, int bid) {
+             const double *__restrict__ force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+             const DpdCharges &ch, int bid) {
   const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
   if (ch.enabled && i == 0) {
     ch.sc->nq = ch.stat.nq;
@@ -101,10 +101,7 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     }
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    pos[3 * i + a] = r[a];
-    v0[3 * i + a] = w[a];
-  }
+  for (int a = 0; a < 3; ++a) pos[3 * i + a] = r[a];
   const int n = P.ncell;
   const int cell = (dpd_cell_of(r[0], P.inv_cell, n) * n + dpd_cell_of(r[1], P.inv_cell, n)) * n +
                    dpd_cell_of(r[2], P.inv_cell, n);
@@ -155,9 +152,9 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
 
 __global__ void __launch_bounds__(256)
 k_dpd_pre(int64_t N, int mode, DpdParams P, double *__restrict__ pos, double *__restrict__ vel,
-          const double *__restrict__ force, double *__restrict__ v0, int *dcnt, double4 *cpos,
-          double4 *cvel, int *status, DpdCharges ch) {
-  dpd_pre_body(N, mode, P, pos, vel, force, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
+          const double *__restrict__ force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+          DpdCharges ch) {
+  dpd_pre_body(N, mode, P, pos, vel, force, dcnt, cpos, cvel, status, ch, blockIdx.x);
 }
 
 // Minimum-image separation d = a - b and |d|^2, with the rounding written
@@ -630,18 +627,17 @@ k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict
               const unsigned long long *__restrict__ freal, const double4 *__restrict__ part, int P2S,
               double fscale, int nblk, double *blk_eg, const unsigned long long *__restrict__ ereal,
               long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
-              DpdParams P, double *pos, double *v0, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+              DpdParams P, double *pos, int *dcnt, double4 *cpos, double4 *cvel, int *status,
               DpdCharges ch) {
   combine_body(N, to_g(slot), to_g(xq), to_g(freal), to_g(part), P2S, fscale, nblk, blk_eg, to_g(ereal), blk_er,
                ccnt, ncell3, xcnt, M * kXSub, fa, forces, blockIdx.x);
   __syncthreads();  // the step's loads and stores come before the next step's
-  dpd_pre_body(N, 0, P, pos, fa.vel, forces, v0, dcnt, cpos, cvel, status, ch, blockIdx.x);
+  dpd_pre_body(N, 0, P, pos, fa.vel, forces, dcnt, cpos, cvel, status, ch, blockIdx.x);
 }
 
 hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
-                              const FinishArgs &fa, const DpdParams &P, double *pos, double *v0, int *dcnt,
-                              double4 *cpos, double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st,
-                              KernelTimer *tm) {
+                              const FinishArgs &fa, const DpdParams &P, double *pos, int *dcnt, double4 *cpos,
+                              double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
   // the per-block energy partials are sized for blocks of kPrepThreads
   if (fa.energies) return hipErrorInvalidValue;
   const double fscale = combine_fscale(cfg);
@@ -652,7 +648,7 @@ hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b,
                      2 * cfg.mesh.win.p * cfg.mesh.nslot, fscale, nb, b.blk_eg,
                      (const unsigned long long *)b.ereal, b.blk_er, b.ccnt,
                      cfg.cells.ncell * cfg.cells.ncell * cfg.cells.ncell, b.xcnt, cfg.mesh.M, fa, forces, P, pos,
-                     v0, dcnt, cpos, cvel, status, ch);
+                     dcnt, cpos, cvel, status, ch);
   if (tm) tm->after(9, st);
   return hipGetLastError();
 }
@@ -664,7 +660,7 @@ __global__ void __launch_bounds__(256)
 kb_dpd_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map, int mode) {
   const int2 w = map[blockIdx.x];
   const BatchMember &m = mem[w.x];
-  dpd_pre_body(m.N, mode, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt, m.cpos, m.cvel, m.status, m.ch, w.y);
+  dpd_pre_body(m.N, mode, m.P, m.pos, m.vel, m.force, m.dcnt, m.cpos, m.cvel, m.status, m.ch, w.y);
 }
 
 template <int U>
@@ -698,7 +694,7 @@ kb_combine_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map
                2 * m.cfg.mesh.win.p * m.cfg.mesh.nslot, m.fscale, m.nblk, m.buf.blk_eg, to_g(m.buf.ereal),
                m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M * kXSub, fa, m.force, w.y);
   __syncthreads();  // the step's loads and stores come before the next step's
-  dpd_pre_body(m.N, 0, m.P, m.pos, m.vel, m.force, m.v0, m.dcnt_next, m.cpos, m.cvel, m.status, m.ch_next, w.y);
+  dpd_pre_body(m.N, 0, m.P, m.pos, m.vel, m.force, m.dcnt_next, m.cpos, m.cvel, m.status, m.ch_next, w.y);
 }
 
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
@@ -756,22 +752,20 @@ hipError_t launch_set_u64(unsigned long long *dst, unsigned long long value, hip
 }
 
 hipError_t launch_dpd_pre(int64_t N, int mode, const DpdParams &P, double *pos, double *vel,
-                          const double *force, double *v0, int *dcnt, double4 *cpos, double4 *cvel,
-                          int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
+                          const double *force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+                          const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
   const int nb = (int)((N + 255) / 256);
   if (tm) tm->before(0, st);
-  hipLaunchKernelGGL(k_dpd_pre, dim3(nb), dim3(256), 0, st, N, mode, P, pos, vel, force, v0, dcnt, cpos,
-                     cvel, status, ch);
+  hipLaunchKernelGGL(k_dpd_pre, dim3(nb), dim3(256), 0, st, N, mode, P, pos, vel, force, dcnt, cpos, cvel,
+                     status, ch);
   if (tm) tm->after(0, st);
   return hipGetLastError();
 }
 
-hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos,
-                           const double *v0, const int *dcnt, const double4 *cpos, const double4 *cvel,
-                           const int *bond_start, const int *bond_to, double *fdpd, hipStream_t st,
-                           KernelTimer *tm, const unsigned long long *step_dev) {
+hipError_t launch_dpd_pair(int64_t N, const DpdParams &P, uint64_t step, const double *pos, const int *dcnt,
+                           const double4 *cpos, const double4 *cvel, const int *bond_start, const int *bond_to,
+                           double *fdpd, hipStream_t st, KernelTimer *tm, const unsigned long long *step_dev) {
   (void)N;
-  (void)v0;
   const int nb = pair_blocks(P);
   if (tm) tm->before(1, st);
   hipLaunchKernelGGL(k_dpd_pair, dim3(nb), dim3(kPairThreads), pair_lds_bytes(P, true), st, P, step, step_dev, pos,

@@ -1065,7 +1065,7 @@ void dpd_geometry(int64_t N, double box, int *nc_out, int *cap_out) {
   *cap_out = (int)std::ceil(mean + 6.0 * std::sqrt(mean) + 16.0);
 }
 
-constexpr int kDpdBuffers = 13;
+constexpr int kDpdBuffers = 12;
 
 // Bytes of every device buffer of a DPD integrator, in allocation order.
 std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t nbonds) {
@@ -1073,7 +1073,6 @@ std::array<size_t, kDpdBuffers> dpd_buffer_bytes(int64_t N, double box, int64_t 
   dpd_geometry(N, box, &nc, &cap);
   const size_t n = (size_t)N, nc3 = (size_t)nc * nc * nc;
   return {n * sizeof(double),                                        // q
-          3 * n * sizeof(double),                                    // v0
           3 * n * sizeof(double),                                    // fdpd
           5 * sizeof(double),                                        // e5
           2 * nc3 * sizeof(int),                                     // dcnt (two sets)
@@ -1096,7 +1095,6 @@ struct enuf_dpd {
   DpdParams P{};
   enuf_plan *plan = nullptr;  // not owned
   double *q = nullptr;        // [N]
-  double *v0 = nullptr;       // [N * 3] predicted velocities
   double *fdpd = nullptr;     // [N * 3] pair + bond forces
   double *e5 = nullptr;       // [5]
   int *dcnt = nullptr;        // [2 ncell^3] two sets, like the plan's bin counts
@@ -1234,18 +1232,17 @@ enuf_dpd *enuf_dpd_create(int64_t N, double box, const enuf_dpd_params *prm, enu
   void *ptr[kDpdBuffers];
   if (!d->alloc_arena(sz.data(), kDpdBuffers, ptr)) { set_error("device allocation failed"); delete d; return nullptr; }
   d->q = (double *)ptr[0];
-  d->v0 = (double *)ptr[1];
-  d->fdpd = (double *)ptr[2];
-  d->e5 = (double *)ptr[3];
-  d->dcnt = (int *)ptr[4];
-  d->cpos = (double4 *)ptr[5];
-  d->cvel = (double4 *)ptr[6];
-  d->bond_start = (int *)ptr[7];
-  d->bond_to = (int *)ptr[8];
-  d->status = (int *)ptr[9];
-  d->dslot = (int *)ptr[10];
-  d->step_ctr = (unsigned long long *)ptr[11];
-  d->species = (int *)ptr[12];
+  d->fdpd = (double *)ptr[1];
+  d->e5 = (double *)ptr[2];
+  d->dcnt = (int *)ptr[3];
+  d->cpos = (double4 *)ptr[4];
+  d->cvel = (double4 *)ptr[5];
+  d->bond_start = (int *)ptr[6];
+  d->bond_to = (int *)ptr[7];
+  d->status = (int *)ptr[8];
+  d->dslot = (int *)ptr[9];
+  d->step_ctr = (unsigned long long *)ptr[10];
+  d->species = (int *)ptr[11];
   P.nspec = 0;
   P.species = d->species;
   if (hipMemcpy(d->q, q, n * sizeof(double), hipMemcpyDeviceToDevice) != hipSuccess ||
@@ -1401,15 +1398,15 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
   int *dcnt = dpd_counts_set(d, par), *dcnt_next = dpd_counts_set(d, par ^ 1);
   hipError_t e = hipSuccess;
   if (pre)
-    e = launch_dpd_pre(N, mode, d->P, pos, vel, force, d->v0, dcnt, d->cpos, d->cvel, d->status, ch, st, tm);
+    e = launch_dpd_pre(N, mode, d->P, pos, vel, force, dcnt, d->cpos, d->cvel, d->status, ch, st, tm);
   if (!d->plan) {
     if (e == hipSuccess)
-      e = launch_dpd_pair(N, d->P, step, pos, d->v0, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+      e = launch_dpd_pair(N, d->P, step, pos, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, st, tm, step_dev);
     if (e == hipSuccess) e = launch_dpd_post(N, mode, d->P, d->fdpd, nullptr, force, vel, dcnt, st, tm);
     if (graph && e == hipSuccess) e = launch_add_u64(d->step_ctr, st);
     if (next && e == hipSuccess)
-      e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
+      e = launch_dpd_pre(N, 0, d->P, pos, vel, force, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
                          st, tm);
   } else {
     enuf_plan *pl = d->plan;
@@ -1435,7 +1432,7 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
     if (graph && fork && e == hipSuccess)
       e = hipStreamUpdateCaptureDependencies(st, &n_pre, c_pre, hipStreamSetCaptureDependencies);
     if (e == hipSuccess)
-      e = launch_dpd_pair(N, d->P, step, pos, d->v0, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
+      e = launch_dpd_pair(N, d->P, step, pos, dcnt, d->cpos, d->cvel, d->bond_start, d->bond_to,
                           d->fdpd, s1, tm, step_dev);
     const int ndcell3 = d->P.ncell * d->P.ncell * d->P.ncell;
     if (e == hipSuccess) e = launch_real(pl->cfg, bk, d->nq, s1, tm);
@@ -1456,12 +1453,12 @@ static int dpd_eval(enuf_dpd *d, int mode, double *pos, double *vel, double *for
       fa.energies = energies ? 1 : 0;
       fa.step_inc = graph ? d->step_ctr : nullptr;
       if (next && !energies)
-        e = launch_combine_pre(pl->cfg, bk, force, fa, d->P, pos, d->v0, dcnt_next, d->cpos, d->cvel, d->status,
+        e = launch_combine_pre(pl->cfg, bk, force, fa, d->P, pos, dcnt_next, d->cpos, d->cvel, d->status,
                                ch_next, st, tm);
       else {
         e = launch_combine(pl->cfg, bk, force, nullptr, d->e5, fa, st, tm);
         if (next && e == hipSuccess)
-          e = launch_dpd_pre(N, 0, d->P, pos, vel, force, d->v0, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
+          e = launch_dpd_pre(N, 0, d->P, pos, vel, force, dcnt_next, d->cpos, d->cvel, d->status, ch_next,
                              st, tm);
       }
     }
@@ -1580,7 +1577,7 @@ int enuf_dpd_run(enuf_dpd *d, double *pos, double *vel, double *force, uint64_t 
   // the first step's pre kernel; each later one runs fused into the combine
   // kernel of the step before
   KernelTimer *tm = d->timer.active();
-  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, d->v0, dpd_counts_set(d, par),
+  HIP_OR_RETURN(launch_dpd_pre(d->N, 0, d->P, pos, vel, force, dpd_counts_set(d, par),
                                d->cpos, d->cvel, d->status, dpd_charges_set(d, par), d->stream, tm),
                 ENUF_EDEVICE);
   int s = 0;
@@ -1812,7 +1809,6 @@ BatchMember member_view(const enuf_batch::Member &mb, const enuf_batch::Tuning &
   m.pos = mb.pos;
   m.vel = mb.vel;
   m.force = mb.force;
-  m.v0 = d->v0;
   m.fdpd = d->fdpd;
   m.e5 = d->e5;
   m.dcnt = dpd_counts_set(d, par);
