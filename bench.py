@@ -36,8 +36,8 @@ Also reported in the same JSON line:
                  time; 1 % of the requests carry an accuracy sample checked
                  against the oracle after the stream.
 
-Prints one JSON line.  --gpus above 1 is not supported: this build runs on
-one GPU.
+Prints one JSON line.  --gpus above 1 is not supported: the library and this
+benchmark run on one GPU.
 """
 import argparse
 import json
@@ -596,7 +596,7 @@ def main():
         copy_calibration()
         return 0
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} is not supported; this build runs on a single GPU "
+        print(f"bench.py: --gpus {a.gpus} is not supported; the library runs on a single GPU "
               "(independent systems would run one process per GPU)", file=sys.stderr)
         return 2
     import torch
