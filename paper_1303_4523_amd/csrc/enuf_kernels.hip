@@ -192,6 +192,10 @@ k_prep_compact(int64_t N, const double *__restrict__ pos, const double *__restri
 // Abramowitz & Stegun 7.1.6).
 // ---------------------------------------------------------------------------
 __device__ inline bool real_pair(double r, double a, double lam, double *u, double *us, double *f) {
+  // no contraction left to the compiler: every instantiation of the
+  // real-space kernels rounds these terms alike (a system's forces are
+  // bitwise the same alone and in a batch)
+#pragma clang fp contract(off)
   const double k2 = 1.1283791670955125739;  // 2/sqrt(pi)
   if (lam > 0.0 && r < 0.5 * lam) {
     const double x = r / lam, y = 2.0 * x, z = a * r, z2 = z * z;
@@ -264,13 +268,16 @@ __device__ __forceinline__ void real_flush(int qn, const int *qs, const int *qk,
   const int lane = threadIdx.x & (kWave - 1);
   const double4 ci = gload(xq + j);
   for (int e = lane; e < qn; e += kWave) {
+    // minimum image and r^2 with their fused multiply-adds written out (no
+    // contraction left to the compiler, as in real_pair)
+#pragma clang fp contract(off)
     const int k = qk[e];
     const double4 cj = gload(cgrid + qs[e]);
     double dx = ci.x - cj.x, dy = ci.y - cj.y, dz = ci.z - cj.z;
-    dx -= L * rint(dx * invL);
-    dy -= L * rint(dy * invL);
-    dz -= L * rint(dz * invL);
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    dx = fma(-L, rint(dx * invL), dx);
+    dy = fma(-L, rint(dy * invL), dy);
+    dz = fma(-L, rint(dz * invL), dz);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     if (!(r2 < rc2)) continue;  // inside the FP32 margin only
     double u, us, f;
     if (!real_pair(sqrt(r2), alpha, lam, &u, &us, &f)) {
