@@ -82,6 +82,10 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
     const int j = slot[i];
     double fx = 0.0, fy = 0.0, fz = 0.0;
     if (j >= 0) {
+      // the fused multiply-adds of this body are written out (no contraction
+      // left to the compiler): the combine is inlined into several kernels,
+      // which must round alike
+#pragma clang fp contract(off)
       er = (long long)ereal[2 * (size_t)j];
       esl = (long long)ereal[2 * (size_t)j + 1];
       double bx = 0.0, by = 0.0, bz = 0.0, a = 0.0;
@@ -94,9 +98,10 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
         a += v.w;
       }
       const double qj = gload(xq + j).w;
-      fx = (double)(long long)freal[3 * (size_t)j] * kRealFxInv - qj * fscale * bx;
-      fy = (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv - qj * fscale * by;
-      fz = (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv - qj * fscale * bz;
+      const double qs = -(qj * fscale);
+      fx = fma(qs, bx, (double)(long long)freal[3 * (size_t)j] * kRealFxInv);
+      fy = fma(qs, by, (double)(long long)freal[3 * (size_t)j + 1] * kRealFxInv);
+      fz = fma(qs, bz, (double)(long long)freal[3 * (size_t)j + 2] * kRealFxInv);
       eg = qj * a;
     }
     if (fa.mode < 0) {
@@ -104,12 +109,13 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
       forces[3 * i + 1] = fy;
       forces[3 * i + 2] = fz;
     } else {
+#pragma clang fp contract(off)
       const double fe[3] = {fx, fy, fz};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double f = fp[a] + fa.kappa * fe[a];
+        const double f = fma(fa.kappa, fe[a], fp[a]);
         forces[3 * i + a] = f;
-        if (fa.mode == 0) fa.vel[3 * i + a] = vv[a] + 0.5 * fa.dt * f;
+        if (fa.mode == 0) fa.vel[3 * i + a] = fma(0.5 * fa.dt, f, vv[a]);
       }
     }
   }

@@ -46,8 +46,13 @@ __device__ inline double dpd_theta(uint64_t seed, uint64_t step, int i, int j) {
   return 1.7320508075688772935 * (2.0 * u - 1.0);
 }
 
+// The update arithmetic below (wrap, predictor, kicks, drift) states its
+// fused multiply-adds (no contraction left to the compiler): it is inlined
+// into several kernels (one system, batches, fused with the combine), which
+// must round alike.
 __device__ inline double wrap_box(double x, double L) {
-  double y = x - L * floor(x / L);
+#pragma clang fp contract(off)
+  double y = fma(-L, floor(x / L), x);
   if (!(y < L) || y < 0.0) y = 0.0;
   return y;
 }
@@ -86,11 +91,12 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     f[a] = force[3 * i + a];
   }
   if (mode == 0) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      w[a] = v[a] + P.lam * P.dt * f[a];
-      v[a] += 0.5 * P.dt * f[a];
-      r[a] = wrap_box(r[a] + P.dt * v[a], P.L);
+      w[a] = fma(P.lam * P.dt, f[a], v[a]);
+      v[a] = fma(0.5 * P.dt, f[a], v[a]);
+      r[a] = wrap_box(fma(P.dt, v[a], r[a]), P.L);
       vel[3 * i + a] = v[a];
     }
   } else {
