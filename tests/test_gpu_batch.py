@@ -229,18 +229,24 @@ def test_auto_graph_policy_matches_eager():
         assert _same(a, c)
 
 
-def test_tuning_does_not_change_results():
+_TUNED = [dict(pass_threads=512, x_threads=256, stage=128, pair_steps=8, x_split_mul=4, pair_seg=3),
+          dict(pass_threads=256, x_threads=512, stage=32, pair_steps=4, x_split_mul=8, pair_seg=1)]
+
+
+@pytest.mark.parametrize("tuning", _TUNED, ids=["mid", "extremes"])
+def test_tuning_does_not_change_results(tuning):
     """Launch parameters other than the defaults (512-thread mesh passes,
     256-thread x pass, stage 128, 8 pair steps, 4x x-split, 3-cell pair
-    segments) give bitwise the states and energies of the defaults."""
+    segments; or the extremes: stage 32, 8x x-split, 1-cell pair segments)
+    give bitwise the states and energies of the defaults."""
     from paper_1303_4523_amd.batch import Batch
     reps = _replicas([0, 3, 5, 10])
-    print("case: tuning", [r.meta["name"] for r in reps], flush=True)
+    print("case: tuning", tuning, [r.meta["name"] for r in reps], flush=True)
     out = {}
     for tuned in (False, True):
         b = Batch("mixed", device=0)
         if tuned:
-            b.set_tuning(pass_threads=512, x_threads=256, stage=128, pair_steps=8, x_split_mul=4, pair_seg=3)
+            b.set_tuning(**tuning)
         mem = [_member(s) for s in reps]
         for m in mem:
             b.add(*m, first_step=1)
