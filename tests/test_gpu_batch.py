@@ -77,6 +77,33 @@ def test_batch_equals_each_system_alone(use_graph, concurrent):
         d.close()
 
 
+def test_chunked_pair_segments_equal_alone():
+    """A member with 22-25 DPD cells per side: in the batch its whole columns
+    (one segment each) stage more particles than the batched pair kernel's
+    stage holds, so every segment is taken in chunks, with velocities read
+    from their cell slots; alone it runs 10-cell segments with staged
+    velocities and no chunks.  After three replayed steps the states and
+    energies are bitwise equal."""
+    from paper_1303_4523_amd.batch import Batch
+    big = wl.replica(2, n_min=36000, n_max=48000)
+    small = wl.replica(5, n_max=6000)
+    reps = [big, small]
+    print("case: chunked segments", [r.meta["name"] for r in reps], flush=True)
+    b = Batch("mixed", device=0, use_graph=True, concurrent=False)
+    mem = [_member(r) for r in reps]
+    for m in mem:
+        b.add(*m, first_step=1)
+    b.run(3)
+    torch.cuda.synchronize()
+    for r, (d, pos, vel, F) in zip(reps, mem):
+        assert d.status() == 0
+        got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy())
+        assert _same(got, _alone(r, 3)), r.meta["name"]
+    b.close()
+    for m in mem:
+        m[0].close()
+
+
 def test_replayed_runs_of_any_length_equal_eager():
     """Replayed runs fuse each step's combine with the next step's pre kernel
     and alternate the two bin-count sets, the last step of a run using the
