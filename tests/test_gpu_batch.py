@@ -104,6 +104,55 @@ def test_chunked_pair_segments_equal_alone():
         m[0].close()
 
 
+@pytest.mark.parametrize("L,density", [(2.5, 3.0), (6.0, 12.0), (4.0, 40.0)])
+def test_batched_pair_regimes_equal_alone(L, density):
+    """The batched pair kernel's other routes: a grid of 2 cells per side,
+    dense cells whose segments are taken in chunks, and cells so dense that a
+    z-cell's neighbourhood exceeds the stage (candidates and velocities from
+    global memory).  Three replayed batched steps give bitwise the state the
+    system gets stepped alone (whose kernel stages its velocities and takes
+    10-cell segments)."""
+    from paper_1303_4523_amd.batch import Batch
+    from paper_1303_4523_amd.dpd import DPD
+    rs = np.random.default_rng(11)
+    n = int(round(density * L ** 3))
+    pos0 = rs.uniform(0.0, L, (n, 3))
+    vel0 = rs.normal(size=(n, 3))
+    vel0 -= vel0.mean(0)
+    q = np.zeros(n)
+    nq = min(40, 2 * (n // 4))
+    q[:nq // 2] = 1.0
+    q[nq // 2:nq] = -1.0
+    prm = dict(a=25.0, gamma=4.5, sigma=3.0, dt=0.01, lam=0.65, k_bond=4.0, r0_bond=0.7, kappa=1.1, seed=17)
+    M = wl.mesh_size(max(3.2 * L, 16.0))  # the plan needs 2p <= M/2
+    enuf = wl.enuf_params(L, M=M, Kc=max(1, min(int(0.8 * L), M // 4)), r_cut=min(3.0, 0.45 * L))
+    print(f"case: batched pair regime L={L} density={density} N={n} M={M}", flush=True)
+
+    def member():
+        d = DPD(L, q, prm, enuf=enuf, precision="mixed", device=0)
+        pos, vel = _t(pos0), _t(vel0)
+        F = torch.empty_like(pos)
+        d.forces(pos, vel, F, step=0)
+        return d, pos, vel, F
+
+    d, pos, vel, F = member()
+    d.run(pos, vel, F, 1, 3)
+    torch.cuda.synchronize()
+    ref = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy())
+    assert d.status() == 0
+    d.close()
+    b = Batch("mixed", device=0, use_graph=True, concurrent=False)
+    d, pos, vel, F = member()
+    b.add(d, pos, vel, F, first_step=1)
+    b.run(3)
+    torch.cuda.synchronize()
+    got = (pos.cpu().numpy(), vel.cpu().numpy(), F.cpu().numpy(), d.energy().cpu().numpy())
+    assert d.status() == 0
+    b.close()
+    d.close()
+    assert _same(got, ref)
+
+
 def test_replayed_runs_of_any_length_equal_eager():
     """Replayed runs fuse each step's combine with the next step's pre kernel
     and alternate the two bin-count sets, the last step of a run using the
