@@ -51,7 +51,7 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
              gptr<const unsigned long long> freal, gptr<const double4> __restrict__ part, int P2S,
              double fscale, int nblk, double *blk_eg, gptr<const unsigned long long> __restrict__ ereal,
              long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, const FinishArgs &fa, double *forces,
-             int bid) {
+             int bid, double *f_out = nullptr, double *v_out = nullptr) {
   __shared__ double s_dbl[kPrepThreads / kWave];
   __shared__ long long s_ll[kPrepThreads / kWave];
   const int tid = threadIdx.x;
@@ -115,7 +115,16 @@ combine_body(int64_t N, gptr<const int> __restrict__ slot, gptr<const double4> _
       for (int a = 0; a < 3; ++a) {
         const double f = fma(fa.kappa, fe[a], fp[a]);
         forces[3 * i + a] = f;
-        if (fa.mode == 0) fa.vel[3 * i + a] = fma(0.5 * fa.dt, f, vv[a]);
+        const double v = fma(0.5 * fa.dt, f, vv[a]);
+        // a fused next step (v_out) takes the force and the half-kicked
+        // velocity from here and stores the velocity after its own kick, so
+        // this store would be overwritten by the same thread
+        if (v_out) {
+          f_out[a] = f;
+          v_out[a] = v;
+        } else if (fa.mode == 0) {
+          fa.vel[3 * i + a] = v;
+        }
       }
     }
   }

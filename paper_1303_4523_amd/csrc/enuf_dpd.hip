@@ -62,15 +62,9 @@ __device__ inline int dpd_cell_of(double x, double inv_cell, int n) {
   return c < n ? (c < 0 ? 0 : c) : n - 1;
 }
 
-// mode 0: full predictor / half kick / drift; mode 1: forces only (v0 = v).
-// Each particle is binned into a slot of its DPD cell together with its
-// position (and index) and predicted velocity, so that the pair kernel reads
-// neighbour data contiguously.
-__device__ __forceinline__ void
-dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, double *__restrict__ vel,
-             const double *__restrict__ force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
-             const DpdCharges &ch, int bid) {
-  const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
+// The plan scalars of the charges (static for a DPD system), written by
+// particle 0's thread.
+__device__ __forceinline__ void dpd_pre_scalars(const DpdCharges &ch, int64_t i) {
   if (ch.enabled && i == 0) {
     ch.sc->nq = ch.stat.nq;
     ch.sc->scale = ch.stat.scale;
@@ -79,17 +73,25 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
     ch.sc->sum_absq = ch.stat.sum_absq;
     ch.sc->sum_q2 = ch.stat.sum_q2;
   }
-  if (i >= N) return;
-  // the static compaction slot and charge are loaded with the state
+}
+
+// Compaction slot j of particle i (-1: neutral) and its charge.
+__device__ __forceinline__ int dpd_pre_slot(const DpdCharges &ch, int64_t i, double *qi) {
   const int j = ch.enabled ? ch.dslot[i] : -1;
-  const double qi = j >= 0 ? ch.q[i] : 0.0;
-  double r[3], v[3], f[3], w[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r[a] = pos[3 * i + a];
-    v[a] = vel[3 * i + a];
-    f[a] = force[3 * i + a];
-  }
+  *qi = j >= 0 ? ch.q[i] : 0.0;
+  return j;
+}
+
+// The pre step of particle i < N from its position r, velocity v and force f.
+// mode 0: full predictor / half kick / drift; mode 1: forces only (v0 = v).
+// Each particle is binned into a slot of its DPD cell together with its
+// position (and index) and predicted velocity, so that the pair kernel reads
+// neighbour data contiguously.
+__device__ __forceinline__ void
+dpd_pre_particle(int64_t i, int mode, const DpdParams &P, double *r, double *v, const double *f, int j, double qi,
+                 double *__restrict__ pos, double *__restrict__ vel, int *dcnt, double4 *cpos, double4 *cvel,
+                 int *status, const DpdCharges &ch) {
+  double w[3];
   if (mode == 0) {
 #pragma clang fp contract(off)
 #pragma unroll
@@ -154,6 +156,26 @@ dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, 
         atomicCAS(&ch.sc->status, 0, kEOverflow);
     }
   }
+}
+
+__device__ __forceinline__ void
+dpd_pre_body(int64_t N, int mode, const DpdParams &P, double *__restrict__ pos, double *__restrict__ vel,
+             const double *__restrict__ force, int *dcnt, double4 *cpos, double4 *cvel, int *status,
+             const DpdCharges &ch, int bid) {
+  const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
+  dpd_pre_scalars(ch, i);
+  if (i >= N) return;
+  // the static compaction slot and charge are loaded with the state
+  double qi;
+  const int j = dpd_pre_slot(ch, i, &qi);
+  double r[3], v[3], f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = pos[3 * i + a];
+    v[a] = vel[3 * i + a];
+    f[a] = force[3 * i + a];
+  }
+  dpd_pre_particle(i, mode, P, r, v, f, j, qi, pos, vel, dcnt, cpos, cvel, status, ch);
 }
 
 __global__ void __launch_bounds__(256)
@@ -635,17 +657,31 @@ k_combine_pre(int64_t N, const int *__restrict__ slot, const double4 *__restrict
               long long *blk_er, int *ccnt, int ncell3, int *xcnt, int M, FinishArgs fa, double *forces,
               DpdParams P, double *pos, int *dcnt, double4 *cpos, double4 *cvel, int *status,
               DpdCharges ch) {
+  // the next step's own loads (position, compaction slot, charge) go out with
+  // the combine's; the new force and half-kicked velocity stay in registers
+  // (the velocity is stored once, after the next step's kick).  No barrier:
+  // a thread's two halves touch only its own particle, and the combine
+  // clears one set of bin counts while the pre part fills the other.
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0}, qi = 0.0, f[3], v[3];
+  int j = -1;
+  if (i < N) {
+    j = dpd_pre_slot(ch, i, &qi);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] = pos[3 * i + a];
+  }
   combine_body(N, to_g(slot), to_g(xq), to_g(freal), to_g(part), P2S, fscale, nblk, blk_eg, to_g(ereal), blk_er,
-               ccnt, ncell3, xcnt, M * kXSub, fa, forces, blockIdx.x);
-  __syncthreads();  // the step's loads and stores come before the next step's
-  dpd_pre_body(N, 0, P, pos, fa.vel, forces, dcnt, cpos, cvel, status, ch, blockIdx.x);
+               ccnt, ncell3, xcnt, M * kXSub, fa, forces, blockIdx.x, f, v);
+  dpd_pre_scalars(ch, i);
+  if (i < N) dpd_pre_particle(i, 0, P, r, v, f, j, qi, pos, fa.vel, dcnt, cpos, cvel, status, ch);
 }
 
 hipError_t launch_combine_pre(const ComputeConfig &cfg, const ComputeBuffers &b, double *forces,
                               const FinishArgs &fa, const DpdParams &P, double *pos, int *dcnt, double4 *cpos,
                               double4 *cvel, int *status, const DpdCharges &ch, hipStream_t st, KernelTimer *tm) {
-  // the per-block energy partials are sized for blocks of kPrepThreads
-  if (fa.energies) return hipErrorInvalidValue;
+  // the per-block energy partials are sized for blocks of kPrepThreads; the
+  // fused pre step takes the combine's half-kicked velocities (mode 0 only)
+  if (fa.energies || fa.mode != 0) return hipErrorInvalidValue;
   const double fscale = combine_fscale(cfg);
   const int nb = (int)((cfg.N + kCombinePreThreads - 1) / kCombinePreThreads);
   if (tm) tm->before(9, st);
@@ -696,11 +732,22 @@ kb_combine_pre(const BatchMember *__restrict__ mem, const int2 *__restrict__ map
   fa.energies = 0;
   fa.step_inc = m.step;
   const int nc = m.cfg.cells.ncell;
+  // as in k_combine_pre: the next step's loads early, force and velocity in
+  // registers, the velocity stored once
+  const int64_t i = (int64_t)w.y * blockDim.x + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0}, qi = 0.0, f[3], v[3];
+  int j = -1;
+  if (i < m.N) {
+    j = dpd_pre_slot(m.ch_next, i, &qi);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] = m.pos[3 * i + a];
+  }
   combine_body(m.N, to_g(m.buf.slot), to_g(m.buf.xq), to_g(m.buf.freal), to_g(m.buf.part),
                2 * m.cfg.mesh.win.p * m.cfg.mesh.nslot, m.fscale, m.nblk, m.buf.blk_eg, to_g(m.buf.ereal),
-               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M * kXSub, fa, m.force, w.y);
-  __syncthreads();  // the step's loads and stores come before the next step's
-  dpd_pre_body(m.N, 0, m.P, m.pos, m.vel, m.force, m.dcnt_next, m.cpos, m.cvel, m.status, m.ch_next, w.y);
+               m.buf.blk_er, m.buf.ccnt, nc * nc * nc, m.buf.xcnt, m.cfg.mesh.M * kXSub, fa, m.force, w.y, f, v);
+  dpd_pre_scalars(m.ch_next, i);
+  if (i < m.N)
+    dpd_pre_particle(i, 0, m.P, r, v, f, j, qi, m.pos, m.vel, m.dcnt_next, m.cpos, m.cvel, m.status, m.ch_next);
 }
 
 __global__ void k_set_u64(unsigned long long *dst, unsigned long long value) {
